@@ -1,0 +1,185 @@
+/*
+ * tdp.h -- C ABI of the MI355X time-domain preconditioner for the Helmholtz
+ * equation (C. C. Stolk, "A time-domain preconditioner for the Helmholtz
+ * equation").
+ *
+ * Problem (Sec. 1, eq. 3 and the linear system H U = F of Sec. 1):
+ *     -Lap U - omega^2/c(x)^2 U + i omega R(x) U = F
+ * on an interior grid of n_0 x n_1 [x n_2] nodes with spacing h and U = 0
+ * outside the box (Dirichlet, Sec. 3.1).  Re H is the compact 9-point (2-D) /
+ * 27-point cube (3-D) stencil assembled cell by cell (App. A): each grid cell
+ * couples its corners b, g with h^-2 S[Delta] - omega^2 m_cell M[Delta],
+ * Delta = number of axes on which b and g differ, m_cell the mean of 1/c^2
+ * over the cell's corners (corners outside the box take the nearest interior
+ * node).  Im H = diag(omega R).
+ *
+ * Conventions for every entry point:
+ *  - Arrays are DEVICE pointers owned by the caller, contiguous, row-major
+ *    [n0][n1][n2] (last axis fastest).  Complex arrays are interleaved
+ *    complex128 (re, im pairs; torch.complex128).  Real node arrays are FP64.
+ *  - All work is issued on the op's stream (tdp_op_desc.stream).  Calls that
+ *    return results to the host (gmres) synchronise that stream.
+ *  - Return value: TDP_OK (0), a positive status for a completed call with a
+ *    caveat, or a negative error.  On a negative return nothing was written
+ *    to the output arrays.  tdp_last_error() gives a message (per thread).
+ *  - The op never keeps caller pointers after a call returns.  Input and
+ *    output arrays of one call must not overlap.
+ *  - One op must not be used by two host threads at the same time.
+ */
+#ifndef TDP_H
+#define TDP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TDP_OK = 0,
+    TDP_ENOTCONV = 1,   /* gmres: iteration limit reached, U holds the last iterate */
+    TDP_EINVAL = -1,    /* invalid argument (sizes, c <= 0, R < 0, h <= 0, ...)     */
+    TDP_ENOMEM = -2,    /* device allocation failed                                 */
+    TDP_EHIP = -3,      /* HIP runtime error                                        */
+    TDP_ECFL = -4       /* requested steps per period violate the CFL bound         */
+};
+
+typedef enum { TDP_F64 = 0, TDP_F32 = 1 } tdp_prec;
+
+typedef struct tdp_op tdp_op;
+
+/* Operator description (Sec. 2.2: the preconditioner's parameters follow from
+ * H alone).
+ *  ndim              2 or 3
+ *  n[0..ndim-1]      interior nodes per axis (>= 1); n[ndim..2] ignored
+ *  h                 grid spacing (> 0)
+ *  omega             physical angular frequency (> 0)
+ *  c                 device, [N] wave speed at the nodes (> 0)
+ *  R                 device, [N] damping at the nodes (>= 0), or NULL for 0
+ *  stiff, mass       HOST, ndim+1 cell-table entries each (by Delta = 0..d);
+ *                    NULL selects the classical fourth-order compact scheme:
+ *                    2-D S = {5/6, -1/3, -1/6},  M = {1/6, 1/24, 0}
+ *                    3-D S = {1/2, -1/12, -1/12, 0}, M = {1/16, 1/48, 0, 0}.
+ *                    The cell tables must be positive semidefinite as element
+ *                    matrices with max eigenvalue of M <= 2^-d (App. A bound).
+ *  steps_per_period  n_P; 0 selects the smallest multiple of 4 above the CFL
+ *                    bound of Sec. 2.2; a given value must be a multiple of 4
+ *                    above that bound, else TDP_ECFL.
+ *  prec              precision of the recurrence fields (Table 1 loop).
+ *                    Krylov vectors, H and the residuals are always FP64.
+ *  stream            hipStream_t every call of this op issues its work on.
+ *                    NULL (the default stream) makes the op use a private
+ *                    stream ordered after / before the default stream at
+ *                    each call's entry / exit (the step loop is captured
+ *                    into a graph, which the default stream cannot hold). */
+typedef struct {
+    int ndim;
+    int64_t n[3];
+    double h;
+    double omega;
+    const double *c;
+    const double *R;
+    const double *stiff;
+    const double *mass;
+    int steps_per_period;
+    int prec;
+    void *stream;
+} tdp_op_desc;
+
+/* Derived parameters (Sec. 2.2, Prop. 1): omega_c = omega sqrt(max m_cell)
+ * (computational frequency), dt = 2 pi / (omega_c n_P),
+ * alpha = (omega_c dt)^2 / (4 sin^2(omega_c dt / 2)),
+ * beta = omega_c dt / sin(omega_c dt), lam_bar = upper bound on lambda_max(A). */
+typedef struct {
+    double omega_c, dt, alpha, beta, lam_bar;
+    int n_P;
+    int ndim;
+    int64_t N;
+} tdp_op_info;
+
+/* GMRES configuration (Sec. 2.4: left preconditioning P H U = P F with
+ * P = S_T of Table 1).
+ *  restart      Krylov dimension m per cycle (>= 1)
+ *  max_iters    limit on preconditioned operator applications (>= 1)
+ *  periods_T    T, periods per preconditioner application (N_s = T n_P)
+ *  rho          window parameter in (0, 1]; <= 0 means rho = 1/T
+ *  tol          target for the true relative residual ||F - H U|| / ||F||
+ *  x0_given     1: U holds the initial guess on entry; 0: start from 0
+ *  fixed_iters  > 0: run exactly this many iterations, no early stop      */
+typedef struct {
+    int restart, max_iters, periods_T;
+    double rho, tol;
+    int x0_given;
+    int fixed_iters;
+} tdp_gmres_cfg;
+
+/* GMRES report (host struct).  history (host, may be NULL) receives the
+ * Givens estimate of ||P r|| / ||P r_0|| after each iteration, up to
+ * history_cap entries. */
+typedef struct {
+    int iters, restarts;
+    double relres_true, relres_prec;
+    int64_t steps;           /* recurrence steps executed               */
+    double ms_total;         /* host wall time of the call              */
+    double *history;
+    int history_cap, history_len;
+} tdp_gmres_info;
+
+/* Create an operator: validates the description, copies c and R, computes
+ * the cell slowness, omega_c, n_P, dt, alpha, beta and per-node damping
+ * factors, and allocates the recurrence fields.  Sec. 2.2, App. A. */
+int tdp_op_create(const tdp_op_desc *desc, tdp_op **out);
+
+/* Free an operator and its device buffers (NULL is accepted). */
+int tdp_op_destroy(tdp_op *op);
+
+/* Copy the derived parameters to *out (host). */
+int tdp_op_query(const tdp_op *op, tdp_op_info *out);
+
+/* y = H x.  x, y: device complex128 [N].  Sec. 1 (H U = F), App. A. */
+int tdp_apply_H(const tdp_op *op, const void *x, void *y);
+
+/* U = S_T F, the real-field algorithm of Table 1 (Sec. 2.3): zero fields,
+ * N_s = T n_P steps of the integrator I_acd (Def. 2) driven by
+ * chi(1 - j/N_s) [cos(2 pi j/n_P) Re F - sin(2 pi j/n_P) Im F], then
+ * U = u_{N_s} + i u_{N_s - n_P/4}.  chi is the sine-square window with
+ * parameter rho (rho <= 0: rho = 1/T).  F, U: device complex128 [N]. */
+int tdp_precond_apply(const tdp_op *op, int periods_T, double rho, const void *F, void *U);
+
+/* Solve H U = F with left-preconditioned restarted GMRES (Sec. 2.4).
+ * Stops when the true relative residual is <= tol (recomputed in FP64 after
+ * each cycle); a cycle ends when the Givens estimate of the preconditioned
+ * residual drops below an inner tolerance (tightened by tol/true on each
+ * restart) or after `restart` iterations.  Returns TDP_OK, or TDP_ENOTCONV
+ * with the last iterate in U.  F, U: device complex128 [N]; info: host or NULL. */
+int tdp_gmres_solve(const tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void *U,
+                    tdp_gmres_info *info);
+
+/* Gradient of a real loss with respect to the squared slowness m = 1/c^2 at
+ * the nodes, given U = H^-1 F and the adjoint field lam = H^-H (dL/dU*):
+ * dL/dm_cell = omega^2 Re sum_{b,g in cell} M[Delta(b,g)] conj(lam_b) U_g
+ * (since dH/dm_cell = -omega^2 M_cell), mapped to the nodes by the adjoint of
+ * the corner averaging that defines m_cell.  lam, U: device complex128 [N];
+ * grad: device FP64 [N] (overwritten). */
+int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
+
+/* Tuning of the recurrence sweep (no effect on results beyond rounding).
+ *  kernel       0 auto, 1 one step per launch, 2 temporally blocked
+ *  tb_depth     steps per launch for the blocked kernel (0 auto)
+ *  use_graph    1 capture the step loop in a hipGraph and replay it        */
+typedef struct {
+    int kernel;
+    int tb_depth;
+    int use_graph;
+} tdp_tuning;
+
+int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t);
+int tdp_op_get_tuning(const tdp_op *op, tdp_tuning *t);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *tdp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,625 @@
+// HIP kernels of libtdp for CDNA4 (gfx950): the fused recurrence sweep of the
+// time-domain preconditioner (Table 1 with the integrator I_acd of Def. 2),
+// the complex H-apply, setup kernels, Krylov BLAS-1 kernels with
+// deterministic FP64 reductions, and the m-gradient contraction.
+//
+// Data layout: node arrays row-major [n0][n1][n2] (last axis fastest); cell
+// arrays [(n0+1)][(n1+1)][(n2+1)], cell with storage index (z, y, x) has lower
+// corner (z-1, y-1, x-1), so the 2^d cells around node (z, y, x) are the
+// storage cells (z+ez, y+ey, x+ex), e in {0,1}^d.  In 2-D the z axis is absent
+// (nz = 1, z = 0) and the two node axes are (y, x) = (axis 0, axis 1).
+#include <hip/hip_runtime.h>
+
+#include "tdp_internal.h"
+
+namespace tdp {
+
+template <typename T>
+struct V2;
+template <>
+struct V2<double> {
+    using type = double2;
+};
+template <>
+struct V2<float> {
+    using type = float2;
+};
+
+// ---------------------------------------------------------------------------
+// assembled stencil: see Stencil<T> in tdp_internal.h.  w[e] are the 2^D
+// cell values around the node, e = ex + 2 ey (+ 4 ez).  U(oz, oy, ox)
+// returns the field at the offset node (0 outside the box).
+template <int D, int SC, int MC, typename T, typename LoadU>
+__device__ __forceinline__ T eval_stencil(const LoadU &U, const T *w, const Stencil<T> &st)
+{
+    constexpr int NC = SC > MC ? SC : MC;
+    constexpr int NOFF = D == 2 ? 9 : 27;
+    T us[4] = {T(0), T(0), T(0), T(0)};
+    T ws[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < NOFF; ++k) {
+        const int ox = k % 3 - 1, oy = (k / 3) % 3 - 1, oz = D == 3 ? k / 9 - 1 : 0;
+        const int cls = (ox != 0) + (oy != 0) + (oz != 0);
+        if (cls >= NC) continue;
+        const T v = U(oz, oy, ox);
+        if (cls < SC || cls == 0) us[cls] += v;
+        if (cls < MC) {
+            T W = T(0);
+#pragma unroll
+            for (int e = 0; e < (1 << D); ++e) {
+                const int ex = e & 1, ey = (e >> 1) & 1, ez = D == 3 ? (e >> 2) & 1 : 0;
+                const bool okx = ox == 0 || (ox < 0 ? ex == 0 : ex == 1);
+                const bool oky = oy == 0 || (oy < 0 ? ey == 0 : ey == 1);
+                const bool okz = D == 2 || oz == 0 || (oz < 0 ? ez == 0 : ez == 1);
+                if (okx && oky && okz) W += w[e];
+            }
+            ws[cls] += W * v;
+        }
+    }
+    T r = st.c0 * us[0];
+#pragma unroll
+    for (int k = 1; k < SC; ++k) r += st.s[k] * us[k];
+#pragma unroll
+    for (int k = 0; k < MC; ++k) r += st.m[k] * ws[k];
+    return r;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void load_cells(const T *__restrict__ m, int z, int y, int x, int ny,
+                                           int nx, T *w)
+{
+    const int64_t cy = nx + 1, cz = (int64_t)(ny + 1) * (nx + 1);
+    const int64_t c = (int64_t)z * cz + (int64_t)y * cy + x;
+#pragma unroll
+    for (int e = 0; e < (1 << D); ++e) {
+        const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+        w[e] = m[c + ez * cz + ey * cy + ex];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// one recurrence step (Def. 2 with the Table 1 forcing), one node per thread:
+//   u_{j+1} = d (S[u_j] + fa Re F + fb Im F) - (2d - 1) u_{j-1},
+// S[.] the stencil with the step constants (it equals (2 - K) u), d = 1/(1+l/2).
+// u_{j+1} overwrites u_{j-1} in place.
+template <int D, int SC, int MC, typename T>
+__global__ __launch_bounds__(256) void k_sweep(const T *__restrict__ u, T *__restrict__ up,
+                                               const T *__restrict__ m,
+                                               const T *__restrict__ dn,
+                                               const typename V2<T>::type *__restrict__ F,
+                                               int nz, int ny, int nx, Stencil<T> st, T fa,
+                                               T fb, double *__restrict__ out)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= nx || y >= ny) return;
+    const int64_t i = ((int64_t)z * ny + y) * nx + x;
+    T w[1 << D];
+    load_cells<D>(m, z, y, x, ny, nx, w);
+    auto U = [&](int oz, int oy, int ox) -> T {
+        const bool in = (unsigned)(y + oy) < (unsigned)ny && (unsigned)(x + ox) < (unsigned)nx &&
+                        (D == 2 || (unsigned)(z + oz) < (unsigned)nz);
+        return in ? u[i + ((int64_t)oz * ny + oy) * nx + ox] : T(0);
+    };
+    const T acc = eval_stencil<D, SC, MC>(U, w, st);
+    const auto f = F[i];
+    const T d = dn[i];
+    const T r = d * (acc + fa * f.x + fb * f.y) - (T(2) * d - T(1)) * up[i];
+    up[i] = r;
+    if (out) out[2 * i] = (double)r;
+}
+
+template <typename T>
+static hipError_t launch_sweep_t(const SweepArgs &a, const Stencil<T> &st, T fa, T fb,
+                                 hipStream_t s)
+{
+    const int nz = a.ndim == 3 ? a.n[0] : 1;
+    const int ny = a.ndim == 3 ? a.n[1] : a.n[0];
+    const int nx = a.ndim == 3 ? a.n[2] : a.n[1];
+    dim3 blk(64, 4, 1);
+    dim3 grd((nx + 63) / 64, (ny + 3) / 4, nz);
+    const T *u = (const T *)a.u;
+    T *up = (T *)a.up;
+    const T *m = (const T *)a.m;
+    const T *dn = (const T *)a.dn;
+    const auto *F = (const typename V2<T>::type *)a.F;
+#define TDP_SWEEP(D, SC, MC) \
+    hipLaunchKernelGGL((k_sweep<D, SC, MC, T>), grd, blk, 0, s, u, up, m, dn, F, nz, ny, nx, st, fa, fb, a.out)
+    if (a.ndim == 2) {
+        if (a.sc <= 3 && a.mc <= 2) TDP_SWEEP(2, 3, 2);
+        else TDP_SWEEP(2, 3, 3);
+    } else {
+        if (a.sc <= 3 && a.mc <= 2) TDP_SWEEP(3, 3, 2);
+        else TDP_SWEEP(3, 4, 4);
+    }
+#undef TDP_SWEEP
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_f64(const SweepArgs &a, const Stencil<double> &st, double fa, double fb,
+                            hipStream_t s)
+{
+    return launch_sweep_t<double>(a, st, fa, fb, s);
+}
+
+hipError_t launch_sweep_f32(const SweepArgs &a, const Stencil<float> &st, float fa, float fb,
+                            hipStream_t s)
+{
+    return launch_sweep_t<float>(a, st, fa, fb, s);
+}
+
+// ---------------------------------------------------------------------------
+// complex H-apply: y = H x or y = F - H x, H = stencil + i diag(rw)
+template <int D, int SC, int MC>
+__global__ __launch_bounds__(256) void k_apply_H(const double *__restrict__ m,
+                                                 const double *__restrict__ rw,
+                                                 Stencil<double> st,
+                                                 const double2 *__restrict__ xv,
+                                                 const double2 *__restrict__ F,
+                                                 double2 *__restrict__ y_out, int nz, int ny,
+                                                 int nx)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= nx || y >= ny) return;
+    const int64_t i = ((int64_t)z * ny + y) * nx + x;
+    double w[1 << D];
+    load_cells<D>(m, z, y, x, ny, nx, w);
+    const double *xs = (const double *)xv;
+    auto Ur = [&](int oz, int oy, int ox) -> double {
+        const bool in = (unsigned)(y + oy) < (unsigned)ny && (unsigned)(x + ox) < (unsigned)nx &&
+                        (D == 2 || (unsigned)(z + oz) < (unsigned)nz);
+        return in ? xs[2 * (i + ((int64_t)oz * ny + oy) * nx + ox)] : 0.0;
+    };
+    auto Ui = [&](int oz, int oy, int ox) -> double {
+        const bool in = (unsigned)(y + oy) < (unsigned)ny && (unsigned)(x + ox) < (unsigned)nx &&
+                        (D == 2 || (unsigned)(z + oz) < (unsigned)nz);
+        return in ? xs[2 * (i + ((int64_t)oz * ny + oy) * nx + ox) + 1] : 0.0;
+    };
+    const double hr = eval_stencil<D, SC, MC>(Ur, w, st);
+    const double hi = eval_stencil<D, SC, MC>(Ui, w, st);
+    const double2 xc = xv[i];
+    const double r = rw[i];
+    double2 o;
+    o.x = hr - r * xc.y;
+    o.y = hi + r * xc.x;
+    if (F) {
+        const double2 f = F[i];
+        o.x = f.x - o.x;
+        o.y = f.y - o.y;
+    }
+    y_out[i] = o;
+}
+
+hipError_t launch_apply_H(int ndim, const int *n, int sc, int mc, const double *m,
+                          const double *rw, const Stencil<double> &st, const void *x,
+                          const void *F, void *y, hipStream_t s)
+{
+    const int nz = ndim == 3 ? n[0] : 1;
+    const int ny = ndim == 3 ? n[1] : n[0];
+    const int nx = ndim == 3 ? n[2] : n[1];
+    dim3 blk(64, 4, 1);
+    dim3 grd((nx + 63) / 64, (ny + 3) / 4, nz);
+    const double2 *xv = (const double2 *)x;
+    const double2 *Fv = (const double2 *)F;
+    double2 *yv = (double2 *)y;
+#define TDP_HAPPLY(D, SC, MC) \
+    hipLaunchKernelGGL((k_apply_H<D, SC, MC>), grd, blk, 0, s, m, rw, st, xv, Fv, yv, nz, ny, nx)
+    if (ndim == 2) {
+        if (sc <= 3 && mc <= 2) TDP_HAPPLY(2, 3, 2);
+        else TDP_HAPPLY(2, 3, 3);
+    } else {
+        if (sc <= 3 && mc <= 2) TDP_HAPPLY(3, 3, 2);
+        else TDP_HAPPLY(3, 4, 4);
+    }
+#undef TDP_HAPPLY
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// elementwise helpers
+__global__ void k_fill_zero(uint32_t *p, int64_t nwords)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+static int grid_for(int64_t n, int per_block = 256)
+{
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
+{
+    const int64_t nw = (int64_t)(bytes / 4);
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(nw)), dim3(256), 0, s, (uint32_t *)p, nw);
+    return hipGetLastError();
+}
+
+__global__ void k_cvt_c128_c64(const double2 *__restrict__ a, float2 *__restrict__ b, int64_t N)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 v = a[i];
+        b[i] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+hipError_t launch_cvt_c128_to_c64(const void *F, void *Fs, int64_t N, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cvt_c128_c64, dim3(grid_for(N)), dim3(256), 0, s, (const double2 *)F,
+                       (float2 *)Fs, N);
+    return hipGetLastError();
+}
+
+__global__ void k_cvt_f64_f32(const double *__restrict__ a, float *__restrict__ b, int64_t N)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+hipError_t launch_cvt_f64_to_f32(const double *x, float *y, int64_t N, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cvt_f64_f32, dim3(grid_for(N)), dim3(256), 0, s, x, y, N);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// setup: m_cell = 2^-D sum over corners of 1/c^2 (corner indices clamped)
+template <int D>
+__global__ void k_cell_slowness(const double *__restrict__ c, double *__restrict__ m, int nz,
+                                int ny, int nx)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;   // storage 0..nx
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;   // storage 0..ny
+    const int z = blockIdx.z;                              // storage 0..nz (3-D)
+    if (x > nx || y > ny) return;
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < (1 << D); ++e) {
+        const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+        int cx = x - 1 + ex, cy = y - 1 + ey, cz = D == 3 ? z - 1 + ez : 0;
+        cx = cx < 0 ? 0 : (cx >= nx ? nx - 1 : cx);
+        cy = cy < 0 ? 0 : (cy >= ny ? ny - 1 : cy);
+        cz = cz < 0 ? 0 : (cz >= nz ? nz - 1 : cz);
+        const double v = c[((int64_t)cz * ny + cy) * nx + cx];
+        s += 1.0 / (v * v);
+    }
+    m[((int64_t)z * (ny + 1) + y) * (nx + 1) + x] = s * (1.0 / (1 << D));
+}
+
+hipError_t launch_cell_slowness(int ndim, const int *n, const double *c, double *m,
+                                hipStream_t s)
+{
+    const int nz = ndim == 3 ? n[0] : 1;
+    const int ny = ndim == 3 ? n[1] : n[0];
+    const int nx = ndim == 3 ? n[2] : n[1];
+    dim3 blk(64, 4, 1);
+    dim3 grd((nx + 1 + 63) / 64, (ny + 1 + 3) / 4, ndim == 3 ? nz + 1 : 1);
+    if (ndim == 2)
+        hipLaunchKernelGGL(k_cell_slowness<2>, grd, blk, 0, s, c, m, nz, ny, nx);
+    else
+        hipLaunchKernelGGL(k_cell_slowness<3>, grd, blk, 0, s, c, m, nz, ny, nx);
+    return hipGetLastError();
+}
+
+// wave64 + LDS block reductions (blockDim.x == 256)
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_max_partial(const double *__restrict__ x, int64_t N,
+                                                     double *__restrict__ partial)
+{
+    __shared__ double sm[4];
+    double v = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x)
+        v = fmax(v, x[i]);
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+}
+
+__global__ __launch_bounds__(256) void k_max_final(const double *__restrict__ partial, int nblk,
+                                                   double *__restrict__ out)
+{
+    __shared__ double sm[4];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) v = fmax(v, partial[i]);
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+}
+
+hipError_t launch_max_reduce(const double *x, int64_t N, double *partial, int nblk,
+                             double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_max_partial, dim3(nblk), dim3(256), 0, s, x, N, partial);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, partial, nblk, out);
+    return hipGetLastError();
+}
+
+// rw = omega R,  dn = 1 / (1 + l/2) with l = lscale R   (L of Def. 2)
+__global__ void k_node_factors(const double *__restrict__ R, int64_t N, double omega,
+                               double lscale, double *__restrict__ rw, double *__restrict__ dn)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double r = R ? R[i] : 0.0;
+        rw[i] = omega * r;
+        dn[i] = 1.0 / (1.0 + 0.5 * lscale * r);
+    }
+}
+
+hipError_t launch_node_factors(const double *R, int64_t N, double omega, double lscale,
+                               double *rw, double *dn, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_node_factors, dim3(grid_for(N)), dim3(256), 0, s, R, N, omega, lscale,
+                       rw, dn);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Krylov BLAS-1 (complex128).  Reductions: per-block partial sums in a fixed
+// order, then one block per output sums the partials in a fixed order, so
+// results are bitwise reproducible run to run.
+int blas_nblocks(int64_t N)
+{
+    int64_t b = (N + 1023) / 1024;
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+__global__ __launch_bounds__(256) void k_mdot_partial(const double2 *__restrict__ V, int64_t ldv,
+                                                      const double2 *__restrict__ w, int64_t N,
+                                                      double *__restrict__ partial)
+{
+    __shared__ double sm[8];
+    const int k = blockIdx.y;
+    const double2 *v = V + (int64_t)k * ldv;
+    double re = 0.0, im = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 a = v[i], b = w[i];
+        re += a.x * b.x + a.y * b.y;     // conj(a) * b
+        im += a.x * b.y - a.y * b.x;
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if ((threadIdx.x & 63) == 0) {
+        sm[threadIdx.x >> 6] = re;
+        sm[4 + (threadIdx.x >> 6)] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double* p = partial + 2 * ((int64_t)k * gridDim.x + blockIdx.x);
+        p[0] = (sm[0] + sm[1]) + (sm[2] + sm[3]);
+        p[1] = (sm[4] + sm[5]) + (sm[6] + sm[7]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mdot_final(const double *__restrict__ partial, int nblk,
+                                                    double *__restrict__ out)
+{
+    __shared__ double sm[8];
+    const int k = blockIdx.x;
+    const double *p = partial + 2 * (int64_t)k * nblk;
+    double re = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+        re += p[2 * i];
+        im += p[2 * i + 1];
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if ((threadIdx.x & 63) == 0) {
+        sm[threadIdx.x >> 6] = re;
+        sm[4 + (threadIdx.x >> 6)] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[2 * k] = (sm[0] + sm[1]) + (sm[2] + sm[3]);
+        out[2 * k + 1] = (sm[4] + sm[5]) + (sm[6] + sm[7]);
+    }
+}
+
+hipError_t launch_mdot(const void *V, int64_t ldv, int nv, const void *w, int64_t N,
+                       double *partial, int nblk, double *out, hipStream_t s)
+{
+    if (nv <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mdot_partial, dim3(nblk, nv), dim3(256), 0, s, (const double2 *)V, ldv,
+                       (const double2 *)w, N, partial);
+    hipLaunchKernelGGL(k_mdot_final, dim3(nv), dim3(256), 0, s, partial, nblk, out);
+    return hipGetLastError();
+}
+
+// w += sign * sum_k coef[k] V_k   (coef: device complex128 [nv])
+__global__ __launch_bounds__(256) void k_maxpy(double2 *__restrict__ w,
+                                               const double2 *__restrict__ V, int64_t ldv,
+                                               int nv, const double *__restrict__ coef,
+                                               double sign, int64_t N)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k < nv; ++k) {
+            const double2 v = V[(int64_t)k * ldv + i];
+            const double cr = coef[2 * k], ci = coef[2 * k + 1];
+            re += cr * v.x - ci * v.y;
+            im += cr * v.y + ci * v.x;
+        }
+        double2 o = w[i];
+        o.x += sign * re;
+        o.y += sign * im;
+        w[i] = o;
+    }
+}
+
+hipError_t launch_maxpy(void *w, const void *V, int64_t ldv, int nv, const double *coef,
+                        double sign, int64_t N, hipStream_t s)
+{
+    if (nv <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_maxpy, dim3(grid_for(N)), dim3(256), 0, s, (double2 *)w,
+                       (const double2 *)V, ldv, nv, coef, sign, N);
+    return hipGetLastError();
+}
+
+__global__ void k_scale_invnorm(double2 *v, const double2 *w,
+                                const double *__restrict__ nrm2, int64_t N)
+{
+    const double s = 1.0 / sqrt(nrm2[0]);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 a = w[i];
+        v[i] = make_double2(a.x * s, a.y * s);
+    }
+}
+
+hipError_t launch_scale_by_invnorm(void *v, const void *w, const double *nrm2, int64_t N,
+                                   hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale_invnorm, dim3(grid_for(N)), dim3(256), 0, s, (double2 *)v,
+                       (const double2 *)w, nrm2, N);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// gradient: g_cell = w2 Re sum_{b,g in cell} M[Delta(b,g)] conj(lam_b) U_g
+struct MassTable {
+    double M[4];
+};
+
+template <int D>
+__global__ void k_grad_cells(const double2 *__restrict__ lam, const double2 *__restrict__ U,
+                             MassTable mt, double w2, double *__restrict__ gcell, int nz,
+                             int ny, int nx)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;   // storage 0..nx
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x > nx || y > ny) return;
+    double2 lv[1 << D], uv[1 << D];
+    bool ok[1 << D];
+#pragma unroll
+    for (int e = 0; e < (1 << D); ++e) {
+        const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+        const int cx = x - 1 + ex, cy = y - 1 + ey, cz = D == 3 ? z - 1 + ez : 0;
+        ok[e] = (unsigned)cx < (unsigned)nx && (unsigned)cy < (unsigned)ny &&
+                (unsigned)cz < (unsigned)nz;
+        const int64_t i = ((int64_t)cz * ny + cy) * nx + cx;
+        lv[e] = ok[e] ? lam[i] : make_double2(0.0, 0.0);
+        uv[e] = ok[e] ? U[i] : make_double2(0.0, 0.0);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < (1 << D); ++b)
+#pragma unroll
+        for (int g = 0; g < (1 << D); ++g) {
+            const int cls = __popc(b ^ g);
+            // Re(conj(l) u) = l.x u.x + l.y u.y
+            s += mt.M[cls] * (lv[b].x * uv[g].x + lv[b].y * uv[g].y);
+        }
+    gcell[((int64_t)z * (ny + 1) + y) * (nx + 1) + x] = w2 * s;
+}
+
+hipError_t launch_grad_cells(int ndim, const int *n, double w2, const double *mass,
+                             const void *lam, const void *U, double *gcell, hipStream_t s)
+{
+    const int nz = ndim == 3 ? n[0] : 1;
+    const int ny = ndim == 3 ? n[1] : n[0];
+    const int nx = ndim == 3 ? n[2] : n[1];
+    MassTable mt{{mass[0], mass[1], mass[2], ndim == 3 ? mass[3] : 0.0}};
+    dim3 blk(64, 4, 1);
+    dim3 grd((nx + 1 + 63) / 64, (ny + 1 + 3) / 4, ndim == 3 ? nz + 1 : 1);
+    if (ndim == 2)
+        hipLaunchKernelGGL(k_grad_cells<2>, grd, blk, 0, s, (const double2 *)lam,
+                           (const double2 *)U, mt, w2, gcell, nz, ny, nx);
+    else
+        hipLaunchKernelGGL(k_grad_cells<3>, grd, blk, 0, s, (const double2 *)lam,
+                           (const double2 *)U, mt, w2, gcell, nz, ny, nx);
+    return hipGetLastError();
+}
+
+// adjoint of m_cell = 2^-D sum_e m_node(clamp(alpha + e)): per axis, the cell
+// lower corners a (storage a+1) whose corner a+e clamps to node i, with the
+// number of such e in {0,1}.
+__device__ __forceinline__ int axis_cells(int i, int n, int *st, int *mult)
+{
+    int cnt = 0;
+    for (int a = i - 2; a <= i + 1; ++a) {
+        if (a < -1 || a > n - 1) continue;
+        int mlt = 0;
+        for (int e = 0; e < 2; ++e) {
+            int c = a + e;
+            c = c < 0 ? 0 : (c >= n ? n - 1 : c);
+            mlt += c == i;
+        }
+        if (mlt) {
+            st[cnt] = a + 1;
+            mult[cnt] = mlt;
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+template <int D>
+__global__ void k_grad_nodes(const double *__restrict__ gcell, double *__restrict__ grad, int nz,
+                             int ny, int nx)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= nx || y >= ny) return;
+    int sx[4], mx[4], sy[4], my[4], sz[4], mz[4];
+    const int cxn = axis_cells(x, nx, sx, mx);
+    const int cyn = axis_cells(y, ny, sy, my);
+    int czn = 1;
+    sz[0] = 0;
+    mz[0] = 1;
+    if (D == 3) czn = axis_cells(z, nz, sz, mz);
+    double s = 0.0;
+    for (int c = 0; c < czn; ++c)
+        for (int b = 0; b < cyn; ++b)
+            for (int a = 0; a < cxn; ++a)
+                s += (double)(mz[c] * my[b] * mx[a]) *
+                     gcell[((int64_t)sz[c] * (ny + 1) + sy[b]) * (nx + 1) + sx[a]];
+    grad[((int64_t)z * ny + y) * nx + x] = s * (1.0 / (1 << D));
+}
+
+hipError_t launch_grad_nodes(int ndim, const int *n, const double *gcell, double *grad,
+                             hipStream_t s)
+{
+    const int nz = ndim == 3 ? n[0] : 1;
+    const int ny = ndim == 3 ? n[1] : n[0];
+    const int nx = ndim == 3 ? n[2] : n[1];
+    dim3 blk(64, 4, 1);
+    dim3 grd((nx + 63) / 64, (ny + 3) / 4, nz);
+    if (ndim == 2)
+        hipLaunchKernelGGL(k_grad_nodes<2>, grd, blk, 0, s, gcell, grad, nz, ny, nx);
+    else
+        hipLaunchKernelGGL(k_grad_nodes<3>, grd, blk, 0, s, gcell, grad, nz, ny, nx);
+    return hipGetLastError();
+}
+
+}  // namespace tdp

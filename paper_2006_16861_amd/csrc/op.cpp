@@ -1,0 +1,699 @@
+// Host side of libtdp: operator setup (Sec. 2.2, Prop. 1, App. A), the
+// preconditioner driver (Table 1), left-preconditioned restarted GMRES
+// (Sec. 2.4) and the m-gradient, behind the C ABI of include/tdp.h.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tdp_internal.h"
+
+namespace tdp {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+static void clear_error() { g_last_error.clear(); }
+
+#define TDP_FAIL(code, ...)        \
+    do {                           \
+        ::tdp::set_error(__VA_ARGS__); \
+        return (code);             \
+    } while (0)
+
+// Classical fourth-order compact scheme in the cell form (entries by the
+// number of axes on which two corners of a cell differ).
+static const double kStiff2[3] = {5.0 / 6.0, -1.0 / 3.0, -1.0 / 6.0};
+static const double kMass2[3] = {1.0 / 6.0, 1.0 / 24.0, 0.0};
+static const double kStiff3[4] = {0.5, -1.0 / 12.0, -1.0 / 12.0, 0.0};
+static const double kMass3[4] = {1.0 / 16.0, 1.0 / 48.0, 0.0, 0.0};
+
+// Elementary symmetric polynomial e_k of the d values s (each +-1).
+static double esym(int d, const int *s, int k)
+{
+    double tot = 0.0;
+    for (int mask = 0; mask < (1 << d); ++mask) {
+        if (__builtin_popcount(mask) != k) continue;
+        double p = 1.0;
+        for (int a = 0; a < d; ++a)
+            if (mask >> a & 1) p *= s[a];
+        tot += p;
+    }
+    return tot;
+}
+
+// For a cell table T (entries by class k) the element matrix over the 2^d
+// corners is diagonalised by the Walsh vectors prod_a s_a^{corner_a},
+// s in {-1,1}^d, with eigenvalue sum_k T_k e_k(s).  The same sum times 2^d is
+// the symbol of the assembled stencil at theta in {0, pi}^d (cos theta = s);
+// the symbol is multi-affine in the cos theta_a, so its maximum over all
+// theta is attained at one of these vertices.
+static void table_spectrum(int d, const double *T, double *lo, double *hi)
+{
+    *lo = INFINITY;
+    *hi = -INFINITY;
+    for (int v = 0; v < (1 << d); ++v) {
+        int s[3];
+        for (int a = 0; a < d; ++a) s[a] = (v >> a & 1) ? -1 : 1;
+        double e = 0.0;
+        for (int k = 0; k <= d; ++k) e += T[k] * esym(d, s, k);
+        *lo = std::fmin(*lo, e);
+        *hi = std::fmax(*hi, e);
+    }
+}
+
+// Stream discipline: work is issued on the caller's stream when one is given.
+// For the default (NULL) stream, which cannot be captured into a graph, the op
+// owns a stream and orders it after the caller's stream at entry and before
+// it at exit.
+struct StreamJoin {
+    hipStream_t user, own;
+    hipEvent_t ev;
+    StreamJoin(hipStream_t u, hipStream_t o, hipEvent_t e) : user(u), own(o), ev(e)
+    {
+        if (ev && hipEventRecord(ev, user) == hipSuccess) (void)hipStreamWaitEvent(own, ev, 0);
+    }
+    ~StreamJoin()
+    {
+        if (ev && hipEventRecord(ev, own) == hipSuccess) (void)hipStreamWaitEvent(user, ev, 0);
+    }
+};
+
+}  // namespace tdp
+
+using namespace tdp;
+
+extern "C" const char *tdp_last_error(void) { return g_last_error.c_str(); }
+
+static int free_op(tdp_op *op)
+{
+    if (!op) return TDP_OK;
+    if (op->ev) (void)hipEventDestroy(op->ev);
+    (void)hipFree(op->Fstage);
+    (void)hipFree(op->Ustage);
+    (void)hipFree(op->gcell);
+    for (auto &kv : op->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : op->dtables) (void)hipFree(kv.second);
+    void *bufs[] = {op->m, op->rw, op->dn, op->m32, op->dn32, op->u0, op->u1, op->u2,
+                    op->u3, op->Fst, op->scratch, op->V, op->wv, op->tv, op->rv,
+                    op->red, op->dcoef};
+    for (void *b : bufs) (void)hipFree(b);
+    if (op->hres) (void)hipHostFree(op->hres);
+    if (op->own_stream && op->stream) (void)hipStreamDestroy(op->stream);
+    delete op;
+    return TDP_OK;
+}
+
+extern "C" int tdp_op_destroy(tdp_op *op)
+{
+    clear_error();
+    if (op) (void)hipStreamSynchronize(op->stream);
+    return free_op(op);
+}
+
+static int create_impl(const tdp_op_desc *d, tdp_op *op)
+{
+    if (d->ndim != 2 && d->ndim != 3) TDP_FAIL(TDP_EINVAL, "ndim must be 2 or 3 (got %d)", d->ndim);
+    if (!(d->h > 0.0)) TDP_FAIL(TDP_EINVAL, "h must be > 0");
+    if (!(d->omega > 0.0)) TDP_FAIL(TDP_EINVAL, "omega must be > 0");
+    if (!d->c) TDP_FAIL(TDP_EINVAL, "c must not be NULL");
+    if (d->prec != TDP_F64 && d->prec != TDP_F32) TDP_FAIL(TDP_EINVAL, "prec must be TDP_F64 or TDP_F32");
+    op->ndim = d->ndim;
+    op->N = 1;
+    op->Nc = 1;
+    for (int a = 0; a < d->ndim; ++a) {
+        if (d->n[a] < 1 || d->n[a] > (1 << 20))
+            TDP_FAIL(TDP_EINVAL, "n[%d] = %lld out of range [1, 2^20]", a, (long long)d->n[a]);
+        op->n[a] = (int)d->n[a];
+        op->N *= d->n[a];
+        op->Nc *= d->n[a] + 1;
+    }
+    if (op->N > (int64_t)1 << 36) TDP_FAIL(TDP_EINVAL, "grid too large");
+    op->h = d->h;
+    op->omega = d->omega;
+    op->prec = d->prec;
+    const int D = d->ndim;
+    const double *S = d->stiff ? d->stiff : (D == 2 ? kStiff2 : kStiff3);
+    const double *M = d->mass ? d->mass : (D == 2 ? kMass2 : kMass3);
+    for (int k = 0; k <= D; ++k) {
+        op->S[k] = S[k];
+        op->M[k] = M[k];
+        if (!std::isfinite(S[k]) || !std::isfinite(M[k])) TDP_FAIL(TDP_EINVAL, "non-finite cell table");
+    }
+    // App. A conditions: element stiffness PSD, element mass PSD with
+    // largest eigenvalue <= 2^-d (so Re H >= -k_max^2).
+    double slo, shi, mlo, mhi;
+    table_spectrum(D, op->S, &slo, &shi);
+    table_spectrum(D, op->M, &mlo, &mhi);
+    const double tol = 1e-12;
+    if (slo < -tol * std::fmax(1.0, shi)) TDP_FAIL(TDP_EINVAL, "stiffness cell table is not PSD");
+    if (mlo < -tol || mhi > std::ldexp(1.0, -D) * (1 + tol))
+        TDP_FAIL(TDP_EINVAL, "mass cell table must be PSD with eigenvalues <= 2^-d");
+    if (!(shi > 0.0)) TDP_FAIL(TDP_EINVAL, "stiffness cell table is zero");
+    op->sc = 1;
+    op->mc = 0;
+    for (int k = 1; k <= D; ++k)
+        if (op->S[k] != 0.0) op->sc = k + 1;
+    for (int k = 0; k <= D; ++k)
+        if (op->M[k] != 0.0) op->mc = k + 1;
+
+    op->user_stream = (hipStream_t)d->stream;
+    if (op->user_stream) {
+        op->stream = op->user_stream;
+    } else {
+        TDP_CHECK_HIP(hipStreamCreateWithFlags(&op->stream, hipStreamNonBlocking));
+        op->own_stream = true;
+        TDP_CHECK_HIP(hipEventCreateWithFlags(&op->ev, hipEventDisableTiming));
+    }
+    StreamJoin join(op->user_stream, op->stream, op->ev);
+    hipStream_t s = op->stream;
+
+    const size_t nb = sizeof(double) * op->N;
+    if (hipMalloc(&op->m, sizeof(double) * op->Nc) != hipSuccess ||
+        hipMalloc(&op->rw, nb) != hipSuccess || hipMalloc(&op->dn, nb) != hipSuccess)
+        TDP_FAIL(TDP_ENOMEM, "device allocation of operator arrays failed");
+    op->scratch_bytes = sizeof(double) * 2048;
+    if (hipMalloc(&op->scratch, op->scratch_bytes) != hipSuccess)
+        TDP_FAIL(TDP_ENOMEM, "device allocation failed");
+
+    // validate c > 0 and R >= 0 on the host (one pass, setup only)
+    {
+        std::vector<double> hc(op->N);
+        TDP_CHECK_HIP(hipMemcpyAsync(hc.data(), d->c, nb, hipMemcpyDeviceToHost, s));
+        std::vector<double> hr;
+        if (d->R) {
+            hr.resize(op->N);
+            TDP_CHECK_HIP(hipMemcpyAsync(hr.data(), d->R, nb, hipMemcpyDeviceToHost, s));
+        }
+        TDP_CHECK_HIP(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < op->N; ++i) {
+            if (!(hc[i] > 0.0) || !std::isfinite(hc[i]))
+                TDP_FAIL(TDP_EINVAL, "c must be finite and > 0 (node %lld)", (long long)i);
+            if (d->R && (!(hr[i] >= 0.0) || !std::isfinite(hr[i])))
+                TDP_FAIL(TDP_EINVAL, "R must be finite and >= 0 (node %lld)", (long long)i);
+        }
+    }
+
+    // cell slowness and its maximum (App. A: k constant per cell)
+    TDP_CHECK_HIP(launch_cell_slowness(D, op->n, d->c, op->m, s));
+    const int nblk = 256;
+    TDP_CHECK_HIP(launch_max_reduce(op->m, op->Nc, op->scratch, nblk, op->scratch + nblk, s));
+    double mmax = 0.0;
+    TDP_CHECK_HIP(hipMemcpyAsync(&mmax, op->scratch + nblk, sizeof(double), hipMemcpyDeviceToHost, s));
+    TDP_CHECK_HIP(hipStreamSynchronize(s));
+
+    // Sec. 2.2: omega_c bounds sqrt(-lambda_min(Re H)); the CFL bound uses
+    // lambda_max(A) <= h^-2 max S(theta) + omega_c^2.
+    op->omega_c = op->omega * std::sqrt(mmax);
+    op->lam_bar = std::ldexp(shi, D) / (op->h * op->h) + op->omega_c * op->omega_c;
+    const double nmin = M_PI / std::asin(op->omega_c / std::sqrt(op->lam_bar));
+    int nP = d->steps_per_period;
+    if (nP == 0) {
+        nP = 4 * ((int)std::floor(nmin / 4.0) + 1);
+    } else if (nP < 0 || nP % 4 != 0 || !((double)nP > nmin)) {
+        TDP_FAIL(TDP_ECFL, "steps_per_period %d must be a multiple of 4 above the CFL bound %.6f",
+                 nP, nmin);
+    }
+    op->nP = nP;
+    op->dt = 2.0 * M_PI / (op->omega_c * nP);
+    const double th = 2.0 * M_PI / nP;   // omega_c * dt
+    const double sh = std::sin(0.5 * th);
+    op->alpha = th * th / (4.0 * sh * sh);   // Prop. 1
+    op->beta = th / std::sin(th);
+    op->g = op->dt * op->dt / op->alpha;
+    op->cS = op->g / (op->h * op->h);
+    op->cM = op->g * op->omega * op->omega;
+    op->cw = op->g * op->omega_c * op->omega_c;
+    const double lscale = op->beta * op->dt / op->alpha * op->omega / op->omega_c;
+
+    // stencil constants: (2 - K) u for the step, Re H x for the H-apply
+    op->st_step.c0 = 2.0 - op->cw - op->cS * std::ldexp(op->S[0], D);
+    op->st_H.c0 = std::ldexp(op->S[0], D) / (op->h * op->h);
+    op->st_step.s[0] = op->st_H.s[0] = 0.0;
+    for (int k = 1; k < 4; ++k) {
+        const double sk = k <= D ? std::ldexp(op->S[k], D - k) : 0.0;
+        op->st_step.s[k] = -op->cS * sk;
+        op->st_H.s[k] = sk / (op->h * op->h);
+    }
+    for (int k = 0; k < 4; ++k) {
+        const double mk = k <= D ? op->M[k] : 0.0;
+        op->st_step.m[k] = op->cM * mk;
+        op->st_H.m[k] = -op->omega * op->omega * mk;
+    }
+    op->st_step32.c0 = (float)op->st_step.c0;
+    for (int k = 0; k < 4; ++k) {
+        op->st_step32.s[k] = (float)op->st_step.s[k];
+        op->st_step32.m[k] = (float)op->st_step.m[k];
+    }
+
+    TDP_CHECK_HIP(launch_node_factors(d->R, op->N, op->omega, lscale, op->rw, op->dn, s));
+
+    const size_t fb = (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
+    if (hipMalloc(&op->u0, fb) != hipSuccess || hipMalloc(&op->u1, fb) != hipSuccess)
+        TDP_FAIL(TDP_ENOMEM, "device allocation of recurrence fields failed");
+    if (op->prec == TDP_F32) {
+        if (hipMalloc(&op->m32, sizeof(float) * op->Nc) != hipSuccess ||
+            hipMalloc(&op->dn32, sizeof(float) * op->N) != hipSuccess ||
+            hipMalloc(&op->Fst, sizeof(float) * 2 * op->N) != hipSuccess)
+            TDP_FAIL(TDP_ENOMEM, "device allocation of FP32 arrays failed");
+        TDP_CHECK_HIP(launch_cvt_f64_to_f32(op->m, op->m32, op->Nc, s));
+        TDP_CHECK_HIP(launch_cvt_f64_to_f32(op->dn, op->dn32, op->N, s));
+    }
+    if (hipMalloc(&op->Fstage, 16 * op->N) != hipSuccess || hipMalloc(&op->Ustage, 16 * op->N) != hipSuccess)
+        TDP_FAIL(TDP_ENOMEM, "device allocation of staging buffers failed");
+    TDP_CHECK_HIP(hipStreamSynchronize(s));
+    return TDP_OK;
+}
+
+extern "C" int tdp_op_create(const tdp_op_desc *d, tdp_op **out)
+{
+    clear_error();
+    if (!d || !out) TDP_FAIL(TDP_EINVAL, "NULL argument");
+    *out = nullptr;
+    tdp_op *op = new tdp_op();
+    int rc = create_impl(d, op);
+    if (rc != TDP_OK) {
+        std::string msg = g_last_error;
+        if (op->stream) (void)hipStreamSynchronize(op->stream);
+        free_op(op);
+        g_last_error = msg;
+        return rc;
+    }
+    *out = op;
+    return TDP_OK;
+}
+
+extern "C" int tdp_op_query(const tdp_op *op, tdp_op_info *o)
+{
+    clear_error();
+    if (!op || !o) TDP_FAIL(TDP_EINVAL, "NULL argument");
+    o->omega_c = op->omega_c;
+    o->dt = op->dt;
+    o->alpha = op->alpha;
+    o->beta = op->beta;
+    o->lam_bar = op->lam_bar;
+    o->n_P = op->nP;
+    o->ndim = op->ndim;
+    o->N = op->N;
+    return TDP_OK;
+}
+
+extern "C" int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t)
+{
+    clear_error();
+    if (!op || !t) TDP_FAIL(TDP_EINVAL, "NULL argument");
+    if (t->kernel < 0 || t->kernel > 2) TDP_FAIL(TDP_EINVAL, "kernel must be 0, 1 or 2");
+    if (t->tb_depth < 0 || t->tb_depth > 16) TDP_FAIL(TDP_EINVAL, "tb_depth must be in [0, 16]");
+    op->tune = *t;
+    return TDP_OK;
+}
+
+extern "C" int tdp_op_get_tuning(const tdp_op *op, tdp_tuning *t)
+{
+    clear_error();
+    if (!op || !t) TDP_FAIL(TDP_EINVAL, "NULL argument");
+    *t = op->tune;
+    return TDP_OK;
+}
+
+// ---------------------------------------------------------------------------
+static int apply_H_impl(const tdp_op *op, const void *x, const void *F, void *y)
+{
+    TDP_CHECK_HIP(launch_apply_H(op->ndim, op->n, op->sc, op->mc, op->m, op->rw, op->st_H, x, F,
+                                 y, op->stream));
+    return TDP_OK;
+}
+
+extern "C" int tdp_apply_H(const tdp_op *op, const void *x, void *y)
+{
+    clear_error();
+    if (!op || !x || !y) TDP_FAIL(TDP_EINVAL, "NULL argument");
+    if (x == y) TDP_FAIL(TDP_EINVAL, "x and y must not alias");
+    StreamJoin join(op->user_stream, op->stream, op->ev);
+    return apply_H_impl(op, x, nullptr, y);
+}
+
+// Sec. 2.3 window: 1 on |s| <= 1-rho, sin^2(pi (1-|s|) / (2 rho)) on the taper.
+static double window(double s, double rho)
+{
+    const double a = std::fabs(s);
+    if (a >= 1.0) return 0.0;
+    if (a <= 1.0 - rho) return 1.0;
+    const double v = std::sin(M_PI * (1.0 - a) / (2.0 * rho));
+    return v * v;
+}
+
+// Forcing scalars of Table 1 for steps j = 0..N_s-1, already scaled by
+// g = dt^2/alpha (Def. 2):  fa_j = g chi_j cos(2 pi j/n_P),
+// fb_j = -g chi_j sin(2 pi j/n_P), chi_j = chi(1 - j/N_s).
+static const std::vector<double> &forcing_table(tdp_op *op, int T, double rho)
+{
+    auto key = std::make_pair(T, rho);
+    auto it = op->tables.find(key);
+    if (it != op->tables.end()) return it->second;
+    const int64_t Ns = (int64_t)T * op->nP;
+    std::vector<double> t(2 * Ns);
+    for (int64_t j = 0; j < Ns; ++j) {
+        const double chi = window(1.0 - (double)j / (double)Ns, rho);
+        const double ph = 2.0 * M_PI * (double)j / op->nP;
+        t[2 * j] = op->g * chi * std::cos(ph);
+        t[2 * j + 1] = -op->g * chi * std::sin(ph);
+    }
+    return op->tables.emplace(key, std::move(t)).first->second;
+}
+
+// Issue the Table 1 loop reading F (complex128, or float2 staged for FP32)
+// and writing U (complex128).
+static int issue_steps(tdp_op *op, int T, double rho, const void *Fin, void *U)
+{
+    hipStream_t s = op->stream;
+    const std::vector<double> &tab = forcing_table(op, T, rho);
+    const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - op->nP / 4;
+    const size_t fb = (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
+    TDP_CHECK_HIP(launch_fill_zero(op->u0, fb, s));
+    TDP_CHECK_HIP(launch_fill_zero(op->u1, fb, s));
+    void *cur = op->u0, *prev = op->u1;
+    SweepArgs a;
+    a.ndim = op->ndim;
+    for (int k = 0; k < 3; ++k) a.n[k] = op->n[k];
+    a.sc = op->sc;
+    a.mc = op->mc;
+    a.F = Fin;
+    double *Ud = (double *)U;
+    for (int64_t j = 0; j < Ns; ++j) {
+        a.u = cur;
+        a.up = prev;
+        a.out = (j + 1 == jsnap) ? Ud + 1 : (j + 1 == Ns ? Ud : nullptr);
+        if (op->prec == TDP_F64) {
+            a.m = op->m;
+            a.dn = op->dn;
+            TDP_CHECK_HIP(launch_sweep_f64(a, op->st_step, tab[2 * j], tab[2 * j + 1], s));
+        } else {
+            a.m = op->m32;
+            a.dn = op->dn32;
+            TDP_CHECK_HIP(launch_sweep_f32(a, op->st_step32, (float)tab[2 * j],
+                                           (float)tab[2 * j + 1], s));
+        }
+        std::swap(cur, prev);
+    }
+    return TDP_OK;
+}
+
+static int precond_impl(tdp_op *op, int T, double rho, const void *F, void *U)
+{
+    if (T < 1) TDP_FAIL(TDP_EINVAL, "periods_T must be >= 1");
+    if (rho <= 0.0) rho = 1.0 / T;
+    if (rho > 1.0) TDP_FAIL(TDP_EINVAL, "rho must be <= 1");
+    if ((int64_t)T * op->nP > ((int64_t)1 << 31)) TDP_FAIL(TDP_EINVAL, "too many steps");
+    hipStream_t s = op->stream;
+    if (!op->tune.use_graph) {
+        const void *Fin = F;
+        if (op->prec == TDP_F32) {
+            TDP_CHECK_HIP(launch_cvt_c128_to_c64(F, op->Fst, op->N, s));
+            Fin = op->Fst;
+        }
+        return issue_steps(op, T, rho, Fin, U);
+    }
+    // captured loop: reads e.Fstage (F64) / op->Fst (F32), writes e.Ustage
+    auto key = std::make_tuple(T, rho, (const void *)nullptr, (void *)nullptr, op->tune.kernel,
+                               op->tune.tb_depth);
+    auto it = op->graphs.find(key);
+    if (it == op->graphs.end()) {
+        hipGraph_t g;
+        TDP_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        int rc = issue_steps(op, T, rho, op->prec == TDP_F64 ? op->Fstage : op->Fst, op->Ustage);
+        hipError_t ce = hipStreamEndCapture(s, &g);
+        if (rc != TDP_OK) return rc;
+        TDP_CHECK_HIP(ce);
+        hipGraphExec_t ge;
+        hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        TDP_CHECK_HIP(ie);
+        it = op->graphs.emplace(key, ge).first;
+    }
+    if (op->prec == TDP_F64)
+        TDP_CHECK_HIP(hipMemcpyAsync(op->Fstage, F, 16 * op->N, hipMemcpyDeviceToDevice, s));
+    else
+        TDP_CHECK_HIP(launch_cvt_c128_to_c64(F, op->Fst, op->N, s));
+    TDP_CHECK_HIP(hipGraphLaunch(it->second, s));
+    TDP_CHECK_HIP(hipMemcpyAsync(U, op->Ustage, 16 * op->N, hipMemcpyDeviceToDevice, s));
+    return TDP_OK;
+}
+
+extern "C" int tdp_precond_apply(const tdp_op *cop, int T, double rho, const void *F, void *U)
+{
+    clear_error();
+    if (!cop || !F || !U) TDP_FAIL(TDP_EINVAL, "NULL argument");
+    if (F == U) TDP_FAIL(TDP_EINVAL, "F and U must not alias");
+    tdp_op *op = const_cast<tdp_op *>(cop);
+    StreamJoin join(op->user_stream, op->stream, op->ev);
+    return precond_impl(op, T, rho, F, U);
+}
+
+// ---------------------------------------------------------------------------
+// GMRES
+static int ensure_krylov(tdp_op *op, int m)
+{
+    if (op->V && op->V_cols >= m + 1) return TDP_OK;
+    (void)hipStreamSynchronize(op->stream);
+    (void)hipFree(op->V);
+    op->V = nullptr;
+    if (hipMalloc(&op->V, (size_t)16 * op->N * (m + 1)) != hipSuccess)
+        TDP_FAIL(TDP_ENOMEM, "Krylov basis allocation (%d x %lld complex) failed", m + 1,
+                 (long long)op->N);
+    op->V_cols = m + 1;
+    if (!op->wv) {
+        if (hipMalloc(&op->wv, 16 * op->N) != hipSuccess || hipMalloc(&op->tv, 16 * op->N) != hipSuccess ||
+            hipMalloc(&op->rv, 16 * op->N) != hipSuccess)
+            TDP_FAIL(TDP_ENOMEM, "GMRES work vector allocation failed");
+    }
+    const int nblk = blas_nblocks(op->N);
+    const size_t rb = sizeof(double) * 2 * (size_t)nblk * (m + 2);
+    if (rb > op->red_bytes) {
+        (void)hipFree(op->red);
+        if (hipMalloc(&op->red, rb) != hipSuccess) TDP_FAIL(TDP_ENOMEM, "allocation failed");
+        op->red_bytes = rb;
+    }
+    (void)hipFree(op->dcoef);
+    (void)hipHostFree(op->hres);
+    op->dcoef = nullptr;
+    op->hres = nullptr;
+    const size_t cb = sizeof(double) * (8 * (size_t)(m + 2));
+    if (hipMalloc(&op->dcoef, cb) != hipSuccess || hipHostMalloc(&op->hres, cb) != hipSuccess)
+        TDP_FAIL(TDP_ENOMEM, "allocation failed");
+    return TDP_OK;
+}
+
+// ||x||^2 of a complex vector, result in dres[0] (device) -> host
+static int norm2_host(tdp_op *op, const void *x, double *out)
+{
+    const int nblk = blas_nblocks(op->N);
+    TDP_CHECK_HIP(launch_mdot(x, op->N, 1, x, op->N, op->red, nblk, op->dcoef, op->stream));
+    TDP_CHECK_HIP(hipMemcpyAsync(op->hres, op->dcoef, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                 op->stream));
+    TDP_CHECK_HIP(hipStreamSynchronize(op->stream));
+    *out = op->hres[0];
+    return TDP_OK;
+}
+
+typedef std::complex<double> cplx;
+
+static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void *U,
+                      tdp_gmres_info *info)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    const int m = cfg->restart;
+    if (m < 1 || m > 512) TDP_FAIL(TDP_EINVAL, "restart must be in [1, 512]");
+    if (cfg->max_iters < 1) TDP_FAIL(TDP_EINVAL, "max_iters must be >= 1");
+    if (cfg->periods_T < 1) TDP_FAIL(TDP_EINVAL, "periods_T must be >= 1");
+    if (!(cfg->tol > 0.0)) TDP_FAIL(TDP_EINVAL, "tol must be > 0");
+    if (cfg->rho > 1.0) TDP_FAIL(TDP_EINVAL, "rho must be <= 1");
+    TDP_CHECK(ensure_krylov(op, m));
+    hipStream_t s = op->stream;
+    const int64_t N = op->N;
+    const int T = cfg->periods_T;
+    const double rho = cfg->rho;
+    const int fixed = cfg->fixed_iters;
+    const int limit = fixed > 0 ? fixed : cfg->max_iters;
+    const int nblk = blas_nblocks(N);
+    char *V = (char *)op->V;
+    auto col = [&](int k) -> void * { return V + (size_t)16 * N * k; };
+    double *d1 = op->dcoef;                 // CGS pass 1 coefficients [2(m+1)]
+    double *d2 = op->dcoef + 2 * (m + 1);   // pass 2
+    double *dn2 = op->dcoef + 4 * (m + 1);  // ||w||^2
+    double *dy = op->dcoef + 4 * (m + 1) + 2;
+
+    if (!cfg->x0_given) TDP_CHECK_HIP(launch_fill_zero(U, 16 * N, s));
+    double b2;
+    TDP_CHECK(norm2_host(op, F, &b2));
+    const double bnorm = std::sqrt(b2);
+    int its = 0, restarts = 0, nhist = 0, status = TDP_ENOTCONV;
+    int64_t napply = 0;
+    double tol_inner = cfg->tol, pnorm0 = -1.0, est = 1.0, rel = 1.0;
+    std::vector<cplx> Hm((size_t)(m + 1) * m), gv(m + 1), sn(m), y(m);
+    std::vector<double> cs(m);
+    auto HM = [&](int i, int j) -> cplx & { return Hm[(size_t)j * (m + 1) + i]; };
+    if (bnorm == 0.0) {
+        TDP_CHECK_HIP(launch_fill_zero(U, 16 * N, s));
+        status = TDP_OK;
+        rel = 0.0;
+        est = 0.0;
+        goto done;
+    }
+    for (;;) {
+        double r2;
+        TDP_CHECK(apply_H_impl(op, U, F, op->rv));   // r = F - H U
+        TDP_CHECK(norm2_host(op, op->rv, &r2));
+        rel = std::sqrt(r2) / bnorm;
+        if (fixed <= 0 && rel <= cfg->tol) {
+            status = TDP_OK;
+            break;
+        }
+        if (its >= limit) break;
+        TDP_CHECK(precond_impl(op, T, rho, op->rv, col(0)));
+        ++napply;
+        double z2;
+        TDP_CHECK(norm2_host(op, col(0), &z2));
+        const double beta0 = std::sqrt(z2);
+        if (pnorm0 < 0.0) pnorm0 = beta0;
+        if (beta0 == 0.0) break;
+        // norm2_host left ||col0||^2 in dcoef[0]
+        TDP_CHECK_HIP(launch_scale_by_invnorm(col(0), col(0), op->dcoef, N, s));
+        for (int k = 0; k <= m; ++k) gv[k] = 0.0;
+        gv[0] = beta0;
+        int k_used = 0, inner_conv = 0;
+        for (int i = 0; i < m && its < limit; ++i) {
+            TDP_CHECK(apply_H_impl(op, col(i), nullptr, op->tv));
+            TDP_CHECK(precond_impl(op, T, rho, op->tv, op->wv));
+            ++napply;
+            ++its;
+            // classical Gram-Schmidt, two passes
+            TDP_CHECK_HIP(launch_mdot(op->V, N, i + 1, op->wv, N, op->red, nblk, d1, s));
+            TDP_CHECK_HIP(launch_maxpy(op->wv, op->V, N, i + 1, d1, -1.0, N, s));
+            TDP_CHECK_HIP(launch_mdot(op->V, N, i + 1, op->wv, N, op->red, nblk, d2, s));
+            TDP_CHECK_HIP(launch_maxpy(op->wv, op->V, N, i + 1, d2, -1.0, N, s));
+            TDP_CHECK_HIP(launch_mdot(op->wv, N, 1, op->wv, N, op->red, nblk, dn2, s));
+            TDP_CHECK_HIP(launch_scale_by_invnorm(col(i + 1), op->wv, dn2, N, s));
+            TDP_CHECK_HIP(hipMemcpyAsync(op->hres, op->dcoef, sizeof(double) * (4 * (m + 1) + 2),
+                                         hipMemcpyDeviceToHost, s));
+            TDP_CHECK_HIP(hipStreamSynchronize(s));
+            const double *h1 = op->hres, *h2 = op->hres + 2 * (m + 1);
+            for (int k = 0; k <= i; ++k)
+                HM(k, i) = cplx(h1[2 * k] + h2[2 * k], h1[2 * k + 1] + h2[2 * k + 1]);
+            const double hn = std::sqrt(op->hres[4 * (m + 1)]);
+            HM(i + 1, i) = hn;
+            for (int k = 0; k < i; ++k) {
+                const cplx a = HM(k, i), b = HM(k + 1, i);
+                HM(k, i) = cs[k] * a + sn[k] * b;
+                HM(k + 1, i) = -std::conj(sn[k]) * a + cs[k] * b;
+            }
+            const cplx a = HM(i, i);
+            const double rr = std::hypot(std::abs(a), hn);
+            if (std::abs(a) == 0.0) {
+                cs[i] = 0.0;
+                sn[i] = 1.0;
+                HM(i, i) = hn;
+            } else {
+                const cplx ph = a / std::abs(a);
+                cs[i] = std::abs(a) / rr;
+                sn[i] = ph * hn / rr;
+                HM(i, i) = ph * rr;
+            }
+            HM(i + 1, i) = 0.0;
+            gv[i + 1] = -std::conj(sn[i]) * gv[i];
+            gv[i] = cs[i] * gv[i];
+            est = std::abs(gv[i + 1]) / pnorm0;
+            if (info && info->history && nhist < info->history_cap) info->history[nhist] = est;
+            ++nhist;
+            k_used = i + 1;
+            if (hn == 0.0) break;
+            if (fixed <= 0 && est <= tol_inner) {
+                inner_conv = 1;
+                break;
+            }
+        }
+        for (int k = k_used - 1; k >= 0; --k) {
+            cplx sum = gv[k];
+            for (int j = k + 1; j < k_used; ++j) sum -= HM(k, j) * y[j];
+            y[k] = sum / HM(k, k);
+        }
+        for (int k = 0; k < k_used; ++k) {
+            op->hres[2 * k] = y[k].real();
+            op->hres[2 * k + 1] = y[k].imag();
+        }
+        TDP_CHECK_HIP(hipMemcpyAsync(dy, op->hres, sizeof(double) * 2 * k_used,
+                                     hipMemcpyHostToDevice, s));
+        TDP_CHECK_HIP(launch_maxpy(U, op->V, N, k_used, dy, 1.0, N, s));
+        ++restarts;
+        TDP_CHECK(apply_H_impl(op, U, F, op->rv));
+        TDP_CHECK(norm2_host(op, op->rv, &r2));
+        rel = std::sqrt(r2) / bnorm;
+        if (fixed > 0) {
+            if (its >= limit) {
+                status = TDP_OK;
+                break;
+            }
+            continue;
+        }
+        if (rel <= cfg->tol) {
+            status = TDP_OK;
+            break;
+        }
+        if (its >= limit) break;
+        if (inner_conv) tol_inner *= cfg->tol / rel;
+    }
+done:
+    TDP_CHECK_HIP(hipStreamSynchronize(s));
+    if (info) {
+        info->iters = its;
+        info->restarts = restarts;
+        info->relres_true = rel;
+        info->relres_prec = est;
+        info->steps = napply * (int64_t)T * op->nP;
+        info->history_len = nhist < info->history_cap ? nhist : info->history_cap;
+        info->ms_total =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}
+
+extern "C" int tdp_gmres_solve(const tdp_op *cop, const tdp_gmres_cfg *cfg, const void *F,
+                               void *U, tdp_gmres_info *info)
+{
+    clear_error();
+    if (!cop || !cfg || !F || !U) TDP_FAIL(TDP_EINVAL, "NULL argument");
+    if (F == U) TDP_FAIL(TDP_EINVAL, "F and U must not alias");
+    tdp_op *op = const_cast<tdp_op *>(cop);
+    StreamJoin join(op->user_stream, op->stream, op->ev);
+    return gmres_impl(op, cfg, F, U, info);
+}
+
+// ---------------------------------------------------------------------------
+extern "C" int tdp_grad_m(const tdp_op *cop, const void *lam, const void *U, double *grad)
+{
+    clear_error();
+    if (!cop || !lam || !U || !grad) TDP_FAIL(TDP_EINVAL, "NULL argument");
+    tdp_op *op = const_cast<tdp_op *>(cop);
+    if (!op->gcell && hipMalloc(&op->gcell, sizeof(double) * op->Nc) != hipSuccess)
+        TDP_FAIL(TDP_ENOMEM, "allocation failed");
+    StreamJoin join(op->user_stream, op->stream, op->ev);
+    TDP_CHECK_HIP(launch_grad_cells(op->ndim, op->n, op->omega * op->omega, op->M, lam, U,
+                                    op->gcell, op->stream));
+    TDP_CHECK_HIP(launch_grad_nodes(op->ndim, op->n, op->gcell, grad, op->stream));
+    return TDP_OK;
+}

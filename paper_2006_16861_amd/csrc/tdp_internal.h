@@ -1,0 +1,155 @@
+// Internal declarations shared by the host library and the HIP kernels of
+// libtdp.  Nothing here is part of the public ABI (include/tdp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/tdp.h"
+
+namespace tdp {
+
+void set_error(const char *fmt, ...);
+
+#define TDP_CHECK_HIP(call)                                                              \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            ::tdp::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),      \
+                             __FILE__, __LINE__);                                        \
+            return TDP_EHIP;                                                             \
+        }                                                                                \
+    } while (0)
+
+#define TDP_CHECK(rc_expr)                 \
+    do {                                   \
+        int rc_ = (rc_expr);               \
+        if (rc_ < 0) return rc_;           \
+    } while (0)
+
+// Constants of one application of the assembled stencil to a real field u,
+// with the cell slowness m_cell:
+//   result_i = c0 u_i + sum_{k>=1} s[k] sum_{|o|=k} u_{i+o}
+//                    + sum_{k>=0} m[k] sum_{|o|=k} W_o u_{i+o},
+// where o runs over the 3^d offsets, |o| = number of nonzero components
+// (the Delta class of App. A) and W_o = sum of m_cell over the cells that
+// contain both node i and node i+o.
+template <typename T>
+struct Stencil {
+    T c0;
+    T s[4];
+    T m[4];
+};
+
+// Launch geometry / variant choice for the sweep.
+struct SweepCfg {
+    int kernel = 1;       // 1 one step per launch, 2 temporally blocked
+    int tb_depth = 0;     // steps per launch for kernel 2
+};
+
+// Device kernels (kernels.hip).  Every launcher enqueues on `s` and returns
+// hipSuccess or the launch error.
+struct SweepArgs {
+    int ndim;
+    int n[3];             // interior nodes per axis (n[2] = 1 in 2-D)
+    int sc, mc;           // number of leading nonzero stiffness / mass classes
+    const void *u;        // u_j
+    void *up;             // in: u_{j-1}, out: u_{j+1}
+    const void *m;        // cell slowness [(n0+1)(n1+1)(n2+1)]
+    const void *dn;       // node factor 1/(1 + l/2)
+    const void *F;        // complex right-hand side (double2 or float2)
+    double *out;          // if non-null, u_{j+1} written here with stride 2
+};
+
+hipError_t launch_sweep_f64(const SweepArgs &a, const Stencil<double> &st, double fa, double fb,
+                            hipStream_t s);
+hipError_t launch_sweep_f32(const SweepArgs &a, const Stencil<float> &st, float fa, float fb,
+                            hipStream_t s);
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_cvt_c128_to_c64(const void *F, void *Fs, int64_t N, hipStream_t s);
+hipError_t launch_cvt_f64_to_f32(const double *x, float *y, int64_t N, hipStream_t s);
+
+// y = H x   or   y = F - H x  (when F != null); complex128.
+hipError_t launch_apply_H(int ndim, const int *n, int sc, int mc, const double *m,
+                          const double *rw, const Stencil<double> &st, const void *x,
+                          const void *F, void *y, hipStream_t s);
+
+// setup kernels
+hipError_t launch_cell_slowness(int ndim, const int *n, const double *c, double *m,
+                                hipStream_t s);
+hipError_t launch_max_reduce(const double *x, int64_t N, double *partial, int nblk,
+                             double *out, hipStream_t s);
+hipError_t launch_node_factors(const double *R, int64_t N, double omega, double lscale,
+                               double *rw, double *dn, hipStream_t s);
+
+// Krylov kernels (complex128, FP64 reductions, deterministic order)
+int blas_nblocks(int64_t N);
+hipError_t launch_mdot(const void *V, int64_t ldv, int nv, const void *w, int64_t N,
+                       double *partial, int nblk, double *out, hipStream_t s);
+hipError_t launch_maxpy(void *w, const void *V, int64_t ldv, int nv, const double *coef,
+                        double sign, int64_t N, hipStream_t s);
+hipError_t launch_scale_by_invnorm(void *v, const void *w, const double *nrm2, int64_t N,
+                                   hipStream_t s);
+
+// gradient
+hipError_t launch_grad_cells(int ndim, const int *n, double w2, const double *mass,
+                             const void *lam, const void *U, double *gcell, hipStream_t s);
+hipError_t launch_grad_nodes(int ndim, const int *n, const double *gcell, double *grad,
+                             hipStream_t s);
+
+}  // namespace tdp
+
+// The opaque operator.
+struct tdp_op {
+    int ndim = 0;
+    int n[3] = {1, 1, 1};
+    int64_t N = 0, Nc = 0;
+    double h = 0, omega = 0;
+    double S[4] = {0, 0, 0, 0}, M[4] = {0, 0, 0, 0};
+    int sc = 0, mc = 0;
+    int prec = TDP_F64;
+    hipStream_t stream = nullptr;
+    // derived parameters
+    double omega_c = 0, lam_bar = 0, dt = 0, alpha = 0, beta = 0;
+    int nP = 0;
+    double cS = 0, cM = 0, cw = 0, g = 0;
+    tdp::Stencil<double> st_step{}, st_H{};
+    tdp::Stencil<float> st_step32{};
+    // device buffers
+    double *m = nullptr;       // cell slowness
+    double *rw = nullptr;      // omega * R at nodes
+    double *dn = nullptr;      // 1 / (1 + l/2) at nodes
+    float *m32 = nullptr, *dn32 = nullptr;
+    void *u0 = nullptr, *u1 = nullptr;      // recurrence fields (prec)
+    void *u2 = nullptr, *u3 = nullptr;      // extra fields for the blocked kernel
+    void *Fst = nullptr;                    // staged F (float2) for FP32
+    double *scratch = nullptr;              // small device scratch
+    size_t scratch_bytes = 0;
+    // Krylov workspace (lazily sized)
+    void *V = nullptr;
+    int V_cols = 0;
+    void *wv = nullptr, *tv = nullptr, *rv = nullptr;
+    double *red = nullptr;     // reduction partials
+    size_t red_bytes = 0;
+    double *dcoef = nullptr;   // device small vector (coefficients / results)
+    double *hres = nullptr;    // pinned host mirror
+    // forcing tables per (T, rho)
+    std::map<std::pair<int, double>, std::vector<double>> tables;
+    std::map<std::pair<int, double>, double *> dtables;
+    // captured step loops, keyed by (T, rho, F, U pointers, kernel, depth)
+    std::map<std::tuple<int, double, const void *, void *, int, int>, hipGraphExec_t> graphs;
+    tdp_tuning tune{0, 0, 1};
+    // stream join with the caller, staging buffers of the captured loop
+    hipStream_t user_stream = nullptr;
+    bool own_stream = false;
+    hipEvent_t ev = nullptr;
+    void *Fstage = nullptr;    // complex128 input of the captured loop (FP64)
+    void *Ustage = nullptr;    // complex128 output of the captured loop
+    double *gcell = nullptr;   // per-cell gradient scratch
+};

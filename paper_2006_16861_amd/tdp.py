@@ -1,0 +1,236 @@
+"""ctypes binding of libtdp (include/tdp.h): argument marshalling only.
+
+Every array is a torch tensor on the GPU; the binding passes its data pointer
+and the current torch stream to the C ABI.  There is no CPU fallback: if
+libtdp.so is missing or fails to load, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtdp.so")
+
+OK, ENOTCONV, EINVAL, ENOMEM, EHIP, ECFL = 0, 1, -1, -2, -3, -4
+F64, F32 = 0, 1
+
+SYMBOLS = ("tdp_op_create", "tdp_op_destroy", "tdp_op_query", "tdp_apply_H",
+           "tdp_precond_apply", "tdp_gmres_solve", "tdp_grad_m", "tdp_op_set_tuning",
+           "tdp_op_get_tuning", "tdp_last_error")
+
+
+class TdpError(RuntimeError):
+    def __init__(self, code, what, msg):
+        super().__init__(f"{what} failed ({code}): {msg}")
+        self.code = code
+
+
+class OpDesc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int64 * 3), ("h", ctypes.c_double),
+                ("omega", ctypes.c_double), ("c", ctypes.c_void_p), ("R", ctypes.c_void_p),
+                ("stiff", ctypes.c_void_p), ("mass", ctypes.c_void_p),
+                ("steps_per_period", ctypes.c_int), ("prec", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
+
+
+class OpInfo(ctypes.Structure):
+    _fields_ = [("omega_c", ctypes.c_double), ("dt", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("lam_bar", ctypes.c_double), ("n_P", ctypes.c_int), ("ndim", ctypes.c_int),
+                ("N", ctypes.c_int64)]
+
+
+class GmresCfg(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
+                ("periods_T", ctypes.c_int), ("rho", ctypes.c_double), ("tol", ctypes.c_double),
+                ("x0_given", ctypes.c_int), ("fixed_iters", ctypes.c_int)]
+
+
+class GmresInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("relres_true", ctypes.c_double), ("relres_prec", ctypes.c_double),
+                ("steps", ctypes.c_int64), ("ms_total", ctypes.c_double),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int),
+                ("history_len", ctypes.c_int)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int), ("tb_depth", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libtdp.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libtdp.so not found at {path}; run paper_2006_16861_amd.build")
+    L = ctypes.CDLL(path)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.tdp_op_create.argtypes = [ctypes.POINTER(OpDesc), ctypes.POINTER(P)]
+    L.tdp_op_destroy.argtypes = [P]
+    L.tdp_op_query.argtypes = [P, ctypes.POINTER(OpInfo)]
+    L.tdp_apply_H.argtypes = [P, P, P]
+    L.tdp_precond_apply.argtypes = [P, I, D, P, P]
+    L.tdp_gmres_solve.argtypes = [P, ctypes.POINTER(GmresCfg), P, P, ctypes.POINTER(GmresInfo)]
+    L.tdp_grad_m.argtypes = [P, P, P, P]
+    L.tdp_op_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    L.tdp_op_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    L.tdp_last_error.restype = ctypes.c_char_p
+    for name in SYMBOLS:
+        L[name].restype = L[name].restype if name == "tdp_last_error" else ctypes.c_int
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return load().tdp_last_error().decode()
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise TdpError(rc, what, last_error())
+    return rc
+
+
+def _stream_ptr():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, dtype, numel, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{what} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    iters: int
+    restarts: int
+    relres: float
+    relres_prec: float
+    steps: int
+    ms_total: float
+    history: list
+
+
+class Operator:
+    """H for -Lap U - omega^2/c^2 U + i omega R U = F on an interior grid `n`
+    with spacing `h` (Dirichlet walls); c and R are FP64 tensors on the GPU."""
+
+    def __init__(self, c, R, omega, h, prec=F64, steps_per_period=0, stiff=None, mass=None):
+        import torch
+        L = load()
+        self.n = tuple(int(v) for v in c.shape)
+        self.ndim = len(self.n)
+        if self.ndim not in (2, 3):
+            raise ValueError("c must be 2-D or 3-D")
+        self.N = int(c.numel())
+        desc = OpDesc()
+        desc.ndim = self.ndim
+        for a in range(3):
+            desc.n[a] = self.n[a] if a < self.ndim else 1
+        desc.h = float(h)
+        desc.omega = float(omega)
+        desc.c = _dev_ptr(c, torch.float64, self.N, "c")
+        desc.R = None if R is None else _dev_ptr(R, torch.float64, self.N, "R")
+        self._tables = []
+        for name, tab in (("stiff", stiff), ("mass", mass)):
+            if tab is None:
+                setattr(desc, name, None)
+            else:
+                arr = (ctypes.c_double * (self.ndim + 1))(*[float(v) for v in tab])
+                self._tables.append(arr)
+                setattr(desc, name, ctypes.cast(arr, ctypes.c_void_p))
+        desc.steps_per_period = int(steps_per_period)
+        desc.prec = int(prec)
+        desc.stream = _stream_ptr()
+        self.prec = int(prec)
+        h_ = ctypes.c_void_p()
+        _check(L.tdp_op_create(ctypes.byref(desc), ctypes.byref(h_)), "tdp_op_create")
+        self._h = h_
+        info = OpInfo()
+        _check(L.tdp_op_query(self._h, ctypes.byref(info)), "tdp_op_query")
+        self.omega_c, self.dt, self.alpha, self.beta = info.omega_c, info.dt, info.alpha, info.beta
+        self.lam_bar, self.nP = info.lam_bar, info.n_P
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().tdp_op_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def _cplx(self, t, what):
+        import torch
+        return _dev_ptr(t, torch.complex128, self.N, what)
+
+    def apply_H(self, x, out=None):
+        import torch
+        out = torch.empty_like(x) if out is None else out
+        _check(load().tdp_apply_H(self._h, self._cplx(x, "x"), self._cplx(out, "y")),
+               "tdp_apply_H")
+        return out
+
+    def precond(self, F, T, rho=0.25, out=None):
+        import torch
+        out = torch.empty_like(F) if out is None else out
+        _check(load().tdp_precond_apply(self._h, int(T), float(rho), self._cplx(F, "F"),
+                                        self._cplx(out, "U")), "tdp_precond_apply")
+        return out
+
+    def solve(self, F, T, rho=0.25, tol=1e-6, restart=30, max_iters=3000, fixed_iters=0,
+              x0=None, history_cap=4096):
+        import torch
+        U = torch.zeros_like(F) if x0 is None else x0.clone()
+        cfg = GmresCfg(int(restart), int(max_iters), int(T), float(rho), float(tol),
+                       int(x0 is not None), int(fixed_iters))
+        hist = (ctypes.c_double * max(1, history_cap))()
+        info = GmresInfo()
+        info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        info.history_cap = int(history_cap)
+        rc = _check(load().tdp_gmres_solve(self._h, ctypes.byref(cfg), self._cplx(F, "F"),
+                                           self._cplx(U, "U"), ctypes.byref(info)),
+                    "tdp_gmres_solve")
+        return U, SolveInfo(rc, info.iters, info.restarts, info.relres_true, info.relres_prec,
+                            info.steps, info.ms_total, list(hist[: info.history_len]))
+
+    def grad_m(self, lam, U, out=None):
+        import torch
+        out = torch.empty(self.n, dtype=torch.float64, device=U.device) if out is None else out
+        _check(load().tdp_grad_m(self._h, self._cplx(lam, "lam"), self._cplx(U, "U"),
+                                 _dev_ptr(out, torch.float64, self.N, "grad")), "tdp_grad_m")
+        return out
+
+    def set_tuning(self, kernel=0, tb_depth=0, use_graph=1):
+        t = Tuning(int(kernel), int(tb_depth), int(use_graph))
+        _check(load().tdp_op_set_tuning(self._h, ctypes.byref(t)), "tdp_op_set_tuning")
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(load().tdp_op_get_tuning(self._h, ctypes.byref(t)), "tdp_op_get_tuning")
+        return {"kernel": t.kernel, "tb_depth": t.tb_depth, "use_graph": t.use_graph}
+
+
+def operator_from_problem(p, device="cuda", **kw):
+    """Operator for an inputs.Problem (copies c and R to the device)."""
+    import torch
+    c = torch.as_tensor(p.c, dtype=torch.float64, device=device).contiguous()
+    R = torch.as_tensor(p.R, dtype=torch.float64, device=device).contiguous()
+    op = Operator(c, R, p.omega, p.h, **kw)
+    op._keep = (c, R)
+    return op
