@@ -42,19 +42,19 @@ def make_problem(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def sweep_timing(op, F, T, rho, reps, stream):
+def sweep_timing(op, F, T, rho, reps, stream, variant=0):
     """Average duration of one recurrence-step launch, from HIP events on the
     stream the sweep kernels are launched on, over `reps` preconditioner
     applications (each N_s = T n_P launches plus two staging copies)."""
     import torch
     U = torch.empty_like(F)
-    op.precond(F, T, rho, out=U)          # capture / warm
+    op.precond(F, T, rho, out=U, variant=variant)          # capture / warm
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        op.precond(F, T, rho, out=U)
+        op.precond(F, T, rho, out=U, variant=variant)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--rho", type=float, default=0.25)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--variant", type=int, default=0,
+                    help="0: Table 1 real-field preconditioner, 1: Definition 4 complex field")
     ap.add_argument("--kernel", type=int, default=0)
     ap.add_argument("--tb-depth", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
@@ -130,12 +132,14 @@ def main():
         log(f"n={p.n} N={p.N} n_P={op.nP} T={T} N_s={Ns} setup {setup_ms:.1f} ms")
         infos = []
         for w in range(args.warmup):
-            U, info = op.solve(F, T=T, rho=args.rho, tol=args.tol, restart=args.restart)
+            U, info = op.solve(F, T=T, rho=args.rho, tol=args.tol, restart=args.restart,
+                               variant=args.variant)
             log(f"warmup {w}: iters={info.iters} relres={info.relres:.3e} {info.ms_total:.1f} ms")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
-            U, info = op.solve(F, T=T, rho=args.rho, tol=args.tol, restart=args.restart)
+            U, info = op.solve(F, T=T, rho=args.rho, tol=args.tol, restart=args.restart,
+                               variant=args.variant)
             infos.append(info)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -148,8 +152,10 @@ def main():
         r = F - op.apply_H(U)
         relres = float(torch.linalg.norm(r) / torch.linalg.norm(F))
         log(f"timed {args.steps} solves in {wall:.3f} s; last true relres {relres:.3e}")
-        apply_ms, step_ms = sweep_timing(op, F, T, args.rho, args.sweep_reps, stream)
-    bytes_per = WORDS_PER_NODE_STEP * (8 if prec == tdp.F64 else 4)
+        apply_ms, step_ms = sweep_timing(op, F, T, args.rho, args.sweep_reps, stream,
+                                         args.variant)
+    words = WORDS_PER_NODE_STEP if args.variant == 0 else 10
+    bytes_per = words * (8 if prec == tdp.F64 else 4)
     achieved = p.N * bytes_per / (step_ms * 1e-3) / 1e9
     napply = infos[-1].steps // Ns
     log(f"precond apply {apply_ms:.3f} ms, {step_ms * 1e3:.2f} us/step, {achieved:.1f} GB/s algorithmic")
@@ -168,8 +174,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": list(p.n), "h": p.h, "omega": p.omega,
                    "ppw": p.ppw, "damping_width": p.width, "periods_T": T, "n_P": op.nP,
-                   "N_s": Ns, "rho": args.rho, "restart": args.restart, "tol": args.tol,
-                   "gmres_iters": infos[-1].iters, "precond_applications": int(napply),
+                   "N_s": Ns, "rho": args.rho, "variant": args.variant, "restart": args.restart, "tol": args.tol,
+                   "gmres_iters": infos[-1].iters, "gmres_restarts": infos[-1].restarts,
+                   "precond_applications": int(napply),
                    "true_relres": relres, "setup_ms": setup_ms,
                    "kernel": op.get_tuning(), "parallelism": "single-gpu"},
         "recurrence_GBps": achieved,

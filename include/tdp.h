@@ -105,12 +105,16 @@ typedef struct {
  *  rho          window parameter in (0, 1]; <= 0 means rho = 1/T
  *  tol          target for the true relative residual ||F - H U|| / ||F||
  *  x0_given     1: U holds the initial guess on entry; 0: start from 0
- *  fixed_iters  > 0: run exactly this many iterations, no early stop      */
+ *  fixed_iters  > 0: run exactly this many iterations (restarting every
+ *               `restart`), no early stop
+ *  variant      0: P = Table 1 (real field, 7 words per node-step);
+ *               1: P = Definition 4 as stated (complex field, 10 words) */
 typedef struct {
     int restart, max_iters, periods_T;
     double rho, tol;
     int x0_given;
     int fixed_iters;
+    int variant;
 } tdp_gmres_cfg;
 
 /* GMRES report (host struct).  history (host, may be NULL) receives the
@@ -146,12 +150,23 @@ int tdp_apply_H(const tdp_op *op, const void *x, void *y);
  * parameter rho (rho <= 0: rho = 1/T).  F, U: device complex128 [N]. */
 int tdp_precond_apply(const tdp_op *op, int periods_T, double rho, const void *F, void *U);
 
+/* U = S_T F by Definition 4 (Sec. 2.3) as stated: the integrator I_acd on a
+ * complex field driven by chi(1 - j/N_s) e^{i 2 pi j/n_P} F from zero fields,
+ * U = e^{-i 2 pi T} u_{N_s} = u_{N_s}.  Complex-linear, unlike Table 1 whose
+ * output is only real-linear; costs 10 instead of 7 words per node-step.
+ * F, U: device complex128 [N]. */
+int tdp_precond_apply_complex(const tdp_op *op, int periods_T, double rho, const void *F,
+                              void *U);
+
 /* Solve H U = F with left-preconditioned restarted GMRES (Sec. 2.4).
- * Stops when the true relative residual is <= tol (recomputed in FP64 after
- * each cycle); a cycle ends when the Givens estimate of the preconditioned
- * residual drops below an inner tolerance (tightened by tol/true on each
- * restart) or after `restart` iterations.  Returns TDP_OK, or TDP_ENOTCONV
- * with the last iterate in U.  F, U: device complex128 [N]; info: host or NULL. */
+ * After every iteration the current iterate x0 + V y is formed and its true
+ * relative residual ||F - H x|| / ||F|| evaluated in FP64; the solve stops as
+ * soon as it is <= tol.  A cycle ends after `restart` iterations, or earlier
+ * when the true residual stalls while the Givens estimate of the
+ * preconditioned residual keeps falling (relt > 2 rel_start est_cycle and
+ * relt > 0.7 rel_prev; the Table 1 map is only real-linear, so the Arnoldi
+ * relation holds only approximately).  Returns TDP_OK, or TDP_ENOTCONV with
+ * the last iterate in U.  F, U: device complex128 [N]; info: host or NULL. */
 int tdp_gmres_solve(const tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void *U,
                     tdp_gmres_info *info);
 

@@ -74,7 +74,8 @@ def lib():
         L.tdpo_window.argtypes = [D, D]
         L.tdpo_window.restype = D
         L.tdpo_precond_apply.argtypes = [P, I, D, P, P]
-        L.tdpo_gmres_solve.argtypes = [P, I, I, I, D, D, I, I, P, P, P, P, I]
+        L.tdpo_gmres_solve.argtypes = [P, I, I, I, D, D, I, I, I, P, P, P, P, I]
+        L.tdpo_precond_apply_complex.argtypes = [P, I, D, P, P]
         L.tdpo_grad_m.argtypes = [P, P, P, P]
         _lib = L
     return _lib
@@ -168,28 +169,30 @@ class Op:
         lib().tdpo_step(self._h, _ptr(u), _ptr(um), fp, _ptr(up))
         return up
 
-    def precond(self, F, T, rho=0.25):
+    def precond(self, F, T, rho=0.25, variant=0):
         F = np.ascontiguousarray(F, dtype=np.complex128).reshape(self.n)
         U = np.empty_like(F)
-        rc = lib().tdpo_precond_apply(self._h, int(T), float(rho), _ptr(F), _ptr(U))
+        fn = lib().tdpo_precond_apply_complex if variant else lib().tdpo_precond_apply
+        rc = fn(self._h, int(T), float(rho), _ptr(F), _ptr(U))
         if rc != OK:
             raise OracleError(rc, "tdpo_precond_apply")
         return U
 
     def gmres(self, F, T, rho=0.25, tol=1e-6, restart=30, max_iters=3000, fixed_iters=0,
-              x0=None, history_cap=4096):
+              x0=None, history_cap=4096, variant=0):
         F = np.ascontiguousarray(F, dtype=np.complex128).reshape(self.n)
         U = np.zeros_like(F) if x0 is None else np.ascontiguousarray(x0, dtype=np.complex128).reshape(self.n).copy()
-        info = np.zeros(5)
+        info = np.zeros(6)
         hist = np.zeros(history_cap)
         rc = lib().tdpo_gmres_solve(self._h, int(restart), int(max_iters), int(T), float(rho),
-                                    float(tol), int(fixed_iters), int(x0 is not None), _ptr(F),
-                                    _ptr(U), _ptr(info), _ptr(hist), int(history_cap))
+                                    float(tol), int(fixed_iters), int(x0 is not None),
+                                    int(variant), _ptr(F), _ptr(U), _ptr(info), _ptr(hist),
+                                    int(history_cap))
         if rc < 0:
             raise OracleError(rc, "tdpo_gmres_solve")
         res = {"status": rc, "iters": int(info[0]), "restarts": int(info[1]),
                "relres": float(info[2]), "relres_prec": float(info[3]),
-               "history": hist[: int(info[4])].copy()}
+               "history": hist[: int(info[4])].copy(), "applications": int(info[5])}
         return U, res
 
     def grad_m(self, lam, U):

@@ -35,10 +35,15 @@ void tdpo_step(const tdpo_op *op, const double *u, const double *um, const doubl
 double tdpo_window(double s, double rho);
 int tdpo_precond_apply(const tdpo_op *op, int T, double rho, const double complex *F,
                        double complex *U);
-/* info = {iters, restarts, true relres, last Givens estimate, history length} */
+int tdpo_precond_apply_complex(const tdpo_op *op, int T, double rho,
+                               const double complex *F, double complex *U);
+/* variant 0: Table 1 preconditioner, 1: Definition 4 (complex-linear).
+ * info = {iters, restarts, true relres, last Givens estimate, history length,
+ *         preconditioner applications} */
 int tdpo_gmres_solve(const tdpo_op *op, int restart, int max_iters, int T, double rho,
-                     double tol, int fixed_iters, int x0_given, const double complex *F,
-                     double complex *U, double *info, double *history, int history_cap);
+                     double tol, int fixed_iters, int x0_given, int variant,
+                     const double complex *F, double complex *U, double *info,
+                     double *history, int history_cap);
 void tdpo_grad_m(const tdpo_op *op, const double complex *lam, const double complex *U,
                  double *grad_nodes);
 

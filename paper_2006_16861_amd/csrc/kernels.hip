@@ -25,23 +25,48 @@ struct V2<float> {
     using type = float2;
 };
 
+// complex pair of the complex-linear variant's field (re, im)
+template <typename T>
+struct C2 {
+    T x, y;
+};
+template <typename T>
+__device__ __forceinline__ C2<T> operator+(C2<T> a, C2<T> b)
+{
+    return {a.x + b.x, a.y + b.y};
+}
+template <typename T>
+__device__ __forceinline__ C2<T> &operator+=(C2<T> &a, C2<T> b)
+{
+    a.x += b.x;
+    a.y += b.y;
+    return a;
+}
+template <typename T>
+__device__ __forceinline__ C2<T> operator*(T s, C2<T> a)
+{
+    return {s * a.x, s * a.y};
+}
+
 // ---------------------------------------------------------------------------
 // assembled stencil: see Stencil<T> in tdp_internal.h.  w[e] are the 2^D
 // cell values around the node, e = ex + 2 ey (+ 4 ez).  U(oz, oy, ox)
-// returns the field at the offset node (0 outside the box).
+// returns the field value (T, or C2<T> for a complex field) at the offset
+// node (0 outside the box).
 template <int D, int SC, int MC, typename T, typename LoadU>
-__device__ __forceinline__ T eval_stencil(const LoadU &U, const T *w, const Stencil<T> &st)
+__device__ __forceinline__ auto eval_stencil(const LoadU &U, const T *w, const Stencil<T> &st)
 {
+    using V = decltype(U(0, 0, 0));
     constexpr int NC = SC > MC ? SC : MC;
     constexpr int NOFF = D == 2 ? 9 : 27;
-    T us[4] = {T(0), T(0), T(0), T(0)};
-    T ws[4] = {T(0), T(0), T(0), T(0)};
+    V us[4] = {V{}, V{}, V{}, V{}};
+    V ws[4] = {V{}, V{}, V{}, V{}};
 #pragma unroll
     for (int k = 0; k < NOFF; ++k) {
         const int ox = k % 3 - 1, oy = (k / 3) % 3 - 1, oz = D == 3 ? k / 9 - 1 : 0;
         const int cls = (ox != 0) + (oy != 0) + (oz != 0);
         if (cls >= NC) continue;
-        const T v = U(oz, oy, ox);
+        const V v = U(oz, oy, ox);
         if (cls < SC || cls == 0) us[cls] += v;
         if (cls < MC) {
             T W = T(0);
@@ -56,7 +81,7 @@ __device__ __forceinline__ T eval_stencil(const LoadU &U, const T *w, const Sten
             ws[cls] += W * v;
         }
     }
-    T r = st.c0 * us[0];
+    V r = st.c0 * us[0];
 #pragma unroll
     for (int k = 1; k < SC; ++k) r += st.s[k] * us[k];
 #pragma unroll
@@ -147,6 +172,82 @@ hipError_t launch_sweep_f32(const SweepArgs &a, const Stencil<float> &st, float 
                             hipStream_t s)
 {
     return launch_sweep_t<float>(a, st, fa, fb, s);
+}
+
+// ---------------------------------------------------------------------------
+// complex-linear variant (Definition 4): complex field u driven by the complex
+// forcing g chi_j e^{i phi_j} F; (fa, fb) = g chi_j (cos phi_j, sin phi_j).
+//   u_{j+1} = d (S[u_j] + (fa + i fb) F) - (2d - 1) u_{j-1}
+template <int D, int SC, int MC, typename T>
+__global__ __launch_bounds__(256) void k_sweep_c(const C2<T> *__restrict__ u,
+                                                 C2<T> *__restrict__ up,
+                                                 const T *__restrict__ m,
+                                                 const T *__restrict__ dn,
+                                                 const typename V2<T>::type *__restrict__ F,
+                                                 int nz, int ny, int nx, Stencil<T> st, T fa,
+                                                 T fb, double2 *__restrict__ out)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= nx || y >= ny) return;
+    const int64_t i = ((int64_t)z * ny + y) * nx + x;
+    T w[1 << D];
+    load_cells<D>(m, z, y, x, ny, nx, w);
+    auto U = [&](int oz, int oy, int ox) -> C2<T> {
+        const bool in = (unsigned)(y + oy) < (unsigned)ny && (unsigned)(x + ox) < (unsigned)nx &&
+                        (D == 2 || (unsigned)(z + oz) < (unsigned)nz);
+        return in ? u[i + ((int64_t)oz * ny + oy) * nx + ox] : C2<T>{T(0), T(0)};
+    };
+    const C2<T> acc = eval_stencil<D, SC, MC>(U, w, st);
+    const auto f = F[i];
+    const T d = dn[i], e = T(2) * d - T(1);
+    const C2<T> p = up[i];
+    C2<T> r;
+    r.x = d * (acc.x + fa * f.x - fb * f.y) - e * p.x;
+    r.y = d * (acc.y + fa * f.y + fb * f.x) - e * p.y;
+    up[i] = r;
+    if (out) out[i] = make_double2((double)r.x, (double)r.y);
+}
+
+template <typename T>
+static hipError_t launch_sweep_c_t(const SweepArgs &a, const Stencil<T> &st, T fa, T fb,
+                                   hipStream_t s)
+{
+    const int nz = a.ndim == 3 ? a.n[0] : 1;
+    const int ny = a.ndim == 3 ? a.n[1] : a.n[0];
+    const int nx = a.ndim == 3 ? a.n[2] : a.n[1];
+    dim3 blk(64, 4, 1);
+    dim3 grd((nx + 63) / 64, (ny + 3) / 4, nz);
+    const C2<T> *u = (const C2<T> *)a.u;
+    C2<T> *up = (C2<T> *)a.up;
+    const T *m = (const T *)a.m;
+    const T *dn = (const T *)a.dn;
+    const auto *F = (const typename V2<T>::type *)a.F;
+    double2 *out = (double2 *)a.out;
+#define TDP_SWEEPC(D, SC, MC) \
+    hipLaunchKernelGGL((k_sweep_c<D, SC, MC, T>), grd, blk, 0, s, u, up, m, dn, F, nz, ny, nx, st, fa, fb, out)
+    if (a.ndim == 2) {
+        if (a.sc <= 3 && a.mc <= 2) TDP_SWEEPC(2, 3, 2);
+        else TDP_SWEEPC(2, 3, 3);
+    } else {
+        if (a.sc <= 3 && a.mc <= 2) TDP_SWEEPC(3, 3, 2);
+        else TDP_SWEEPC(3, 4, 4);
+    }
+#undef TDP_SWEEPC
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_c_f64(const SweepArgs &a, const Stencil<double> &st, double fa,
+                              double fb, hipStream_t s)
+{
+    return launch_sweep_c_t<double>(a, st, fa, fb, s);
+}
+
+hipError_t launch_sweep_c_f32(const SweepArgs &a, const Stencil<float> &st, float fa, float fb,
+                              hipStream_t s)
+{
+    return launch_sweep_c_t<float>(a, st, fa, fb, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -108,9 +108,8 @@ static int free_op(tdp_op *op)
     (void)hipFree(op->Ustage);
     (void)hipFree(op->gcell);
     for (auto &kv : op->graphs) (void)hipGraphExecDestroy(kv.second);
-    for (auto &kv : op->dtables) (void)hipFree(kv.second);
     void *bufs[] = {op->m, op->rw, op->dn, op->m32, op->dn32, op->u0, op->u1, op->u2,
-                    op->u3, op->Fst, op->scratch, op->V, op->wv, op->tv, op->rv,
+                    op->u3, op->Fst, op->scratch, op->V, op->wv, op->tv, op->rv, op->xv,
                     op->red, op->dcoef};
     for (void *b : bufs) (void)hipFree(b);
     if (op->hres) (void)hipHostFree(op->hres);
@@ -358,12 +357,15 @@ static double window(double s, double rho)
     return v * v;
 }
 
-// Forcing scalars of Table 1 for steps j = 0..N_s-1, already scaled by
-// g = dt^2/alpha (Def. 2):  fa_j = g chi_j cos(2 pi j/n_P),
-// fb_j = -g chi_j sin(2 pi j/n_P), chi_j = chi(1 - j/N_s).
-static const std::vector<double> &forcing_table(tdp_op *op, int T, double rho)
+// Forcing scalars for steps j = 0..N_s-1, already scaled by g = dt^2/alpha
+// (Def. 2), chi_j = chi(1 - j/N_s), phi_j = 2 pi j/n_P:
+//   Table 1 (real field):   fa_j = g chi_j cos phi_j,  fb_j = -g chi_j sin phi_j,
+//                           forcing fa Re F + fb Im F = g Re(chi_j e^{i phi_j} F);
+//   Definition 4 (complex): fa_j = g chi_j cos phi_j,  fb_j = g chi_j sin phi_j,
+//                           forcing (fa + i fb) F = g chi_j e^{i phi_j} F.
+static const std::vector<double> &forcing_table(tdp_op *op, int T, double rho, int variant)
 {
-    auto key = std::make_pair(T, rho);
+    auto key = std::make_tuple(T, rho, variant);
     auto it = op->tables.find(key);
     if (it != op->tables.end()) return it->second;
     const int64_t Ns = (int64_t)T * op->nP;
@@ -372,54 +374,71 @@ static const std::vector<double> &forcing_table(tdp_op *op, int T, double rho)
         const double chi = window(1.0 - (double)j / (double)Ns, rho);
         const double ph = 2.0 * M_PI * (double)j / op->nP;
         t[2 * j] = op->g * chi * std::cos(ph);
-        t[2 * j + 1] = -op->g * chi * std::sin(ph);
+        t[2 * j + 1] = (variant ? 1.0 : -1.0) * op->g * chi * std::sin(ph);
     }
     return op->tables.emplace(key, std::move(t)).first->second;
 }
 
-// Issue the Table 1 loop reading F (complex128, or float2 staged for FP32)
-// and writing U (complex128).
-static int issue_steps(tdp_op *op, int T, double rho, const void *Fin, void *U)
+static int ensure_complex_fields(tdp_op *op)
+{
+    if (op->u2) return TDP_OK;
+    const size_t fb = 2 * (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
+    if (hipMalloc(&op->u2, fb) != hipSuccess || hipMalloc(&op->u3, fb) != hipSuccess)
+        TDP_FAIL(TDP_ENOMEM, "device allocation of complex recurrence fields failed");
+    return TDP_OK;
+}
+
+// Issue the recurrence loop reading F (complex128, or float2 staged for FP32)
+// and writing U (complex128).  variant 0: Table 1 (real field, snapshot a
+// quarter period before the end gives Im U); variant 1: Definition 4.
+static int issue_steps(tdp_op *op, int T, double rho, int variant, const void *Fin, void *U)
 {
     hipStream_t s = op->stream;
-    const std::vector<double> &tab = forcing_table(op, T, rho);
+    const std::vector<double> &tab = forcing_table(op, T, rho, variant);
     const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - op->nP / 4;
-    const size_t fb = (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
-    TDP_CHECK_HIP(launch_fill_zero(op->u0, fb, s));
-    TDP_CHECK_HIP(launch_fill_zero(op->u1, fb, s));
-    void *cur = op->u0, *prev = op->u1;
+    const size_t fb = (variant ? 2 : 1) * (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
+    void *cur = variant ? op->u2 : op->u0, *prev = variant ? op->u3 : op->u1;
+    TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
+    TDP_CHECK_HIP(launch_fill_zero(prev, fb, s));
     SweepArgs a;
     a.ndim = op->ndim;
     for (int k = 0; k < 3; ++k) a.n[k] = op->n[k];
     a.sc = op->sc;
     a.mc = op->mc;
     a.F = Fin;
+    a.m = op->prec == TDP_F64 ? (const void *)op->m : (const void *)op->m32;
+    a.dn = op->prec == TDP_F64 ? (const void *)op->dn : (const void *)op->dn32;
     double *Ud = (double *)U;
     for (int64_t j = 0; j < Ns; ++j) {
         a.u = cur;
         a.up = prev;
-        a.out = (j + 1 == jsnap) ? Ud + 1 : (j + 1 == Ns ? Ud : nullptr);
-        if (op->prec == TDP_F64) {
-            a.m = op->m;
-            a.dn = op->dn;
-            TDP_CHECK_HIP(launch_sweep_f64(a, op->st_step, tab[2 * j], tab[2 * j + 1], s));
+        const double fa = tab[2 * j], fbv = tab[2 * j + 1];
+        if (variant) {
+            a.out = (j + 1 == Ns) ? Ud : nullptr;
+            if (op->prec == TDP_F64)
+                TDP_CHECK_HIP(launch_sweep_c_f64(a, op->st_step, fa, fbv, s));
+            else
+                TDP_CHECK_HIP(launch_sweep_c_f32(a, op->st_step32, (float)fa, (float)fbv, s));
         } else {
-            a.m = op->m32;
-            a.dn = op->dn32;
-            TDP_CHECK_HIP(launch_sweep_f32(a, op->st_step32, (float)tab[2 * j],
-                                           (float)tab[2 * j + 1], s));
+            a.out = (j + 1 == jsnap) ? Ud + 1 : (j + 1 == Ns ? Ud : nullptr);
+            if (op->prec == TDP_F64)
+                TDP_CHECK_HIP(launch_sweep_f64(a, op->st_step, fa, fbv, s));
+            else
+                TDP_CHECK_HIP(launch_sweep_f32(a, op->st_step32, (float)fa, (float)fbv, s));
         }
         std::swap(cur, prev);
     }
     return TDP_OK;
 }
 
-static int precond_impl(tdp_op *op, int T, double rho, const void *F, void *U)
+static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *F, void *U)
 {
     if (T < 1) TDP_FAIL(TDP_EINVAL, "periods_T must be >= 1");
     if (rho <= 0.0) rho = 1.0 / T;
     if (rho > 1.0) TDP_FAIL(TDP_EINVAL, "rho must be <= 1");
+    if (variant != 0 && variant != 1) TDP_FAIL(TDP_EINVAL, "variant must be 0 or 1");
     if ((int64_t)T * op->nP > ((int64_t)1 << 31)) TDP_FAIL(TDP_EINVAL, "too many steps");
+    if (variant) TDP_CHECK(ensure_complex_fields(op));
     hipStream_t s = op->stream;
     if (!op->tune.use_graph) {
         const void *Fin = F;
@@ -427,16 +446,16 @@ static int precond_impl(tdp_op *op, int T, double rho, const void *F, void *U)
             TDP_CHECK_HIP(launch_cvt_c128_to_c64(F, op->Fst, op->N, s));
             Fin = op->Fst;
         }
-        return issue_steps(op, T, rho, Fin, U);
+        return issue_steps(op, T, rho, variant, Fin, U);
     }
-    // captured loop: reads e.Fstage (F64) / op->Fst (F32), writes e.Ustage
-    auto key = std::make_tuple(T, rho, (const void *)nullptr, (void *)nullptr, op->tune.kernel,
-                               op->tune.tb_depth);
+    // captured loop: reads op->Fstage (F64) / op->Fst (F32), writes op->Ustage
+    auto key = std::make_tuple(T, rho, variant, op->tune.kernel, op->tune.tb_depth);
     auto it = op->graphs.find(key);
     if (it == op->graphs.end()) {
         hipGraph_t g;
         TDP_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        int rc = issue_steps(op, T, rho, op->prec == TDP_F64 ? op->Fstage : op->Fst, op->Ustage);
+        int rc = issue_steps(op, T, rho, variant, op->prec == TDP_F64 ? op->Fstage : op->Fst,
+                             op->Ustage);
         hipError_t ce = hipStreamEndCapture(s, &g);
         if (rc != TDP_OK) return rc;
         TDP_CHECK_HIP(ce);
@@ -455,14 +474,25 @@ static int precond_impl(tdp_op *op, int T, double rho, const void *F, void *U)
     return TDP_OK;
 }
 
-extern "C" int tdp_precond_apply(const tdp_op *cop, int T, double rho, const void *F, void *U)
+static int precond_entry(const tdp_op *cop, int T, double rho, int variant, const void *F, void *U)
 {
     clear_error();
     if (!cop || !F || !U) TDP_FAIL(TDP_EINVAL, "NULL argument");
     if (F == U) TDP_FAIL(TDP_EINVAL, "F and U must not alias");
     tdp_op *op = const_cast<tdp_op *>(cop);
     StreamJoin join(op->user_stream, op->stream, op->ev);
-    return precond_impl(op, T, rho, F, U);
+    return precond_impl(op, T, rho, variant, F, U);
+}
+
+extern "C" int tdp_precond_apply(const tdp_op *op, int T, double rho, const void *F, void *U)
+{
+    return precond_entry(op, T, rho, 0, F, U);
+}
+
+extern "C" int tdp_precond_apply_complex(const tdp_op *op, int T, double rho, const void *F,
+                                         void *U)
+{
+    return precond_entry(op, T, rho, 1, F, U);
 }
 
 // ---------------------------------------------------------------------------
@@ -479,7 +509,7 @@ static int ensure_krylov(tdp_op *op, int m)
     op->V_cols = m + 1;
     if (!op->wv) {
         if (hipMalloc(&op->wv, 16 * op->N) != hipSuccess || hipMalloc(&op->tv, 16 * op->N) != hipSuccess ||
-            hipMalloc(&op->rv, 16 * op->N) != hipSuccess)
+            hipMalloc(&op->rv, 16 * op->N) != hipSuccess || hipMalloc(&op->xv, 16 * op->N) != hipSuccess)
             TDP_FAIL(TDP_ENOMEM, "GMRES work vector allocation failed");
     }
     const int nblk = blas_nblocks(op->N);
@@ -513,6 +543,13 @@ static int norm2_host(tdp_op *op, const void *x, double *out)
 
 typedef std::complex<double> cplx;
 
+// Restarted GMRES on P H U = P F, the same iteration as the CPU oracle but
+// with classical Gram-Schmidt applied twice (fused multi-dot / multi-axpy
+// kernels).  Tolerance mode evaluates the true residual of the current iterate
+// after every iteration (a multi-axpy, one H-apply and a norm: under 1% of a
+// preconditioner application), stops as soon as it is <= tol, and restarts
+// the cycle early when the true residual stalls while the Givens estimate
+// keeps falling (the Table 1 preconditioner is only real-linear).
 static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void *U,
                       tdp_gmres_info *info)
 {
@@ -523,13 +560,14 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
     if (cfg->periods_T < 1) TDP_FAIL(TDP_EINVAL, "periods_T must be >= 1");
     if (!(cfg->tol > 0.0)) TDP_FAIL(TDP_EINVAL, "tol must be > 0");
     if (cfg->rho > 1.0) TDP_FAIL(TDP_EINVAL, "rho must be <= 1");
+    if (cfg->variant != 0 && cfg->variant != 1) TDP_FAIL(TDP_EINVAL, "variant must be 0 or 1");
     TDP_CHECK(ensure_krylov(op, m));
     hipStream_t s = op->stream;
     const int64_t N = op->N;
     const int T = cfg->periods_T;
     const double rho = cfg->rho;
-    const int fixed = cfg->fixed_iters;
-    const int limit = fixed > 0 ? fixed : cfg->max_iters;
+    const bool tolmode = cfg->fixed_iters <= 0;
+    const int limit = tolmode ? cfg->max_iters : cfg->fixed_iters;
     const int nblk = blas_nblocks(N);
     char *V = (char *)op->V;
     auto col = [&](int k) -> void * { return V + (size_t)16 * N * k; };
@@ -544,28 +582,47 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
     const double bnorm = std::sqrt(b2);
     int its = 0, restarts = 0, nhist = 0, status = TDP_ENOTCONV;
     int64_t napply = 0;
-    double tol_inner = cfg->tol, pnorm0 = -1.0, est = 1.0, rel = 1.0;
+    double pnorm0 = -1.0, est = 1.0, rel = 1.0;
     std::vector<cplx> Hm((size_t)(m + 1) * m), gv(m + 1), sn(m), y(m);
     std::vector<double> cs(m);
     auto HM = [&](int i, int j) -> cplx & { return Hm[(size_t)j * (m + 1) + i]; };
+    auto solve_y = [&](int k_used) {
+        for (int k = k_used - 1; k >= 0; --k) {
+            cplx sum = gv[k];
+            for (int j = k + 1; j < k_used; ++j) sum -= HM(k, j) * y[j];
+            y[k] = sum / HM(k, k);
+        }
+    };
+    // x_out = x_in + V y  (y from the host), x_out may equal x_in
+    auto update = [&](void *x_out, const void *x_in, int k_used) -> int {
+        for (int k = 0; k < k_used; ++k) {
+            op->hres[2 * k] = y[k].real();
+            op->hres[2 * k + 1] = y[k].imag();
+        }
+        TDP_CHECK_HIP(hipMemcpyAsync(dy, op->hres, sizeof(double) * 2 * k_used,
+                                     hipMemcpyHostToDevice, s));
+        if (x_out != x_in)
+            TDP_CHECK_HIP(hipMemcpyAsync(x_out, x_in, 16 * N, hipMemcpyDeviceToDevice, s));
+        TDP_CHECK_HIP(launch_maxpy(x_out, op->V, N, k_used, dy, 1.0, N, s));
+        return TDP_OK;
+    };
     if (bnorm == 0.0) {
         TDP_CHECK_HIP(launch_fill_zero(U, 16 * N, s));
         status = TDP_OK;
         rel = 0.0;
         est = 0.0;
-        goto done;
     }
-    for (;;) {
+    while (status != TDP_OK) {
         double r2;
         TDP_CHECK(apply_H_impl(op, U, F, op->rv));   // r = F - H U
         TDP_CHECK(norm2_host(op, op->rv, &r2));
         rel = std::sqrt(r2) / bnorm;
-        if (fixed <= 0 && rel <= cfg->tol) {
+        if (tolmode && rel <= cfg->tol) {
             status = TDP_OK;
             break;
         }
         if (its >= limit) break;
-        TDP_CHECK(precond_impl(op, T, rho, op->rv, col(0)));
+        TDP_CHECK(precond_impl(op, T, rho, cfg->variant, op->rv, col(0)));
         ++napply;
         double z2;
         TDP_CHECK(norm2_host(op, col(0), &z2));
@@ -576,10 +633,12 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
         TDP_CHECK_HIP(launch_scale_by_invnorm(col(0), col(0), op->dcoef, N, s));
         for (int k = 0; k <= m; ++k) gv[k] = 0.0;
         gv[0] = beta0;
-        int k_used = 0, inner_conv = 0;
+        double rel_start = rel, rel_prev = rel;
+        int k_used = 0;
+        bool converged = false, have_xt = false;
         for (int i = 0; i < m && its < limit; ++i) {
             TDP_CHECK(apply_H_impl(op, col(i), nullptr, op->tv));
-            TDP_CHECK(precond_impl(op, T, rho, op->tv, op->wv));
+            TDP_CHECK(precond_impl(op, T, rho, cfg->variant, op->tv, op->wv));
             ++napply;
             ++its;
             // classical Gram-Schmidt, two passes
@@ -618,46 +677,49 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
             gv[i + 1] = -std::conj(sn[i]) * gv[i];
             gv[i] = cs[i] * gv[i];
             est = std::abs(gv[i + 1]) / pnorm0;
+            const double est_cycle = std::abs(gv[i + 1]) / beta0;
             if (info && info->history && nhist < info->history_cap) info->history[nhist] = est;
             ++nhist;
             k_used = i + 1;
-            if (hn == 0.0) break;
-            if (fixed <= 0 && est <= tol_inner) {
-                inner_conv = 1;
+            if (tolmode) {
+                solve_y(k_used);
+                TDP_CHECK(update(op->xv, U, k_used));
+                TDP_CHECK(apply_H_impl(op, op->xv, F, op->rv));
+                TDP_CHECK(norm2_host(op, op->rv, &r2));
+                const double relt = std::sqrt(r2) / bnorm;
+                have_xt = true;
+                rel = relt;
+                if (relt <= cfg->tol) {
+                    converged = true;
+                    break;
+                }
+                if (hn == 0.0) break;
+                if (relt > 2.0 * rel_start * est_cycle && relt > 0.7 * rel_prev) break;
+                rel_prev = relt;
+            } else if (hn == 0.0) {
                 break;
             }
         }
-        for (int k = k_used - 1; k >= 0; --k) {
-            cplx sum = gv[k];
-            for (int j = k + 1; j < k_used; ++j) sum -= HM(k, j) * y[j];
-            y[k] = sum / HM(k, k);
-        }
-        for (int k = 0; k < k_used; ++k) {
-            op->hres[2 * k] = y[k].real();
-            op->hres[2 * k + 1] = y[k].imag();
-        }
-        TDP_CHECK_HIP(hipMemcpyAsync(dy, op->hres, sizeof(double) * 2 * k_used,
-                                     hipMemcpyHostToDevice, s));
-        TDP_CHECK_HIP(launch_maxpy(U, op->V, N, k_used, dy, 1.0, N, s));
         ++restarts;
-        TDP_CHECK(apply_H_impl(op, U, F, op->rv));
-        TDP_CHECK(norm2_host(op, op->rv, &r2));
-        rel = std::sqrt(r2) / bnorm;
-        if (fixed > 0) {
-            if (its >= limit) {
-                status = TDP_OK;
-                break;
-            }
-            continue;
+        if (have_xt) {
+            TDP_CHECK_HIP(hipMemcpyAsync(U, op->xv, 16 * N, hipMemcpyDeviceToDevice, s));
+        } else if (k_used > 0) {
+            solve_y(k_used);
+            TDP_CHECK(update(U, U, k_used));
         }
-        if (rel <= cfg->tol) {
+        if (converged) {
+            status = TDP_OK;
+            break;
+        }
+        if (!tolmode && its >= limit) {
+            TDP_CHECK(apply_H_impl(op, U, F, op->rv));
+            TDP_CHECK(norm2_host(op, op->rv, &r2));
+            rel = std::sqrt(r2) / bnorm;
             status = TDP_OK;
             break;
         }
         if (its >= limit) break;
-        if (inner_conv) tol_inner *= cfg->tol / rel;
     }
-done:
     TDP_CHECK_HIP(hipStreamSynchronize(s));
     if (info) {
         info->iters = its;

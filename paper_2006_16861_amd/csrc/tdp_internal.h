@@ -71,6 +71,13 @@ hipError_t launch_sweep_f64(const SweepArgs &a, const Stencil<double> &st, doubl
 hipError_t launch_sweep_f32(const SweepArgs &a, const Stencil<float> &st, float fa, float fb,
                             hipStream_t s);
 
+// complex-linear variant: u, up are complex fields (re, im pairs of T); `out`
+// (if non-null) receives u_{j+1} as complex128.
+hipError_t launch_sweep_c_f64(const SweepArgs &a, const Stencil<double> &st, double fa,
+                              double fb, hipStream_t s);
+hipError_t launch_sweep_c_f32(const SweepArgs &a, const Stencil<float> &st, float fa, float fb,
+                              hipStream_t s);
+
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_cvt_c128_to_c64(const void *F, void *Fs, int64_t N, hipStream_t s);
 hipError_t launch_cvt_f64_to_f32(const double *x, float *y, int64_t N, hipStream_t s);
@@ -127,23 +134,22 @@ struct tdp_op {
     double *dn = nullptr;      // 1 / (1 + l/2) at nodes
     float *m32 = nullptr, *dn32 = nullptr;
     void *u0 = nullptr, *u1 = nullptr;      // recurrence fields (prec)
-    void *u2 = nullptr, *u3 = nullptr;      // extra fields for the blocked kernel
+    void *u2 = nullptr, *u3 = nullptr;      // complex fields of the complex-linear variant
     void *Fst = nullptr;                    // staged F (float2) for FP32
     double *scratch = nullptr;              // small device scratch
     size_t scratch_bytes = 0;
     // Krylov workspace (lazily sized)
     void *V = nullptr;
     int V_cols = 0;
-    void *wv = nullptr, *tv = nullptr, *rv = nullptr;
+    void *wv = nullptr, *tv = nullptr, *rv = nullptr, *xv = nullptr;
     double *red = nullptr;     // reduction partials
     size_t red_bytes = 0;
     double *dcoef = nullptr;   // device small vector (coefficients / results)
     double *hres = nullptr;    // pinned host mirror
     // forcing tables per (T, rho)
-    std::map<std::pair<int, double>, std::vector<double>> tables;
-    std::map<std::pair<int, double>, double *> dtables;
-    // captured step loops, keyed by (T, rho, F, U pointers, kernel, depth)
-    std::map<std::tuple<int, double, const void *, void *, int, int>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, double, int>, std::vector<double>> tables;
+    // captured step loops, keyed by (T, rho, variant, kernel, depth)
+    std::map<std::tuple<int, double, int, int, int>, hipGraphExec_t> graphs;
     tdp_tuning tune{0, 0, 1};
     // stream join with the caller, staging buffers of the captured loop
     hipStream_t user_stream = nullptr;

@@ -17,7 +17,7 @@ OK, ENOTCONV, EINVAL, ENOMEM, EHIP, ECFL = 0, 1, -1, -2, -3, -4
 F64, F32 = 0, 1
 
 SYMBOLS = ("tdp_op_create", "tdp_op_destroy", "tdp_op_query", "tdp_apply_H",
-           "tdp_precond_apply", "tdp_gmres_solve", "tdp_grad_m", "tdp_op_set_tuning",
+           "tdp_precond_apply", "tdp_precond_apply_complex", "tdp_gmres_solve", "tdp_grad_m", "tdp_op_set_tuning",
            "tdp_op_get_tuning", "tdp_last_error")
 
 
@@ -45,7 +45,8 @@ class OpInfo(ctypes.Structure):
 class GmresCfg(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
                 ("periods_T", ctypes.c_int), ("rho", ctypes.c_double), ("tol", ctypes.c_double),
-                ("x0_given", ctypes.c_int), ("fixed_iters", ctypes.c_int)]
+                ("x0_given", ctypes.c_int), ("fixed_iters", ctypes.c_int),
+                ("variant", ctypes.c_int)]
 
 
 class GmresInfo(ctypes.Structure):
@@ -77,6 +78,7 @@ def load(path: str = LIB_PATH):
     L.tdp_op_query.argtypes = [P, ctypes.POINTER(OpInfo)]
     L.tdp_apply_H.argtypes = [P, P, P]
     L.tdp_precond_apply.argtypes = [P, I, D, P, P]
+    L.tdp_precond_apply_complex.argtypes = [P, I, D, P, P]
     L.tdp_gmres_solve.argtypes = [P, ctypes.POINTER(GmresCfg), P, P, ctypes.POINTER(GmresInfo)]
     L.tdp_grad_m.argtypes = [P, P, P, P]
     L.tdp_op_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
@@ -186,19 +188,21 @@ class Operator:
                "tdp_apply_H")
         return out
 
-    def precond(self, F, T, rho=0.25, out=None):
+    def precond(self, F, T, rho=0.25, out=None, variant=0):
+        """Table 1 (variant 0) or Definition 4 (variant 1) preconditioner."""
         import torch
         out = torch.empty_like(F) if out is None else out
-        _check(load().tdp_precond_apply(self._h, int(T), float(rho), self._cplx(F, "F"),
-                                        self._cplx(out, "U")), "tdp_precond_apply")
+        fn = load().tdp_precond_apply_complex if variant else load().tdp_precond_apply
+        _check(fn(self._h, int(T), float(rho), self._cplx(F, "F"), self._cplx(out, "U")),
+               "tdp_precond_apply")
         return out
 
     def solve(self, F, T, rho=0.25, tol=1e-6, restart=30, max_iters=3000, fixed_iters=0,
-              x0=None, history_cap=4096):
+              x0=None, history_cap=4096, variant=0):
         import torch
         U = torch.zeros_like(F) if x0 is None else x0.clone()
         cfg = GmresCfg(int(restart), int(max_iters), int(T), float(rho), float(tol),
-                       int(x0 is not None), int(fixed_iters))
+                       int(x0 is not None), int(fixed_iters), int(variant))
         hist = (ctypes.c_double * max(1, history_cap))()
         info = GmresInfo()
         info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))

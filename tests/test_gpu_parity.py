@@ -187,3 +187,83 @@ def test_gmres_f32_reaches_tolerance():
     Uo, _ = o.gmres(p.F, T=p.periods, tol=1e-10)
     note(f"  f32-path error vs oracle(1e-10): {rel(U, Uo):.3e}")
     assert rel(U, Uo) <= 1e-3
+
+
+# ---------------------------------------------------------------- Definition 4 variant
+@pytest.mark.parametrize("name,mk", [CASES[0], CASES[1], CASES[3], CASES[4]])
+def test_precond_complex_variant(name, mk):
+    p = mk()
+    note(f"precond complex variant {name}")
+    g, o = make_ops(p)
+    T = min(p.periods, 4)
+    for graph in (0, 1):
+        g.set_tuning(kernel=1, use_graph=graph)
+        U = host(g.precond(dev(p.F), T, 0.25, variant=1))
+        assert rel(U, o.precond(p.F, T, 0.25, variant=1)) <= TOL64
+
+
+def test_gmres_complex_variant_fixed_and_converged():
+    p = inputs.random_medium((30, 41), seed=15, width=3)
+    note("gmres complex variant 30x41")
+    g, o = make_ops(p)
+    Ug, ig = g.solve(dev(p.F), T=p.periods, restart=4, fixed_iters=9, variant=1)
+    Uo, io = o.gmres(p.F, T=p.periods, restart=4, fixed_iters=9, variant=1)
+    assert rel(host(Ug), Uo) <= TOL64
+    Ug, ig = g.solve(dev(p.F), T=p.periods, tol=1e-8, variant=1)
+    Uo, io = o.gmres(p.F, T=p.periods, tol=1e-8, variant=1)
+    assert ig.status == 0 and rel(o.apply_H(host(Ug)), p.F) <= 1e-8 * (1 + 1e-9)
+    assert ig.iters == io["iters"] and rel(host(Ug), Uo) <= TOL64
+
+
+def test_gmres_applications_match_oracle():
+    """Same stopping and restart decisions: same iteration / application counts."""
+    p = inputs.smooth2d(96, width=8)
+    note("gmres application count smooth2d-96")
+    g, o = make_ops(p)
+    Ug, ig = g.solve(dev(p.F), T=p.periods, tol=1e-6)
+    Uo, io = o.gmres(p.F, T=p.periods, tol=1e-6)
+    assert ig.iters == io["iters"] and ig.restarts == io["restarts"]
+    assert ig.steps == io["applications"] * p.periods * o.nP
+    assert rel(host(Ug), Uo) <= TOL64
+
+
+# ---------------------------------------------------------------- full-size workloads
+def test_full_size_2d_one_period_and_H():
+    """1024^2 smooth medium (the benchmark workload) in the benchmark's launch
+    configuration: one period of the recurrence (12 launches over every tile and
+    the ragged edges) and the H-apply against the oracle."""
+    p = inputs.smooth2d(1024)
+    note("full-size smooth2d-1024: P F with T=1, H-apply")
+    g, o = make_ops(p)
+    F = dev(p.F)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
+    assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
+    U = host(g.precond(F, 1, 0.25))
+    assert rel(U, o.precond(p.F, 1, 0.25)) <= TOL64
+    U = host(g.precond(dev(x), 1, 0.25))
+    assert rel(U, o.precond(x, 1, 0.25)) <= TOL64
+
+
+def test_full_size_2d_solve_residual_checked_by_oracle():
+    p = inputs.smooth2d(1024)
+    note("full-size smooth2d-1024 solve to 1e-6")
+    g, o = make_ops(p)
+    Ug, ig = g.solve(dev(p.F), T=p.periods, tol=1e-6)
+    assert ig.status == 0
+    r = rel(o.apply_H(host(Ug)), p.F)
+    note(f"  iters {ig.iters} restarts {ig.restarts} oracle-checked relres {r:.3e}")
+    assert r <= 1e-6 * (1 + 1e-9)
+
+
+def test_full_size_3d_one_period():
+    p = inputs.layered3d(256)
+    note("full-size layered3d-256: P F with T=1, H-apply")
+    g, o = make_ops(p)
+    assert g.nP == o.nP
+    F = dev(p.F)
+    U = host(g.precond(F, 1, 0.25))
+    assert rel(U, o.precond(p.F, 1, 0.25)) <= TOL64
+    rng = np.random.default_rng(4)
+    x = (rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n))
+    assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
