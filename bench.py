@@ -102,9 +102,12 @@ def main():
                     help="0: Table 1 real-field preconditioner, 1: Definition 4 complex field")
     ap.add_argument("--kernel", type=int, default=0)
     ap.add_argument("--tb-depth", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sweep-reps", type=int, default=3)
+    ap.add_argument("--tune-only", action="store_true",
+                    help="print the autotuner's per-variant step times and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -125,7 +128,19 @@ def main():
         op = tdp.operator_from_problem(p, prec=prec)
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t) * 1e3
-        op.set_tuning(kernel=args.kernel, tb_depth=args.tb_depth, use_graph=0 if args.no_graph else 1)
+        tune_table = []
+        if args.kernel == 0 and not args.no_graph:
+            t = time.perf_counter()
+            best, tune_table = op.autotune(T=4, rho=args.rho, variant=args.variant)
+            log(f"autotune ({(time.perf_counter() - t) * 1e3:.0f} ms): best {best}")
+            for row in tune_table:
+                log(f"   kernel={int(row[0])} depth={int(row[1])} tile={int(row[2])}: "
+                    f"{row[3]:.2f} us/step")
+            if args.tune_only:
+                return
+        else:
+            op.set_tuning(kernel=args.kernel, tb_depth=args.tb_depth, tile=args.tile,
+                          use_graph=0 if args.no_graph else 1)
         T = p.periods
         Ns = T * op.nP
         F = torch.as_tensor(p.F, device="cuda")

@@ -179,16 +179,31 @@ int tdp_gmres_solve(const tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, v
 int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
 
 /* Tuning of the recurrence sweep (no effect on results beyond rounding).
- *  kernel       0 auto, 1 one step per launch, 2 temporally blocked
- *  tb_depth     steps per launch for the blocked kernel (0 auto)
- *  use_graph    1 capture the step loop in a hipGraph and replay it        */
+ *  kernel       0 auto, 1 one step per launch, 2 temporally blocked (2-D,
+ *               Table 1 variant; other cases fall back to 1)
+ *  tb_depth     steps per launch for the blocked kernel, 1..16 (0 auto)
+ *  use_graph    1 capture the step loop in a hipGraph and replay it
+ *  tile         blocked-kernel tile (rows x columns): 0 64x64 (8 rows per
+ *               lane x 8 waves), 1 64x64 (4 x 16 waves), 2 128x64 (FP32
+ *               only), 3 32x64 (4 x 8 waves)                                */
 typedef struct {
     int kernel;
     int tb_depth;
     int use_graph;
+    int tile;
 } tdp_tuning;
 
 int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t);
+
+/* Autotuner: times each sweep variant applicable to this op (one step per
+ * launch; blocked tile shapes x depths 2, 3, 4, 6, 8 for the 2-D Table 1
+ * loop) over periods_T periods with HIP events on the op's stream, and makes
+ * the fastest the op's tuning.  best (host, may be NULL) receives it; table
+ * (host, may be NULL) receives up to cap rows of {kernel, tb_depth, tile,
+ * microseconds per step}.  Returns the number of candidates timed (> 0) or a
+ * negative error.  Overwrites the op's internal staging buffers only. */
+int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int variant, tdp_tuning *best,
+                    double *table, int cap);
 int tdp_op_get_tuning(const tdp_op *op, tdp_tuning *t);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -108,7 +108,7 @@ static int free_op(tdp_op *op)
     (void)hipFree(op->Ustage);
     (void)hipFree(op->gcell);
     for (auto &kv : op->graphs) (void)hipGraphExecDestroy(kv.second);
-    void *bufs[] = {op->m, op->rw, op->dn, op->m32, op->dn32, op->u0, op->u1, op->u2,
+    void *bufs[] = {op->m, op->rw, op->dn, op->m32, op->dn32, op->u0, op->u1, op->u2, op->v0, op->v1,
                     op->u3, op->Fst, op->scratch, op->V, op->wv, op->tv, op->rv, op->xv,
                     op->red, op->dcoef};
     for (void *b : bufs) (void)hipFree(b);
@@ -317,7 +317,9 @@ extern "C" int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t)
     clear_error();
     if (!op || !t) TDP_FAIL(TDP_EINVAL, "NULL argument");
     if (t->kernel < 0 || t->kernel > 2) TDP_FAIL(TDP_EINVAL, "kernel must be 0, 1 or 2");
-    if (t->tb_depth < 0 || t->tb_depth > 16) TDP_FAIL(TDP_EINVAL, "tb_depth must be in [0, 16]");
+    if (t->tb_depth < 0 || t->tb_depth > TDP_TB_KMAX) TDP_FAIL(TDP_EINVAL, "tb_depth must be in [0, 16]");
+    if (t->tile < 0 || t->tile > 3) TDP_FAIL(TDP_EINVAL, "tile must be 0, 1, 2 or 3");
+    if (t->tile == 2 && op->prec == TDP_F64) TDP_FAIL(TDP_EINVAL, "tile 2 is FP32 only");
     op->tune = *t;
     return TDP_OK;
 }
@@ -388,11 +390,84 @@ static int ensure_complex_fields(tdp_op *op)
     return TDP_OK;
 }
 
+// Which sweep kernel and depth the loop uses.
+static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth)
+{
+    int kern = op->tune.kernel, k = op->tune.tb_depth;
+    if (kern == 0) kern = (op->ndim == 2 && variant == 0) ? 2 : 1;
+    if (kern == 2 && !(op->ndim == 2 && variant == 0)) kern = 1;
+    if (k == 0) k = 4;
+    const int rows = tb2d_tile_rows(op->tune.tile, op->prec == TDP_F64);
+    if (4 * k > rows || 4 * k > 64) k = rows / 8;   // keep at least half the tile exact
+    *kernel = kern;
+    *depth = kern == 2 ? k : 1;
+}
+
+static int ensure_tb_fields(tdp_op *op)
+{
+    if (op->v0) return TDP_OK;
+    const size_t fb = (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
+    if (hipMalloc(&op->v0, fb) != hipSuccess || hipMalloc(&op->v1, fb) != hipSuccess)
+        TDP_FAIL(TDP_ENOMEM, "device allocation of blocked-sweep fields failed");
+    return TDP_OK;
+}
+
+// Blocked loop: launches of k steps, ping-ponging between the field pairs
+// (u0, u1) and (v0, v1).
+static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, const void *Fin, void *U)
+{
+    hipStream_t s = op->stream;
+    TDP_CHECK(ensure_tb_fields(op));
+    const std::vector<double> &tab = forcing_table(op, T, rho, 0);
+    const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - op->nP / 4;
+    const size_t fb = (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
+    void *cur = op->u0, *prev = op->u1, *ncur = op->v0, *nprev = op->v1;
+    TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
+    TDP_CHECK_HIP(launch_fill_zero(prev, fb, s));
+    TBArgs a;
+    a.ny = op->n[0];
+    a.nx = op->n[1];
+    a.sc = op->sc;
+    a.mc = op->mc;
+    a.shape = op->tune.tile;
+    a.m = op->prec == TDP_F64 ? (const void *)op->m : (const void *)op->m32;
+    a.dn = op->prec == TDP_F64 ? (const void *)op->dn : (const void *)op->dn32;
+    a.F = Fin;
+    double *Ud = (double *)U;
+    for (int64_t j0 = 0; j0 < Ns; j0 += depth) {
+        const int k = (int)std::min<int64_t>(depth, Ns - j0);
+        a.u_in = cur;
+        a.up_in = prev;
+        a.u_out = ncur;
+        a.up_out = nprev;
+        a.cf.k = k;
+        for (int q = 0; q < k; ++q) {
+            a.cf.fa[q] = tab[2 * (j0 + q)];
+            a.cf.fb[q] = tab[2 * (j0 + q) + 1];
+        }
+        // step q (1-based) of this launch produces u_{j0+q}
+        a.cf.out_step[0] = (jsnap > j0 && jsnap <= j0 + k) ? (int)(jsnap - j0) : 0;
+        a.cf.out[0] = Ud + 1;
+        a.cf.out_step[1] = (Ns > j0 && Ns <= j0 + k) ? (int)(Ns - j0) : 0;
+        a.cf.out[1] = Ud;
+        if (op->prec == TDP_F64)
+            TDP_CHECK_HIP(launch_sweep2d_tb_f64(a, op->st_step, s));
+        else
+            TDP_CHECK_HIP(launch_sweep2d_tb_f32(a, op->st_step32, s));
+        std::swap(cur, ncur);
+        std::swap(prev, nprev);
+    }
+    return TDP_OK;
+}
+
 // Issue the recurrence loop reading F (complex128, or float2 staged for FP32)
 // and writing U (complex128).  variant 0: Table 1 (real field, snapshot a
 // quarter period before the end gives Im U); variant 1: Definition 4.
 static int issue_steps(tdp_op *op, int T, double rho, int variant, const void *Fin, void *U)
 {
+    int kern, depth;
+    sweep_plan(op, variant, &kern, &depth);
+    if (kern == 2) return issue_steps_tb(op, T, rho, depth, Fin, U);
     hipStream_t s = op->stream;
     const std::vector<double> &tab = forcing_table(op, T, rho, variant);
     const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - op->nP / 4;
@@ -439,6 +514,11 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
     if (variant != 0 && variant != 1) TDP_FAIL(TDP_EINVAL, "variant must be 0 or 1");
     if ((int64_t)T * op->nP > ((int64_t)1 << 31)) TDP_FAIL(TDP_EINVAL, "too many steps");
     if (variant) TDP_CHECK(ensure_complex_fields(op));
+    {   // allocate before any stream capture: no allocation may happen inside it
+        int kern, depth;
+        sweep_plan(op, variant, &kern, &depth);
+        if (kern == 2) TDP_CHECK(ensure_tb_fields(op));
+    }
     hipStream_t s = op->stream;
     if (!op->tune.use_graph) {
         const void *Fin = F;
@@ -449,7 +529,7 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
         return issue_steps(op, T, rho, variant, Fin, U);
     }
     // captured loop: reads op->Fstage (F64) / op->Fst (F32), writes op->Ustage
-    auto key = std::make_tuple(T, rho, variant, op->tune.kernel, op->tune.tb_depth);
+    auto key = std::make_tuple(T, rho, variant, op->tune.kernel, op->tune.tb_depth, op->tune.tile);
     auto it = op->graphs.find(key);
     if (it == op->graphs.end()) {
         hipGraph_t g;
@@ -493,6 +573,89 @@ extern "C" int tdp_precond_apply_complex(const tdp_op *op, int T, double rho, co
                                          void *U)
 {
     return precond_entry(op, T, rho, 1, F, U);
+}
+
+// Autotuner: times every sweep variant that applies to this op (one step per
+// launch; blocked tiles x depths in 2-D) on `periods_T` periods of the loop,
+// with HIP events on the op's stream, keeps the fastest.
+extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int variant,
+                               tdp_tuning *best, double *table, int cap)
+{
+    clear_error();
+    if (!op) TDP_FAIL(TDP_EINVAL, "NULL argument");
+    if (periods_T < 1) TDP_FAIL(TDP_EINVAL, "periods_T must be >= 1");
+    if (variant != 0 && variant != 1) TDP_FAIL(TDP_EINVAL, "variant must be 0 or 1");
+    StreamJoin join(op->user_stream, op->stream, op->ev);
+    hipStream_t s = op->stream;
+    std::vector<tdp_tuning> cand;
+    cand.push_back({1, 0, 1, 0});
+    if (op->ndim == 2 && variant == 0) {
+        const int tiles[] = {0, 1, 2, 3};
+        const int depths[] = {2, 3, 4, 6, 8};
+        for (int tile : tiles) {
+            if (tile == 2 && op->prec == TDP_F64) continue;
+            const int rows = tb2d_tile_rows(tile, op->prec == TDP_F64);
+            for (int k : depths)
+                if (4 * k <= rows && 4 * k <= 64) cand.push_back({2, k, 1, tile});
+        }
+    }
+    const tdp_tuning saved = op->tune;
+    void *tin = nullptr, *tout = nullptr;
+    if (hipMalloc(&tin, 16 * op->N) != hipSuccess || hipMalloc(&tout, 16 * op->N) != hipSuccess) {
+        (void)hipFree(tin);
+        TDP_FAIL(TDP_ENOMEM, "autotune buffers");
+    }
+    TDP_CHECK_HIP(launch_fill_zero(tin, 16 * op->N, s));
+    hipEvent_t e0, e1;
+    TDP_CHECK_HIP(hipEventCreate(&e0));
+    TDP_CHECK_HIP(hipEventCreate(&e1));
+    double best_ms = INFINITY;
+    tdp_tuning bt = saved;
+    const int reps = 3;
+    const double steps = (double)periods_T * op->nP * reps;
+    int i = 0;
+    int rc = TDP_OK;
+    for (const tdp_tuning &c : cand) {
+        op->tune = c;
+        rc = precond_impl(op, periods_T, rho, variant, tin, tout);
+        if (rc != TDP_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = TDP_EHIP; break; }
+        for (int r = 0; r < reps && rc == TDP_OK; ++r)
+            rc = precond_impl(op, periods_T, rho, variant, tin, tout);
+        if (rc != TDP_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = TDP_EHIP;
+            break;
+        }
+        const double per = ms / steps;
+        if (table && i < cap) {
+            table[4 * i] = c.kernel;
+            table[4 * i + 1] = c.tb_depth;
+            table[4 * i + 2] = c.tile;
+            table[4 * i + 3] = per * 1e3;   // microseconds per step
+        }
+        if (per < best_ms) {
+            best_ms = per;
+            bt = c;
+        }
+        ++i;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(tin);
+    (void)hipFree(tout);
+    for (auto &kv : op->graphs) (void)hipGraphExecDestroy(kv.second);
+    op->graphs.clear();
+    if (rc != TDP_OK) {
+        op->tune = saved;
+        return rc;
+    }
+    op->tune = bt;
+    if (best) *best = bt;
+    return i;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,223 @@
+// Temporally blocked 2-D recurrence sweep (Table 1 loop, integrator I_acd of
+// Def. 2): one launch advances the real field by k <= TB_KMAX steps.
+//
+// Each workgroup owns an extended tile of EY x EX nodes (EX = 64 = one wave
+// across x, EY = R rows per lane x W waves).  It loads u_j into LDS, the cell
+// slowness of the tile into LDS, and keeps u_{j-1}, the damping factor and
+// the right-hand side of its R nodes in registers.  Every step updates the
+// whole tile from LDS; values within s nodes of the tile edge are wrong after
+// s steps (their neighbours outside the tile are taken as 0), so after k steps
+// the inner (EY - 2k) x (EX - 2k) nodes are exact and are the ones written
+// back.  Nodes outside the domain carry d = 0, F = 0, u = 0 and stay 0
+// (Dirichlet).  HBM traffic per node-step falls from 7 words to about
+// (5 (EY EX) / (out area) + cells + 2) / k words.
+//
+// Workgroups are mapped XCD-aware: the hardware deals consecutive workgroup
+// ids round-robin to the 8 XCDs, so id -> tile is remapped to give each XCD a
+// contiguous band of tiles (halo rows shared by neighbouring tiles then hit in
+// that XCD's L2).
+#include <hip/hip_runtime.h>
+
+#include "tdp_internal.h"
+
+namespace tdp {
+
+template <typename T>
+struct V2t;
+template <>
+struct V2t<double> {
+    using type = double2;
+};
+template <>
+struct V2t<float> {
+    using type = float2;
+};
+
+// assembled 9-point stencil from LDS (same formula as eval_stencil in
+// kernels.hip, specialised to 2-D): uc(r, e) is the field at tile row r,
+// column e (padded by one zero row/column on each side), cl the cells.
+template <int SC, int MC, typename T>
+__device__ __forceinline__ T stencil9(const T *__restrict__ ul, int us, const T *__restrict__ cl,
+                                      int cs, const Stencil<T> &st)
+{
+    // ul points at the node, us = LDS row stride; cl points at the cell with
+    // storage (y, x) of the node (its lower-left cell), cs = cell row stride.
+    const T uC = ul[0];
+    const T uW = ul[-1], uE = ul[1], uS = ul[-us], uN = ul[us];
+    const T uSW = ul[-us - 1], uSE = ul[-us + 1], uNW = ul[us - 1], uNE = ul[us + 1];
+    const T mSW = cl[0], mSE = cl[1], mNW = cl[cs], mNE = cl[cs + 1];
+    T r = st.c0 * uC;
+    const T e1 = (uW + uE) + (uS + uN);
+    const T e2 = (uSW + uSE) + (uNW + uNE);
+    r += st.s[1] * e1;
+    if (SC > 2) r += st.s[2] * e2;
+    if (MC > 0) r += st.m[0] * (((mSW + mSE) + (mNW + mNE)) * uC);
+    if (MC > 1)
+        r += st.m[1] * ((mSW + mNW) * uW + (mSE + mNE) * uE + (mSW + mSE) * uS + (mNW + mNE) * uN);
+    if (MC > 2) r += st.m[2] * (mSW * uSW + mSE * uSE + mNW * uNW + mNE * uNE);
+    return r;
+}
+
+template <typename T, int SC, int MC, int R, int W>
+__global__ __launch_bounds__(64 * W) void k_sweep2d_tb(
+    const T *__restrict__ u_in, const T *__restrict__ up_in, T *__restrict__ u_out,
+    T *__restrict__ up_out, const T *__restrict__ m, const T *__restrict__ dn,
+    const typename V2t<T>::type *__restrict__ F, int ny, int nx, Stencil<T> st, TBCoef cf,
+    int tiles_x, int ntiles, int per_xcd)
+{
+    constexpr int EX = 64, EY = R * W;
+    constexpr int US = EX + 2;          // LDS row stride of u (one zero pad each side)
+    constexpr int CS = EX + 1;          // LDS row stride of the cells
+    __shared__ T ul[(EY + 2) * US];
+    __shared__ T cl[(EY + 1) * CS];
+
+    // XCD-aware tile id
+    const int id = blockIdx.x;
+    const int tile = (id % 8) * per_xcd + id / 8;
+    if (tile >= ntiles) return;
+    const int k = cf.k;
+    const int OX = EX - 2 * k, OY = EY - 2 * k;
+    const int ty = tile / tiles_x, tx = tile % tiles_x;
+    const int gy0 = ty * OY - k, gx0 = tx * OX - k;   // global coords of tile (0, 0)
+
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gx = gx0 + lane;
+    const bool xin = (unsigned)gx < (unsigned)nx;
+
+    // zero the LDS pads (rows 0 and EY+1, columns 0 and EX+1)
+    for (int t = threadIdx.x; t < US; t += 64 * W) {
+        ul[t] = T(0);
+        ul[(EY + 1) * US + t] = T(0);
+    }
+    for (int t = threadIdx.x; t < EY + 2; t += 64 * W) {
+        ul[t * US] = T(0);
+        ul[t * US + EX + 1] = T(0);
+    }
+    // cells: storage rows gy0 .. gy0+EY, columns gx0 .. gx0+EX
+    for (int t = threadIdx.x; t < (EY + 1) * (EX + 1); t += 64 * W) {
+        const int cy = t / (EX + 1), cx = t % (EX + 1);
+        const int sy = gy0 + cy, sx = gx0 + cx;
+        const bool ok = (unsigned)sy <= (unsigned)ny && (unsigned)sx <= (unsigned)nx;
+        cl[cy * CS + cx] = ok ? m[(int64_t)sy * (nx + 1) + sx] : T(0);
+    }
+    T uprev[R], d[R], fr[R], fi[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int r = wv * R + i;
+        const int gy = gy0 + r;
+        const bool in = xin && (unsigned)gy < (unsigned)ny;
+        const int64_t g = (int64_t)gy * nx + gx;
+        T uc = T(0);
+        uprev[i] = d[i] = fr[i] = fi[i] = T(0);
+        if (in) {
+            uc = u_in[g];
+            uprev[i] = up_in[g];
+            d[i] = dn[g];
+            const auto f = F[g];
+            fr[i] = f.x;
+            fi[i] = f.y;
+        }
+        ul[(r + 1) * US + lane + 1] = uc;
+    }
+    __syncthreads();
+
+    T unew[R];
+    for (int s = 0; s < k; ++s) {
+        const T fa = (T)cf.fa[s], fb = (T)cf.fb[s];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = wv * R + i;
+            const T acc = stencil9<SC, MC>(&ul[(r + 1) * US + lane + 1], US, &cl[r * CS + lane],
+                                           CS, st);
+            unew[i] = d[i] * (acc + fa * fr[i] + fb * fi[i]) - (T(2) * d[i] - T(1)) * uprev[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = wv * R + i;
+            T *p = &ul[(r + 1) * US + lane + 1];
+            uprev[i] = *p;
+            *p = unew[i];
+        }
+        // outputs of this step (snapshot of Table 1 / final field): the
+        // exact region only
+        if (s + 1 == cf.out_step[0] || s + 1 == cf.out_step[1]) {
+            double *o = (s + 1 == cf.out_step[0]) ? cf.out[0] : cf.out[1];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int r = wv * R + i;
+                const int gy = gy0 + r;
+                if (r >= k && r < EY - k && lane >= k && lane < EX - k && xin &&
+                    (unsigned)gy < (unsigned)ny)
+                    o[2 * ((int64_t)gy * nx + gx)] = (double)unew[i];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int r = wv * R + i;
+        const int gy = gy0 + r;
+        if (r >= k && r < EY - k && lane >= k && lane < EX - k && xin &&
+            (unsigned)gy < (unsigned)ny) {
+            const int64_t g = (int64_t)gy * nx + gx;
+            u_out[g] = ul[(r + 1) * US + lane + 1];
+            up_out[g] = uprev[i];
+        }
+    }
+}
+
+template <typename T, int R, int W>
+static hipError_t launch_tb_t(const TBArgs &a, const Stencil<T> &st, hipStream_t s)
+{
+    constexpr int EX = 64, EY = R * W;
+    const int k = a.cf.k;
+    const int OX = EX - 2 * k, OY = EY - 2 * k;
+    const int tiles_x = (a.nx + OX - 1) / OX, tiles_y = (a.ny + OY - 1) / OY;
+    const int ntiles = tiles_x * tiles_y;
+    const int per_xcd = (ntiles + 7) / 8;
+    dim3 grd(8 * per_xcd), blk(64 * W);
+    const T *u = (const T *)a.u_in, *up = (const T *)a.up_in;
+    T *uo = (T *)a.u_out, *upo = (T *)a.up_out;
+    const T *m = (const T *)a.m, *dn = (const T *)a.dn;
+    const auto *F = (const typename V2t<T>::type *)a.F;
+    if (a.sc <= 3 && a.mc <= 2)
+        hipLaunchKernelGGL((k_sweep2d_tb<T, 3, 2, R, W>), grd, blk, 0, s, u, up, uo, upo, m, dn, F,
+                           a.ny, a.nx, st, a.cf, tiles_x, ntiles, per_xcd);
+    else
+        hipLaunchKernelGGL((k_sweep2d_tb<T, 3, 3, R, W>), grd, blk, 0, s, u, up, uo, upo, m, dn, F,
+                           a.ny, a.nx, st, a.cf, tiles_x, ntiles, per_xcd);
+    return hipGetLastError();
+}
+
+// Tile shapes (rows per lane R x waves W; the tile is 64 columns wide):
+//   0: 8 x 8  -> 64 x 64 tile, 512 threads
+//   1: 4 x 16 -> 64 x 64 tile, 1024 threads
+//   2: 8 x 16 -> 128 x 64 tile, 1024 threads (FP32 only: FP64 would not fit)
+//   3: 4 x 8  -> 32 x 64 tile, 512 threads
+int tb2d_tile_rows(int shape, bool f64)
+{
+    (void)f64;
+    return shape == 2 ? 128 : (shape == 3 ? 32 : 64);
+}
+
+hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hipStream_t s)
+{
+    switch (a.shape) {
+    case 1: return launch_tb_t<double, 4, 16>(a, st, s);
+    case 3: return launch_tb_t<double, 4, 8>(a, st, s);
+    default: return launch_tb_t<double, 8, 8>(a, st, s);
+    }
+}
+
+hipError_t launch_sweep2d_tb_f32(const TBArgs &a, const Stencil<float> &st, hipStream_t s)
+{
+    switch (a.shape) {
+    case 1: return launch_tb_t<float, 4, 16>(a, st, s);
+    case 2: return launch_tb_t<float, 8, 16>(a, st, s);
+    case 3: return launch_tb_t<float, 4, 8>(a, st, s);
+    default: return launch_tb_t<float, 8, 8>(a, st, s);
+    }
+}
+
+}  // namespace tdp

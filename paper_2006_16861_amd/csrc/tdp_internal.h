@@ -71,6 +71,28 @@ hipError_t launch_sweep_f64(const SweepArgs &a, const Stencil<double> &st, doubl
 hipError_t launch_sweep_f32(const SweepArgs &a, const Stencil<float> &st, float fa, float fb,
                             hipStream_t s);
 
+// Temporally blocked 2-D sweep (sweep_tb.hip): one launch = k steps.
+#define TDP_TB_KMAX 16
+struct TBCoef {
+    int k;                   // steps in this launch (1..TDP_TB_KMAX, < tile half-size)
+    int out_step[2];         // 1-based step whose result goes to out[i] (0: none)
+    double *out[2];          // stride-2 outputs (complex128 real or imaginary part)
+    double fa[TDP_TB_KMAX];  // forcing scalars of the k steps
+    double fb[TDP_TB_KMAX];
+};
+struct TBArgs {
+    int ny, nx;              // interior nodes (axis 0, axis 1)
+    int sc, mc;
+    int shape;               // tile shape index (see sweep_tb.hip)
+    const void *u_in, *up_in;    // u_j, u_{j-1}
+    void *u_out, *up_out;        // u_{j+k}, u_{j+k-1}  (distinct from the inputs)
+    const void *m, *dn, *F;
+    TBCoef cf;
+};
+hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hipStream_t s);
+hipError_t launch_sweep2d_tb_f32(const TBArgs &a, const Stencil<float> &st, hipStream_t s);
+int tb2d_tile_rows(int shape, bool f64);
+
 // complex-linear variant: u, up are complex fields (re, im pairs of T); `out`
 // (if non-null) receives u_{j+1} as complex128.
 hipError_t launch_sweep_c_f64(const SweepArgs &a, const Stencil<double> &st, double fa,
@@ -135,6 +157,7 @@ struct tdp_op {
     float *m32 = nullptr, *dn32 = nullptr;
     void *u0 = nullptr, *u1 = nullptr;      // recurrence fields (prec)
     void *u2 = nullptr, *u3 = nullptr;      // complex fields of the complex-linear variant
+    void *v0 = nullptr, *v1 = nullptr;      // second field pair of the blocked sweep
     void *Fst = nullptr;                    // staged F (float2) for FP32
     double *scratch = nullptr;              // small device scratch
     size_t scratch_bytes = 0;
@@ -148,9 +171,9 @@ struct tdp_op {
     double *hres = nullptr;    // pinned host mirror
     // forcing tables per (T, rho)
     std::map<std::tuple<int, double, int>, std::vector<double>> tables;
-    // captured step loops, keyed by (T, rho, variant, kernel, depth)
-    std::map<std::tuple<int, double, int, int, int>, hipGraphExec_t> graphs;
-    tdp_tuning tune{0, 0, 1};
+    // captured step loops, keyed by (T, rho, variant, kernel, depth, tile)
+    std::map<std::tuple<int, double, int, int, int, int>, hipGraphExec_t> graphs;
+    tdp_tuning tune{0, 0, 1, 0};
     // stream join with the caller, staging buffers of the captured loop
     hipStream_t user_stream = nullptr;
     bool own_stream = false;

@@ -17,7 +17,7 @@ OK, ENOTCONV, EINVAL, ENOMEM, EHIP, ECFL = 0, 1, -1, -2, -3, -4
 F64, F32 = 0, 1
 
 SYMBOLS = ("tdp_op_create", "tdp_op_destroy", "tdp_op_query", "tdp_apply_H",
-           "tdp_precond_apply", "tdp_precond_apply_complex", "tdp_gmres_solve", "tdp_grad_m", "tdp_op_set_tuning",
+           "tdp_precond_apply", "tdp_precond_apply_complex", "tdp_gmres_solve", "tdp_grad_m", "tdp_op_set_tuning", "tdp_op_autotune",
            "tdp_op_get_tuning", "tdp_last_error")
 
 
@@ -58,7 +58,8 @@ class GmresInfo(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("kernel", ctypes.c_int), ("tb_depth", ctypes.c_int), ("use_graph", ctypes.c_int)]
+    _fields_ = [("kernel", ctypes.c_int), ("tb_depth", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("tile", ctypes.c_int)]
 
 
 _lib = None
@@ -83,6 +84,7 @@ def load(path: str = LIB_PATH):
     L.tdp_grad_m.argtypes = [P, P, P, P]
     L.tdp_op_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
     L.tdp_op_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    L.tdp_op_autotune.argtypes = [P, I, D, I, ctypes.POINTER(Tuning), P, I]
     L.tdp_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
         L[name].restype = L[name].restype if name == "tdp_last_error" else ctypes.c_int
@@ -220,14 +222,28 @@ class Operator:
                                  _dev_ptr(out, torch.float64, self.N, "grad")), "tdp_grad_m")
         return out
 
-    def set_tuning(self, kernel=0, tb_depth=0, use_graph=1):
-        t = Tuning(int(kernel), int(tb_depth), int(use_graph))
+    def set_tuning(self, kernel=0, tb_depth=0, use_graph=1, tile=0):
+        t = Tuning(int(kernel), int(tb_depth), int(use_graph), int(tile))
         _check(load().tdp_op_set_tuning(self._h, ctypes.byref(t)), "tdp_op_set_tuning")
+
+    def autotune(self, T=4, rho=0.25, variant=0):
+        """Time the sweep variants and keep the fastest; returns (best, table)
+        with table rows (kernel, tb_depth, tile, us_per_step)."""
+        cap = 64
+        tab = (ctypes.c_double * (4 * cap))()
+        best = Tuning()
+        n = _check(load().tdp_op_autotune(self._h, int(T), float(rho), int(variant),
+                                          ctypes.byref(best), ctypes.cast(tab, ctypes.c_void_p),
+                                          cap), "tdp_op_autotune")
+        rows = [tuple(tab[4 * i: 4 * i + 4]) for i in range(min(n, cap))]
+        return ({"kernel": best.kernel, "tb_depth": best.tb_depth, "use_graph": best.use_graph,
+                 "tile": best.tile}, rows)
 
     def get_tuning(self):
         t = Tuning()
         _check(load().tdp_op_get_tuning(self._h, ctypes.byref(t)), "tdp_op_get_tuning")
-        return {"kernel": t.kernel, "tb_depth": t.tb_depth, "use_graph": t.use_graph}
+        return {"kernel": t.kernel, "tb_depth": t.tb_depth, "use_graph": t.use_graph,
+                "tile": t.tile}
 
 
 def operator_from_problem(p, device="cuda", **kw):

@@ -267,3 +267,69 @@ def test_full_size_3d_one_period():
     rng = np.random.default_rng(4)
     x = (rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n))
     assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
+
+
+# ---------------------------------------------------------------- temporally blocked sweep
+TB_CASES = [
+    ("const2d-64", lambda: inputs.const2d()),
+    ("rand2d-37x150", lambda: inputs.random_medium((37, 150), seed=1, width=4)),
+    ("rand2d-130x61", lambda: inputs.random_medium((130, 61), seed=17, width=5)),
+    ("rand2d-1x9", lambda: inputs.random_medium((1, 9), seed=2, width=0)),
+]
+
+
+@pytest.mark.parametrize("tile", [0, 1, 3])
+@pytest.mark.parametrize("depth", [1, 3, 4, 5, 8])
+@pytest.mark.parametrize("name,mk", TB_CASES)
+def test_precond_blocked_f64(name, mk, depth, tile):
+    p = mk()
+    if tile == 3 and depth > 4:
+        depth = 4
+    note(f"precond blocked f64 {name} depth={depth} tile={tile}")
+    g, o = make_ops(p)
+    g.set_tuning(kernel=2, tb_depth=depth, tile=tile, use_graph=1)
+    T = min(p.periods, 3)
+    U = host(g.precond(dev(p.F), T, 0.25))
+    err = rel(U, o.precond(p.F, T, 0.25))
+    assert err <= TOL64, err
+    g.set_tuning(kernel=1, use_graph=0)
+    U1 = host(g.precond(dev(p.F), T, 0.25))
+    assert rel(U, U1) <= 1e-13
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+def test_precond_blocked_f32(tile):
+    p = inputs.random_medium((150, 200), seed=18, width=6)
+    note(f"precond blocked f32 150x200 tile={tile}")
+    g, o = make_ops(p, prec=1)
+    g.set_tuning(kernel=2, tb_depth=4, tile=tile)
+    U = host(g.precond(dev(p.F), 3, 0.25))
+    g.set_tuning(kernel=1)
+    U1 = host(g.precond(dev(p.F), 3, 0.25))
+    Uo = o.precond(p.F, 3, 0.25)
+    assert rel(U, Uo) <= 1e-4 and rel(U1, Uo) <= 1e-4
+    assert rel(U, U1) <= 1e-5
+
+
+def test_gmres_blocked_full_size_matches_one_step():
+    p = inputs.smooth2d(1024)
+    note("gmres blocked vs one-step at 1024^2 (fixed 3 its)")
+    from paper_2006_16861_amd import tdp
+    g = tdp.operator_from_problem(p)
+    F = dev(p.F)
+    g.set_tuning(kernel=1)
+    U1, _ = g.solve(F, T=p.periods, fixed_iters=3)
+    g.set_tuning(kernel=2, tb_depth=4, tile=0)
+    U2, _ = g.solve(F, T=p.periods, fixed_iters=3)
+    assert rel(host(U2), host(U1)) <= 1e-11
+
+
+def test_autotune_picks_a_variant_and_stays_exact():
+    p = inputs.random_medium((200, 180), seed=19, width=6)
+    note("autotune 200x180")
+    g, o = make_ops(p)
+    best, table = g.autotune(T=2)
+    assert len(table) >= 2 and best["kernel"] in (1, 2)
+    assert min(r[3] for r in table) > 0
+    U = host(g.precond(dev(p.F), 3, 0.25))
+    assert rel(U, o.precond(p.F, 3, 0.25)) <= TOL64
