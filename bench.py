@@ -25,6 +25,24 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
 WORDS_PER_NODE_STEP = 7          # u_j, u_{j-1}, u_{j+1}, m, damping, Re F, Im F
 
 
+# FP64/FP32 operations of one 9-point node update (stencil with the cell-mass
+# terms of the compact table, forcing, damping; an FMA counts 2)
+FLOPS_PER_NODE_STEP = 39
+
+
+def measured_traffic(workload, prec, variant, tun):
+    """HBM bytes per launch of the dominant kernel, from the rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs recorded in profiles/traffic.json (scaled by
+    the copy-kernel calibration); None when that kernel configuration was not
+    measured."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    key = f"{workload}|{prec}|v{variant}|k{tun['kernel']}|d{tun['tb_depth']}|t{tun['tile']}"
+    rec = json.load(open(path)).get(key)
+    return None if rec is None else rec["bytes_per_launch"]
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -108,6 +126,9 @@ def main():
     ap.add_argument("--sweep-reps", type=int, default=3)
     ap.add_argument("--tune-only", action="store_true",
                     help="print the autotuner's per-variant step times and exit")
+    ap.add_argument("--profile-sweeps", type=int, default=0,
+                    help="profiling mode: one 256 MiB device copy (counter calibration), then "
+                         "this many preconditioner applications, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -144,6 +165,20 @@ def main():
         T = p.periods
         Ns = T * op.nP
         F = torch.as_tensor(p.F, device="cuda")
+        if args.profile_sweeps:
+            src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            dst.copy_(src)                       # plain copy: 256 MiB read + 256 MiB written
+            torch.cuda.synchronize()
+            apply_ms, step_ms = sweep_timing(op, F, T, args.rho, args.profile_sweeps, stream,
+                                             args.variant)
+            tun = op.get_tuning()
+            launches = Ns if tun["kernel"] != 2 else -(-Ns // tun["tb_depth"])
+            print(json.dumps({"mode": "profile", "workload": args.workload, "N": p.N,
+                              "N_s": Ns, "tuning": tun, "launches_per_apply": launches,
+                              "apply_ms": apply_ms, "us_per_step": step_ms * 1e3,
+                              "us_per_launch": apply_ms * 1e3 / launches}), flush=True)
+            return
         log(f"n={p.n} N={p.N} n_P={op.nP} T={T} N_s={Ns} setup {setup_ms:.1f} ms")
         infos = []
         for w in range(args.warmup):
@@ -171,8 +206,18 @@ def main():
                                          args.variant)
     words = WORDS_PER_NODE_STEP if args.variant == 0 else 10
     bytes_per = words * (8 if prec == tdp.F64 else 4)
-    achieved = p.N * bytes_per / (step_ms * 1e-3) / 1e9
+    tun = op.get_tuning()
+    blocked = tun["kernel"] == 2
+    steps_per_launch = tun["tb_depth"] if blocked else 1
+    launches = -(-Ns // steps_per_launch)
+    launch_us = apply_ms * 1e3 / launches
+    # algorithmic bytes of one launch: 7 words per node-step (u_j, u_{j-1}, u_{j+1},
+    # m, damping, Re F, Im F) x N nodes x the steps the launch advances
+    achieved = p.N * bytes_per * (Ns / launches) / (launch_us * 1e-6) / 1e9
     napply = infos[-1].steps // Ns
+    kname = (f"k_sweep2d_tb<{'double' if prec == tdp.F64 else 'float'}> depth={steps_per_launch} "
+             f"tile={tun['tile']}" if blocked else "k_sweep (one step per launch)")
+    traffic = measured_traffic(args.workload, args.prec, args.variant, tun)
     log(f"precond apply {apply_ms:.3f} ms, {step_ms * 1e3:.2f} us/step, {achieved:.1f} GB/s algorithmic")
     out = {
         "metric": "Helmholtz solves/s at 1e-6 residual; recurrence-step GB/s vs HBM peak",
@@ -196,9 +241,13 @@ def main():
                    "kernel": op.get_tuning(), "parallelism": "single-gpu"},
         "recurrence_GBps": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "recurrence sweep", "bytes_per_node_step": bytes_per,
-                     "nodes_per_launch": p.N, "avg_launch_us": step_ms * 1e3},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": kname, "bytes_per_node_step": bytes_per,
+                     "nodes_per_launch": p.N, "steps_per_launch": Ns / launches,
+                     "avg_launch_us": launch_us,
+                     "alu": {"flops_per_node_step": FLOPS_PER_NODE_STEP,
+                             "achieved_TFLOPs": FLOPS_PER_NODE_STEP * p.N * Ns / (apply_ms * 1e-3) / 1e12,
+                             "peak_TFLOPs": 78.6 if prec == tdp.F64 else 157.3}},
     }
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
