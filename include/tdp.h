@@ -180,12 +180,15 @@ int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
 
 /* Tuning of the recurrence sweep (no effect on results beyond rounding).
  *  kernel       0 auto, 1 one step per launch, 2 temporally blocked (2-D,
- *               Table 1 variant; other cases fall back to 1)
- *  tb_depth     steps per launch for the blocked kernel, 1..16 (0 auto)
+ *               Table 1 variant), 3 streamed along axis 0 (3-D, Table 1
+ *               variant); inapplicable choices fall back to 1
+ *  tb_depth     kernel 2: steps per launch, 1..16 (0 auto);
+ *               kernel 3: planes per chunk (0 auto = 32)
  *  use_graph    1 capture the step loop in a hipGraph and replay it
- *  tile         blocked-kernel tile (rows x columns): 0 64x64 (8 rows per
- *               lane x 8 waves), 1 64x64 (4 x 16 waves), 2 128x64 (FP32
- *               only), 3 32x64 (4 x 8 waves)                                */
+ *  tile         kernel 2 tile (rows x columns): 0 64x64 (8 rows per lane x
+ *               8 waves), 1 64x64 (4 x 16 waves), 2 128x64 (FP32 only),
+ *               3 32x64 (4 x 8 waves); kernel 3: 0 8x64 columns (4 waves x 2
+ *               rows each), 1 16x64 (4 waves x 4 rows), 2 16x64 (8 x 2)    */
 typedef struct {
     int kernel;
     int tb_depth;
@@ -197,7 +200,8 @@ int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t);
 
 /* Autotuner: times each sweep variant applicable to this op (one step per
  * launch; blocked tile shapes x depths 2, 3, 4, 6, 8 for the 2-D Table 1
- * loop) over periods_T periods with HIP events on the op's stream, and makes
+ * loop; streamed column shapes x chunk lengths 16, 32, 64 in 3-D) over
+ * periods_T periods with HIP events on the op's stream, and makes
  * the fastest the op's tuning.  best (host, may be NULL) receives it; table
  * (host, may be NULL) receives up to cap rows of {kernel, tb_depth, tile,
  * microseconds per step}.  Returns the number of candidates timed (> 0) or a

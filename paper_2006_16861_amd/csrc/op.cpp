@@ -316,10 +316,16 @@ extern "C" int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t)
 {
     clear_error();
     if (!op || !t) TDP_FAIL(TDP_EINVAL, "NULL argument");
-    if (t->kernel < 0 || t->kernel > 2) TDP_FAIL(TDP_EINVAL, "kernel must be 0, 1 or 2");
-    if (t->tb_depth < 0 || t->tb_depth > TDP_TB_KMAX) TDP_FAIL(TDP_EINVAL, "tb_depth must be in [0, 16]");
-    if (t->tile < 0 || t->tile > 3) TDP_FAIL(TDP_EINVAL, "tile must be 0, 1, 2 or 3");
-    if (t->tile == 2 && op->prec == TDP_F64) TDP_FAIL(TDP_EINVAL, "tile 2 is FP32 only");
+    if (t->kernel < 0 || t->kernel > 3) TDP_FAIL(TDP_EINVAL, "kernel must be 0, 1, 2 or 3");
+    if (t->kernel == 3) {
+        if (t->tb_depth < 0 || t->tb_depth > (1 << 20)) TDP_FAIL(TDP_EINVAL, "bad chunk length");
+        if (t->tile < 0 || t->tile > 2) TDP_FAIL(TDP_EINVAL, "tile must be 0, 1 or 2 for kernel 3");
+    } else {
+        if (t->tb_depth < 0 || t->tb_depth > TDP_TB_KMAX) TDP_FAIL(TDP_EINVAL, "tb_depth must be in [0, 16]");
+        if (t->tile < 0 || t->tile > 3) TDP_FAIL(TDP_EINVAL, "tile must be 0, 1, 2 or 3");
+        if (t->kernel == 2 && t->tile == 2 && op->prec == TDP_F64)
+            TDP_FAIL(TDP_EINVAL, "tile 2 is FP32 only");
+    }
     op->tune = *t;
     return TDP_OK;
 }
@@ -390,17 +396,26 @@ static int ensure_complex_fields(tdp_op *op)
     return TDP_OK;
 }
 
-// Which sweep kernel and depth the loop uses.
+// Which sweep kernel and depth the loop uses: 1 one step per launch, 2 the
+// blocked 2-D kernel (k steps per launch), 3 the streamed 3-D kernel (depth =
+// planes per chunk).
 static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth)
 {
     int kern = op->tune.kernel, k = op->tune.tb_depth;
-    if (kern == 0) kern = (op->ndim == 2 && variant == 0) ? 2 : 1;
+    if (kern == 0) kern = variant == 0 ? (op->ndim == 2 ? 2 : 3) : 1;
     if (kern == 2 && !(op->ndim == 2 && variant == 0)) kern = 1;
-    if (k == 0) k = 4;
-    const int rows = tb2d_tile_rows(op->tune.tile, op->prec == TDP_F64);
-    if (4 * k > rows || 4 * k > 64) k = rows / 8;   // keep at least half the tile exact
+    if (kern == 3 && !(op->ndim == 3 && variant == 0)) kern = 1;
+    if (kern == 2) {
+        if (k == 0) k = 4;
+        const int rows = tb2d_tile_rows(op->tune.tile, op->prec == TDP_F64);
+        if (4 * k > rows || 4 * k > 64) k = rows / 8;   // keep at least half the tile exact
+    } else if (kern == 3) {
+        if (k == 0) k = 32;
+    } else {
+        k = 1;
+    }
     *kernel = kern;
-    *depth = kern == 2 ? k : 1;
+    *depth = k;
 }
 
 static int ensure_tb_fields(tdp_op *op)
@@ -468,6 +483,7 @@ static int issue_steps(tdp_op *op, int T, double rho, int variant, const void *F
     int kern, depth;
     sweep_plan(op, variant, &kern, &depth);
     if (kern == 2) return issue_steps_tb(op, T, rho, depth, Fin, U);
+    const int shape3 = op->tune.tile > 2 ? 1 : op->tune.tile;
     hipStream_t s = op->stream;
     const std::vector<double> &tab = forcing_table(op, T, rho, variant);
     const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - op->nP / 4;
@@ -496,10 +512,17 @@ static int issue_steps(tdp_op *op, int T, double rho, int variant, const void *F
                 TDP_CHECK_HIP(launch_sweep_c_f32(a, op->st_step32, (float)fa, (float)fbv, s));
         } else {
             a.out = (j + 1 == jsnap) ? Ud + 1 : (j + 1 == Ns ? Ud : nullptr);
-            if (op->prec == TDP_F64)
+            if (kern == 3) {
+                if (op->prec == TDP_F64)
+                    TDP_CHECK_HIP(launch_sweep3d_stream_f64(a, op->st_step, fa, fbv, shape3, depth, s));
+                else
+                    TDP_CHECK_HIP(launch_sweep3d_stream_f32(a, op->st_step32, (float)fa,
+                                                            (float)fbv, shape3, depth, s));
+            } else if (op->prec == TDP_F64) {
                 TDP_CHECK_HIP(launch_sweep_f64(a, op->st_step, fa, fbv, s));
-            else
+            } else {
                 TDP_CHECK_HIP(launch_sweep_f32(a, op->st_step32, (float)fa, (float)fbv, s));
+            }
         }
         std::swap(cur, prev);
     }
@@ -598,6 +621,10 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
             for (int k : depths)
                 if (4 * k <= rows && 4 * k <= 64) cand.push_back({2, k, 1, tile});
         }
+    }
+    if (op->ndim == 3 && variant == 0) {
+        for (int shape = 0; shape < 3; ++shape)
+            for (int zc : {16, 32, 64}) cand.push_back({3, zc, 1, shape});
     }
     const tdp_tuning saved = op->tune;
     void *tin = nullptr, *tout = nullptr;

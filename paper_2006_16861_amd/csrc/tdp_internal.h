@@ -93,6 +93,14 @@ hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hip
 hipError_t launch_sweep2d_tb_f32(const TBArgs &a, const Stencil<float> &st, hipStream_t s);
 int tb2d_tile_rows(int shape, bool f64);
 
+// 3-D sweep streamed along axis 0 (sweep3d.hip), one step per launch.
+// shape 0/1/2: 8 x 64 (4 waves x 2 rows), 16 x 64 (4 waves x 4 rows), 16 x 64
+// (8 waves x 2 rows) node columns per workgroup; zc planes per chunk.
+hipError_t launch_sweep3d_stream_f64(const SweepArgs &a, const Stencil<double> &st, double fa,
+                                     double fb, int shape, int zc, hipStream_t s);
+hipError_t launch_sweep3d_stream_f32(const SweepArgs &a, const Stencil<float> &st, float fa,
+                                     float fb, int shape, int zc, hipStream_t s);
+
 // complex-linear variant: u, up are complex fields (re, im pairs of T); `out`
 // (if non-null) receives u_{j+1} as complex128.
 hipError_t launch_sweep_c_f64(const SweepArgs &a, const Stencil<double> &st, double fa,

@@ -333,3 +333,54 @@ def test_autotune_picks_a_variant_and_stays_exact():
     assert min(r[3] for r in table) > 0
     U = host(g.precond(dev(p.F), 3, 0.25))
     assert rel(U, o.precond(p.F, 3, 0.25)) <= TOL64
+
+
+# ---------------------------------------------------------------- 3-D streamed sweep, general tables
+Q1_2D = ((2 / 3, -1 / 6, -1 / 3), (1 / 9, 1 / 18, 1 / 36))
+Q1_3D = ((1 / 3, 0.0, -1 / 12, -1 / 12), (1 / 27, 1 / 54, 1 / 108, 1 / 216))
+
+
+@pytest.mark.parametrize("shape,zc", [(0, 16), (1, 7), (2, 32), (1, 64)])
+@pytest.mark.parametrize("n", [(9, 11, 70), (17, 5, 130), (40, 23, 9)])
+def test_precond_3d_streamed_f64(n, shape, zc):
+    p = inputs.random_medium(n, seed=21, width=2)
+    note(f"precond 3d streamed {n} shape={shape} zc={zc}")
+    g, o = make_ops(p)
+    g.set_tuning(kernel=3, tb_depth=zc, tile=shape)
+    U = host(g.precond(dev(p.F), 2, 0.25))
+    assert rel(U, o.precond(p.F, 2, 0.25)) <= TOL64
+    g.set_tuning(kernel=1)
+    assert rel(host(g.precond(dev(p.F), 2, 0.25)), U) <= 1e-13
+
+
+def test_precond_3d_streamed_f32():
+    p = inputs.random_medium((24, 30, 70), seed=22, width=3)
+    note("precond 3d streamed f32")
+    g, o = make_ops(p, prec=1)
+    g.set_tuning(kernel=3, tb_depth=16, tile=1)
+    U = host(g.precond(dev(p.F), 2, 0.25))
+    assert rel(U, o.precond(p.F, 2, 0.25)) <= 1e-4
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_general_cell_tables(ndim):
+    """Trilinear / bilinear finite-element cell tables: every stencil class
+    nonzero, so the general kernels (all 9 / 27 points, all mass classes) run."""
+    from paper_2006_16861_amd import tdp
+    n = (45, 77) if ndim == 2 else (11, 13, 66)
+    stiff, mass = Q1_2D if ndim == 2 else Q1_3D
+    p = inputs.random_medium(n, seed=23, width=2)
+    note(f"general tables {ndim}-D")
+    o = oracle.Op(p.n, p.h, p.omega, p.c, p.R, stiff=stiff, mass=mass)
+    g = tdp.Operator(dev(p.c), dev(p.R), p.omega, p.h, stiff=stiff, mass=mass)
+    assert g.nP == o.nP and abs(g.lam_bar - o.lam_bar) <= 1e-12 * o.lam_bar
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
+    assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
+    kernels = [(1, 0, 0), (2, 4, 0), (2, 3, 3)] if ndim == 2 else [(1, 0, 0), (3, 16, 1)]
+    Uo = o.precond(p.F, 2, 0.25)
+    for kern, depth, tile in kernels:
+        g.set_tuning(kernel=kern, tb_depth=depth, tile=tile)
+        assert rel(host(g.precond(dev(p.F), 2, 0.25)), Uo) <= TOL64
+    grad_l = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
+    assert rel(host(g.grad_m(dev(grad_l), dev(x))), o.grad_m(grad_l, x)) <= 1e-13

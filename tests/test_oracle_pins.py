@@ -349,3 +349,33 @@ def test_gradient_matches_lu_finite_differences():
         fd = (loss(m0 + eps * v) - loss(m0 - eps * v)) / (2 * eps)
         an = float(np.vdot(g, v))
         assert abs(fd - an) <= 1e-6 * max(abs(fd), 1e-30) + 1e-12, (fd, an)
+
+
+# ---------------------------------------------------------------- general cell tables
+Q1_2D = ((2 / 3, -1 / 6, -1 / 3), (1 / 9, 1 / 18, 1 / 36))
+Q1_3D = ((1 / 3, 0.0, -1 / 12, -1 / 12), (1 / 27, 1 / 54, 1 / 108, 1 / 216))
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_bilinear_fe_tables_sine_modes(ndim):
+    """With the bilinear / trilinear finite-element cell matrices the sine modes
+    are eigenvectors with the tensor-product symbols of 1-D linear elements:
+    K1(t) = 2(1 - cos t), M1(t) = (2 + cos t)/3; S = sum_a K1(t_a) prod_{b!=a} M1(t_b),
+    M = prod_a M1(t_a)."""
+    n = (7, 9) if ndim == 2 else (5, 4, 6)
+    stiff, mass = Q1_2D if ndim == 2 else Q1_3D
+    h = 1.0 / (max(n) + 1)
+    omega = 7.0
+    c = np.full(n, 1.2)
+    op = oracle.Op(n, h, omega, c, None, stiff=stiff, mass=mass)
+    k2 = (omega / 1.2) ** 2
+    for p in [(1,) * ndim, tuple(range(2, 2 + ndim)), n]:
+        e = sine_mode(n, p)
+        t = [math.pi * pa / (na + 1) for na, pa in zip(n, p)]
+        K1 = [2 * (1 - math.cos(x)) for x in t]
+        M1 = [(2 + math.cos(x)) / 3 for x in t]
+        S = sum(K1[a] * np.prod([M1[b] for b in range(ndim) if b != a]) for a in range(ndim))
+        M = np.prod(M1)
+        lam = S / h ** 2 - k2 * M
+        He = op.apply_H(e.astype(np.complex128))
+        assert np.linalg.norm(He - lam * e) <= 1e-12 * abs(lam) * np.linalg.norm(e)
