@@ -210,6 +210,34 @@ int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int variant, tdp_tuni
                     double *table, int cap);
 int tdp_op_get_tuning(const tdp_op *op, tdp_tuning *t);
 
+/* ---------------------------------------------------------------------
+ * Batched form: many right-hand sides per operator and many operators of
+ * uneven sizes (2-D, one precision, one stream, one stencil class pattern)
+ * solved together.  Field q enumerates (op 0, rhs 0..nrhs[0]-1), (op 1, ...).
+ * One batched preconditioner application (Table 1) advances every live field
+ * by k steps per launch of the blocked sweep, each with its own medium,
+ * forcing table and step count, and is replayed from one hipGraph; GMRES runs
+ * per field in lockstep and takes the same decisions as tdp_gmres_solve.
+ * The batch keeps pointers to the ops: they must outlive it. */
+typedef struct tdp_batch tdp_batch;
+
+int tdp_batch_create(tdp_op *const *ops, int nops, const int *nrhs, tdp_batch **out);
+int tdp_batch_destroy(tdp_batch *b);
+
+/* Steps per launch (1..15) and tile shape (as tdp_tuning.tile) of the batched
+ * blocked sweep. */
+int tdp_batch_set_tuning(tdp_batch *b, int depth, int tile);
+
+/* U[q] = S_T F[q] for every field (Table 1).  periods_T: host [nops];
+ * F, U: host arrays of device complex128 pointers, one per field. */
+int tdp_batch_precond(tdp_batch *b, const int *periods_T, double rho, const void *const *F,
+                      void *const *U);
+
+/* Solve every field (cfg->variant must be 0).  infos: host [nfields] or NULL.
+ * Returns TDP_OK if every field converged, TDP_ENOTCONV otherwise. */
+int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int *periods_T,
+                    const void *const *F, void *const *U, tdp_gmres_info *infos);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *tdp_last_error(void);
 

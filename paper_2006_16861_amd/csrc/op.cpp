@@ -77,23 +77,6 @@ static void table_spectrum(int d, const double *T, double *lo, double *hi)
     }
 }
 
-// Stream discipline: work is issued on the caller's stream when one is given.
-// For the default (NULL) stream, which cannot be captured into a graph, the op
-// owns a stream and orders it after the caller's stream at entry and before
-// it at exit.
-struct StreamJoin {
-    hipStream_t user, own;
-    hipEvent_t ev;
-    StreamJoin(hipStream_t u, hipStream_t o, hipEvent_t e) : user(u), own(o), ev(e)
-    {
-        if (ev && hipEventRecord(ev, user) == hipSuccess) (void)hipStreamWaitEvent(own, ev, 0);
-    }
-    ~StreamJoin()
-    {
-        if (ev && hipEventRecord(ev, own) == hipSuccess) (void)hipStreamWaitEvent(user, ev, 0);
-    }
-};
-
 }  // namespace tdp
 
 using namespace tdp;
@@ -339,7 +322,7 @@ extern "C" int tdp_op_get_tuning(const tdp_op *op, tdp_tuning *t)
 }
 
 // ---------------------------------------------------------------------------
-static int apply_H_impl(const tdp_op *op, const void *x, const void *F, void *y)
+int apply_H_impl(const tdp_op *op, const void *x, const void *F, void *y)
 {
     TDP_CHECK_HIP(launch_apply_H(op->ndim, op->n, op->sc, op->mc, op->m, op->rw, op->st_H, x, F,
                                  y, op->stream));
@@ -371,7 +354,7 @@ static double window(double s, double rho)
 //                           forcing fa Re F + fb Im F = g Re(chi_j e^{i phi_j} F);
 //   Definition 4 (complex): fa_j = g chi_j cos phi_j,  fb_j = g chi_j sin phi_j,
 //                           forcing (fa + i fb) F = g chi_j e^{i phi_j} F.
-static const std::vector<double> &forcing_table(tdp_op *op, int T, double rho, int variant)
+const std::vector<double> &forcing_table(tdp_op *op, int T, double rho, int variant)
 {
     auto key = std::make_tuple(T, rho, variant);
     auto it = op->tables.find(key);

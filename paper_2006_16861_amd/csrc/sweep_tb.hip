@@ -58,28 +58,22 @@ __device__ __forceinline__ T stencil9(const T *__restrict__ ul, int us, const T 
     return r;
 }
 
+// One tile of the blocked sweep: extended tile origin (gy0, gx0) (the exact
+// output starts k rows/columns further in), k steps with forcing scalars
+// fa[s], fb[s] (scaled by g), outputs of step out_step[i] (1-based) to out[i].
 template <typename T, int SC, int MC, int R, int W>
-__global__ __launch_bounds__(64 * W) void k_sweep2d_tb(
-    const T *__restrict__ u_in, const T *__restrict__ up_in, T *__restrict__ u_out,
-    T *__restrict__ up_out, const T *__restrict__ m, const T *__restrict__ dn,
-    const typename V2t<T>::type *__restrict__ F, int ny, int nx, Stencil<T> st, TBCoef cf,
-    int tiles_x, int ntiles, int per_xcd)
+__device__ __forceinline__ void tb_tile(T *__restrict__ ul, T *__restrict__ cl,
+                                        const T *__restrict__ u_in, const T *__restrict__ up_in,
+                                        T *__restrict__ u_out, T *__restrict__ up_out,
+                                        const T *__restrict__ m, const T *__restrict__ dn,
+                                        const typename V2t<T>::type *__restrict__ F, int ny,
+                                        int nx, const Stencil<T> &st, int k, int halo,
+                                        int gy0, int gx0, const double *fa, const double *fb,
+                                        int fstride, const int *out_step, double *const *out)
 {
     constexpr int EX = 64, EY = R * W;
     constexpr int US = EX + 2;          // LDS row stride of u (one zero pad each side)
     constexpr int CS = EX + 1;          // LDS row stride of the cells
-    __shared__ T ul[(EY + 2) * US];
-    __shared__ T cl[(EY + 1) * CS];
-
-    // XCD-aware tile id
-    const int id = blockIdx.x;
-    const int tile = (id % 8) * per_xcd + id / 8;
-    if (tile >= ntiles) return;
-    const int k = cf.k;
-    const int OX = EX - 2 * k, OY = EY - 2 * k;
-    const int ty = tile / tiles_x, tx = tile % tiles_x;
-    const int gy0 = ty * OY - k, gx0 = tx * OX - k;   // global coords of tile (0, 0)
-
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int gx = gx0 + lane;
     const bool xin = (unsigned)gx < (unsigned)nx;
@@ -123,13 +117,13 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_tb(
 
     T unew[R];
     for (int s = 0; s < k; ++s) {
-        const T fa = (T)cf.fa[s], fb = (T)cf.fb[s];
+        const T fas = (T)fa[s * fstride], fbs = (T)fb[s * fstride];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const int r = wv * R + i;
             const T acc = stencil9<SC, MC>(&ul[(r + 1) * US + lane + 1], US, &cl[r * CS + lane],
                                            CS, st);
-            unew[i] = d[i] * (acc + fa * fr[i] + fb * fi[i]) - (T(2) * d[i] - T(1)) * uprev[i];
+            unew[i] = d[i] * (acc + fas * fr[i] + fbs * fi[i]) - (T(2) * d[i] - T(1)) * uprev[i];
         }
         __syncthreads();
 #pragma unroll
@@ -141,13 +135,13 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_tb(
         }
         // outputs of this step (snapshot of Table 1 / final field): the
         // exact region only
-        if (s + 1 == cf.out_step[0] || s + 1 == cf.out_step[1]) {
-            double *o = (s + 1 == cf.out_step[0]) ? cf.out[0] : cf.out[1];
+        if (s + 1 == out_step[0] || s + 1 == out_step[1]) {
+            double *o = (s + 1 == out_step[0]) ? out[0] : out[1];
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 const int r = wv * R + i;
                 const int gy = gy0 + r;
-                if (r >= k && r < EY - k && lane >= k && lane < EX - k && xin &&
+                if (r >= halo && r < EY - halo && lane >= halo && lane < EX - halo && xin &&
                     (unsigned)gy < (unsigned)ny)
                     o[2 * ((int64_t)gy * nx + gx)] = (double)unew[i];
             }
@@ -158,13 +152,72 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_tb(
     for (int i = 0; i < R; ++i) {
         const int r = wv * R + i;
         const int gy = gy0 + r;
-        if (r >= k && r < EY - k && lane >= k && lane < EX - k && xin &&
+        if (r >= halo && r < EY - halo && lane >= halo && lane < EX - halo && xin &&
             (unsigned)gy < (unsigned)ny) {
             const int64_t g = (int64_t)gy * nx + gx;
             u_out[g] = ul[(r + 1) * US + lane + 1];
             up_out[g] = uprev[i];
         }
     }
+}
+
+template <typename T, int SC, int MC, int R, int W>
+__global__ __launch_bounds__(64 * W) void k_sweep2d_tb(
+    const T *__restrict__ u_in, const T *__restrict__ up_in, T *__restrict__ u_out,
+    T *__restrict__ up_out, const T *__restrict__ m, const T *__restrict__ dn,
+    const typename V2t<T>::type *__restrict__ F, int ny, int nx, Stencil<T> st, TBCoef cf,
+    int tiles_x, int ntiles, int per_xcd)
+{
+    constexpr int EX = 64, EY = R * W;
+    __shared__ T ul[(EY + 2) * (EX + 2)];
+    __shared__ T cl[(EY + 1) * (EX + 1)];
+    // XCD-aware tile id
+    const int id = blockIdx.x;
+    const int tile = (id % 8) * per_xcd + id / 8;
+    if (tile >= ntiles) return;
+    const int k = cf.k;
+    const int OX = EX - 2 * k, OY = EY - 2 * k;
+    const int ty = tile / tiles_x, tx = tile % tiles_x;
+    tb_tile<T, SC, MC, R, W>(ul, cl, u_in, up_in, u_out, up_out, m, dn, F, ny, nx, st, k, k,
+                             ty * OY - k, tx * OX - k, cf.fa, cf.fb, 1, cf.out_step, cf.out);
+}
+
+// Batched form: one launch advances every field of the work list by up to K
+// steps; workgroup -> (field, tile) through the per-launch tile prefix sums.
+template <typename T, int SC, int MC, int R, int W>
+__global__ __launch_bounds__(64 * W) void k_sweep2d_tb_batch(
+    const BFieldT<T> *__restrict__ fields, const int *__restrict__ list,
+    const int *__restrict__ prefix, int nlist, int j0, int K, int parity, int ntiles,
+    int per_xcd)
+{
+    constexpr int EX = 64, EY = R * W;
+    __shared__ T ul[(EY + 2) * (EX + 2)];
+    __shared__ T cl[(EY + 1) * (EX + 1)];
+    const int id = blockIdx.x;
+    const int tile = (id % 8) * per_xcd + id / 8;
+    if (tile >= ntiles) return;
+    int lo = 0, hi = nlist;            // prefix[lo] <= tile < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= tile) lo = mid;
+        else hi = mid;
+    }
+    const BFieldT<T> &f = fields[list[lo]];
+    const int t = tile - prefix[lo];
+    const int OX = EX - 2 * K, OY = EY - 2 * K;
+    const int tiles_x = (f.nx + OX - 1) / OX;
+    const int ty = t / tiles_x, tx = t % tiles_x;
+    const int k = min(K, f.Ns - j0);
+    int out_step[2];
+    double *out[2] = {f.U + 1, f.U};
+    out_step[0] = (f.jsnap > j0 && f.jsnap <= j0 + k) ? f.jsnap - j0 : 0;
+    out_step[1] = (f.Ns > j0 && f.Ns <= j0 + k) ? f.Ns - j0 : 0;
+    const T *u_in = parity ? f.b0 : f.a0, *up_in = parity ? f.b1 : f.a1;
+    T *u_out = parity ? f.a0 : f.b0, *up_out = parity ? f.a1 : f.b1;
+    tb_tile<T, SC, MC, R, W>(ul, cl, u_in, up_in, u_out, up_out, f.m, f.dn,
+                             (const typename V2t<T>::type *)f.F, f.ny, f.nx, f.st, k, K,
+                             ty * OY - K, tx * OX - K, f.tab + 2 * j0, f.tab + 2 * j0 + 1, 2,
+                             out_step, out);
 }
 
 template <typename T, int R, int W>
@@ -188,6 +241,45 @@ static hipError_t launch_tb_t(const TBArgs &a, const Stencil<T> &st, hipStream_t
         hipLaunchKernelGGL((k_sweep2d_tb<T, 3, 3, R, W>), grd, blk, 0, s, u, up, uo, upo, m, dn, F,
                            a.ny, a.nx, st, a.cf, tiles_x, ntiles, per_xcd);
     return hipGetLastError();
+}
+
+template <typename T, int R, int W>
+static hipError_t launch_tb_batch_t(const TBBatchLaunch &L, hipStream_t s)
+{
+    const int per_xcd = (L.ntiles + 7) / 8;
+    dim3 grd(8 * per_xcd), blk(64 * W);
+    const BFieldT<T> *f = (const BFieldT<T> *)L.fields;
+    if (L.general)
+        hipLaunchKernelGGL((k_sweep2d_tb_batch<T, 3, 3, R, W>), grd, blk, 0, s, f, L.list,
+                           L.prefix, L.nlist, L.j0, L.K, L.parity, L.ntiles, per_xcd);
+    else
+        hipLaunchKernelGGL((k_sweep2d_tb_batch<T, 3, 2, R, W>), grd, blk, 0, s, f, L.list,
+                           L.prefix, L.nlist, L.j0, L.K, L.parity, L.ntiles, per_xcd);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep2d_tb_batch(const TBBatchLaunch &L, bool f64, hipStream_t s)
+{
+    if (f64) {
+        switch (L.shape) {
+        case 1: return launch_tb_batch_t<double, 4, 16>(L, s);
+        case 3: return launch_tb_batch_t<double, 4, 8>(L, s);
+        default: return launch_tb_batch_t<double, 8, 8>(L, s);
+        }
+    }
+    switch (L.shape) {
+    case 1: return launch_tb_batch_t<float, 4, 16>(L, s);
+    case 2: return launch_tb_batch_t<float, 8, 16>(L, s);
+    case 3: return launch_tb_batch_t<float, 4, 8>(L, s);
+    default: return launch_tb_batch_t<float, 8, 8>(L, s);
+    }
+}
+
+int tb2d_tiles(int shape, int K, int ny, int nx)
+{
+    const int EY = tb2d_tile_rows(shape, true), EX = 64;
+    const int OX = EX - 2 * K, OY = EY - 2 * K;
+    return ((nx + OX - 1) / OX) * ((ny + OY - 1) / OY);
 }
 
 // Tile shapes (rows per lane R x waves W; the tile is 64 columns wide):

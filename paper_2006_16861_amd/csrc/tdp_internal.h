@@ -89,6 +89,29 @@ struct TBArgs {
     const void *m, *dn, *F;
     TBCoef cf;
 };
+// Batched blocked sweep: per-field descriptor (device array).  Buffers a0/a1
+// hold (u_j, u_{j-1}) when parity = 0 and receive the result when parity = 1.
+template <typename T>
+struct BFieldT {
+    int ny, nx;
+    int Ns, jsnap;
+    const T *m, *dn;
+    const void *F;              // staged right-hand side (complex, T pairs)
+    T *a0, *a1, *b0, *b1;
+    const double *tab;          // forcing scalars (fa, fb) of steps 0..Ns-1
+    double *U;                  // complex128 output
+    Stencil<T> st;
+};
+struct TBBatchLaunch {
+    const void *fields;         // device BFieldT<T>[]
+    const int *list;            // device: active field indices of this launch
+    const int *prefix;          // device: tile prefix sums, nlist + 1 entries
+    int nlist, j0, K, parity, ntiles, shape;
+    bool general;               // class pattern (3,3) instead of (3,2)
+};
+hipError_t launch_sweep2d_tb_batch(const TBBatchLaunch &L, bool f64, hipStream_t s);
+int tb2d_tiles(int shape, int K, int ny, int nx);
+
 hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hipStream_t s);
 hipError_t launch_sweep2d_tb_f32(const TBArgs &a, const Stencil<float> &st, hipStream_t s);
 int tb2d_tile_rows(int shape, bool f64);
@@ -140,7 +163,29 @@ hipError_t launch_grad_cells(int ndim, const int *n, double w2, const double *ma
 hipError_t launch_grad_nodes(int ndim, const int *n, const double *gcell, double *grad,
                              hipStream_t s);
 
+// Stream discipline: work is issued on the caller's stream when one is given.
+// For the default (NULL) stream, which cannot be captured into a graph, the op
+// owns a stream and orders it after the caller's stream at entry and before
+// it at exit.
+struct StreamJoin {
+    hipStream_t user, own;
+    hipEvent_t ev;
+    StreamJoin(hipStream_t u, hipStream_t o, hipEvent_t e) : user(u), own(o), ev(e)
+    {
+        if (ev && hipEventRecord(ev, user) == hipSuccess) (void)hipStreamWaitEvent(own, ev, 0);
+    }
+    ~StreamJoin()
+    {
+        if (ev && hipEventRecord(ev, own) == hipSuccess) (void)hipStreamWaitEvent(user, ev, 0);
+    }
+};
+
 }  // namespace tdp
+
+struct tdp_op;
+// host helpers shared by op.cpp and batch.cpp
+const std::vector<double> &forcing_table(tdp_op *op, int T, double rho, int variant);
+int apply_H_impl(const tdp_op *op, const void *x, const void *F, void *y);
 
 // The opaque operator.
 struct tdp_op {

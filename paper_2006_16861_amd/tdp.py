@@ -18,7 +18,8 @@ F64, F32 = 0, 1
 
 SYMBOLS = ("tdp_op_create", "tdp_op_destroy", "tdp_op_query", "tdp_apply_H",
            "tdp_precond_apply", "tdp_precond_apply_complex", "tdp_gmres_solve", "tdp_grad_m", "tdp_op_set_tuning", "tdp_op_autotune",
-           "tdp_op_get_tuning", "tdp_last_error")
+           "tdp_op_get_tuning", "tdp_last_error", "tdp_batch_create", "tdp_batch_destroy",
+           "tdp_batch_set_tuning", "tdp_batch_precond", "tdp_batch_solve")
 
 
 class TdpError(RuntimeError):
@@ -85,6 +86,11 @@ def load(path: str = LIB_PATH):
     L.tdp_op_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
     L.tdp_op_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
     L.tdp_op_autotune.argtypes = [P, I, D, I, ctypes.POINTER(Tuning), P, I]
+    L.tdp_batch_create.argtypes = [P, I, P, ctypes.POINTER(P)]
+    L.tdp_batch_destroy.argtypes = [P]
+    L.tdp_batch_set_tuning.argtypes = [P, I, I]
+    L.tdp_batch_precond.argtypes = [P, P, D, P, P]
+    L.tdp_batch_solve.argtypes = [P, ctypes.POINTER(GmresCfg), P, P, P, P]
     L.tdp_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
         L[name].restype = L[name].restype if name == "tdp_last_error" else ctypes.c_int
@@ -254,3 +260,74 @@ def operator_from_problem(p, device="cuda", **kw):
     op = Operator(c, R, p.omega, p.h, **kw)
     op._keep = (c, R)
     return op
+
+
+class Batch:
+    """Batched form over operators `ops` with nrhs[i] right-hand sides each.
+    Fields are ordered (op 0 rhs 0..), (op 1 rhs 0..), ..."""
+
+    def __init__(self, ops, nrhs):
+        L = load()
+        self.ops = list(ops)
+        self.nrhs = [int(v) for v in nrhs]
+        arr = (ctypes.c_void_p * len(self.ops))(*[o._h.value for o in self.ops])
+        nr = (ctypes.c_int * len(self.ops))(*self.nrhs)
+        h_ = ctypes.c_void_p()
+        _check(L.tdp_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(self.ops),
+                                  ctypes.cast(nr, ctypes.c_void_p), ctypes.byref(h_)),
+               "tdp_batch_create")
+        self._h = h_
+        self.field_op = [i for i, r in enumerate(self.nrhs) for _ in range(r)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().tdp_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def set_tuning(self, depth, tile):
+        _check(load().tdp_batch_set_tuning(self._h, int(depth), int(tile)), "tdp_batch_set_tuning")
+
+    def _ptrs(self, tensors, what):
+        import torch
+        if len(tensors) != len(self.field_op):
+            raise ValueError(f"{what}: expected {len(self.field_op)} tensors")
+        for t, q in zip(tensors, self.field_op):
+            _dev_ptr(t, torch.complex128, self.ops[q].N, what)
+        return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+
+    def precond(self, Fs, T, rho=0.25):
+        import torch
+        Us = [torch.empty_like(F) for F in Fs]
+        Tv = (ctypes.c_int * len(self.ops))(*[int(t) for t in T])
+        _check(load().tdp_batch_precond(self._h, ctypes.cast(Tv, ctypes.c_void_p), float(rho),
+                                        ctypes.cast(self._ptrs(Fs, "F"), ctypes.c_void_p),
+                                        ctypes.cast(self._ptrs(Us, "U"), ctypes.c_void_p)),
+               "tdp_batch_precond")
+        return Us
+
+    def solve(self, Fs, T, rho=0.25, tol=1e-6, restart=30, max_iters=3000, fixed_iters=0,
+              history_cap=512):
+        import torch
+        Us = [torch.zeros_like(F) for F in Fs]
+        Tv = (ctypes.c_int * len(self.ops))(*[int(t) for t in T])
+        cfg = GmresCfg(int(restart), int(max_iters), 1, float(rho), float(tol), 0,
+                       int(fixed_iters), 0)
+        n = len(Fs)
+        infos = (GmresInfo * n)()
+        hists = [(ctypes.c_double * history_cap)() for _ in range(n)]
+        for i in range(n):
+            infos[i].history = ctypes.cast(hists[i], ctypes.POINTER(ctypes.c_double))
+            infos[i].history_cap = history_cap
+        rc = _check(load().tdp_batch_solve(self._h, ctypes.byref(cfg),
+                                           ctypes.cast(Tv, ctypes.c_void_p),
+                                           ctypes.cast(self._ptrs(Fs, "F"), ctypes.c_void_p),
+                                           ctypes.cast(self._ptrs(Us, "U"), ctypes.c_void_p),
+                                           ctypes.cast(infos, ctypes.c_void_p)),
+                    "tdp_batch_solve")
+        out = [SolveInfo(0 if infos[i].relres_true <= tol or fixed_iters else 1, infos[i].iters,
+                         infos[i].restarts, infos[i].relres_true, infos[i].relres_prec,
+                         infos[i].steps, infos[i].ms_total,
+                         list(hists[i][: infos[i].history_len])) for i in range(n)]
+        return Us, out, rc

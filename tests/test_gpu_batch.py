@@ -1,0 +1,130 @@
+"""Batched form: many right-hand sides per medium and uneven problems in one
+batched preconditioner launch sequence, GMRES in lockstep.  Every field must
+match its own single solve and the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_16861_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[case] {msg}", file=sys.stderr, flush=True)
+
+
+def dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def small_batch(prec=0):
+    from paper_2006_16861_amd import tdp
+    probs = [inputs.random_medium((37, 150), seed=1, width=4), inputs.const2d(),
+             inputs.random_medium((90, 70), seed=5, width=6, cmin=1.0, cmax=3.0)]
+    nrhs = [3, 1, 2]
+    ops = [tdp.operator_from_problem(p, prec=prec) for p in probs]
+    rng = np.random.default_rng(7)
+    Fs = []
+    for p, r in zip(probs, nrhs):
+        for k in range(r):
+            Fs.append(rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n) if k else p.F)
+    return probs, nrhs, ops, Fs
+
+
+@pytest.mark.parametrize("depth,tile", [(8, 1), (4, 0), (3, 3)])
+def test_batch_precond_matches_single_and_oracle(depth, tile):
+    from paper_2006_16861_amd import tdp
+    probs, nrhs, ops, Fs = small_batch()
+    note(f"batch precond depth={depth} tile={tile}")
+    b = tdp.Batch(ops, nrhs)
+    b.set_tuning(depth, tile)
+    T = [3, 2, 4]
+    Us = b.precond([dev(F) for F in Fs], T)
+    q = 0
+    for i, (p, r) in enumerate(zip(probs, nrhs)):
+        o = oracle.Op.from_problem(p)
+        for k in range(r):
+            got = Us[q].cpu().numpy()
+            single = ops[i].precond(dev(Fs[q]), T[i]).cpu().numpy()
+            assert rel(got, single) <= 1e-13
+            assert rel(got, o.precond(Fs[q], T[i])) <= 1e-10
+            q += 1
+
+
+def test_batch_gmres_fixed_and_converged_match_oracle():
+    from paper_2006_16861_amd import tdp
+    probs, nrhs, ops, Fs = small_batch()
+    note("batch gmres fixed / converged")
+    b = tdp.Batch(ops, nrhs)
+    T = [p.periods for p in probs]
+    Us, infos, rc = b.solve([dev(F) for F in Fs], T, restart=4, fixed_iters=7)
+    q = 0
+    for i, (p, r) in enumerate(zip(probs, nrhs)):
+        o = oracle.Op.from_problem(p)
+        for k in range(r):
+            Uo, io = o.gmres(Fs[q], T[i], restart=4, fixed_iters=7)
+            assert infos[q].iters == 7 and infos[q].restarts == io["restarts"]
+            assert rel(Us[q].cpu().numpy(), Uo) <= 1e-10
+            q += 1
+    Us, infos, rc = b.solve([dev(F) for F in Fs], T, tol=1e-8)
+    assert rc == 0
+    q = 0
+    for i, (p, r) in enumerate(zip(probs, nrhs)):
+        o = oracle.Op.from_problem(p)
+        for k in range(r):
+            Uo, io = o.gmres(Fs[q], T[i], tol=1e-8)
+            U = Us[q].cpu().numpy()
+            assert infos[q].iters == io["iters"] and infos[q].restarts == io["restarts"]
+            assert rel(o.apply_H(U), Fs[q]) <= 1e-8 * (1 + 1e-9)
+            assert rel(U, Uo) <= 1e-10
+            q += 1
+
+
+def test_batch_f32_reaches_tolerance():
+    from paper_2006_16861_amd import tdp
+    probs, nrhs, ops, Fs = small_batch(prec=1)
+    note("batch f32 to 1e-6")
+    b = tdp.Batch(ops, nrhs)
+    T = [p.periods for p in probs]
+    Us, infos, rc = b.solve([dev(F) for F in Fs], T, tol=1e-6)
+    assert rc == 0
+    q = 0
+    for i, (p, r) in enumerate(zip(probs, nrhs)):
+        o = oracle.Op.from_problem(p)
+        for k in range(r):
+            assert rel(o.apply_H(Us[q].cpu().numpy()), Fs[q]) <= 1e-6 * (1 + 1e-9)
+            q += 1
+
+
+def test_batch_full_config_sampled():
+    """64 right-hand sides on the 512^2 medium plus 32 uneven problems
+    (128..768 per side), FP32 fields, all to 1e-6; the true residual of a
+    sample of fields is recomputed by the oracle."""
+    from paper_2006_16861_amd import tdp
+    note("batch full config (64 RHS 512^2 + 32 uneven), f32")
+    base = inputs.smooth2d(512, seed=4, src_seed=5)
+    srcs = inputs.random_sources(base.n, 64, seed=5, margin=32)
+    uneven = inputs.uneven_problems()
+    probs = [base] + uneven
+    nrhs = [64] + [1] * len(uneven)
+    ops = [tdp.operator_from_problem(p, prec=1) for p in probs]
+    b = tdp.Batch(ops, nrhs)
+    Fs = [dev(srcs[k]) for k in range(64)] + [dev(p.F) for p in uneven]
+    Us, infos, rc = b.solve(Fs, [p.periods for p in probs], tol=1e-6)
+    assert rc == 0
+    assert all(inf.relres <= 1e-6 for inf in infos)
+    for q in [0, 17, 63, 64, 80, 95]:
+        p = base if q < 64 else uneven[q - 64]
+        F = srcs[q] if q < 64 else p.F
+        o = oracle.Op.from_problem(p)
+        r = rel(o.apply_H(Us[q].cpu().numpy()), F)
+        note(f"  field {q}: iters {infos[q].iters} oracle-checked relres {r:.3e}")
+        assert r <= 1e-6 * (1 + 1e-9)
