@@ -14,6 +14,8 @@ from __future__ import annotations
 
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -106,6 +108,119 @@ def cpu_baseline(p, T, rho, napply, target_s=12.0):
                       f"applications of {T * op.nP} steps per solve"}
 
 
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t
+
+
+def form_precision(rho):
+    """Precision form on the 3-D layered medium (256^3, 8 ppw, T = 32): FP32
+    recurrence fields inside FP64 GMRES (whose restarts recompute the true
+    residual in FP64: the outer refinement), against the FP64 path."""
+    import torch
+    from paper_2006_16861_amd import inputs, tdp
+    p = inputs.layered3d(256)
+    F = torch.as_tensor(p.F, device="cuda")
+    res = {"workload": "layered3d-256", "n": list(p.n), "periods_T": p.periods}
+    U = {}
+    for name, prec in (("f64", tdp.F64), ("f32", tdp.F32)):
+        op = tdp.operator_from_problem(p, prec=prec)
+        best, _ = op.autotune(T=1, rho=rho)
+        op.solve(F, T=p.periods, rho=rho, tol=1e-6)                 # warm (graphs)
+        (Uq, info), dt = _timed(lambda: op.solve(F, T=p.periods, rho=rho, tol=1e-6))
+        r = float(torch.linalg.norm(F - op.apply_H(Uq)) / torch.linalg.norm(F))
+        U[name] = Uq
+        res[name] = {"solves_per_s": 1.0 / dt, "seconds": dt, "iters": info.iters,
+                     "precond_applications": info.steps // (p.periods * op.nP),
+                     "true_relres_fp64": r, "tuning": best}
+        log(f"form precision {name}: {dt:.3f} s, iters {info.iters}, relres {r:.2e}")
+        del op
+    res["f32_rel_error_vs_f64_gpu_solution"] = float(
+        torch.linalg.norm(U["f32"] - U["f64"]) / torch.linalg.norm(U["f64"]))
+    res["speedup_f32_vs_f64"] = res["f32"]["solves_per_s"] / res["f64"]["solves_per_s"]
+    return res
+
+
+def form_batched(rho):
+    """Batched form: 64 right-hand sides (seeded unit sources) on one 512^2
+    smooth medium plus 32 independent problems of sizes 128..768 per side,
+    FP32 fields / FP64 GMRES, all in one batched launch sequence."""
+    import torch
+    from paper_2006_16861_amd import inputs, tdp
+    base = inputs.smooth2d(512, seed=4, src_seed=5)
+    srcs = inputs.random_sources(base.n, 64, seed=5, margin=32)
+    uneven = inputs.uneven_problems()
+    probs = [base] + uneven
+    nrhs = [64] + [1] * len(uneven)
+    T = [p.periods for p in probs]
+    ops = [tdp.operator_from_problem(p, prec=tdp.F32) for p in probs]
+    b = tdp.Batch(ops, nrhs)
+    Fs = [torch.as_tensor(srcs[k], device="cuda") for k in range(64)] + \
+         [torch.as_tensor(p.F, device="cuda") for p in uneven]
+    b.solve(Fs, T, rho=rho, tol=1e-6)                                   # warm (graphs)
+    (out, dt) = _timed(lambda: b.solve(Fs, T, rho=rho, tol=1e-6))
+    Us, infos, rc = out
+    worst = max(i.relres for i in infos)
+    nodes = sum(p.N * r for p, r in zip(probs, nrhs))
+    steps = sum(i.steps * probs_n for i, probs_n in
+                zip(infos, [base.N] * 64 + [p.N for p in uneven]))
+    res = {"workload": "64 rhs on smooth2d-512 + 32 uneven 128..768", "fields": len(Fs),
+           "solves_per_s": len(Fs) / dt, "seconds": dt, "status": rc, "worst_relres": worst,
+           "node_steps_per_s": steps / dt, "total_nodes": nodes}
+    # the plain FP64 single-solve path on a sample of the same fields
+    sample = [0, 1, 64, 65]
+    t_single = 0.0
+    for q in sample:
+        p = base if q < 64 else uneven[q - 64]
+        op = tdp.operator_from_problem(p, prec=tdp.F64)
+        op.solve(Fs[q], T=p.periods, rho=rho, tol=1e-6)
+        (_, dt1) = _timed(lambda: op.solve(Fs[q], T=p.periods, rho=rho, tol=1e-6))
+        t_single += dt1 * (64 if q < 64 else len(uneven)) / 2
+        del op
+    res["plain_f64_single_solves_per_s_extrapolated"] = len(Fs) / t_single
+    res["plain_f64_sample"] = "2 of the 64 sources and 2 of the 32 uneven problems, scaled"
+    res["speedup_vs_plain_f64"] = res["solves_per_s"] / res["plain_f64_single_solves_per_s_extrapolated"]
+    log(f"form batched: {len(Fs)} solves in {dt:.3f} s, worst relres {worst:.2e}")
+    b.close()
+    return res
+
+
+def form_adjoint(rho):
+    """Differentiation form: 128^3 smooth medium in [1.5, 3.0], 4 sources, 256
+    receivers on the top face, misfit 1/2 ||P_r U(m) - d||^2; one gradient
+    evaluation = 4 forward + 4 adjoint solves to 1e-6."""
+    import torch
+    from paper_2006_16861_amd import inputs, tdp
+    from paper_2006_16861_amd.autograd import helmholtz_solve
+    p = inputs.smooth3d(128, width=16)
+    F = torch.as_tensor(inputs.sources_on_plane(p.n, 4, seed=8, plane=18), device="cuda")
+    mask = torch.as_tensor(inputs.receiver_mask(p.n, plane=17, per_side=16).astype(np.float64),
+                           device="cuda")
+    m0 = 1.0 / p.c ** 2
+    m_true = m0 * (1.0 + 0.05 * inputs.gaussian_blob(p.n, seed=9))
+    R = torch.as_tensor(p.R, device="cuda")
+    with torch.no_grad():
+        d = helmholtz_solve(torch.as_tensor(m_true, device="cuda"), F, R, p.omega, p.h,
+                            T=p.periods, tol=1e-6) * mask
+
+    def grad_eval():
+        m = torch.as_tensor(m0, device="cuda").clone().requires_grad_(True)
+        U = helmholtz_solve(m, F, R, p.omega, p.h, T=p.periods, tol=1e-6)
+        L = 0.5 * (((U - d) * mask).abs() ** 2).sum()
+        L.backward()
+        return m.grad
+
+    grad_eval()
+    g, dt = _timed(grad_eval)
+    log(f"form adjoint: gradient in {dt:.3f} s")
+    return {"workload": "smooth3d-128, 4 sources, 256 receivers", "gradients_per_s": 1.0 / dt,
+            "solves_per_s": 8.0 / dt, "seconds": dt, "grad_norm": float(torch.linalg.norm(g))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +241,8 @@ def main():
     ap.add_argument("--sweep-reps", type=int, default=3)
     ap.add_argument("--tune-only", action="store_true",
                     help="print the autotuner's per-variant step times and exit")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the precision / batched / adjoint form measurements")
     ap.add_argument("--profile-sweeps", type=int, default=0,
                     help="profiling mode: one 256 MiB device copy (counter calibration), then "
                          "this many preconditioner applications, then exit")
@@ -249,6 +366,14 @@ def main():
                              "achieved_TFLOPs": FLOPS_PER_NODE_STEP * p.N * Ns / (apply_ms * 1e-3) / 1e12,
                              "peak_TFLOPs": 78.6 if prec == tdp.F64 else 157.3}},
     }
+    if not args.no_forms and args.workload == "smooth2d-1024":
+        import numpy as np  # noqa: F811
+        forms = {}
+        for name, fn in (("precision", form_precision), ("batched", form_batched),
+                         ("adjoint", form_adjoint)):
+            log(f"form {name} ...")
+            forms[name] = fn(args.rho)
+        out["forms"] = forms
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(p, T, args.rho, int(napply))
