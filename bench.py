@@ -161,6 +161,11 @@ def form_batched(rho):
     b = tdp.Batch(ops, nrhs)
     Fs = [torch.as_tensor(srcs[k], device="cuda") for k in range(64)] + \
          [torch.as_tensor(p.F, device="cuda") for p in uneven]
+    t = time.perf_counter()
+    table = b.autotune([max(1, t_ // 8) for t_ in T], rho=rho)
+    best = min(table, key=lambda r: r[2])
+    log(f"form batched: autotune {len(table)} variants in {time.perf_counter() - t:.2f} s, "
+        f"best depth {int(best[0])} tile {int(best[1])}")
     b.solve(Fs, T, rho=rho, tol=1e-6)                                   # warm (graphs)
     (out, dt) = _timed(lambda: b.solve(Fs, T, rho=rho, tol=1e-6))
     Us, infos, rc = out
@@ -169,6 +174,7 @@ def form_batched(rho):
     steps = sum(i.steps * probs_n for i, probs_n in
                 zip(infos, [base.N] * 64 + [p.N for p in uneven]))
     res = {"workload": "64 rhs on smooth2d-512 + 32 uneven 128..768", "fields": len(Fs),
+           "tuning": {"depth": int(best[0]), "tile": int(best[1])},
            "solves_per_s": len(Fs) / dt, "seconds": dt, "status": rc, "worst_relres": worst,
            "node_steps_per_s": steps / dt, "total_nodes": nodes}
     # the plain FP64 single-solve path on a sample of the same fields

@@ -187,7 +187,9 @@ int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
  *  use_graph    1 capture the step loop in a hipGraph and replay it
  *  tile         kernel 2 tile (rows x columns): 0 64x64 (8 rows per lane x
  *               8 waves), 1 64x64 (4 x 16 waves), 2 128x64 (FP32 only),
- *               3 32x64 (4 x 8 waves); kernel 3: 0 8x64 columns (4 waves x 2
+ *               3 32x64 (4 x 8 waves); 4..7 the same family with per-node
+ *               coefficients in registers: 4 64x64 (4 x 16), 5 32x64 (4 x 8),
+ *               6 64x64 (8 x 8), 7 32x64 (2 x 16); kernel 3: 0 8x64 columns (4 waves x 2
  *               rows each), 1 16x64 (4 waves x 4 rows), 2 16x64 (8 x 2)    */
 typedef struct {
     int kernel;
@@ -227,6 +229,12 @@ int tdp_batch_destroy(tdp_batch *b);
 /* Steps per launch (1..15) and tile shape (as tdp_tuning.tile) of the batched
  * blocked sweep. */
 int tdp_batch_set_tuning(tdp_batch *b, int depth, int tile);
+
+/* Autotuner of the batched sweep: times one batched application for every
+ * tile shape x depth (4, 6, 8) and keeps the fastest.  table (host, may be
+ * NULL) receives up to cap rows {depth, tile, milliseconds per application}.
+ * Returns the number of candidates timed or a negative error. */
+int tdp_batch_autotune(tdp_batch *b, const int *periods_T, double rho, double *table, int cap);
 
 /* U[q] = S_T F[q] for every field (Table 1).  periods_T: host [nops];
  * F, U: host arrays of device complex128 pointers, one per field. */

@@ -108,8 +108,8 @@ extern "C" int tdp_batch_create(tdp_op *const *ops, int nops, const int *nrhs, t
     }
     b->f64 = ops[0]->prec == TDP_F64;
     b->s = ops[0]->stream;
-    if (b->f64) b->shape = 1;
-    else b->shape = 1;
+    b->shape = 4;
+    b->K = 8;
     const size_t es = b->f64 ? sizeof(double) : sizeof(float);
     for (int i = 0; i < nops; ++i) {
         for (int r = 0; r < nrhs[i]; ++r) {
@@ -138,7 +138,7 @@ extern "C" int tdp_batch_set_tuning(tdp_batch *b, int depth, int tile)
 {
     if (!b) TDP_BFAIL(TDP_EINVAL, "NULL batch");
     if (depth < 1 || depth > 15) TDP_BFAIL(TDP_EINVAL, "depth must be in [1, 15]");
-    if (tile < 0 || tile > 3 || (tile == 2 && b->f64)) TDP_BFAIL(TDP_EINVAL, "bad tile");
+    if (tile < 0 || tile > 7 || (tile == 2 && b->f64)) TDP_BFAIL(TDP_EINVAL, "bad tile");
     const int rows = tb2d_tile_rows(tile, b->f64);
     if (4 * depth > rows) TDP_BFAIL(TDP_EINVAL, "depth too large for the tile");
     b->K = depth;
@@ -303,6 +303,70 @@ extern "C" int tdp_batch_precond(tdp_batch *b, const int *periods_T, double rho,
     for (size_t q = 0; q < b->f.size(); ++q)
         TDP_CHECK_HIP(hipMemcpyAsync(U[q], b->f[q].pout, 16 * b->f[q].N, hipMemcpyDeviceToDevice, b->s));
     return TDP_OK;
+}
+
+// Autotuner of the batched sweep: times one batched application (periods_T
+// per op) for every tile shape x depth, keeps the fastest.
+extern "C" int tdp_batch_autotune(tdp_batch *b, const int *periods_T, double rho, double *table,
+                                  int cap)
+{
+    if (!b || !periods_T) TDP_BFAIL(TDP_EINVAL, "NULL argument");
+    StreamJoin join(b->ops[0]->user_stream, b->s, b->ops[0]->ev);
+    std::vector<char> active(b->f.size(), 1);
+    for (auto &fl : b->f) TDP_CHECK_HIP(launch_fill_zero(fl.pin, 16 * fl.N, b->s));
+    const int K0 = b->K, S0 = b->shape;
+    double best = INFINITY;
+    int bk = K0, bs = S0, n = 0;
+    hipEvent_t e0, e1;
+    TDP_CHECK_HIP(hipEventCreate(&e0));
+    TDP_CHECK_HIP(hipEventCreate(&e1));
+    int rc = TDP_OK;
+    for (int shape = 0; shape < 8 && rc == TDP_OK; ++shape) {
+        if (shape == 2 && b->f64) continue;
+        const int rows = tb2d_tile_rows(shape, b->f64);
+        for (int K : {4, 6, 8}) {
+            if (4 * K > rows) continue;
+            b->K = K;
+            b->shape = shape;
+            rc = batch_precond(b, periods_T, rho, active);   // capture + warm
+            if (rc != TDP_OK) break;
+            float ms = 0.f;
+            if (hipEventRecord(e0, b->s) != hipSuccess) { rc = TDP_EHIP; break; }
+            for (int r = 0; r < 2 && rc == TDP_OK; ++r) rc = batch_precond(b, periods_T, rho, active);
+            if (rc != TDP_OK) break;
+            if (hipEventRecord(e1, b->s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = TDP_EHIP;
+                break;
+            }
+            if (table && n < cap) {
+                table[3 * n] = K;
+                table[3 * n + 1] = shape;
+                table[3 * n + 2] = ms / 2;
+            }
+            ++n;
+            if (ms < best) {
+                best = ms;
+                bk = K;
+                bs = shape;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (auto &kv : b->graphs) {
+        (void)hipGraphExecDestroy(kv.second.first);
+        (void)hipFree(kv.second.second);
+    }
+    b->graphs.clear();
+    if (rc != TDP_OK) {
+        b->K = K0;
+        b->shape = S0;
+        return rc;
+    }
+    b->K = bk;
+    b->shape = bs;
+    return n;
 }
 
 // ---------------------------------------------------------------------------

@@ -305,7 +305,7 @@ extern "C" int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t)
         if (t->tile < 0 || t->tile > 2) TDP_FAIL(TDP_EINVAL, "tile must be 0, 1 or 2 for kernel 3");
     } else {
         if (t->tb_depth < 0 || t->tb_depth > TDP_TB_KMAX) TDP_FAIL(TDP_EINVAL, "tb_depth must be in [0, 16]");
-        if (t->tile < 0 || t->tile > 3) TDP_FAIL(TDP_EINVAL, "tile must be 0, 1, 2 or 3");
+        if (t->tile < 0 || t->tile > 7) TDP_FAIL(TDP_EINVAL, "tile must be in [0, 7]");
         if (t->kernel == 2 && t->tile == 2 && op->prec == TDP_F64)
             TDP_FAIL(TDP_EINVAL, "tile 2 is FP32 only");
     }
@@ -596,7 +596,7 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
     std::vector<tdp_tuning> cand;
     cand.push_back({1, 0, 1, 0});
     if (op->ndim == 2 && variant == 0) {
-        const int tiles[] = {0, 1, 2, 3};
+        const int tiles[] = {0, 1, 2, 3, 4, 5, 6, 7};
         const int depths[] = {2, 3, 4, 6, 8};
         for (int tile : tiles) {
             if (tile == 2 && op->prec == TDP_F64) continue;

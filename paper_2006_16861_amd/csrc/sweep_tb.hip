@@ -161,6 +161,166 @@ __device__ __forceinline__ void tb_tile(T *__restrict__ ul, T *__restrict__ cl,
     }
 }
 
+// Second form of the tile update: the cell-mass sums do not change in time,
+// so each lane folds them once per launch into per-node stencil coefficients
+// held in registers (centre, W, E, S, N; corners too for a general mass
+// table) and keeps no cells in LDS; each lane then reads its column of R+2
+// rows at x-1, x, x+1 from LDS once per step and reuses it for its R nodes.
+// The exact-region, Dirichlet and output rules are those of tb_tile.
+template <typename T, int SC, int MC, int R, int W>
+__device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict__ u_in,
+                                         const T *__restrict__ up_in, T *__restrict__ u_out,
+                                         T *__restrict__ up_out, const T *__restrict__ m,
+                                         const T *__restrict__ dn,
+                                         const typename V2t<T>::type *__restrict__ F, int ny,
+                                         int nx, const Stencil<T> &st, int k, int halo, int gy0,
+                                         int gx0, const double *fa, const double *fb,
+                                         int fstride, const int *out_step, double *const *out)
+{
+    constexpr int EX = 64, EY = R * W;
+    constexpr int US = EX + 2;
+    constexpr int NCO = MC > 2 ? 9 : 5;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r0 = wv * R;
+    const int gx = gx0 + lane;
+    const bool xin = (unsigned)gx < (unsigned)nx;
+
+    // per-node coefficients from the cells around each node (storage rows
+    // gy0+r0 .. gy0+r0+R, columns gx and gx+1)
+    T co[R][NCO];
+    {
+        T ca[R + 1], cb[R + 1];
+#pragma unroll
+        for (int i = 0; i <= R; ++i) {
+            const int sy = gy0 + r0 + i;
+            const bool rok = (unsigned)sy <= (unsigned)ny;
+            const int64_t base = (int64_t)sy * (nx + 1);
+            ca[i] = (rok && (unsigned)gx <= (unsigned)nx) ? m[base + gx] : T(0);
+            cb[i] = (rok && (unsigned)(gx + 1) <= (unsigned)nx) ? m[base + gx + 1] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const T mSW = ca[i], mSE = cb[i], mNW = ca[i + 1], mNE = cb[i + 1];
+            co[i][0] = st.c0 + st.m[0] * ((mSW + mSE) + (mNW + mNE));
+            co[i][1] = st.s[1] + st.m[1] * (mSW + mNW);   // W
+            co[i][2] = st.s[1] + st.m[1] * (mSE + mNE);   // E
+            co[i][3] = st.s[1] + st.m[1] * (mSW + mSE);   // S
+            co[i][4] = st.s[1] + st.m[1] * (mNW + mNE);   // N
+            if (MC > 2) {
+                co[i][5] = st.s[2] + st.m[2] * mSW;
+                co[i][6] = st.s[2] + st.m[2] * mSE;
+                co[i][7] = st.s[2] + st.m[2] * mNW;
+                co[i][8] = st.s[2] + st.m[2] * mNE;
+            }
+        }
+    }
+    // zero the LDS pads
+    for (int t = threadIdx.x; t < US; t += 64 * W) {
+        ul[t] = T(0);
+        ul[(EY + 1) * US + t] = T(0);
+    }
+    for (int t = threadIdx.x; t < EY + 2; t += 64 * W) {
+        ul[t * US] = T(0);
+        ul[t * US + EX + 1] = T(0);
+    }
+    T uprev[R], d[R], fr[R], fi[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int gy = gy0 + r0 + i;
+        const bool in = xin && (unsigned)gy < (unsigned)ny;
+        const int64_t g = (int64_t)gy * nx + gx;
+        T uc = T(0);
+        uprev[i] = d[i] = fr[i] = fi[i] = T(0);
+        if (in) {
+            uc = u_in[g];
+            uprev[i] = up_in[g];
+            d[i] = dn[g];
+            const auto f = F[g];
+            fr[i] = f.x;
+            fi[i] = f.y;
+        }
+        ul[(r0 + i + 1) * US + lane + 1] = uc;
+    }
+    __syncthreads();
+
+    T unew[R];
+    for (int s = 0; s < k; ++s) {
+        const T fas = (T)fa[s * fstride], fbs = (T)fb[s * fstride];
+        T cw[R + 2], cc[R + 2], ce[R + 2];   // LDS rows r0-1 .. r0+R at x-1, x, x+1
+#pragma unroll
+        for (int i = 0; i < R + 2; ++i) {
+            const T *p = &ul[(r0 + i) * US + lane + 1];
+            cw[i] = p[-1];
+            cc[i] = p[0];
+            ce[i] = p[1];
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            // node row r0+i: centre cc[i+1], S cc[i], N cc[i+2]
+            T acc = co[i][0] * cc[i + 1];
+            acc += co[i][1] * cw[i + 1];
+            acc += co[i][2] * ce[i + 1];
+            acc += co[i][3] * cc[i];
+            acc += co[i][4] * cc[i + 2];
+            if (MC > 2) {
+                acc += co[i][5] * cw[i];
+                acc += co[i][6] * ce[i];
+                acc += co[i][7] * cw[i + 2];
+                acc += co[i][8] * ce[i + 2];
+            } else if (SC > 2) {
+                acc += st.s[2] * ((cw[i] + ce[i]) + (cw[i + 2] + ce[i + 2]));
+            }
+            unew[i] = d[i] * (acc + fas * fr[i] + fbs * fi[i]) - (T(2) * d[i] - T(1)) * uprev[i];
+            uprev[i] = cc[i + 1];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < R; ++i) ul[(r0 + i + 1) * US + lane + 1] = unew[i];
+        if (s + 1 == out_step[0] || s + 1 == out_step[1]) {
+            double *o = (s + 1 == out_step[0]) ? out[0] : out[1];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int r = r0 + i;
+                const int gy = gy0 + r;
+                if (r >= halo && r < EY - halo && lane >= halo && lane < EX - halo && xin &&
+                    (unsigned)gy < (unsigned)ny)
+                    o[2 * ((int64_t)gy * nx + gx)] = (double)unew[i];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int r = r0 + i;
+        const int gy = gy0 + r;
+        if (r >= halo && r < EY - halo && lane >= halo && lane < EX - halo && xin &&
+            (unsigned)gy < (unsigned)ny) {
+            const int64_t g = (int64_t)gy * nx + gx;
+            u_out[g] = unew[i];
+            up_out[g] = uprev[i];
+        }
+    }
+}
+
+template <typename T, int SC, int MC, int R, int W>
+__global__ __launch_bounds__(64 * W) void k_sweep2d_tb2(
+    const T *__restrict__ u_in, const T *__restrict__ up_in, T *__restrict__ u_out,
+    T *__restrict__ up_out, const T *__restrict__ m, const T *__restrict__ dn,
+    const typename V2t<T>::type *__restrict__ F, int ny, int nx, Stencil<T> st, TBCoef cf,
+    int tiles_x, int ntiles, int per_xcd)
+{
+    constexpr int EX = 64, EY = R * W;
+    __shared__ T ul[(EY + 2) * (EX + 2)];
+    const int id = blockIdx.x;
+    const int tile = (id % 8) * per_xcd + id / 8;
+    if (tile >= ntiles) return;
+    const int k = cf.k;
+    const int OX = EX - 2 * k, OY = EY - 2 * k;
+    const int ty = tile / tiles_x, tx = tile % tiles_x;
+    tb_tile2<T, SC, MC, R, W>(ul, u_in, up_in, u_out, up_out, m, dn, F, ny, nx, st, k, k,
+                              ty * OY - k, tx * OX - k, cf.fa, cf.fb, 1, cf.out_step, cf.out);
+}
+
 template <typename T, int SC, int MC, int R, int W>
 __global__ __launch_bounds__(64 * W) void k_sweep2d_tb(
     const T *__restrict__ u_in, const T *__restrict__ up_in, T *__restrict__ u_out,
@@ -184,7 +344,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_tb(
 
 // Batched form: one launch advances every field of the work list by up to K
 // steps; workgroup -> (field, tile) through the per-launch tile prefix sums.
-template <typename T, int SC, int MC, int R, int W>
+template <typename T, int SC, int MC, int R, int W, bool V2F>
 __global__ __launch_bounds__(64 * W) void k_sweep2d_tb_batch(
     const BFieldT<T> *__restrict__ fields, const int *__restrict__ list,
     const int *__restrict__ prefix, int nlist, int j0, int K, int parity, int ntiles,
@@ -192,7 +352,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_tb_batch(
 {
     constexpr int EX = 64, EY = R * W;
     __shared__ T ul[(EY + 2) * (EX + 2)];
-    __shared__ T cl[(EY + 1) * (EX + 1)];
+    __shared__ T cl[V2F ? 1 : (EY + 1) * (EX + 1)];
     const int id = blockIdx.x;
     const int tile = (id % 8) * per_xcd + id / 8;
     if (tile >= ntiles) return;
@@ -214,10 +374,39 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_tb_batch(
     out_step[1] = (f.Ns > j0 && f.Ns <= j0 + k) ? f.Ns - j0 : 0;
     const T *u_in = parity ? f.b0 : f.a0, *up_in = parity ? f.b1 : f.a1;
     T *u_out = parity ? f.a0 : f.b0, *up_out = parity ? f.a1 : f.b1;
-    tb_tile<T, SC, MC, R, W>(ul, cl, u_in, up_in, u_out, up_out, f.m, f.dn,
-                             (const typename V2t<T>::type *)f.F, f.ny, f.nx, f.st, k, K,
-                             ty * OY - K, tx * OX - K, f.tab + 2 * j0, f.tab + 2 * j0 + 1, 2,
-                             out_step, out);
+    if (V2F)
+        tb_tile2<T, SC, MC, R, W>(ul, u_in, up_in, u_out, up_out, f.m, f.dn,
+                                  (const typename V2t<T>::type *)f.F, f.ny, f.nx, f.st, k, K,
+                                  ty * OY - K, tx * OX - K, f.tab + 2 * j0, f.tab + 2 * j0 + 1,
+                                  2, out_step, out);
+    else
+        tb_tile<T, SC, MC, R, W>(ul, cl, u_in, up_in, u_out, up_out, f.m, f.dn,
+                                 (const typename V2t<T>::type *)f.F, f.ny, f.nx, f.st, k, K,
+                                 ty * OY - K, tx * OX - K, f.tab + 2 * j0, f.tab + 2 * j0 + 1, 2,
+                                 out_step, out);
+}
+
+template <typename T, int R, int W>
+static hipError_t launch_tb2_t(const TBArgs &a, const Stencil<T> &st, hipStream_t s)
+{
+    constexpr int EX = 64, EY = R * W;
+    const int k = a.cf.k;
+    const int OX = EX - 2 * k, OY = EY - 2 * k;
+    const int tiles_x = (a.nx + OX - 1) / OX, tiles_y = (a.ny + OY - 1) / OY;
+    const int ntiles = tiles_x * tiles_y;
+    const int per_xcd = (ntiles + 7) / 8;
+    dim3 grd(8 * per_xcd), blk(64 * W);
+    const T *u = (const T *)a.u_in, *up = (const T *)a.up_in;
+    T *uo = (T *)a.u_out, *upo = (T *)a.up_out;
+    const T *m = (const T *)a.m, *dn = (const T *)a.dn;
+    const auto *F = (const typename V2t<T>::type *)a.F;
+    if (a.sc <= 3 && a.mc <= 2)
+        hipLaunchKernelGGL((k_sweep2d_tb2<T, 3, 2, R, W>), grd, blk, 0, s, u, up, uo, upo, m, dn,
+                           F, a.ny, a.nx, st, a.cf, tiles_x, ntiles, per_xcd);
+    else
+        hipLaunchKernelGGL((k_sweep2d_tb2<T, 3, 3, R, W>), grd, blk, 0, s, u, up, uo, upo, m, dn,
+                           F, a.ny, a.nx, st, a.cf, tiles_x, ntiles, per_xcd);
+    return hipGetLastError();
 }
 
 template <typename T, int R, int W>
@@ -249,12 +438,18 @@ static hipError_t launch_tb_batch_t(const TBBatchLaunch &L, hipStream_t s)
     const int per_xcd = (L.ntiles + 7) / 8;
     dim3 grd(8 * per_xcd), blk(64 * W);
     const BFieldT<T> *f = (const BFieldT<T> *)L.fields;
-    if (L.general)
-        hipLaunchKernelGGL((k_sweep2d_tb_batch<T, 3, 3, R, W>), grd, blk, 0, s, f, L.list,
-                           L.prefix, L.nlist, L.j0, L.K, L.parity, L.ntiles, per_xcd);
-    else
-        hipLaunchKernelGGL((k_sweep2d_tb_batch<T, 3, 2, R, W>), grd, blk, 0, s, f, L.list,
-                           L.prefix, L.nlist, L.j0, L.K, L.parity, L.ntiles, per_xcd);
+    const bool v2 = L.shape >= 4;
+#define TDP_BL(SC, MC, V) \
+    hipLaunchKernelGGL((k_sweep2d_tb_batch<T, SC, MC, R, W, V>), grd, blk, 0, s, f, L.list, \
+                       L.prefix, L.nlist, L.j0, L.K, L.parity, L.ntiles, per_xcd)
+    if (L.general) {
+        if (v2) TDP_BL(3, 3, true);
+        else TDP_BL(3, 3, false);
+    } else {
+        if (v2) TDP_BL(3, 2, true);
+        else TDP_BL(3, 2, false);
+    }
+#undef TDP_BL
     return hipGetLastError();
 }
 
@@ -262,15 +457,17 @@ hipError_t launch_sweep2d_tb_batch(const TBBatchLaunch &L, bool f64, hipStream_t
 {
     if (f64) {
         switch (L.shape) {
-        case 1: return launch_tb_batch_t<double, 4, 16>(L, s);
-        case 3: return launch_tb_batch_t<double, 4, 8>(L, s);
+        case 1: case 4: return launch_tb_batch_t<double, 4, 16>(L, s);
+        case 3: case 5: return launch_tb_batch_t<double, 4, 8>(L, s);
+        case 7: return launch_tb_batch_t<double, 2, 16>(L, s);
         default: return launch_tb_batch_t<double, 8, 8>(L, s);
         }
     }
     switch (L.shape) {
-    case 1: return launch_tb_batch_t<float, 4, 16>(L, s);
+    case 1: case 4: return launch_tb_batch_t<float, 4, 16>(L, s);
     case 2: return launch_tb_batch_t<float, 8, 16>(L, s);
-    case 3: return launch_tb_batch_t<float, 4, 8>(L, s);
+    case 3: case 5: return launch_tb_batch_t<float, 4, 8>(L, s);
+    case 7: return launch_tb_batch_t<float, 2, 16>(L, s);
     default: return launch_tb_batch_t<float, 8, 8>(L, s);
     }
 }
@@ -282,15 +479,21 @@ int tb2d_tiles(int shape, int K, int ny, int nx)
     return ((nx + OX - 1) / OX) * ((ny + OY - 1) / OY);
 }
 
-// Tile shapes (rows per lane R x waves W; the tile is 64 columns wide):
-//   0: 8 x 8  -> 64 x 64 tile, 512 threads
-//   1: 4 x 16 -> 64 x 64 tile, 1024 threads
-//   2: 8 x 16 -> 128 x 64 tile, 1024 threads (FP32 only: FP64 would not fit)
-//   3: 4 x 8  -> 32 x 64 tile, 512 threads
+// Tile shapes (rows per lane R x waves W; the tile is 64 columns wide).
+// Shapes 0..3 use tb_tile (cells in LDS), 4..7 tb_tile2 (coefficients in
+// registers, column reuse):
+//   0: 8 x 8  -> 64 x 64, 512 threads     4: 4 x 16 -> 64 x 64, 1024 threads
+//   1: 4 x 16 -> 64 x 64, 1024 threads    5: 4 x 8  -> 32 x 64, 512 threads
+//   2: 8 x 16 -> 128 x 64 (FP32 only)     6: 8 x 8  -> 64 x 64, 512 threads
+//   3: 4 x 8  -> 32 x 64, 512 threads     7: 2 x 16 -> 32 x 64, 1024 threads
 int tb2d_tile_rows(int shape, bool f64)
 {
     (void)f64;
-    return shape == 2 ? 128 : (shape == 3 ? 32 : 64);
+    switch (shape) {
+    case 2: return 128;
+    case 3: case 5: case 7: return 32;
+    default: return 64;
+    }
 }
 
 hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hipStream_t s)
@@ -298,6 +501,10 @@ hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hip
     switch (a.shape) {
     case 1: return launch_tb_t<double, 4, 16>(a, st, s);
     case 3: return launch_tb_t<double, 4, 8>(a, st, s);
+    case 4: return launch_tb2_t<double, 4, 16>(a, st, s);
+    case 5: return launch_tb2_t<double, 4, 8>(a, st, s);
+    case 6: return launch_tb2_t<double, 8, 8>(a, st, s);
+    case 7: return launch_tb2_t<double, 2, 16>(a, st, s);
     default: return launch_tb_t<double, 8, 8>(a, st, s);
     }
 }
@@ -308,6 +515,10 @@ hipError_t launch_sweep2d_tb_f32(const TBArgs &a, const Stencil<float> &st, hipS
     case 1: return launch_tb_t<float, 4, 16>(a, st, s);
     case 2: return launch_tb_t<float, 8, 16>(a, st, s);
     case 3: return launch_tb_t<float, 4, 8>(a, st, s);
+    case 4: return launch_tb2_t<float, 4, 16>(a, st, s);
+    case 5: return launch_tb2_t<float, 4, 8>(a, st, s);
+    case 6: return launch_tb2_t<float, 8, 8>(a, st, s);
+    case 7: return launch_tb2_t<float, 2, 16>(a, st, s);
     default: return launch_tb_t<float, 8, 8>(a, st, s);
     }
 }

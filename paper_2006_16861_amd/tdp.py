@@ -19,7 +19,7 @@ F64, F32 = 0, 1
 SYMBOLS = ("tdp_op_create", "tdp_op_destroy", "tdp_op_query", "tdp_apply_H",
            "tdp_precond_apply", "tdp_precond_apply_complex", "tdp_gmres_solve", "tdp_grad_m", "tdp_op_set_tuning", "tdp_op_autotune",
            "tdp_op_get_tuning", "tdp_last_error", "tdp_batch_create", "tdp_batch_destroy",
-           "tdp_batch_set_tuning", "tdp_batch_precond", "tdp_batch_solve")
+           "tdp_batch_set_tuning", "tdp_batch_precond", "tdp_batch_solve", "tdp_batch_autotune")
 
 
 class TdpError(RuntimeError):
@@ -91,6 +91,7 @@ def load(path: str = LIB_PATH):
     L.tdp_batch_set_tuning.argtypes = [P, I, I]
     L.tdp_batch_precond.argtypes = [P, P, D, P, P]
     L.tdp_batch_solve.argtypes = [P, ctypes.POINTER(GmresCfg), P, P, P, P]
+    L.tdp_batch_autotune.argtypes = [P, P, D, P, I]
     L.tdp_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
         L[name].restype = L[name].restype if name == "tdp_last_error" else ctypes.c_int
@@ -288,6 +289,17 @@ class Batch:
 
     def set_tuning(self, depth, tile):
         _check(load().tdp_batch_set_tuning(self._h, int(depth), int(tile)), "tdp_batch_set_tuning")
+
+    def autotune(self, T, rho=0.25):
+        """Time the batched sweep variants, keep the fastest; returns rows
+        (depth, tile, ms per application)."""
+        cap = 64
+        tab = (ctypes.c_double * (3 * cap))()
+        Tv = (ctypes.c_int * len(self.ops))(*[int(t) for t in T])
+        n = _check(load().tdp_batch_autotune(self._h, ctypes.cast(Tv, ctypes.c_void_p), float(rho),
+                                             ctypes.cast(tab, ctypes.c_void_p), cap),
+                   "tdp_batch_autotune")
+        return [tuple(tab[3 * i: 3 * i + 3]) for i in range(min(n, cap))]
 
     def _ptrs(self, tensors, what):
         import torch

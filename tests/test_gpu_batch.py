@@ -39,7 +39,7 @@ def small_batch(prec=0):
     return probs, nrhs, ops, Fs
 
 
-@pytest.mark.parametrize("depth,tile", [(8, 1), (4, 0), (3, 3)])
+@pytest.mark.parametrize("depth,tile", [(8, 1), (4, 0), (3, 3), (8, 4), (4, 5), (3, 7)])
 def test_batch_precond_matches_single_and_oracle(depth, tile):
     from paper_2006_16861_amd import tdp
     probs, nrhs, ops, Fs = small_batch()
@@ -128,3 +128,20 @@ def test_batch_full_config_sampled():
         r = rel(o.apply_H(Us[q].cpu().numpy()), F)
         note(f"  field {q}: iters {infos[q].iters} oracle-checked relres {r:.3e}")
         assert r <= 1e-6 * (1 + 1e-9)
+
+
+def test_batch_autotune_keeps_results_exact():
+    from paper_2006_16861_amd import tdp
+    probs, nrhs, ops, Fs = small_batch()
+    note("batch autotune")
+    b = tdp.Batch(ops, nrhs)
+    table = b.autotune([2, 2, 2])
+    assert len(table) >= 10 and min(r[2] for r in table) > 0
+    T = [3, 2, 4]
+    Us = b.precond([dev(F) for F in Fs], T)
+    q = 0
+    for i, (p, r) in enumerate(zip(probs, nrhs)):
+        o = oracle.Op.from_problem(p)
+        for k in range(r):
+            assert rel(Us[q].cpu().numpy(), o.precond(Fs[q], T[i])) <= 1e-10
+            q += 1

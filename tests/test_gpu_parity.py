@@ -278,12 +278,12 @@ TB_CASES = [
 ]
 
 
-@pytest.mark.parametrize("tile", [0, 1, 3])
+@pytest.mark.parametrize("tile", [0, 1, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("depth", [1, 3, 4, 5, 8])
 @pytest.mark.parametrize("name,mk", TB_CASES)
 def test_precond_blocked_f64(name, mk, depth, tile):
     p = mk()
-    if tile == 3 and depth > 4:
+    if tile in (3, 5, 7) and depth > 4:
         depth = 4
     note(f"precond blocked f64 {name} depth={depth} tile={tile}")
     g, o = make_ops(p)
@@ -297,7 +297,7 @@ def test_precond_blocked_f64(name, mk, depth, tile):
     assert rel(U, U1) <= 1e-13
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_precond_blocked_f32(tile):
     p = inputs.random_medium((150, 200), seed=18, width=6)
     note(f"precond blocked f32 150x200 tile={tile}")
@@ -377,7 +377,8 @@ def test_general_cell_tables(ndim):
     rng = np.random.default_rng(2)
     x = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
     assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
-    kernels = [(1, 0, 0), (2, 4, 0), (2, 3, 3)] if ndim == 2 else [(1, 0, 0), (3, 16, 1)]
+    kernels = [(1, 0, 0), (2, 4, 0), (2, 3, 3), (2, 4, 4), (2, 3, 7)] if ndim == 2 else \
+        [(1, 0, 0), (3, 16, 1)]
     Uo = o.precond(p.F, 2, 0.25)
     for kern, depth, tile in kernels:
         g.set_tuning(kernel=kern, tb_depth=depth, tile=tile)
