@@ -108,6 +108,33 @@ def cpu_baseline(p, T, rho, napply, target_s=12.0):
                       f"applications of {T * op.nP} steps per solve"}
 
 
+def stream_probe(nbytes=2 << 30, reps=5):
+    """Practical HBM ceiling on this device: best of `reps` plain device copies
+    (read + write nbytes) and triads c = a + b (2 reads + 1 write), timed with
+    events; reported next to the 8 TB/s specification."""
+    import torch
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    c = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = {"copy": 0.0, "triad": 0.0}
+    for _ in range(reps):
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best["copy"] = max(best["copy"], 2 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+        e0.record()
+        torch.add(a, b, out=c)
+        e1.record()
+        torch.cuda.synchronize()
+        best["triad"] = max(best["triad"], 3 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b, c
+    torch.cuda.empty_cache()
+    return best
+
+
 def _timed(fn):
     import torch
     torch.cuda.synchronize()
@@ -129,14 +156,17 @@ def form_precision(rho):
     U = {}
     for name, prec in (("f64", tdp.F64), ("f32", tdp.F32)):
         op = tdp.operator_from_problem(p, prec=prec)
-        best, _ = op.autotune(T=1, rho=rho)
+        best, table = op.autotune(T=1, rho=rho)
+        us_step = min(r[3] for r in table)
         op.solve(F, T=p.periods, rho=rho, tol=1e-6)                 # warm (graphs)
         (Uq, info), dt = _timed(lambda: op.solve(F, T=p.periods, rho=rho, tol=1e-6))
         r = float(torch.linalg.norm(F - op.apply_H(Uq)) / torch.linalg.norm(F))
         U[name] = Uq
+        word = 8 if prec == tdp.F64 else 4
         res[name] = {"solves_per_s": 1.0 / dt, "seconds": dt, "iters": info.iters,
                      "precond_applications": info.steps // (p.periods * op.nP),
-                     "true_relres_fp64": r, "tuning": best}
+                     "true_relres_fp64": r, "tuning": best, "sweep_us_per_step": us_step,
+                     "sweep_algorithmic_GBps": 7 * word * p.N / (us_step * 1e-6) / 1e9}
         log(f"form precision {name}: {dt:.3f} s, iters {info.iters}, relres {r:.2e}")
         del op
     res["f32_rel_error_vs_f64_gpu_solution"] = float(
@@ -341,6 +371,8 @@ def main():
     kname = (f"k_sweep2d_tb<{'double' if prec == tdp.F64 else 'float'}> depth={steps_per_launch} "
              f"tile={tun['tile']}" if blocked else "k_sweep (one step per launch)")
     traffic = measured_traffic(args.workload, args.prec, args.variant, tun)
+    ceiling = stream_probe()
+    log(f"stream probe: copy {ceiling['copy']:.0f} GB/s, triad {ceiling['triad']:.0f} GB/s")
     log(f"precond apply {apply_ms:.3f} ms, {step_ms * 1e3:.2f} us/step, {achieved:.1f} GB/s algorithmic")
     out = {
         "metric": "Helmholtz solves/s at 1e-6 residual; recurrence-step GB/s vs HBM peak",
@@ -368,6 +400,7 @@ def main():
                      "kernel": kname, "bytes_per_node_step": bytes_per,
                      "nodes_per_launch": p.N, "steps_per_launch": Ns / launches,
                      "avg_launch_us": launch_us,
+                     "measured_ceiling_GBps": ceiling,
                      "alu": {"flops_per_node_step": FLOPS_PER_NODE_STEP,
                              "achieved_TFLOPs": FLOPS_PER_NODE_STEP * p.N * Ns / (apply_ms * 1e-3) / 1e12,
                              "peak_TFLOPs": 78.6 if prec == tdp.F64 else 157.3}},
