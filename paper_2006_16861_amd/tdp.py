@@ -174,6 +174,7 @@ class Operator:
         h_ = ctypes.c_void_p()
         _check(L.tdp_op_create(ctypes.byref(desc), ctypes.byref(h_)), "tdp_op_create")
         self._h = h_
+        self._destroy = L.tdp_op_destroy
         info = OpInfo()
         _check(L.tdp_op_query(self._h, ctypes.byref(info)), "tdp_op_query")
         self.omega_c, self.dt, self.alpha, self.beta = info.omega_c, info.dt, info.alpha, info.beta
@@ -181,7 +182,7 @@ class Operator:
 
     def close(self):
         if getattr(self, "_h", None):
-            load().tdp_op_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
 
     __del__ = close
@@ -278,11 +279,12 @@ class Batch:
                                   ctypes.cast(nr, ctypes.c_void_p), ctypes.byref(h_)),
                "tdp_batch_create")
         self._h = h_
+        self._destroy = L.tdp_batch_destroy
         self.field_op = [i for i, r in enumerate(self.nrhs) for _ in range(r)]
 
     def close(self):
         if getattr(self, "_h", None):
-            load().tdp_batch_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
 
     __del__ = close
