@@ -157,9 +157,10 @@ def form_precision(rho):
     for name, prec in (("f64", tdp.F64), ("f32", tdp.F32)):
         op = tdp.operator_from_problem(p, prec=prec)
         best, table = op.autotune(T=1, rho=rho)
-        us_step = min(r[3] for r in table)
         op.solve(F, T=p.periods, rho=rho, tol=1e-6)                 # warm (graphs)
         (Uq, info), dt = _timed(lambda: op.solve(F, T=p.periods, rho=rho, tol=1e-6))
+        _, step_ms = sweep_timing(op, F, p.periods, rho, 1, torch.cuda.current_stream())
+        us_step = step_ms * 1e3
         r = float(torch.linalg.norm(F - op.apply_H(Uq)) / torch.linalg.norm(F))
         U[name] = Uq
         word = 8 if prec == tdp.F64 else 4
@@ -368,8 +369,14 @@ def main():
     # m, damping, Re F, Im F) x N nodes x the steps the launch advances
     achieved = p.N * bytes_per * (Ns / launches) / (launch_us * 1e-6) / 1e9
     napply = infos[-1].steps // Ns
-    kname = (f"k_sweep2d_tb<{'double' if prec == tdp.F64 else 'float'}> depth={steps_per_launch} "
-             f"tile={tun['tile']}" if blocked else "k_sweep (one step per launch)")
+    tname = "double" if prec == tdp.F64 else "float"
+    if tun["kernel"] == 2:
+        kname = (f"k_sweep2d_{'tb2' if tun['tile'] >= 4 else 'tb'}<{tname}> "
+                 f"depth={steps_per_launch} tile={tun['tile']}")
+    elif tun["kernel"] == 3:
+        kname = f"k_sweep3d_stream<{tname}> shape={tun['tile']} z-chunk={tun['tb_depth']}"
+    else:
+        kname = f"k_sweep<{tname}> (one step per launch)"
     traffic = measured_traffic(args.workload, args.prec, args.variant, tun)
     ceiling = stream_probe()
     log(f"stream probe: copy {ceiling['copy']:.0f} GB/s, triad {ceiling['triad']:.0f} GB/s")

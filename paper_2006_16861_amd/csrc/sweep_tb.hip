@@ -188,6 +188,7 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
     // per-node coefficients from the cells around each node (storage rows
     // gy0+r0 .. gy0+r0+R, columns gx and gx+1)
     T co[R][NCO];
+    T uc[R], uprev[R], d[R], fr[R], fi[R];
     {
         T ca[R + 1], cb[R + 1];
 #pragma unroll
@@ -197,6 +198,23 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
             const int64_t base = (int64_t)sy * (nx + 1);
             ca[i] = (rok && (unsigned)gx <= (unsigned)nx) ? m[base + gx] : T(0);
             cb[i] = (rok && (unsigned)(gx + 1) <= (unsigned)nx) ? m[base + gx + 1] : T(0);
+        }
+        // the node data of all R rows are requested before any of it is used or
+        // stored to LDS, so the tile load is a single memory round trip
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int gy = gy0 + r0 + i;
+            const bool in = xin && (unsigned)gy < (unsigned)ny;
+            const int64_t g = (int64_t)gy * nx + gx;
+            uc[i] = uprev[i] = d[i] = fr[i] = fi[i] = T(0);
+            if (in) {
+                uc[i] = u_in[g];
+                uprev[i] = up_in[g];
+                d[i] = dn[g];
+                const auto f = F[g];
+                fr[i] = f.x;
+                fi[i] = f.y;
+            }
         }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
@@ -214,42 +232,30 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
             }
         }
     }
-    // zero the LDS pads
+    // two LDS copies of the tile (step s reads copy s&1 and writes the other, so one
+    // barrier per step suffices); zero the pads of both
+    constexpr int UB = (EY + 2) * US;
     for (int t = threadIdx.x; t < US; t += 64 * W) {
-        ul[t] = T(0);
-        ul[(EY + 1) * US + t] = T(0);
+        ul[t] = ul[UB + t] = T(0);
+        ul[(EY + 1) * US + t] = ul[UB + (EY + 1) * US + t] = T(0);
     }
     for (int t = threadIdx.x; t < EY + 2; t += 64 * W) {
-        ul[t * US] = T(0);
-        ul[t * US + EX + 1] = T(0);
+        ul[t * US] = ul[UB + t * US] = T(0);
+        ul[t * US + EX + 1] = ul[UB + t * US + EX + 1] = T(0);
     }
-    T uprev[R], d[R], fr[R], fi[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-        const int gy = gy0 + r0 + i;
-        const bool in = xin && (unsigned)gy < (unsigned)ny;
-        const int64_t g = (int64_t)gy * nx + gx;
-        T uc = T(0);
-        uprev[i] = d[i] = fr[i] = fi[i] = T(0);
-        if (in) {
-            uc = u_in[g];
-            uprev[i] = up_in[g];
-            d[i] = dn[g];
-            const auto f = F[g];
-            fr[i] = f.x;
-            fi[i] = f.y;
-        }
-        ul[(r0 + i + 1) * US + lane + 1] = uc;
-    }
+    for (int i = 0; i < R; ++i) ul[(r0 + i + 1) * US + lane + 1] = uc[i];
     __syncthreads();
 
     T unew[R];
     for (int s = 0; s < k; ++s) {
         const T fas = (T)fa[s * fstride], fbs = (T)fb[s * fstride];
+        const T *cur = ul + (s & 1) * UB;
+        T *nxt = ul + ((s + 1) & 1) * UB;
         T cw[R + 2], cc[R + 2], ce[R + 2];   // LDS rows r0-1 .. r0+R at x-1, x, x+1
 #pragma unroll
         for (int i = 0; i < R + 2; ++i) {
-            const T *p = &ul[(r0 + i) * US + lane + 1];
+            const T *p = &cur[(r0 + i) * US + lane + 1];
             cw[i] = p[-1];
             cc[i] = p[0];
             ce[i] = p[1];
@@ -273,9 +279,8 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
             unew[i] = d[i] * (acc + fas * fr[i] + fbs * fi[i]) - (T(2) * d[i] - T(1)) * uprev[i];
             uprev[i] = cc[i + 1];
         }
-        __syncthreads();
 #pragma unroll
-        for (int i = 0; i < R; ++i) ul[(r0 + i + 1) * US + lane + 1] = unew[i];
+        for (int i = 0; i < R; ++i) nxt[(r0 + i + 1) * US + lane + 1] = unew[i];
         if (s + 1 == out_step[0] || s + 1 == out_step[1]) {
             double *o = (s + 1 == out_step[0]) ? out[0] : out[1];
 #pragma unroll
@@ -310,7 +315,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_tb2(
     int tiles_x, int ntiles, int per_xcd)
 {
     constexpr int EX = 64, EY = R * W;
-    __shared__ T ul[(EY + 2) * (EX + 2)];
+    __shared__ T ul[2 * (EY + 2) * (EX + 2)];
     const int id = blockIdx.x;
     const int tile = (id % 8) * per_xcd + id / 8;
     if (tile >= ntiles) return;
@@ -351,7 +356,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_tb_batch(
     int per_xcd)
 {
     constexpr int EX = 64, EY = R * W;
-    __shared__ T ul[(EY + 2) * (EX + 2)];
+    __shared__ T ul[(V2F ? 2 : 1) * (EY + 2) * (EX + 2)];
     __shared__ T cl[V2F ? 1 : (EY + 1) * (EX + 1)];
     const int id = blockIdx.x;
     const int tile = (id % 8) * per_xcd + id / 8;
