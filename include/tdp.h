@@ -60,6 +60,12 @@ typedef struct tdp_op tdp_op;
  *                    NULL selects the classical fourth-order compact scheme:
  *                    2-D S = {5/6, -1/3, -1/6},  M = {1/6, 1/24, 0}
  *                    3-D S = {1/2, -1/12, -1/12, 0}, M = {1/16, 1/48, 0, 0}.
+ *                    The second-order scheme of Sec. 3.1 (5- / 7-point
+ *                    Laplacian, lumped mass) is
+ *                    2-D S = {1, -1/2, 0},       M = {1/4, 0, 0}
+ *                    3-D S = {3/4, -1/4, 0, 0},  M = {1/8, 0, 0, 0};
+ *                    its mass term uses the cell slowness, so at a node it
+ *                    weighs 1/c^2 over the surrounding 3^d nodes.
  *                    The cell tables must be positive semidefinite as element
  *                    matrices with max eigenvalue of M <= 2^-d (App. A bound).
  *  steps_per_period  n_P; 0 selects the smallest multiple of 4 above the CFL

@@ -22,6 +22,20 @@ SYMBOLS = ("tdp_op_create", "tdp_op_destroy", "tdp_op_query", "tdp_apply_H",
            "tdp_batch_set_tuning", "tdp_batch_precond", "tdp_batch_solve", "tdp_batch_autotune")
 
 
+# Cell tables (stiffness, mass; entry k for node pairs of a cell that differ in k
+# axes, the cell form of App. A) of the discretisations the library knows by name.
+#   "compact": the library default (NULL tables), the fourth-order compact scheme.
+#   "fd2": the second-order scheme of Sec. 3.1 -- assembled, h^-2 times 2d on the
+#          node and -1 on each axis neighbour, with a lumped (diagonal) mass; a node
+#          lies in 2^d cells and an axis pair in 2^(d-1), so S = (2d/2^d, -1/2^(d-1), 0..)
+#          and M = (1/2^d, 0..).
+SCHEMES = {
+    "compact": {2: (None, None), 3: (None, None)},
+    "fd2": {2: ((1.0, -0.5, 0.0), (0.25, 0.0, 0.0)),
+            3: ((0.75, -0.25, 0.0, 0.0), (0.125, 0.0, 0.0, 0.0))},
+}
+
+
 class TdpError(RuntimeError):
     def __init__(self, code, what, msg):
         super().__init__(f"{what} failed ({code}): {msg}")
@@ -143,13 +157,20 @@ class Operator:
     """H for -Lap U - omega^2/c^2 U + i omega R U = F on an interior grid `n`
     with spacing `h` (Dirichlet walls); c and R are FP64 tensors on the GPU."""
 
-    def __init__(self, c, R, omega, h, prec=F64, steps_per_period=0, stiff=None, mass=None):
+    def __init__(self, c, R, omega, h, prec=F64, steps_per_period=0, stiff=None, mass=None,
+                 scheme=None):
         import torch
         L = load()
         self.n = tuple(int(v) for v in c.shape)
         self.ndim = len(self.n)
         if self.ndim not in (2, 3):
             raise ValueError("c must be 2-D or 3-D")
+        if scheme is not None:
+            if stiff is not None or mass is not None:
+                raise ValueError("give either scheme or stiff/mass tables")
+            if scheme not in SCHEMES:
+                raise ValueError(f"unknown scheme {scheme!r}; known: {sorted(SCHEMES)}")
+            stiff, mass = SCHEMES[scheme][self.ndim]
         self.N = int(c.numel())
         desc = OpDesc()
         desc.ndim = self.ndim

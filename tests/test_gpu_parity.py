@@ -385,3 +385,77 @@ def test_general_cell_tables(ndim):
         assert rel(host(g.precond(dev(p.F), 2, 0.25)), Uo) <= TOL64
     grad_l = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
     assert rel(host(g.grad_m(dev(grad_l), dev(x))), o.grad_m(grad_l, x)) <= 1e-13
+
+
+# ---------------------------------------------------------------- second-order scheme (Sec. 3.1)
+# the cell tables of the 5- / 7-point stencil with lumped mass, stated here
+# independently of the binding's named preset
+FD2_TABLES = {2: ((1.0, -0.5, 0.0), (0.25, 0.0, 0.0)),
+              3: ((0.75, -0.25, 0.0, 0.0), (0.125, 0.0, 0.0, 0.0))}
+
+
+@pytest.mark.parametrize("n", [(70, 131), (13, 17, 70)])
+def test_fd2_scheme_every_kernel(n):
+    """The binding's "fd2" scheme against the oracle with the Sec. 3.1 tables:
+    parameters, H, every sweep kernel, fixed-iteration GMRES."""
+    from paper_2006_16861_amd import tdp
+    ndim = len(n)
+    p = inputs.random_medium(n, seed=31, width=3)
+    note(f"fd2 scheme {n}")
+    stiff, mass = FD2_TABLES[ndim]
+    o = oracle.Op(p.n, p.h, p.omega, p.c, p.R, stiff=stiff, mass=mass)
+    g = tdp.Operator(dev(p.c), dev(p.R), p.omega, p.h, scheme="fd2")
+    assert g.nP == o.nP and abs(g.lam_bar - o.lam_bar) <= 1e-12 * o.lam_bar
+    assert abs(g.lam_bar - (4 * ndim / p.h ** 2 + g.omega_c ** 2)) <= 1e-9 * g.lam_bar
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
+    assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
+    kernels = [(1, 0, 0), (2, 8, 4), (2, 6, 5), (2, 3, 1), (2, 4, 3)] if ndim == 2 else \
+        [(1, 0, 0), (3, 16, 1), (3, 32, 2), (3, 7, 0)]
+    Uo = o.precond(p.F, 2, 0.25)
+    for kern, depth, tile in kernels:
+        g.set_tuning(kernel=kern, tb_depth=depth, tile=tile)
+        assert rel(host(g.precond(dev(p.F), 2, 0.25)), Uo) <= TOL64, (kern, depth, tile)
+    g.set_tuning(kernel=0)
+    Ug, ig = g.solve(dev(p.F), T=p.periods, restart=6, fixed_iters=10)
+    Uo, io = o.gmres(p.F, T=p.periods, restart=6, fixed_iters=10)
+    assert ig.iters == io["iters"] == 10
+    assert rel(host(Ug), Uo) <= TOL64
+
+
+def test_fd2_solve_matches_lu_of_the_written_matrix():
+    """Converged GPU solve with the "fd2" scheme on a constant medium against
+    sparse LU of Sec. 3.1's matrix assembled here from its formula."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    from paper_2006_16861_amd import tdp
+    n = (96, 80)
+    h = 1.0 / 97
+    omega = 2 * math.pi / (10 * h)
+    c = np.ones(n)
+    R = np.zeros(n)
+    w = 12
+    for a in range(2):
+        i = np.arange(n[a])
+        dlt = np.maximum(0, w - np.minimum(i, n[a] - 1 - i)) / w
+        shp = [1, 1]
+        shp[a] = n[a]
+        R = np.maximum(R, 2 * omega * dlt.reshape(shp) ** 2)
+    F = np.zeros(n, complex)
+    F[40, 33] = 1.0
+    note("fd2 solve vs LU of the written 5-point matrix")
+    g = tdp.Operator(dev(c), dev(R), omega, h, scheme="fd2")
+    Ug, ig = g.solve(dev(F), T=10, tol=1e-11)
+    assert ig.status == 0
+    N = n[0] * n[1]
+    idx = np.arange(N).reshape(n)
+    A = sp.lil_matrix((N, N), dtype=complex)
+    for i in range(n[0]):
+        for j in range(n[1]):
+            b = idx[i, j]
+            A[b, b] = 4 / h ** 2 - omega ** 2 + 1j * omega * R[i, j]
+            for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                if 0 <= i + di < n[0] and 0 <= j + dj < n[1]:
+                    A[b, idx[i + di, j + dj]] = -1 / h ** 2
+    U = spla.spsolve(A.tocsc(), F.reshape(-1)).reshape(n)
+    assert rel(host(Ug), U) <= 1e-6

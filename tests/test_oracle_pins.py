@@ -10,6 +10,7 @@ import math
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 import oracle
@@ -379,3 +380,119 @@ def test_bilinear_fe_tables_sine_modes(ndim):
         lam = S / h ** 2 - k2 * M
         He = op.apply_H(e.astype(np.complex128))
         assert np.linalg.norm(He - lam * e) <= 1e-12 * abs(lam) * np.linalg.norm(e)
+
+
+# ---------------------------------------------------------------- second-order scheme (Sec. 3.1)
+# A node lies in 2^d cells and an axis-neighbour pair in 2^(d-1) cells, so the
+# 5- / 7-point stencil h^-2 (2d, -1) with a lumped mass has the cell tables below.
+FD2 = {2: ((1.0, -0.5, 0.0), (0.25, 0.0, 0.0)),
+       3: ((0.75, -0.25, 0.0, 0.0), (0.125, 0.0, 0.0, 0.0))}
+
+
+def written_fd2(n, h, k2_node, omega_R):
+    """Sec. 3.1's matrix written out: h^-2 (2d U - sum of the 2d axis neighbours)
+    - k^2 U + i omega R U at every node (Dirichlet outside)."""
+    d = len(n)
+    N = int(np.prod(n))
+    idx = np.arange(N).reshape(n)
+    rows, cols, vals = [], [], []
+    diag = 2 * d / h ** 2 - k2_node.reshape(-1) + 1j * omega_R.reshape(-1)
+    rows += list(range(N)); cols += list(range(N)); vals += list(diag)
+    for a in range(d):
+        lo = [slice(None)] * d; hi = [slice(None)] * d
+        lo[a] = slice(0, n[a] - 1); hi[a] = slice(1, n[a])
+        i0 = idx[tuple(lo)].reshape(-1); i1 = idx[tuple(hi)].reshape(-1)
+        for p, q in ((i0, i1), (i1, i0)):
+            rows += list(p); cols += list(q); vals += [-1.0 / h ** 2] * len(p)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
+
+
+def node_slowness_fd2(c):
+    """The mass weight at a node under the cell form with the lumped table: the
+    mean over its 2^d cells of the cell slowness (mean of 1/c^2 over the cell's
+    corners, clamped to the box)."""
+    m = 1.0 / c ** 2
+    d = c.ndim
+    pad = np.pad(m, 1, mode="edge")
+    cells = np.zeros(tuple(s + 1 for s in c.shape))
+    for corner in np.ndindex(*(2,) * d):
+        cells += pad[tuple(slice(o, o + s + 1) for o, s in zip(corner, c.shape))]
+    cells /= 2 ** d
+    node = np.zeros(c.shape)
+    for corner in np.ndindex(*(2,) * d):
+        node += cells[tuple(slice(o, o + s) for o, s in zip(corner, c.shape))]
+    return node / 2 ** d
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_fd2_tables_assemble_the_written_stencil(ndim):
+    """The cell form with the second-order tables is Sec. 3.1's 5- / 7-point
+    matrix: exactly for constant c, and with the 3^d-weighted node slowness for
+    variable c (the corner-averaged cell slowness)."""
+    n = (9, 7) if ndim == 2 else (5, 6, 4)
+    h, omega = 1.0 / 10, 23.0
+    rng = np.random.default_rng(40)
+    R = rng.uniform(0, 2, n)
+    for c in (np.full(n, 1.7), rng.uniform(1.0, 2.0, n)):
+        H = oracle.assemble_H(n, h, omega, c, R, stiff=FD2[ndim][0], mass=FD2[ndim][1])
+        W = written_fd2(n, h, omega ** 2 * node_slowness_fd2(c), omega * R)
+        assert abs(H - W).max() <= 1e-12 * abs(W).max()
+        if np.ptp(c) == 0:
+            W0 = written_fd2(n, h, np.full(n, (omega / 1.7) ** 2), omega * R)
+            assert abs(H - W0).max() <= 1e-12 * abs(W0).max()
+        o = oracle.Op(n, h, omega, c, R, stiff=FD2[ndim][0], mass=FD2[ndim][1])
+        x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        assert np.linalg.norm(o.apply_H(x) - (W @ x.reshape(-1)).reshape(n)) <= \
+            1e-12 * np.linalg.norm(W @ x.reshape(-1))
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_fd2_symbol_bound_and_steps_per_period(ndim):
+    """Sine modes: lambda = h^-2 (2d - 2 sum cos t_a) - k^2 + i omega R.  The
+    upper bound of Re H + omega_c^2 is 4d h^-2 + omega_c^2 (8 h^-2 in 2-D, as
+    Sec. 3.1 states), and n_P follows from it: 10 points per wavelength give
+    omega_c h = 2 pi/10, sin(pi/n_P) < omega_c / sqrt(4d h^-2 + omega_c^2)."""
+    n = (8, 11) if ndim == 2 else (5, 7, 6)
+    h = 1.0 / (max(n) + 1)
+    omega = 2 * math.pi * 1.3 / (10 * h)
+    c = np.full(n, 1.3)
+    o = oracle.Op(n, h, omega, c, np.full(n, 0.4), stiff=FD2[ndim][0], mass=FD2[ndim][1])
+    k2 = (omega / 1.3) ** 2
+    for p in [(1,) * ndim, tuple(range(2, 2 + ndim)), n]:
+        e = sine_mode(n, p)
+        t = [math.pi * pa / (na + 1) for na, pa in zip(n, p)]
+        lam = (2 * ndim - 2 * sum(math.cos(x) for x in t)) / h ** 2 - k2 + 1j * omega * 0.4
+        He = o.apply_H(e.astype(np.complex128))
+        assert np.linalg.norm(He - lam * e) <= 1e-12 * abs(lam) * np.linalg.norm(e)
+    wc = omega / 1.3
+    assert abs(o.omega_c - wc) <= 1e-12 * wc
+    assert abs(o.lam_bar - (4 * ndim / h ** 2 + wc ** 2)) <= 1e-9 * o.lam_bar
+    ratio = wc / math.sqrt(4 * ndim / h ** 2 + wc ** 2)
+    nP = 4
+    while not math.sin(math.pi / nP) < ratio:
+        nP += 4
+    assert o.nP == nP
+    assert nP == (16 if ndim == 2 else 20)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_fd2_step_is_the_written_time_domain_scheme(ndim):
+    """One recurrence step with the second-order tables satisfies Sec. 3.1's
+    time-domain scheme written out:
+      alpha/dt^2 (u+ - 2u + u-) + beta/(2 dt) (omega R / omega_c)(u+ - u-)
+      + h^-2 (2d u - neighbours) + (omega_c^2 - k^2) u = f,
+    with k^2 = omega^2 times the node slowness of the cell form."""
+    n = (12, 10) if ndim == 2 else (6, 7, 5)
+    h, omega = 1.0 / 13, 30.0
+    rng = np.random.default_rng(41)
+    c = rng.uniform(1.0, 2.5, n)
+    R = rng.uniform(0, 3, n)
+    o = oracle.Op(n, h, omega, c, R, stiff=FD2[ndim][0], mass=FD2[ndim][1])
+    u, um, f = (rng.standard_normal(n) for _ in range(3))
+    up = o.step(u, um, f)
+    lap = written_fd2(n, h, np.zeros(n), np.zeros(n)).real
+    k2 = omega ** 2 * node_slowness_fd2(c)
+    lhs = (o.alpha / o.dt ** 2 * (up - 2 * u + um)
+           + o.beta / (2 * o.dt) * (omega * R / o.omega_c) * (up - um)
+           + (lap @ u.reshape(-1)).reshape(n) + (o.omega_c ** 2 - k2) * u)
+    assert np.abs(lhs - f).max() <= 1e-9 * np.abs(f).max()
