@@ -258,6 +258,55 @@ def form_adjoint(rho):
             "solves_per_s": 8.0 / dt, "seconds": dt, "grad_norm": float(torch.linalg.norm(g))}
 
 
+def study_convergence(model, Ts=(10, 20, 40, 80, 160, 320), rhos=(0.0, 0.25, 0.5, 0.75),
+                      gmres_Ts=(5, 10, 20, 40, 80), ref_tol=1e-12):
+    """Sec. 4.1's convergence studies on the constant model and the resonant disc
+    model (6 points per wavelength, 8 steps per period, 32-node damping layers):
+    (a) the relative error of S_T F against H^-1 F as T grows, for each taper rho
+        (rho = 0: the forcing ramps up over one period);
+    (b) preconditioned GMRES (rho = 0.25) to a true relative residual of 1e-6 for
+        several T: iterations, total periods (one application per iteration plus
+        the one for the right-hand side) and the error against H^-1 F, next to the
+        direct application S_T F of the sweep in (a).
+    H^-1 F is the GMRES solution at true relative residual ref_tol."""
+    import torch
+    from paper_2006_16861_amd import inputs, tdp
+    out = {"study": "convergence", "model": model, "ppw": 6.0, "layer": 32}
+    for mk in (inputs.open2d, inputs.disc2d):
+        p = mk(model)
+        op = tdp.operator_from_problem(p)
+        F = torch.as_tensor(p.F, device="cuda")
+        t0 = time.perf_counter()
+        Uref, iref = op.solve(F, T=p.periods, tol=ref_tol, max_iters=20000)
+        log(f"study {p.name}: n={p.n} omega={p.omega:.1f} n_P={op.nP}; reference: "
+            f"{iref.iters} its, relres {iref.relres:.1e}, {time.perf_counter() - t0:.1f} s")
+        nref = float(torch.linalg.norm(Uref))
+        err = lambda U: float(torch.linalg.norm(U - Uref)) / nref
+        res = {"n": list(p.n), "omega": p.omega, "n_P": op.nP,
+               "reference": {"iters": iref.iters, "relres": iref.relres}}
+        direct = {}
+        for rho in rhos:
+            row = []
+            for T in Ts:
+                row.append(err(op.precond(F, T, rho)))
+            direct[str(rho)] = dict(zip(map(str, Ts), row))
+            log(f"  S_T F error, rho={rho:<4}: " + "  ".join(f"T={T}:{e:.1e}" for T, e in zip(Ts, row)))
+        res["precond_error"] = direct
+        gm = {}
+        for T in gmres_Ts:
+            U, info = op.solve(F, T=T, rho=0.25, tol=1e-6, max_iters=5000)
+            periods = info.steps // op.nP
+            gm[str(T)] = {"iters": info.iters, "restarts": info.restarts, "periods": int(periods),
+                          "relres": info.relres, "error": err(U), "status": info.status}
+            log(f"  GMRES T={T:<4}: {info.iters:4d} its, {periods:6d} periods, relres "
+                f"{info.relres:.1e}, error {err(U):.1e}")
+        res["gmres"] = gm
+        out[p.name] = res
+        del op
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,7 +332,15 @@ def main():
     ap.add_argument("--profile-sweeps", type=int, default=0,
                     help="profiling mode: one 256 MiB device copy (counter calibration), then "
                          "this many preconditioner applications, then exit")
+    ap.add_argument("--study", choices=["convergence"], default=None,
+                    help="run Sec. 4.1's convergence study on the constant and resonant "
+                         "models instead of the benchmark")
+    ap.add_argument("--study-model", type=int, default=320,
+                    help="model size (nodes per axis, without the damping layers)")
     args = ap.parse_args()
+    if args.study:
+        study_convergence(args.study_model)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "slab decomposition is a design note, not built", file=sys.stderr)

@@ -125,7 +125,9 @@ typedef struct {
 
 /* GMRES report (host struct).  history (host, may be NULL) receives the
  * Givens estimate of ||P r|| / ||P r_0|| after each iteration, up to
- * history_cap entries. */
+ * history_cap entries.  switched = 1 when a tolerance-mode solve with
+ * variant 0 rejected a cycle and continued with variant 1 (see
+ * tdp_gmres_solve). */
 typedef struct {
     int iters, restarts;
     double relres_true, relres_prec;
@@ -133,6 +135,7 @@ typedef struct {
     double ms_total;         /* host wall time of the call              */
     double *history;
     int history_cap, history_len;
+    int switched;
 } tdp_gmres_info;
 
 /* Create an operator: validates the description, copies c and R, computes
@@ -171,8 +174,15 @@ int tdp_precond_apply_complex(const tdp_op *op, int periods_T, double rho, const
  * when the true residual stalls while the Givens estimate of the
  * preconditioned residual keeps falling (relt > 2 rel_start est_cycle and
  * relt > 0.7 rel_prev; the Table 1 map is only real-linear, so the Arnoldi
- * relation holds only approximately).  Returns TDP_OK, or TDP_ENOTCONV with
- * the last iterate in U.  F, U: device complex128 [N]; info: host or NULL. */
+ * relation holds only approximately).  A cycle keeps its iterate with the
+ * smallest true residual, and stops early if that residual runs away (> 1e6
+ * times the cycle's start, or not finite).  A variant-0 cycle that does not
+ * lower the true residual is rejected (x unchanged) and the solve continues
+ * with variant 1, whose complex-linear map GMRES handles exactly (when T is
+ * short, Table 1's real-linearity defect makes the complex least-squares
+ * update useless); a variant-1 cycle keeps its last iterate in that case.
+ * Returns TDP_OK, or TDP_ENOTCONV with the accepted iterate in U.
+ * F, U: device complex128 [N]; info: host or NULL. */
 int tdp_gmres_solve(const tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void *U,
                     tdp_gmres_info *info);
 
@@ -247,8 +257,11 @@ int tdp_batch_autotune(tdp_batch *b, const int *periods_T, double rho, double *t
 int tdp_batch_precond(tdp_batch *b, const int *periods_T, double rho, const void *const *F,
                       void *const *U);
 
-/* Solve every field (cfg->variant must be 0).  infos: host [nfields] or NULL.
- * Returns TDP_OK if every field converged, TDP_ENOTCONV otherwise. */
+/* Solve every field (cfg->variant must be 0) with the iteration of
+ * tdp_gmres_solve in lockstep; a field whose cycle is rejected stops there
+ * (TDP_ENOTCONV, best iterate in U) since only Table 1 is batched.
+ * infos: host [nfields] or NULL.  Returns TDP_OK if every field converged,
+ * TDP_ENOTCONV otherwise. */
 int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int *periods_T,
                     const void *const *F, void *const *U, tdp_gmres_info *infos);
 

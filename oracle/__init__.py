@@ -182,7 +182,7 @@ class Op:
               x0=None, history_cap=4096, variant=0):
         F = np.ascontiguousarray(F, dtype=np.complex128).reshape(self.n)
         U = np.zeros_like(F) if x0 is None else np.ascontiguousarray(x0, dtype=np.complex128).reshape(self.n).copy()
-        info = np.zeros(6)
+        info = np.zeros(7)
         hist = np.zeros(history_cap)
         rc = lib().tdpo_gmres_solve(self._h, int(restart), int(max_iters), int(T), float(rho),
                                     float(tol), int(fixed_iters), int(x0 is not None),
@@ -192,7 +192,8 @@ class Op:
             raise OracleError(rc, "tdpo_gmres_solve")
         res = {"status": rc, "iters": int(info[0]), "restarts": int(info[1]),
                "relres": float(info[2]), "relres_prec": float(info[3]),
-               "history": hist[: int(info[4])].copy(), "applications": int(info[5])}
+               "history": hist[: int(info[4])].copy(), "applications": int(info[5]),
+               "switched": int(info[6])}
         return U, res
 
     def grad_m(self, lam, U):

@@ -459,19 +459,21 @@ int tdpo_gmres_solve(const tdpo_op *op, int restart, int max_iters, int T, doubl
     double complex *w = malloc(sizeof(double complex) * N);
     double complex *r = malloc(sizeof(double complex) * N);
     double complex *xt = malloc(sizeof(double complex) * N);
+    double complex *xbest = malloc(sizeof(double complex) * N);
     double complex *Hm = calloc((size_t)(m + 1) * m, sizeof(double complex));
     double complex *gv = malloc(sizeof(double complex) * (m + 1));
     double complex *sn = malloc(sizeof(double complex) * m);
     double *cs = malloc(sizeof(double) * m);
     double complex *y = malloc(sizeof(double complex) * m);
-    if (!V || !w || !r || !xt || !Hm || !gv || !sn || !cs || !y) {
-        free(V); free(w); free(r); free(xt); free(Hm); free(gv); free(sn); free(cs); free(y);
+    if (!V || !w || !r || !xt || !xbest || !Hm || !gv || !sn || !cs || !y) {
+        free(V); free(w); free(r); free(xt); free(xbest); free(Hm); free(gv); free(sn); free(cs);
+        free(y);
         return TDPO_ENOMEM;
     }
 #define HM(i, j) Hm[(size_t)(j) * (m + 1) + (i)]
     if (!x0_given) memset(U, 0, sizeof(double complex) * N);
     double bnorm = znrm(N, F);
-    int its = 0, restarts = 0, nhist = 0, status = TDPO_ENOTCONV;
+    int its = 0, restarts = 0, nhist = 0, status = TDPO_ENOTCONV, switched = 0;
     long napply = 0;
     double pnorm0 = -1.0, est = 1.0, rel = 1.0;
     if (bnorm == 0.0) {
@@ -496,8 +498,8 @@ int tdpo_gmres_solve(const tdpo_op *op, int restart, int max_iters, int T, doubl
         for (long i = 0; i < N; ++i) V[i] /= beta0;
         for (int k = 0; k <= m; ++k) gv[k] = 0.0;
         gv[0] = beta0;
-        double rel_start = rel, rel_prev = rel;
-        int k_used = 0, converged = 0, have_xt = 0;
+        double rel_start = rel, rel_prev = rel, best_rel = rel, rel_last = rel;
+        int k_used = 0, converged = 0, best_k = 0;
         for (int i = 0; i < m && its < limit; ++i) {
             double complex *vi = V + (size_t)i * N, *vn = V + (size_t)(i + 1) * N;
             tdpo_apply_H(op, vi, r);
@@ -548,13 +550,18 @@ int tdpo_gmres_solve(const tdpo_op *op, int restart, int max_iters, int T, doubl
                     double complex *vk = V + (size_t)k * N;
                     for (long q = 0; q < N; ++q) xt[q] += y[k] * vk[q];
                 }
-                have_xt = 1;
                 tdpo_apply_H(op, xt, r);
                 for (long q = 0; q < N; ++q) r[q] = F[q] - r[q];
                 double relt = znrm(N, r) / bnorm;
-                rel = relt;
+                rel_last = relt;
+                if (relt < best_rel) {                     /* best iterate of the cycle */
+                    best_rel = relt;
+                    best_k = k_used;
+                    memcpy(xbest, xt, sizeof(double complex) * N);
+                }
                 if (relt <= tol) { converged = 1; break; }
                 if (hn == 0.0) break;
+                if (!(relt <= 1e6 * rel_start)) break;     /* runaway or not finite */
                 if (relt > 2.0 * rel_start * est_cycle && relt > 0.7 * rel_prev) break;
                 rel_prev = relt;
             } else if (hn == 0.0) {
@@ -563,8 +570,21 @@ int tdpo_gmres_solve(const tdpo_op *op, int restart, int max_iters, int T, doubl
             for (long q = 0; q < N; ++q) vn[q] = w[q] / hn;
         }
         ++restarts;
-        if (have_xt) {
-            memcpy(U, xt, sizeof(double complex) * N);
+        if (tolmode) {
+            /* keep the cycle's iterate of least true residual; a Table 1 cycle
+               that did not lower it is rejected and Definition 4 takes over */
+            if (best_k == 0 && k_used > 0 && variant != 0) {
+                /* Definition 4 is complex-linear: GMRES's own last iterate stands */
+                best_k = k_used;
+                best_rel = rel_last;
+                memcpy(xbest, xt, sizeof(double complex) * N);
+            }
+            if (best_k > 0) memcpy(U, xbest, sizeof(double complex) * N);
+            rel = best_rel;
+            if (best_k == 0 && k_used > 0) {
+                variant = 1;
+                switched = 1;
+            }
         } else {
             for (int k = k_used - 1; k >= 0; --k) {        /* back substitution R y = g */
                 double complex s = gv[k];
@@ -594,9 +614,11 @@ done:
         info[3] = est;
         info[4] = nhist;
         info[5] = (double)napply;
+        info[6] = switched;
     }
 #undef HM
-    free(V); free(w); free(r); free(xt); free(Hm); free(gv); free(sn); free(cs); free(y);
+    free(V); free(w); free(r); free(xt); free(xbest); free(Hm); free(gv); free(sn); free(cs);
+    free(y);
     return status;
 }
 

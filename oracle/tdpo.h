@@ -39,7 +39,8 @@ int tdpo_precond_apply_complex(const tdpo_op *op, int T, double rho,
                                const double complex *F, double complex *U);
 /* variant 0: Table 1 preconditioner, 1: Definition 4 (complex-linear).
  * info = {iters, restarts, true relres, last Givens estimate, history length,
- *         preconditioner applications} */
+ *         preconditioner applications, 1 if a rejected cycle moved a variant-0
+ *         solve to variant 1} */
 int tdpo_gmres_solve(const tdpo_op *op, int restart, int max_iters, int T, double rho,
                      double tol, int fixed_iters, int x0_given, int variant,
                      const double complex *F, double complex *U, double *info,

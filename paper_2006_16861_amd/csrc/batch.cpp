@@ -381,8 +381,9 @@ struct FS {
     int its = 0, restarts = 0, nhist = 0, status = TDP_ENOTCONV, i = 0, k_used = 0;
     int64_t napply = 0;
     double bnorm = 0, pnorm0 = -1, est = 1, rel = 1, rel_start = 1, rel_prev = 1, beta0 = 0;
-    bool have_xt = false;
-    std::vector<cplx> Hm, gv, sn, y;
+    double best_rel = 1;
+    int best_k = 0;             // the cycle's candidate with the smallest true residual
+    std::vector<cplx> Hm, gv, sn, y, ybest;
     std::vector<double> cs;
 };
 }  // namespace
@@ -454,6 +455,7 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
         S.gv.assign(m + 1, 0.0);
         S.sn.assign(m, 0.0);
         S.y.assign(m, 0.0);
+        S.ybest.assign(m, 0.0);
         S.cs.assign(m, 0.0);
         if (!cfg->x0_given) TDP_CHECK_HIP(launch_fill_zero(U[q], 16 * b->f[q].N, s));
         TDP_CHECK(norm2_async(q, F[q], b->f[q].dco));
@@ -496,13 +498,23 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
     auto end_cycle = [&](size_t q) -> int {
         FS &S = st[q];
         ++S.restarts;
-        if (S.have_xt) {
-            TDP_CHECK_HIP(hipMemcpyAsync(U[q], b->f[q].xv, 16 * b->f[q].N, hipMemcpyDeviceToDevice, s));
+        S.ph = NEED_RES;
+        if (tolmode) {
+            // keep the cycle's best iterate; a cycle that did not lower the true
+            // residual ends the field (only the real-linear Table 1 map is batched)
+            if (S.best_k > 0 && S.best_k == S.k_used) {
+                TDP_CHECK_HIP(hipMemcpyAsync(U[q], b->f[q].xv, 16 * b->f[q].N, hipMemcpyDeviceToDevice, s));
+            } else if (S.best_k > 0) {
+                std::copy(S.ybest.begin(), S.ybest.begin() + S.best_k, S.y.begin());
+                S.k_used = S.best_k;
+                TDP_CHECK(update(q, U[q], U[q]));
+            }
+            S.rel = S.best_rel;
+            if (S.best_k == 0 && S.k_used > 0) S.ph = DONE;
         } else if (S.k_used > 0) {
             solve_y(S);
             TDP_CHECK(update(q, U[q], U[q]));
         }
-        S.ph = NEED_RES;
         return TDP_OK;
     };
     std::vector<char> needP(nf);
@@ -588,10 +600,10 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
                 }
                 for (int k = 0; k <= m; ++k) S.gv[k] = 0.0;
                 S.gv[0] = S.beta0;
-                S.rel_start = S.rel_prev = S.rel;
+                S.rel_start = S.rel_prev = S.best_rel = S.rel;
+                S.best_k = 0;
                 S.i = 0;
                 S.k_used = 0;
-                S.have_xt = false;
                 S.ph = NEED_HV;
                 continue;
             }
@@ -638,7 +650,6 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
                 TDP_CHECK(apply_H_on(op, b->f[q].xv, F[q], b->f[q].rv, s));
                 TDP_CHECK(norm2_async(q, b->f[q].rv, b->f[q].dco));
                 TDP_CHECK_HIP(hipMemcpyAsync(hb + q * hs, b->f[q].dco, sizeof(double), hipMemcpyDeviceToHost, s));
-                S.have_xt = true;
                 anyD = true;
             }
         }
@@ -653,6 +664,11 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
             if (tolmode) {
                 const double relt = std::sqrt(hb[q * hs]) / S.bnorm;
                 S.rel = relt;
+                if (relt < S.best_rel) {
+                    S.best_rel = relt;
+                    S.best_k = S.k_used;
+                    std::copy(S.y.begin(), S.y.begin() + S.k_used, S.ybest.begin());
+                }
                 if (relt <= cfg->tol) {
                     TDP_CHECK_HIP(hipMemcpyAsync(U[q], b->f[q].xv, 16 * b->f[q].N, hipMemcpyDeviceToDevice, s));
                     ++S.restarts;
@@ -660,7 +676,8 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
                     S.ph = DONE;
                     continue;
                 }
-                if (hn == 0.0 || (relt > 2.0 * S.rel_start * est_cycle && relt > 0.7 * S.rel_prev))
+                if (hn == 0.0 || !(relt <= 1e6 * S.rel_start) ||
+                    (relt > 2.0 * S.rel_start * est_cycle && relt > 0.7 * S.rel_prev))
                     end = true;
                 else
                     S.rel_prev = relt;
@@ -697,6 +714,7 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
             inf.restarts = S.restarts;
             inf.relres_true = S.rel;
             inf.relres_prec = S.est;
+            inf.switched = 0;
             inf.steps = S.napply * (int64_t)periods_T[b->f[q].op] * b->ops[b->f[q].op]->nP;
             inf.history_len = S.nhist < inf.history_cap ? S.nhist : inf.history_cap;
             inf.ms_total = ms;

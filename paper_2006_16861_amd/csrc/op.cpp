@@ -722,7 +722,11 @@ typedef std::complex<double> cplx;
 // after every iteration (a multi-axpy, one H-apply and a norm: under 1% of a
 // preconditioner application), stops as soon as it is <= tol, and restarts
 // the cycle early when the true residual stalls while the Givens estimate
-// keeps falling (the Table 1 preconditioner is only real-linear).
+// keeps falling (the Table 1 preconditioner is only real-linear).  Each cycle
+// keeps its iterate of least true residual; a Table 1 cycle that does not
+// lower the true residual is rejected and the solve continues with the
+// complex-linear variant 1, whose cycles always keep their last iterate when
+// none lowered the true residual.
 static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void *U,
                       tdp_gmres_info *info)
 {
@@ -754,9 +758,10 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
     TDP_CHECK(norm2_host(op, F, &b2));
     const double bnorm = std::sqrt(b2);
     int its = 0, restarts = 0, nhist = 0, status = TDP_ENOTCONV;
+    int variant = cfg->variant, switched = 0;
     int64_t napply = 0;
     double pnorm0 = -1.0, est = 1.0, rel = 1.0;
-    std::vector<cplx> Hm((size_t)(m + 1) * m), gv(m + 1), sn(m), y(m);
+    std::vector<cplx> Hm((size_t)(m + 1) * m), gv(m + 1), sn(m), y(m), ybest(m);
     std::vector<double> cs(m);
     auto HM = [&](int i, int j) -> cplx & { return Hm[(size_t)j * (m + 1) + i]; };
     auto solve_y = [&](int k_used) {
@@ -795,7 +800,7 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
             break;
         }
         if (its >= limit) break;
-        TDP_CHECK(precond_impl(op, T, rho, cfg->variant, op->rv, col(0)));
+        TDP_CHECK(precond_impl(op, T, rho, variant, op->rv, col(0)));
         ++napply;
         double z2;
         TDP_CHECK(norm2_host(op, col(0), &z2));
@@ -806,12 +811,12 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
         TDP_CHECK_HIP(launch_scale_by_invnorm(col(0), col(0), op->dcoef, N, s));
         for (int k = 0; k <= m; ++k) gv[k] = 0.0;
         gv[0] = beta0;
-        double rel_start = rel, rel_prev = rel;
-        int k_used = 0;
-        bool converged = false, have_xt = false;
+        double rel_start = rel, rel_prev = rel, best_rel = rel, rel_last = rel;
+        int k_used = 0, best_k = 0;       // best_k: the cycle's candidate with the
+        bool converged = false;           // smallest true residual (0: the start)
         for (int i = 0; i < m && its < limit; ++i) {
             TDP_CHECK(apply_H_impl(op, col(i), nullptr, op->tv));
-            TDP_CHECK(precond_impl(op, T, rho, cfg->variant, op->tv, op->wv));
+            TDP_CHECK(precond_impl(op, T, rho, variant, op->tv, op->wv));
             ++napply;
             ++its;
             // classical Gram-Schmidt, two passes
@@ -860,13 +865,18 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
                 TDP_CHECK(apply_H_impl(op, op->xv, F, op->rv));
                 TDP_CHECK(norm2_host(op, op->rv, &r2));
                 const double relt = std::sqrt(r2) / bnorm;
-                have_xt = true;
-                rel = relt;
+                rel_last = relt;
+                if (relt < best_rel) {
+                    best_rel = relt;
+                    best_k = k_used;
+                    std::copy(y.begin(), y.begin() + k_used, ybest.begin());
+                }
                 if (relt <= cfg->tol) {
                     converged = true;
                     break;
                 }
                 if (hn == 0.0) break;
+                if (!(relt <= 1e6 * rel_start)) break;      // runaway or non-finite
                 if (relt > 2.0 * rel_start * est_cycle && relt > 0.7 * rel_prev) break;
                 rel_prev = relt;
             } else if (hn == 0.0) {
@@ -874,8 +884,26 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
             }
         }
         ++restarts;
-        if (have_xt) {
-            TDP_CHECK_HIP(hipMemcpyAsync(U, op->xv, 16 * N, hipMemcpyDeviceToDevice, s));
+        if (tolmode) {
+            // keep the best iterate of the cycle; a cycle that did not lower the
+            // true residual is rejected (x unchanged)
+            if (best_k == 0 && k_used > 0 && variant != 0) {
+                // complex-linear P: the Arnoldi relation is exact, so the cycle's
+                // last iterate (least preconditioned residual) is kept regardless
+                best_k = k_used;
+                best_rel = rel_last;
+            }
+            if (best_k > 0 && best_k == k_used) {
+                TDP_CHECK_HIP(hipMemcpyAsync(U, op->xv, 16 * N, hipMemcpyDeviceToDevice, s));
+            } else if (best_k > 0) {
+                std::copy(ybest.begin(), ybest.begin() + best_k, y.begin());
+                TDP_CHECK(update(U, U, best_k));
+            }
+            rel = best_rel;
+            if (best_k == 0 && k_used > 0) {      // Table 1 cycle rejected:
+                variant = 1;                      // continue with Definition 4
+                switched = 1;
+            }
         } else if (k_used > 0) {
             solve_y(k_used);
             TDP_CHECK(update(U, U, k_used));
@@ -901,6 +929,7 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
         info->relres_prec = est;
         info->steps = napply * (int64_t)T * op->nP;
         info->history_len = nhist < info->history_cap ? nhist : info->history_cap;
+        info->switched = switched;
         info->ms_total =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }

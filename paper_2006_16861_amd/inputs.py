@@ -247,3 +247,42 @@ def random_medium(n, seed: int, cmin: float = 1.0, cmax: float = 2.0,
     F = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
     return Problem("random", shape, h, omega, c, R, F, periods_for(shape, ppw), ppw, width,
                    {"seed": seed})
+
+
+def _model2d(name, model: int, width: int, ppw: float, c_of_xy, src_xy) -> Problem:
+    """A model on the unit square sampled at h = 1/(model+1), with damping
+    layers of `width` nodes added outside it (as in Sec. 4.1), so the grid has
+    model + 2 width nodes per axis.  c_of_xy(x, y) gives the speed at model
+    coordinates (nodes in the layers take the speed of the nearest model node);
+    the point source sits at model coordinates src_xy."""
+    n = model + 2 * width
+    shape = (n, n)
+    h = 1.0 / (model + 1)
+    idx = np.clip(np.arange(n) - width, 0, model - 1)
+    xs = (idx + 1) * h
+    X, Y = np.meshgrid(xs, xs, indexing="ij")
+    c = np.ascontiguousarray(c_of_xy(X, Y), dtype=np.float64)
+    omega = omega_for_ppw(float(c.min()), h, ppw)
+    R = damping_profile(shape, width, 2.0 * omega)
+    src = tuple(width + int(round(v / h)) - 1 for v in src_xy)
+    F = point_source(shape, src)
+    return Problem(name, shape, h, omega, c, R, F, periods_for((model, model), ppw), ppw,
+                   width, {"model": model, "src": src})
+
+
+def open2d(model: int = 320, width: int = 32, ppw: float = 6.0) -> Problem:
+    """Constant speed c = 1 on the unit square (the constant model of Sec. 4.1),
+    point source at (0.5, 0.25)."""
+    return _model2d("open2d", model, width, ppw, lambda X, Y: np.ones_like(X), (0.5, 0.25))
+
+
+def disc2d(model: int = 320, width: int = 32, ppw: float = 6.0, c_out: float = 1.0,
+           c_in: float = 0.5, radius: float = 0.2) -> Problem:
+    """Piecewise constant model with a slow disc (speed c_in inside radius
+    `radius` around (0.5, 0.5), c_out outside): waves are trapped in the disc, a
+    resonant stand-in for Sec. 4.1's circular model.  Source at (0.5, 0.2),
+    outside the disc."""
+    def c_of(X, Y):
+        inside = (X - 0.5) ** 2 + (Y - 0.5) ** 2 < radius ** 2
+        return np.where(inside, c_in, c_out)
+    return _model2d("disc2d", model, width, ppw, c_of, (0.5, 0.2))

@@ -69,7 +69,7 @@ class GmresInfo(ctypes.Structure):
                 ("relres_true", ctypes.c_double), ("relres_prec", ctypes.c_double),
                 ("steps", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int),
-                ("history_len", ctypes.c_int)]
+                ("history_len", ctypes.c_int), ("switched", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
@@ -151,6 +151,7 @@ class SolveInfo:
     steps: int
     ms_total: float
     history: list
+    switched: int = 0      # 1: a rejected cycle moved the solve to the complex-linear variant
 
 
 class Operator:
@@ -242,7 +243,8 @@ class Operator:
                                            self._cplx(U, "U"), ctypes.byref(info)),
                     "tdp_gmres_solve")
         return U, SolveInfo(rc, info.iters, info.restarts, info.relres_true, info.relres_prec,
-                            info.steps, info.ms_total, list(hist[: info.history_len]))
+                            info.steps, info.ms_total, list(hist[: info.history_len]),
+                            info.switched)
 
     def grad_m(self, lam, U, out=None):
         import torch

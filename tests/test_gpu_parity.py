@@ -459,3 +459,21 @@ def test_fd2_solve_matches_lu_of_the_written_matrix():
                     A[b, idx[i + di, j + dj]] = -1 / h ** 2
     U = spla.spsolve(A.tocsc(), F.reshape(-1)).reshape(n)
     assert rel(host(Ug), U) <= 1e-6
+
+
+@pytest.mark.parametrize("model,T", [(64, 5), (96, 5), (64, 10)])
+def test_gmres_short_T_matches_oracle(model, T):
+    """Short T: cycles of the real-linear Table 1 map that would raise the true
+    residual are rejected and the solve continues with Definition 4; the GPU
+    takes the same decisions as the oracle and converges."""
+    from paper_2006_16861_amd import tdp
+    p = inputs.disc2d(model, width=16)
+    note(f"gmres short T disc2d-{model} T={T}")
+    g, o = make_ops(p)
+    Ug, ig = g.solve(dev(p.F), T=T, tol=1e-6, max_iters=600)
+    Uo, io = o.gmres(p.F, T=T, tol=1e-6, max_iters=600)
+    assert ig.status == io["status"] == 0
+    assert ig.switched == io["switched"] == (1 if T == 5 else 0)
+    assert rel(o.apply_H(host(Ug)), p.F) <= 1e-6 * (1 + 1e-9)
+    if ig.iters == io["iters"]:
+        assert rel(host(Ug), Uo) <= 1e-8

@@ -1,0 +1,73 @@
+"""Sec. 4.1's convergence findings, reproduced on the constant model and the
+resonant disc model (160^2 model + 32-node damping layers, 6 points per
+wavelength, so 8 steps per period), against sparse LU of the independently
+assembled H:
+  * S_T F -> H^-1 F as T grows (taper rho = 0.25);
+  * without a taper (the forcing ramps up over one period) the convergence
+    stalls far above the tapered one;
+  * in the resonant model the direct application converges poorly;
+  * there GMRES reaches a small error at a total cost (periods) for which the
+    direct application is still far off."""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle
+from paper_2006_16861_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+MODEL = 160
+
+
+def note(msg):
+    print(f"[case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def cases():
+    import torch
+    from paper_2006_16861_amd import tdp
+    out = {}
+    for mk in (inputs.open2d, inputs.disc2d):
+        p = mk(MODEL)
+        H = oracle.assemble_H(p.n, p.h, p.omega, p.c, p.R)
+        Uref = spla.splu(H.tocsc()).solve(p.F.reshape(-1)).reshape(p.n)
+        op = tdp.operator_from_problem(p)
+        assert op.nP == 8
+        F = torch.as_tensor(p.F, device="cuda")
+
+        def err(U, Uref=Uref):
+            u = U.detach().cpu().numpy()
+            return float(np.linalg.norm(u - Uref) / np.linalg.norm(Uref))
+        out[p.name] = (p, op, F, err)
+    return out
+
+
+def test_large_time_convergence_and_taper(cases):
+    p, op, F, err = cases["open2d"]
+    Ts = (10, 20, 40, 80, 160, 320)
+    e25 = [err(op.precond(F, T, 0.25)) for T in Ts]
+    e0 = err(op.precond(F, 320, 0.0))
+    note(f"open2d rho=0.25: {['%.1e' % e for e in e25]}; rho=0 (one-period ramp) T=320: {e0:.1e}")
+    assert all(b < a for a, b in zip(e25, e25[1:]))
+    assert e25[-1] < 1e-6
+    assert e0 > 100 * e25[-1]
+    _, opd, Fd, errd = cases["disc2d"]
+    ed = errd(opd.precond(Fd, 320, 0.25))
+    note(f"disc2d rho=0.25 T=320: {ed:.1e}")
+    assert ed > 1e-2 and ed > 1e4 * e25[-1]
+
+
+def test_gmres_beats_direct_application_in_resonant_model(cases):
+    p, op, F, err = cases["disc2d"]
+    U, info = op.solve(F, T=20, rho=0.25, tol=1e-6, max_iters=3000)
+    periods = info.steps // op.nP
+    eg = err(U)
+    ed = err(op.precond(F, periods, 0.25))
+    note(f"disc2d GMRES T=20: {info.iters} its, {periods} periods, error {eg:.1e}; "
+         f"direct T={periods}: {ed:.1e}")
+    assert info.status == 0 and eg < 1e-4
+    assert ed > 100 * eg

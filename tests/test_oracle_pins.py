@@ -496,3 +496,21 @@ def test_fd2_step_is_the_written_time_domain_scheme(ndim):
            + o.beta / (2 * o.dt) * (omega * R / o.omega_c) * (up - um)
            + (lap @ u.reshape(-1)).reshape(n) + (o.omega_c ** 2 - k2) * u)
     assert np.abs(lhs - f).max() <= 1e-9 * np.abs(f).max()
+
+
+# ---------------------------------------------------------------- GMRES with a short T
+def test_gmres_short_T_rejects_cycles_and_switches_variant():
+    """With T = 5 periods per application Table 1's real-linearity defect is
+    large: accepting a cycle's complex least-squares update would raise the true
+    residual (restarts then compound it).  The solve rejects such a cycle, goes
+    on with the complex-linear Definition 4 map and converges; the residual is
+    checked with the independently assembled H.  A long T never switches."""
+    p = inputs.disc2d(64, width=16)
+    o = oracle.Op.from_problem(p)
+    U, info = o.gmres(p.F, T=5, tol=1e-6, max_iters=600)
+    assert info["status"] == 0 and info["switched"] == 1
+    H = oracle.assemble_H(p.n, p.h, p.omega, p.c, p.R)
+    r = p.F.reshape(-1) - H @ U.reshape(-1)
+    assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(p.F) * (1 + 1e-9)
+    U2, info2 = o.gmres(p.F, T=10, tol=1e-6, max_iters=600)
+    assert info2["status"] == 0 and info2["switched"] == 0
