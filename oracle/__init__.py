@@ -62,13 +62,14 @@ def lib():
         P = ctypes.c_void_p
         D = ctypes.c_double
         I = ctypes.c_int
-        L.tdpo_op_create.argtypes = [I, P, D, D, P, P, P, P, I, ctypes.POINTER(P)]
+        L.tdpo_op_create.argtypes = [I, P, D, D, P, P, P, P, I, I, ctypes.POINTER(P)]
         L.tdpo_op_destroy.argtypes = [P]
         L.tdpo_op_query.argtypes = [P, P, P]
         L.tdpo_cell_slowness.argtypes = [P, P]
         L.tdpo_apply_reH.argtypes = [P, P, P]
         L.tdpo_apply_H.argtypes = [P, P, P]
         L.tdpo_apply_K.argtypes = [P, P, P]
+        L.tdpo_apply_L.argtypes = [P, P, P]
         L.tdpo_damping.argtypes = [P, P]
         L.tdpo_step.argtypes = [P, P, P, P, P]
         L.tdpo_window.argtypes = [D, D]
@@ -94,7 +95,8 @@ class OracleError(RuntimeError):
 class Op:
     """Oracle operator for H built from c, R, omega, h on an interior grid n."""
 
-    def __init__(self, n, h, omega, c, R=None, stiff=None, mass=None, nP=0):
+    def __init__(self, n, h, omega, c, R=None, stiff=None, mass=None, nP=0,
+                 damping="diagonal"):
         L = lib()
         self.n = tuple(int(v) for v in n)
         self.ndim = len(self.n)
@@ -107,10 +109,14 @@ class Op:
         self._R = None if R is None else np.ascontiguousarray(R, dtype=np.float64).reshape(-1)
         nn = np.array(self.n, dtype=np.int64)
         self._nn = nn
+        if damping not in ("diagonal", "cell"):
+            raise ValueError("damping must be 'diagonal' or 'cell'")
+        self.damping_form = damping
         h_ = ctypes.c_void_p()
         rc = L.tdpo_op_create(self.ndim, _ptr(nn), self.h, self.omega, _ptr(self._c),
                               None if self._R is None else _ptr(self._R), _ptr(self.stiff),
-                              _ptr(self.mass), int(nP), ctypes.byref(h_))
+                              _ptr(self.mass), int(nP), 0 if damping == "diagonal" else 1,
+                              ctypes.byref(h_))
         if rc != OK:
             raise OracleError(rc, "tdpo_op_create")
         self._h = h_
@@ -151,6 +157,12 @@ class Op:
         x = np.ascontiguousarray(x, dtype=np.float64).reshape(self.n)
         y = np.empty_like(x)
         lib().tdpo_apply_K(self._h, _ptr(x), _ptr(y))
+        return y
+
+    def apply_L(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(self.n)
+        y = np.empty_like(x)
+        lib().tdpo_apply_L(self._h, _ptr(x), _ptr(y))
         return y
 
     def damping(self):
@@ -208,12 +220,13 @@ def window(s, rho):
     return lib().tdpo_window(float(s), float(rho))
 
 
-def assemble_H(n, h, omega, c, R=None, stiff=None, mass=None):
+def assemble_H(n, h, omega, c, R=None, stiff=None, mass=None, damping="diagonal"):
     """Independent sparse assembly of H (scipy CSR), element by element.
 
     Each cell (lower corner alpha, alpha_a in -1..n_a-1) adds the (2^d x 2^d)
     element matrix h^-2 S[Delta] - omega^2 m_cell M[Delta] over its interior
-    corners (App. A); Im H = diag(omega R)."""
+    corners (App. A); Im H = diag(omega R), or with damping="cell" the element
+    matrices i omega r_cell M[Delta], r_cell the corner mean of R (Sec. 5)."""
     import itertools
     import scipy.sparse as sp
     n = tuple(int(v) for v in n)
@@ -231,6 +244,12 @@ def assemble_H(n, h, omega, c, R=None, stiff=None, mass=None):
         sl = tuple(slice(e[a], e[a] + n[a] + 1) for a in range(d))
         m += padded[sl]
     m /= len(corners)
+    r = np.zeros_like(m)
+    if damping == "cell" and R is not None:
+        padr = np.pad(np.asarray(R, dtype=np.float64).reshape(n), 1, mode="edge")
+        for e in corners:
+            r += padr[tuple(slice(e[a], e[a] + n[a] + 1) for a in range(d))]
+        r /= len(corners)
     N = int(np.prod(n))
     idx = np.arange(N).reshape(n)
     pidx = np.pad(idx, 1, mode="constant", constant_values=-1)
@@ -238,7 +257,7 @@ def assemble_H(n, h, omega, c, R=None, stiff=None, mass=None):
     for eb in corners:
         for eg in corners:
             s = sum(int(eb[a] != eg[a]) for a in range(d))
-            coef = S[s] / h ** 2 - omega ** 2 * m * M[s]
+            coef = S[s] / h ** 2 - omega ** 2 * m * M[s] + 1j * omega * r * M[s]
             bi = pidx[tuple(slice(eb[a], eb[a] + n[a] + 1) for a in range(d))]
             gi = pidx[tuple(slice(eg[a], eg[a] + n[a] + 1) for a in range(d))]
             ok = (bi >= 0) & (gi >= 0)
@@ -249,6 +268,6 @@ def assemble_H(n, h, omega, c, R=None, stiff=None, mass=None):
     cols = np.concatenate(cols)
     vals = np.concatenate(vals).astype(np.complex128)
     H = sp.coo_matrix((vals, (rows, cols)), shape=(N, N)).tocsr()
-    if R is not None:
+    if R is not None and damping == "diagonal":
         H = H + sp.diags(1j * omega * np.asarray(R, dtype=np.float64).reshape(-1))
     return H.tocsr()

@@ -52,7 +52,10 @@ struct tdpo_op {
     double h, omega;
     double S[4], M[4];
     double *mcell;  /* [Nc] cell slowness */
-    double *R;      /* [N]  node damping (Im H = omega R) */
+    double *R;      /* [N]  node damping (Im H = omega R when dform = 0) */
+    int dform;      /* 0: diagonal Im H (I_acd); 1: cell damping Im H = omega sum r_a M (I_abd) */
+    double *rcell;  /* [Nc] cell damping (dform 1) */
+    double lam_im;  /* upper bound of lambda_max(Im H) (dform 1) */
     double omega_c, lam_bar, dt, alpha, beta;
     int nP;
 };
@@ -142,13 +145,32 @@ static double stiffness_symbol(const tdpo_op *op, const double *theta)
     return s;
 }
 
+/* Sec. 5.1's stability condition 4I - K - 2L > 0 for I_abd with
+ * theta = omega dt, using the bounds lam_s >= lambda_max(Re H) (stiffness part)
+ * and lam_im >= lambda_max(Im H):
+ *   (theta^2/alpha)(lam_s/omega^2 + 1) + (theta beta/alpha)(1 + cos theta) lam_im/omega^2 < 4,
+ * with omega^2 = kmax2 + (beta/theta)(1 - cos theta) lam_im (K >= 0).  The printed
+ * full inequality drops the factor theta of its second term; it follows from K
+ * and L of Def. 6 as written, and the section's stronger inequality keeps it. */
+static int abd_stable(double theta, double kmax2, double lam_s, double lam_im, double *w2out)
+{
+    double sh = sin(theta / 2.0);
+    double alpha = theta * theta / (4.0 * sh * sh), beta = theta / sin(theta);
+    double w2 = kmax2 + beta / theta * (1.0 - cos(theta)) * lam_im;
+    double lhs = theta * theta / alpha * (lam_s / w2 + 1.0) +
+                 theta * beta / alpha * (1.0 + cos(theta)) * lam_im / w2;
+    if (w2out) *w2out = w2;
+    return lhs < 4.0;
+}
+
 int tdpo_op_create(int ndim, const long *n, double h, double omega,
                    const double *c, const double *R,
-                   const double *stiff, const double *mass, int nP,
+                   const double *stiff, const double *mass, int nP, int dform,
                    tdpo_op **out)
 {
     *out = NULL;
     if (ndim != 2 && ndim != 3) return TDPO_EINVAL;
+    if (dform != 0 && dform != 1) return TDPO_EINVAL;
     if (!(h > 0.0) || !(omega > 0.0) || !c || !stiff || !mass) return TDPO_EINVAL;
     tdpo_op *op = calloc(1, sizeof(*op));
     if (!op) return TDPO_ENOMEM;
@@ -196,6 +218,28 @@ int tdpo_op_create(int ndim, const long *n, double h, double omega,
 
     /* Sec. 2.2: omega_c = sqrt(-lambda_min(Re H)) bounded by k_max (App. A) */
     op->omega_c = omega * sqrt(mmax);
+    op->dform = dform;
+    if (dform == 1) {
+        /* cell damping: mean of R over the cell's corners (clamped, as for m);
+         * Im H = omega sum_a r_a M_a has lambda_max <= omega max r (App. A bound
+         * of the assembled mass, lambda_max <= 1) */
+        op->rcell = malloc(sizeof(double) * op->Nc);
+        if (!op->rcell) { tdpo_op_destroy(op); return TDPO_ENOMEM; }
+        double rmax = 0.0;
+        for (long q = 0; q < op->Nc; ++q) {
+            long alpha[3], corner[3], e[3];
+            cell_coords(op, q, alpha);
+            double s = 0.0;
+            for (int k = 0; k < ncorner; ++k) {
+                corner_offset(ndim, k, e);
+                for (int a = 0; a < ndim; ++a) corner[a] = alpha[a] + e[a];
+                s += op->R[clamp_node(op, corner)];
+            }
+            op->rcell[q] = s / ncorner;
+            if (op->rcell[q] > rmax) rmax = op->rcell[q];
+        }
+        op->lam_im = omega * rmax;
+    }
 
     /* sup of the stiffness symbol sampled on a uniform grid of [0, pi]^d */
     const int G = ndim == 2 ? 201 : 101;   /* both include 0 and pi */
@@ -208,6 +252,33 @@ int tdpo_op_create(int ndim, const long *n, double h, double omega,
         for (int a = 0; a < ndim; ++a) { th[a] = M_PI * (double)(t % G) / (G - 1); t /= G; }
         double s = stiffness_symbol(op, th);
         if (s > smax) smax = s;
+    }
+    if (dform == 1) {
+        /* Sec. 5.1: n_P = 2 pi / theta, the smallest multiple of 4 for which the
+         * stability condition holds; omega from the K >= 0 condition */
+        double kmax2 = op->omega_c * op->omega_c, lam_s = smax / (h * h), w2 = 0.0;
+        if (nP == 0) {
+            for (nP = 4; nP <= (1 << 22); nP += 4)
+                if (abd_stable(2.0 * M_PI / nP, kmax2, lam_s, op->lam_im, NULL)) break;
+            if (nP > (1 << 22)) { tdpo_op_destroy(op); return TDPO_ECFL; }
+        } else if (nP < 0) {
+            nP = -nP;
+            if (nP % 4) { tdpo_op_destroy(op); return TDPO_EINVAL; }
+        } else if (nP % 4 != 0 || !abd_stable(2.0 * M_PI / nP, kmax2, lam_s, op->lam_im, NULL)) {
+            tdpo_op_destroy(op);
+            return TDPO_ECFL;
+        }
+        double theta = 2.0 * M_PI / nP;
+        abd_stable(theta, kmax2, lam_s, op->lam_im, &w2);
+        op->nP = nP;
+        op->omega_c = sqrt(w2);
+        op->dt = theta / op->omega_c;
+        double sh = sin(theta / 2.0);
+        op->alpha = theta * theta / (4.0 * sh * sh);
+        op->beta = theta / sin(theta);
+        op->lam_bar = lam_s + w2;
+        *out = op;
+        return TDPO_OK;
     }
     op->lam_bar = smax / (h * h) + op->omega_c * op->omega_c;
 
@@ -240,6 +311,7 @@ void tdpo_op_destroy(tdpo_op *op)
     if (!op) return;
     free(op->mcell);
     free(op->R);
+    free(op->rcell);
     free(op);
 }
 
@@ -287,6 +359,31 @@ static double reH_row(const tdpo_op *op, const double *x, long b)
     return y;
 }
 
+/* (Im H x)_b for the cell damping (dform 1): omega sum over cells a containing
+ * b, over corners g of a, of r_a M_{Delta(b,g)} x_g (Sec. 5: non-diagonal B);
+ * omega R_b x_b for the diagonal damping. */
+static double imH_row(const tdpo_op *op, const double *x, long b)
+{
+    if (op->dform == 0) return op->omega * op->R[b] * x[b];
+    long ib[3], alpha[3], e[3], g[3];
+    node_coords(op, b, ib);
+    int d = op->d, nk = 1 << d;
+    double y = 0.0;
+    for (int kb = 0; kb < nk; ++kb) {
+        corner_offset(d, kb, e);
+        for (int a = 0; a < d; ++a) alpha[a] = ib[a] - e[a];
+        double rc = op->rcell[cell_index(op, alpha)];
+        for (int kg = 0; kg < nk; ++kg) {
+            corner_offset(d, kg, e);
+            for (int a = 0; a < d; ++a) g[a] = alpha[a] + e[a];
+            long gi = node_index(op, g);
+            if (gi < 0) continue;
+            y += rc * op->M[delta_class(d, kb, kg)] * x[gi];
+        }
+    }
+    return op->omega * y;
+}
+
 void tdpo_apply_reH(const tdpo_op *op, const double *x, double *y)
 {
 #pragma omp parallel for schedule(static)
@@ -300,19 +397,34 @@ void tdpo_apply_H(const tdpo_op *op, const double complex *x, double complex *y)
     for (long b = 0; b < op->N; ++b) { xr[b] = creal(x[b]); xi[b] = cimag(x[b]); }
 #pragma omp parallel for schedule(static)
     for (long b = 0; b < op->N; ++b) {
-        double yr = reH_row(op, xr, b), yi = reH_row(op, xi, b);
-        y[b] = (yr + I * yi) + I * op->omega * op->R[b] * x[b];
+        double yr = reH_row(op, xr, b) - imH_row(op, xi, b);
+        double yi = reH_row(op, xi, b) + imH_row(op, xr, b);
+        y[b] = yr + I * yi;
     }
     free(xr);
     free(xi);
 }
 
-/* K x = (dt^2/alpha) (Re H + omega_c^2 I) x            (Def. 2, A = Re H + omega^2) */
+/* K x = (dt^2/alpha) A x, A = Re H + omega_c^2 I                 (Def. 2)
+ * dform 1: K x = (dt^2/alpha) A x - (dt beta (1 - cos(omega dt))/alpha) B x,
+ *          B = Im H / omega                                      (Def. 6) */
 void tdpo_apply_K(const tdpo_op *op, const double *x, double *y)
 {
     double s = op->dt * op->dt / op->alpha, wc2 = op->omega_c * op->omega_c;
+    double kb = op->dt * op->beta * (1.0 - cos(op->omega_c * op->dt)) / op->alpha / op->omega_c;
 #pragma omp parallel for schedule(static)
-    for (long b = 0; b < op->N; ++b) y[b] = s * (reH_row(op, x, b) + wc2 * x[b]);
+    for (long b = 0; b < op->N; ++b) {
+        y[b] = s * (reH_row(op, x, b) + wc2 * x[b]);
+        if (op->dform == 1) y[b] -= kb * imH_row(op, x, b);
+    }
+}
+
+/* L x = (beta dt/alpha) B x, B = Im H / omega_c           (Defs. 2 and 6) */
+void tdpo_apply_L(const tdpo_op *op, const double *x, double *y)
+{
+    double lb = op->beta * op->dt / op->alpha / op->omega_c;
+#pragma omp parallel for schedule(static)
+    for (long b = 0; b < op->N; ++b) y[b] = lb * imH_row(op, x, b);
 }
 
 /* diagonal of L = (beta dt/alpha) B, B = omega_c^-1 Im H = omega R / omega_c */
@@ -328,6 +440,19 @@ void tdpo_step(const tdpo_op *op, const double *u, const double *um, const doubl
                double *up)
 {
     double s = op->dt * op->dt / op->alpha, wc2 = op->omega_c * op->omega_c;
+    if (op->dform == 1) {
+        /* I_abd (Def. 6): u+ = (2 - K - L) u - (I - L) u- + g */
+        double kb = op->dt * op->beta * (1.0 - cos(op->omega_c * op->dt)) / op->alpha / op->omega_c;
+        double lb = op->beta * op->dt / op->alpha / op->omega_c;
+#pragma omp parallel for schedule(static)
+        for (long b = 0; b < op->N; ++b) {
+            double iu = imH_row(op, u, b);
+            double Ku = s * (reH_row(op, u, b) + wc2 * u[b]) - kb * iu;
+            double Lu = lb * iu, Lum = lb * imH_row(op, um, b);
+            up[b] = 2.0 * u[b] - Ku - Lu - (um[b] - Lum) + s * (f ? f[b] : 0.0);
+        }
+        return;
+    }
     double ls = op->beta * op->dt / op->alpha;
 #pragma omp parallel for schedule(static)
     for (long b = 0; b < op->N; ++b) {
@@ -353,7 +478,7 @@ double tdpo_window(double s, double rho)
 int tdpo_precond_apply(const tdpo_op *op, int T, double rho, const double complex *F,
                        double complex *U)
 {
-    if (T < 1) return TDPO_EINVAL;
+    if (T < 1 || op->dform != 0) return TDPO_EINVAL;   /* Table 1 runs I_acd */
     if (rho <= 0.0) rho = 1.0 / T;
     if (rho > 1.0) return TDPO_EINVAL;
     long N = op->N;
@@ -383,7 +508,8 @@ int tdpo_precond_apply(const tdpo_op *op, int T, double rho, const double comple
  * complex forcing f_n = chi(1 - n dt/T~) e^{i omega n dt} F, T~ = 2 pi T/omega,
  * from zero fields; S_T F = e^{-i 2 pi T} u_{N_s} = u_{N_s} for integer T.
  * The recurrence is real, so the real and imaginary parts of u are two real
- * recurrences driven by the real and imaginary parts of f_n. */
+ * recurrences driven by the real and imaginary parts of f_n.  With the cell
+ * damping the integrator is I_abd and this is S_T^abd of Def. 7. */
 int tdpo_precond_apply_complex(const tdpo_op *op, int T, double rho, const double complex *F,
                                double complex *U)
 {
@@ -415,10 +541,11 @@ int tdpo_precond_apply_complex(const tdpo_op *op, int T, double rho, const doubl
     return TDPO_OK;
 }
 
+/* with the cell damping (dform 1) S_T is S_T^abd (Def. 7), complex-linear */
 static int precond_variant(const tdpo_op *op, int variant, int T, double rho,
                            const double complex *F, double complex *U)
 {
-    return variant ? tdpo_precond_apply_complex(op, T, rho, F, U)
+    return (variant || op->dform == 1) ? tdpo_precond_apply_complex(op, T, rho, F, U)
                    : tdpo_precond_apply(op, T, rho, F, U);
 }
 
@@ -455,6 +582,7 @@ int tdpo_gmres_solve(const tdpo_op *op, int restart, int max_iters, int T, doubl
     if (m < 1 || T < 1 || max_iters < 1 || !(tol > 0.0)) return TDPO_EINVAL;
     int tolmode = fixed_iters <= 0;
     int limit = tolmode ? max_iters : fixed_iters;
+    if (op->dform == 1) variant = 1;   /* S_T^abd is complex-linear (Def. 7) */
     double complex *V = malloc(sizeof(double complex) * N * (m + 1));
     double complex *w = malloc(sizeof(double complex) * N);
     double complex *r = malloc(sizeof(double complex) * N);

@@ -18,10 +18,13 @@ enum { TDPO_OK = 0, TDPO_ENOTCONV = 1, TDPO_EINVAL = -1, TDPO_ENOMEM = -2, TDPO_
 typedef struct tdpo_op tdpo_op;
 
 /* nP == 0: automatic; nP > 0: checked against the CFL bound; nP < 0: test
- * hook, |nP| used without the CFL check (to exhibit instability). */
+ * hook, |nP| used without the CFL check (to exhibit instability).
+ * dform 0: Im H = diag(omega R), integrator I_acd (Def. 2);
+ * dform 1: Im H = omega sum_cells r_cell M_cell (r_cell = corner mean of R),
+ *          integrator I_abd (Sec. 5, Def. 6), S_T^abd (Def. 7). */
 int tdpo_op_create(int ndim, const long *n, double h, double omega, const double *c,
                    const double *R, const double *stiff, const double *mass, int nP,
-                   tdpo_op **out);
+                   int dform, tdpo_op **out);
 void tdpo_op_destroy(tdpo_op *op);
 /* vals = {omega_c, dt, alpha, beta, lam_bar} */
 void tdpo_op_query(const tdpo_op *op, double *vals, int *nP);
@@ -29,6 +32,7 @@ void tdpo_cell_slowness(const tdpo_op *op, double *m);
 void tdpo_apply_reH(const tdpo_op *op, const double *x, double *y);
 void tdpo_apply_H(const tdpo_op *op, const double complex *x, double complex *y);
 void tdpo_apply_K(const tdpo_op *op, const double *x, double *y);
+void tdpo_apply_L(const tdpo_op *op, const double *x, double *y);
 void tdpo_damping(const tdpo_op *op, double *l);
 void tdpo_step(const tdpo_op *op, const double *u, const double *um, const double *f,
                double *up);
