@@ -32,7 +32,7 @@ WORDS_PER_NODE_STEP = 7          # u_j, u_{j-1}, u_{j+1}, m, damping, Re F, Im F
 FLOPS_PER_NODE_STEP = 39
 
 
-def measured_traffic(workload, prec, variant, tun):
+def measured_traffic(workload, prec, variant, tun, damping="node"):
     """HBM bytes per launch of the dominant kernel, from the rocprofv3
     FETCH_SIZE / WRITE_SIZE runs recorded in profiles/traffic.json (scaled by
     the copy-kernel calibration); None when that kernel configuration was not
@@ -41,6 +41,8 @@ def measured_traffic(workload, prec, variant, tun):
     if not os.path.exists(path):
         return None
     key = f"{workload}|{prec}|v{variant}|k{tun['kernel']}|d{tun['tb_depth']}|t{tun['tile']}"
+    if damping != "node":
+        key += f"|{damping}"
     rec = json.load(open(path)).get(key)
     return None if rec is None else rec["bytes_per_launch"]
 
@@ -226,6 +228,29 @@ def form_batched(rho):
     return res
 
 
+def form_cell_damping(rho):
+    """Sec. 5 path on the headline workload: smooth2d-1024 with the cell
+    (non-diagonal) damping Im H = omega sum_cells r_cell M_cell, preconditioned
+    by S_T^abd (I_abd), FP64, to a true relative residual of 1e-6.  The sweep
+    moves 10 words per node-step (u_n, u_{n-1} and F complex, the two cell
+    arrays, u_{n+1} complex)."""
+    import torch
+    from paper_2006_16861_amd import inputs, tdp
+    p = inputs.smooth2d(1024)
+    op = tdp.operator_from_problem(p, damping="cell")
+    F = torch.as_tensor(p.F, device="cuda")
+    op.solve(F, T=p.periods, rho=rho, tol=1e-6)                     # warm (graph)
+    (U, info), dt = _timed(lambda: op.solve(F, T=p.periods, rho=rho, tol=1e-6))
+    r = float(torch.linalg.norm(F - op.apply_H(U)) / torch.linalg.norm(F))
+    _, step_ms = sweep_timing(op, F, p.periods, rho, 1, torch.cuda.current_stream(), variant=1)
+    us = step_ms * 1e3
+    log(f"form cell damping: {dt:.3f} s, iters {info.iters}, relres {r:.2e}, {us:.2f} us/step")
+    return {"workload": "smooth2d-1024, cell damping (Sec. 5, I_abd)", "n_P": op.nP,
+            "omega_c": op.omega_c, "solves_per_s": 1.0 / dt, "seconds": dt, "iters": info.iters,
+            "precond_applications": info.steps // (p.periods * op.nP), "true_relres": r,
+            "sweep_us_per_step": us, "sweep_algorithmic_GBps": 10 * 8 * p.N / (us * 1e-6) / 1e9}
+
+
 def form_adjoint(rho):
     """Differentiation form: 128^3 smooth medium in [1.5, 3.0], 4 sources, 256
     receivers on the top face, misfit 1/2 ||P_r U(m) - d||^2; one gradient
@@ -317,6 +342,8 @@ def main():
     ap.add_argument("--rho", type=float, default=0.25)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--damping", choices=["node", "cell"], default="node",
+                    help="cell: the non-diagonal damping of Sec. 5 (I_abd; needs --variant 1)")
     ap.add_argument("--variant", type=int, default=0,
                     help="0: Table 1 real-field preconditioner, 1: Definition 4 complex field")
     ap.add_argument("--kernel", type=int, default=0)
@@ -341,6 +368,8 @@ def main():
     if args.study:
         study_convergence(args.study_model)
         return
+    if args.damping == "cell" and args.variant != 1:
+        raise SystemExit("--damping cell runs S_T^abd: pass --variant 1")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "slab decomposition is a design note, not built", file=sys.stderr)
@@ -357,7 +386,7 @@ def main():
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         t = time.perf_counter()
-        op = tdp.operator_from_problem(p, prec=prec)
+        op = tdp.operator_from_problem(p, prec=prec, damping=args.damping)
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t) * 1e3
         tune_table = []
@@ -427,14 +456,16 @@ def main():
     achieved = p.N * bytes_per * (Ns / launches) / (launch_us * 1e-6) / 1e9
     napply = infos[-1].steps // Ns
     tname = "double" if prec == tdp.F64 else "float"
-    if tun["kernel"] == 2:
+    if args.damping == "cell":
+        kname = "k_sweep_abd<double> (I_abd, one step per launch)"
+    elif tun["kernel"] == 2:
         kname = (f"k_sweep2d_{'tb2' if tun['tile'] >= 4 else 'tb'}<{tname}> "
                  f"depth={steps_per_launch} tile={tun['tile']}")
     elif tun["kernel"] == 3:
         kname = f"k_sweep3d_stream<{tname}> shape={tun['tile']} z-chunk={tun['tb_depth']}"
     else:
         kname = f"k_sweep<{tname}> (one step per launch)"
-    traffic = measured_traffic(args.workload, args.prec, args.variant, tun)
+    traffic = measured_traffic(args.workload, args.prec, args.variant, tun, args.damping)
     ceiling = stream_probe()
     log(f"stream probe: copy {ceiling['copy']:.0f} GB/s, triad {ceiling['triad']:.0f} GB/s")
     log(f"precond apply {apply_ms:.3f} ms, {step_ms * 1e3:.2f} us/step, {achieved:.1f} GB/s algorithmic")
@@ -473,7 +504,7 @@ def main():
         import numpy as np  # noqa: F811
         forms = {}
         for name, fn in (("precision", form_precision), ("batched", form_batched),
-                         ("adjoint", form_adjoint)):
+                         ("adjoint", form_adjoint), ("cell_damping", form_cell_damping)):
             log(f"form {name} ...")
             forms[name] = fn(args.rho)
         out["forms"] = forms

@@ -11,7 +11,9 @@
  * couples its corners b, g with h^-2 S[Delta] - omega^2 m_cell M[Delta],
  * Delta = number of axes on which b and g differ, m_cell the mean of 1/c^2
  * over the cell's corners (corners outside the box take the nearest interior
- * node).  Im H = diag(omega R).
+ * node).  Im H = diag(omega R), or with the cell damping of Sec. 5
+ * (tdp_op_desc.damping = TDP_DAMP_CELL) Im H = omega sum_cells r_cell M[Delta],
+ * r_cell the mean of R over the cell's corners.
  *
  * Conventions for every entry point:
  *  - Arrays are DEVICE pointers owned by the caller, contiguous, row-major
@@ -46,6 +48,12 @@ enum {
 
 typedef enum { TDP_F64 = 0, TDP_F32 = 1 } tdp_prec;
 
+/* Damping discretisation and the integrator it selects.
+ *  TDP_DAMP_NODE  Im H = diag(omega R): I_acd (Def. 2), Table 1 / Def. 4.
+ *  TDP_DAMP_CELL  Im H = omega sum_cells r_cell M[Delta], not diagonal: the
+ *                 explicit I_abd of Sec. 5 (Def. 6) and S_T^abd (Def. 7). */
+typedef enum { TDP_DAMP_NODE = 0, TDP_DAMP_CELL = 1 } tdp_damping;
+
 typedef struct tdp_op tdp_op;
 
 /* Operator description (Sec. 2.2: the preconditioner's parameters follow from
@@ -77,7 +85,14 @@ typedef struct tdp_op tdp_op;
  *                    NULL (the default stream) makes the op use a private
  *                    stream ordered after / before the default stream at
  *                    each call's entry / exit (the step loop is captured
- *                    into a graph, which the default stream cannot hold). */
+ *                    into a graph, which the default stream cannot hold).
+ *  damping           tdp_damping (0 = TDP_DAMP_NODE).  TDP_DAMP_CELL: omega_c,
+ *                    dt and n_P follow Sec. 5.1 (omega_c^2 = k_max^2 +
+ *                    (beta/theta)(1 - cos theta) lam_im, theta = omega_c dt =
+ *                    2 pi/n_P the largest for which 4I - K - 2L > 0 holds on
+ *                    the bounds); FP64 only; preconditioning is S_T^abd
+ *                    (tdp_precond_apply returns TDP_EINVAL, GMRES uses the
+ *                    complex-linear map whatever its variant); not batched. */
 typedef struct {
     int ndim;
     int64_t n[3];
@@ -90,17 +105,20 @@ typedef struct {
     int steps_per_period;
     int prec;
     void *stream;
+    int damping;
 } tdp_op_desc;
 
 /* Derived parameters (Sec. 2.2, Prop. 1): omega_c = omega sqrt(max m_cell)
  * (computational frequency), dt = 2 pi / (omega_c n_P),
  * alpha = (omega_c dt)^2 / (4 sin^2(omega_c dt / 2)),
- * beta = omega_c dt / sin(omega_c dt), lam_bar = upper bound on lambda_max(A). */
+ * beta = omega_c dt / sin(omega_c dt), lam_bar = upper bound on lambda_max(A),
+ * lam_im = upper bound on lambda_max(Im H) with the cell damping (else 0). */
 typedef struct {
     double omega_c, dt, alpha, beta, lam_bar;
     int n_P;
     int ndim;
     int64_t N;
+    double lam_im;
 } tdp_op_info;
 
 /* GMRES configuration (Sec. 2.4: left preconditioning P H U = P F with
@@ -163,6 +181,9 @@ int tdp_precond_apply(const tdp_op *op, int periods_T, double rho, const void *F
  * complex field driven by chi(1 - j/N_s) e^{i 2 pi j/n_P} F from zero fields,
  * U = e^{-i 2 pi T} u_{N_s} = u_{N_s}.  Complex-linear, unlike Table 1 whose
  * output is only real-linear; costs 10 instead of 7 words per node-step.
+ * With TDP_DAMP_CELL this is S_T^abd (Sec. 5, Def. 7): the same forcing
+ * driving I_abd (Def. 6), 10 words per node-step (u_{n-1} is read with its
+ * neighbours, so u_{n+1} goes to a third field).
  * F, U: device complex128 [N]. */
 int tdp_precond_apply_complex(const tdp_op *op, int periods_T, double rho, const void *F,
                               void *U);

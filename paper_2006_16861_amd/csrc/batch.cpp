@@ -25,8 +25,8 @@ typedef std::complex<double> cplx;
 // H-apply of field's operator on the batch stream (y = H x, or F - H x)
 static int apply_H_on(const tdp_op *op, const void *x, const void *F, void *y, hipStream_t s)
 {
-    TDP_CHECK_HIP(launch_apply_H(op->ndim, op->n, op->sc, op->mc, op->m, op->rw, op->st_H, x, F,
-                                 y, s));
+    TDP_CHECK_HIP(launch_apply_H(op->ndim, op->n, op->sc, op->mc, op->m, op->rw, nullptr, op->st_H,
+                                 op->st_I, x, F, y, s));
     return TDP_OK;
 }
 
@@ -98,6 +98,7 @@ extern "C" int tdp_batch_create(tdp_op *const *ops, int nops, const int *nrhs, t
         if (!op) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "NULL op %d", i); }
         if (op->ndim != 2) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "batched form is 2-D only (op %d)", i); }
         if (op->prec != ops[0]->prec) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "all ops must share one precision"); }
+        if (op->dform != TDP_DAMP_NODE) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "the batched form runs Table 1 (diagonal damping only)"); }
         if (op->user_stream != ops[0]->user_stream) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "all ops must share one stream"); }
         (void)hipStreamSynchronize(op->stream);
         const bool gen = !(op->sc <= 3 && op->mc <= 2);

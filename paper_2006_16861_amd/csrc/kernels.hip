@@ -251,11 +251,94 @@ hipError_t launch_sweep_c_f32(const SweepArgs &a, const Stencil<float> &st, floa
 }
 
 // ---------------------------------------------------------------------------
-// complex H-apply: y = H x or y = F - H x, H = stencil + i diag(rw)
+// frequency adapted backward-differences damped leapfrog I_abd (Sec. 5, Def. 6)
+// on the complex field of S_T^abd (Def. 7), for the cell damping
+// Im H = omega sum_cells r_cell M_cell:
+//   u_{n+1} = (2 - K - L) u_n - (I - L) u_{n-1} + g f_n
+//           = stA[u_n] + stB_r[u_{n-1} - cos(omega dt) u_n] - u_{n-1} + (fa + i fb) F,
+// stA the I_acd step stencil (2 - (dt^2/alpha) A) over the cell slowness, stB_r
+// the mass-class stencil of (beta dt/(alpha omega)) Im H over the cell damping.
+// u_{n-1} is read at the neighbours too, so u_{n+1} goes to a third field.
 template <int D, int SC, int MC>
+__global__ __launch_bounds__(256) void k_sweep_abd(const C2<double> *__restrict__ u,
+                                                   const C2<double> *__restrict__ um,
+                                                   C2<double> *__restrict__ uo,
+                                                   const double *__restrict__ m,
+                                                   const double *__restrict__ rc,
+                                                   const double2 *__restrict__ F, int nz,
+                                                   int ny, int nx, Stencil<double> stA,
+                                                   Stencil<double> stB, double cth, double fa,
+                                                   double fb, double2 *__restrict__ out)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= nx || y >= ny) return;
+    const int64_t i = ((int64_t)z * ny + y) * nx + x;
+    double wm[1 << D], wr[1 << D];
+    load_cells<D>(m, z, y, x, ny, nx, wm);
+    load_cells<D>(rc, z, y, x, ny, nx, wr);
+    auto inside = [&](int oz, int oy, int ox) -> bool {
+        return (unsigned)(y + oy) < (unsigned)ny && (unsigned)(x + ox) < (unsigned)nx &&
+               (D == 2 || (unsigned)(z + oz) < (unsigned)nz);
+    };
+    auto U = [&](int oz, int oy, int ox) -> C2<double> {
+        return inside(oz, oy, ox) ? u[i + ((int64_t)oz * ny + oy) * nx + ox] : C2<double>{0.0, 0.0};
+    };
+    auto W = [&](int oz, int oy, int ox) -> C2<double> {
+        if (!inside(oz, oy, ox)) return C2<double>{0.0, 0.0};
+        const int64_t j = i + ((int64_t)oz * ny + oy) * nx + ox;
+        const C2<double> a = um[j], b = u[j];
+        return C2<double>{a.x - cth * b.x, a.y - cth * b.y};
+    };
+    const C2<double> acc = eval_stencil<D, SC, MC>(U, wm, stA);
+    const C2<double> dmp = eval_stencil<D, 1, MC>(W, wr, stB);
+    const double2 f = F[i];
+    const C2<double> p = um[i];
+    C2<double> r;
+    r.x = acc.x + dmp.x - p.x + fa * f.x - fb * f.y;
+    r.y = acc.y + dmp.y - p.y + fa * f.y + fb * f.x;
+    uo[i] = r;
+    if (out) out[i] = make_double2(r.x, r.y);
+}
+
+hipError_t launch_sweep_abd(const SweepArgs &a, void *uout, const double *rc,
+                            const Stencil<double> &stA, const Stencil<double> &stB, double cth,
+                            double fa, double fb, hipStream_t s)
+{
+    const int nz = a.ndim == 3 ? a.n[0] : 1;
+    const int ny = a.ndim == 3 ? a.n[1] : a.n[0];
+    const int nx = a.ndim == 3 ? a.n[2] : a.n[1];
+    dim3 blk(64, 4, 1);
+    dim3 grd((nx + 63) / 64, (ny + 3) / 4, nz);
+    const C2<double> *u = (const C2<double> *)a.u;
+    const C2<double> *um = (const C2<double> *)a.up;
+    C2<double> *uo = (C2<double> *)uout;
+    const double *m = (const double *)a.m;
+    const double2 *F = (const double2 *)a.F;
+    double2 *out = (double2 *)a.out;
+#define TDP_SWEEPB(D, SC, MC) \
+    hipLaunchKernelGGL((k_sweep_abd<D, SC, MC>), grd, blk, 0, s, u, um, uo, m, rc, F, nz, ny, nx, stA, stB, cth, fa, fb, out)
+    if (a.ndim == 2) {
+        if (a.sc <= 3 && a.mc <= 2) TDP_SWEEPB(2, 3, 2);
+        else TDP_SWEEPB(2, 3, 3);
+    } else {
+        if (a.sc <= 3 && a.mc <= 2) TDP_SWEEPB(3, 3, 2);
+        else TDP_SWEEPB(3, 4, 4);
+    }
+#undef TDP_SWEEPB
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// complex H-apply: y = H x or y = F - H x, H = stencil + i diag(rw)
+// With the cell damping (CD), Im H = omega sum_cells r_cell M_cell is the
+// mass-class stencil stI over the cell damping rc instead of diag(rw).
+template <int D, int SC, int MC, bool CD>
 __global__ __launch_bounds__(256) void k_apply_H(const double *__restrict__ m,
                                                  const double *__restrict__ rw,
-                                                 Stencil<double> st,
+                                                 const double *__restrict__ rc,
+                                                 Stencil<double> st, Stencil<double> stI,
                                                  const double2 *__restrict__ xv,
                                                  const double2 *__restrict__ F,
                                                  double2 *__restrict__ y_out, int nz, int ny,
@@ -281,11 +364,18 @@ __global__ __launch_bounds__(256) void k_apply_H(const double *__restrict__ m,
     };
     const double hr = eval_stencil<D, SC, MC>(Ur, w, st);
     const double hi = eval_stencil<D, SC, MC>(Ui, w, st);
-    const double2 xc = xv[i];
-    const double r = rw[i];
     double2 o;
-    o.x = hr - r * xc.y;
-    o.y = hi + r * xc.x;
+    if (CD) {
+        double wr[1 << D];
+        load_cells<D>(rc, z, y, x, ny, nx, wr);
+        o.x = hr - eval_stencil<D, 1, MC>(Ui, wr, stI);
+        o.y = hi + eval_stencil<D, 1, MC>(Ur, wr, stI);
+    } else {
+        const double2 xc = xv[i];
+        const double r = rw[i];
+        o.x = hr - r * xc.y;
+        o.y = hi + r * xc.x;
+    }
     if (F) {
         const double2 f = F[i];
         o.x = f.x - o.x;
@@ -295,8 +385,9 @@ __global__ __launch_bounds__(256) void k_apply_H(const double *__restrict__ m,
 }
 
 hipError_t launch_apply_H(int ndim, const int *n, int sc, int mc, const double *m,
-                          const double *rw, const Stencil<double> &st, const void *x,
-                          const void *F, void *y, hipStream_t s)
+                          const double *rw, const double *rc, const Stencil<double> &st,
+                          const Stencil<double> &stI, const void *x, const void *F, void *y,
+                          hipStream_t s)
 {
     const int nz = ndim == 3 ? n[0] : 1;
     const int ny = ndim == 3 ? n[1] : n[0];
@@ -306,15 +397,18 @@ hipError_t launch_apply_H(int ndim, const int *n, int sc, int mc, const double *
     const double2 *xv = (const double2 *)x;
     const double2 *Fv = (const double2 *)F;
     double2 *yv = (double2 *)y;
-#define TDP_HAPPLY(D, SC, MC) \
-    hipLaunchKernelGGL((k_apply_H<D, SC, MC>), grd, blk, 0, s, m, rw, st, xv, Fv, yv, nz, ny, nx)
+#define TDP_HAPPLY(D, SC, MC, CD) \
+    hipLaunchKernelGGL((k_apply_H<D, SC, MC, CD>), grd, blk, 0, s, m, rw, rc, st, stI, xv, Fv, yv, nz, ny, nx)
+#define TDP_HAPPLY2(D, SC, MC) \
+    do { if (rc) TDP_HAPPLY(D, SC, MC, true); else TDP_HAPPLY(D, SC, MC, false); } while (0)
     if (ndim == 2) {
-        if (sc <= 3 && mc <= 2) TDP_HAPPLY(2, 3, 2);
-        else TDP_HAPPLY(2, 3, 3);
+        if (sc <= 3 && mc <= 2) TDP_HAPPLY2(2, 3, 2);
+        else TDP_HAPPLY2(2, 3, 3);
     } else {
-        if (sc <= 3 && mc <= 2) TDP_HAPPLY(3, 3, 2);
-        else TDP_HAPPLY(3, 4, 4);
+        if (sc <= 3 && mc <= 2) TDP_HAPPLY2(3, 3, 2);
+        else TDP_HAPPLY2(3, 4, 4);
     }
+#undef TDP_HAPPLY2
 #undef TDP_HAPPLY
     return hipGetLastError();
 }
@@ -373,8 +467,9 @@ hipError_t launch_cvt_f64_to_f32(const double *x, float *y, int64_t N, hipStream
 }
 
 // ---------------------------------------------------------------------------
-// setup: m_cell = 2^-D sum over corners of 1/c^2 (corner indices clamped)
-template <int D>
+// setup: m_cell = 2^-D sum over corners of 1/c^2 (corner indices clamped);
+// with INV = false the plain corner mean (cell damping r_cell from R).
+template <int D, bool INV>
 __global__ void k_cell_slowness(const double *__restrict__ c, double *__restrict__ m, int nz,
                                 int ny, int nx)
 {
@@ -391,7 +486,7 @@ __global__ void k_cell_slowness(const double *__restrict__ c, double *__restrict
         cy = cy < 0 ? 0 : (cy >= ny ? ny - 1 : cy);
         cz = cz < 0 ? 0 : (cz >= nz ? nz - 1 : cz);
         const double v = c[((int64_t)cz * ny + cy) * nx + cx];
-        s += 1.0 / (v * v);
+        s += INV ? 1.0 / (v * v) : v;
     }
     m[((int64_t)z * (ny + 1) + y) * (nx + 1) + x] = s * (1.0 / (1 << D));
 }
@@ -405,9 +500,24 @@ hipError_t launch_cell_slowness(int ndim, const int *n, const double *c, double 
     dim3 blk(64, 4, 1);
     dim3 grd((nx + 1 + 63) / 64, (ny + 1 + 3) / 4, ndim == 3 ? nz + 1 : 1);
     if (ndim == 2)
-        hipLaunchKernelGGL(k_cell_slowness<2>, grd, blk, 0, s, c, m, nz, ny, nx);
+        hipLaunchKernelGGL((k_cell_slowness<2, true>), grd, blk, 0, s, c, m, nz, ny, nx);
     else
-        hipLaunchKernelGGL(k_cell_slowness<3>, grd, blk, 0, s, c, m, nz, ny, nx);
+        hipLaunchKernelGGL((k_cell_slowness<3, true>), grd, blk, 0, s, c, m, nz, ny, nx);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_mean(int ndim, const int *n, const double *v, double *cells,
+                            hipStream_t s)
+{
+    const int nz = ndim == 3 ? n[0] : 1;
+    const int ny = ndim == 3 ? n[1] : n[0];
+    const int nx = ndim == 3 ? n[2] : n[1];
+    dim3 blk(64, 4, 1);
+    dim3 grd((nx + 1 + 63) / 64, (ny + 1 + 3) / 4, ndim == 3 ? nz + 1 : 1);
+    if (ndim == 2)
+        hipLaunchKernelGGL((k_cell_slowness<2, false>), grd, blk, 0, s, v, cells, nz, ny, nx);
+    else
+        hipLaunchKernelGGL((k_cell_slowness<3, false>), grd, blk, 0, s, v, cells, nz, ny, nx);
     return hipGetLastError();
 }
 

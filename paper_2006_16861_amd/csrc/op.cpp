@@ -77,6 +77,23 @@ static void table_spectrum(int d, const double *T, double *lo, double *hi)
     }
 }
 
+// Sec. 5.1: stability of I_abd at theta = omega dt with the bounds lam_s >=
+// lambda_max of the stiffness part of Re H and lam_im >= lambda_max(Im H):
+// omega^2 = kmax2 + (beta/theta)(1 - cos theta) lam_im makes K >= 0, and
+// 4I - K - 2L > 0 holds when
+//   (theta^2/alpha)(lam_s/omega^2 + 1) + (theta beta/alpha)(1 + cos theta) lam_im/omega^2 < 4
+// (the factor theta of the second term follows from K and L of Def. 6).
+static bool abd_stable(double theta, double kmax2, double lam_s, double lam_im, double *w2out)
+{
+    const double sh = std::sin(0.5 * theta);
+    const double alpha = theta * theta / (4.0 * sh * sh), beta = theta / std::sin(theta);
+    const double w2 = kmax2 + beta / theta * (1.0 - std::cos(theta)) * lam_im;
+    const double lhs = theta * theta / alpha * (lam_s / w2 + 1.0) +
+                       theta * beta / alpha * (1.0 + std::cos(theta)) * lam_im / w2;
+    if (w2out) *w2out = w2;
+    return lhs < 4.0;
+}
+
 }  // namespace tdp
 
 using namespace tdp;
@@ -92,8 +109,8 @@ static int free_op(tdp_op *op)
     (void)hipFree(op->gcell);
     for (auto &kv : op->graphs) (void)hipGraphExecDestroy(kv.second);
     void *bufs[] = {op->m, op->rw, op->dn, op->m32, op->dn32, op->u0, op->u1, op->u2, op->v0, op->v1,
-                    op->u3, op->Fst, op->scratch, op->V, op->wv, op->tv, op->rv, op->xv,
-                    op->red, op->dcoef};
+                    op->u3, op->u4, op->rc, op->Fst, op->scratch, op->V, op->wv, op->tv, op->rv,
+                    op->xv, op->red, op->dcoef};
     for (void *b : bufs) (void)hipFree(b);
     if (op->hres) (void)hipHostFree(op->hres);
     if (op->own_stream && op->stream) (void)hipStreamDestroy(op->stream);
@@ -115,6 +132,11 @@ static int create_impl(const tdp_op_desc *d, tdp_op *op)
     if (!(d->omega > 0.0)) TDP_FAIL(TDP_EINVAL, "omega must be > 0");
     if (!d->c) TDP_FAIL(TDP_EINVAL, "c must not be NULL");
     if (d->prec != TDP_F64 && d->prec != TDP_F32) TDP_FAIL(TDP_EINVAL, "prec must be TDP_F64 or TDP_F32");
+    if (d->damping != TDP_DAMP_NODE && d->damping != TDP_DAMP_CELL)
+        TDP_FAIL(TDP_EINVAL, "damping must be TDP_DAMP_NODE or TDP_DAMP_CELL");
+    if (d->damping == TDP_DAMP_CELL && d->prec != TDP_F64)
+        TDP_FAIL(TDP_EINVAL, "the cell damping (I_abd) path is FP64 only");
+    op->dform = d->damping;
     op->ndim = d->ndim;
     op->N = 1;
     op->Nc = 1;
@@ -202,15 +224,47 @@ static int create_impl(const tdp_op_desc *d, tdp_op *op)
     // Sec. 2.2: omega_c bounds sqrt(-lambda_min(Re H)); the CFL bound uses
     // lambda_max(A) <= h^-2 max S(theta) + omega_c^2.
     op->omega_c = op->omega * std::sqrt(mmax);
-    op->lam_bar = std::ldexp(shi, D) / (op->h * op->h) + op->omega_c * op->omega_c;
-    const double nmin = M_PI / std::asin(op->omega_c / std::sqrt(op->lam_bar));
+    const double lam_s = std::ldexp(shi, D) / (op->h * op->h);
     int nP = d->steps_per_period;
-    if (nP == 0) {
-        nP = 4 * ((int)std::floor(nmin / 4.0) + 1);
-    } else if (nP < 0 || nP % 4 != 0 || !((double)nP > nmin)) {
-        TDP_FAIL(TDP_ECFL, "steps_per_period %d must be a multiple of 4 above the CFL bound %.6f",
-                 nP, nmin);
+    if (op->dform == TDP_DAMP_CELL) {
+        // cell damping r_cell (corner mean of R); lambda_max(Im H) <= omega max r_cell
+        if (hipMalloc(&op->rc, sizeof(double) * op->Nc) != hipSuccess)
+            TDP_FAIL(TDP_ENOMEM, "device allocation of the cell damping failed");
+        if (d->R) {
+            TDP_CHECK_HIP(launch_cell_mean(D, op->n, d->R, op->rc, s));
+        } else {
+            TDP_CHECK_HIP(launch_fill_zero(op->rc, sizeof(double) * op->Nc, s));
+        }
+        TDP_CHECK_HIP(launch_max_reduce(op->rc, op->Nc, op->scratch, nblk, op->scratch + nblk, s));
+        double rmax = 0.0;
+        TDP_CHECK_HIP(hipMemcpyAsync(&rmax, op->scratch + nblk, sizeof(double), hipMemcpyDeviceToHost, s));
+        TDP_CHECK_HIP(hipStreamSynchronize(s));
+        op->lam_im = op->omega * rmax;
+        // Sec. 5.1: theta = omega dt = 2 pi / n_P with n_P the smallest multiple of 4
+        // satisfying the stability condition; omega from the K >= 0 condition
+        const double kmax2 = op->omega_c * op->omega_c;
+        if (nP == 0) {
+            for (nP = 4; nP <= (1 << 22); nP += 4)
+                if (abd_stable(2.0 * M_PI / nP, kmax2, lam_s, op->lam_im, nullptr)) break;
+            if (nP > (1 << 22)) TDP_FAIL(TDP_ECFL, "no stable step for the cell damping");
+        } else if (nP < 0 || nP % 4 != 0 ||
+                   !abd_stable(2.0 * M_PI / nP, kmax2, lam_s, op->lam_im, nullptr)) {
+            TDP_FAIL(TDP_ECFL, "steps_per_period %d violates the I_abd stability condition", nP);
+        }
+        double w2 = 0.0;
+        abd_stable(2.0 * M_PI / nP, kmax2, lam_s, op->lam_im, &w2);
+        op->omega_c = std::sqrt(w2);
+    } else {
+        const double lb = lam_s + op->omega_c * op->omega_c;
+        const double nmin = M_PI / std::asin(op->omega_c / std::sqrt(lb));
+        if (nP == 0) {
+            nP = 4 * ((int)std::floor(nmin / 4.0) + 1);
+        } else if (nP < 0 || nP % 4 != 0 || !((double)nP > nmin)) {
+            TDP_FAIL(TDP_ECFL, "steps_per_period %d must be a multiple of 4 above the CFL bound %.6f",
+                     nP, nmin);
+        }
     }
+    op->lam_bar = lam_s + op->omega_c * op->omega_c;
     op->nP = nP;
     op->dt = 2.0 * M_PI / (op->omega_c * nP);
     const double th = 2.0 * M_PI / nP;   // omega_c * dt
@@ -236,6 +290,15 @@ static int create_impl(const tdp_op_desc *d, tdp_op *op)
         const double mk = k <= D ? op->M[k] : 0.0;
         op->st_step.m[k] = op->cM * mk;
         op->st_H.m[k] = -op->omega * op->omega * mk;
+    }
+    // Im H (cell damping) and (beta dt / (alpha omega_c)) Im H as mass-class
+    // stencils over r_cell (Sec. 5: L = (beta dt/alpha) B, B = Im H / omega_c)
+    op->cos_th = std::cos(th);
+    const double lb = op->beta * op->dt / op->alpha / op->omega_c;
+    for (int k = 0; k < 4; ++k) {
+        const double mk = k <= D ? op->M[k] : 0.0;
+        op->st_I.m[k] = op->omega * mk;
+        op->st_B.m[k] = lb * op->omega * mk;
     }
     op->st_step32.c0 = (float)op->st_step.c0;
     for (int k = 0; k < 4; ++k) {
@@ -292,6 +355,7 @@ extern "C" int tdp_op_query(const tdp_op *op, tdp_op_info *o)
     o->n_P = op->nP;
     o->ndim = op->ndim;
     o->N = op->N;
+    o->lam_im = op->lam_im;
     return TDP_OK;
 }
 
@@ -324,8 +388,9 @@ extern "C" int tdp_op_get_tuning(const tdp_op *op, tdp_tuning *t)
 // ---------------------------------------------------------------------------
 int apply_H_impl(const tdp_op *op, const void *x, const void *F, void *y)
 {
-    TDP_CHECK_HIP(launch_apply_H(op->ndim, op->n, op->sc, op->mc, op->m, op->rw, op->st_H, x, F,
-                                 y, op->stream));
+    TDP_CHECK_HIP(launch_apply_H(op->ndim, op->n, op->sc, op->mc, op->m, op->rw,
+                                 op->dform == TDP_DAMP_CELL ? op->rc : nullptr, op->st_H, op->st_I,
+                                 x, F, y, op->stream));
     return TDP_OK;
 }
 
@@ -372,9 +437,10 @@ const std::vector<double> &forcing_table(tdp_op *op, int T, double rho, int vari
 
 static int ensure_complex_fields(tdp_op *op)
 {
-    if (op->u2) return TDP_OK;
     const size_t fb = 2 * (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
-    if (hipMalloc(&op->u2, fb) != hipSuccess || hipMalloc(&op->u3, fb) != hipSuccess)
+    if (!op->u2 && (hipMalloc(&op->u2, fb) != hipSuccess || hipMalloc(&op->u3, fb) != hipSuccess))
+        TDP_FAIL(TDP_ENOMEM, "device allocation of complex recurrence fields failed");
+    if (op->dform == TDP_DAMP_CELL && !op->u4 && hipMalloc(&op->u4, fb) != hipSuccess)
         TDP_FAIL(TDP_ENOMEM, "device allocation of complex recurrence fields failed");
     return TDP_OK;
 }
@@ -385,6 +451,7 @@ static int ensure_complex_fields(tdp_op *op)
 static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth)
 {
     int kern = op->tune.kernel, k = op->tune.tb_depth;
+    if (op->dform == TDP_DAMP_CELL) kern = 1;    // I_abd: one step per launch
     if (kern == 0) kern = variant == 0 ? (op->ndim == 2 ? 2 : 3) : 1;
     if (kern == 2 && !(op->ndim == 2 && variant == 0)) kern = 1;
     if (kern == 3 && !(op->ndim == 3 && variant == 0)) kern = 1;
@@ -471,7 +538,7 @@ static int issue_steps(tdp_op *op, int T, double rho, int variant, const void *F
     const std::vector<double> &tab = forcing_table(op, T, rho, variant);
     const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - op->nP / 4;
     const size_t fb = (variant ? 2 : 1) * (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
-    void *cur = variant ? op->u2 : op->u0, *prev = variant ? op->u3 : op->u1;
+    void *cur = variant ? op->u2 : op->u0, *prev = variant ? op->u3 : op->u1, *nxt = op->u4;
     TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
     TDP_CHECK_HIP(launch_fill_zero(prev, fb, s));
     SweepArgs a;
@@ -487,6 +554,17 @@ static int issue_steps(tdp_op *op, int T, double rho, int variant, const void *F
         a.u = cur;
         a.up = prev;
         const double fa = tab[2 * j], fbv = tab[2 * j + 1];
+        if (op->dform == TDP_DAMP_CELL) {
+            // I_abd reads u_{n-1} at the neighbours: three fields rotate
+            a.out = (j + 1 == Ns) ? Ud : nullptr;
+            TDP_CHECK_HIP(launch_sweep_abd(a, nxt, op->rc, op->st_step, op->st_B, op->cos_th, fa,
+                                           fbv, s));
+            void *t = prev;
+            prev = cur;
+            cur = nxt;
+            nxt = t;
+            continue;
+        }
         if (variant) {
             a.out = (j + 1 == Ns) ? Ud : nullptr;
             if (op->prec == TDP_F64)
@@ -518,6 +596,8 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
     if (rho <= 0.0) rho = 1.0 / T;
     if (rho > 1.0) TDP_FAIL(TDP_EINVAL, "rho must be <= 1");
     if (variant != 0 && variant != 1) TDP_FAIL(TDP_EINVAL, "variant must be 0 or 1");
+    if (op->dform == TDP_DAMP_CELL && variant == 0)
+        TDP_FAIL(TDP_EINVAL, "Table 1 runs I_acd: with the cell damping use the complex form (S_T^abd)");
     if ((int64_t)T * op->nP > ((int64_t)1 << 31)) TDP_FAIL(TDP_EINVAL, "too many steps");
     if (variant) TDP_CHECK(ensure_complex_fields(op));
     {   // allocate before any stream capture: no allocation may happen inside it
@@ -591,6 +671,7 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
     if (!op) TDP_FAIL(TDP_EINVAL, "NULL argument");
     if (periods_T < 1) TDP_FAIL(TDP_EINVAL, "periods_T must be >= 1");
     if (variant != 0 && variant != 1) TDP_FAIL(TDP_EINVAL, "variant must be 0 or 1");
+    if (op->dform == TDP_DAMP_CELL) variant = 1;      // S_T^abd: one-step kernel only
     StreamJoin join(op->user_stream, op->stream, op->ev);
     hipStream_t s = op->stream;
     std::vector<tdp_tuning> cand;
@@ -758,7 +839,7 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
     TDP_CHECK(norm2_host(op, F, &b2));
     const double bnorm = std::sqrt(b2);
     int its = 0, restarts = 0, nhist = 0, status = TDP_ENOTCONV;
-    int variant = cfg->variant, switched = 0;
+    int variant = op->dform == TDP_DAMP_CELL ? 1 : cfg->variant, switched = 0;
     int64_t napply = 0;
     double pnorm0 = -1.0, est = 1.0, rel = 1.0;
     std::vector<cplx> Hm((size_t)(m + 1) * m), gv(m + 1), sn(m), y(m), ybest(m);

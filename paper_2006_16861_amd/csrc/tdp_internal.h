@@ -131,18 +131,28 @@ hipError_t launch_sweep_c_f64(const SweepArgs &a, const Stencil<double> &st, dou
 hipError_t launch_sweep_c_f32(const SweepArgs &a, const Stencil<float> &st, float fa, float fb,
                               hipStream_t s);
 
+// I_abd step on complex fields (Sec. 5): a.u = u_n, a.up = u_{n-1} (read only),
+// u_{n+1} -> uout; rc the cell damping; stB the mass-class stencil of L/ImH.
+hipError_t launch_sweep_abd(const SweepArgs &a, void *uout, const double *rc,
+                            const Stencil<double> &stA, const Stencil<double> &stB, double cth,
+                            double fa, double fb, hipStream_t s);
+
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_cvt_c128_to_c64(const void *F, void *Fs, int64_t N, hipStream_t s);
 hipError_t launch_cvt_f64_to_f32(const double *x, float *y, int64_t N, hipStream_t s);
 
-// y = H x   or   y = F - H x  (when F != null); complex128.
+// y = H x   or   y = F - H x  (when F != null); complex128.  Im H = diag(rw),
+// or with rc != null the mass-class stencil stI over the cell damping rc.
 hipError_t launch_apply_H(int ndim, const int *n, int sc, int mc, const double *m,
-                          const double *rw, const Stencil<double> &st, const void *x,
-                          const void *F, void *y, hipStream_t s);
+                          const double *rw, const double *rc, const Stencil<double> &st,
+                          const Stencil<double> &stI, const void *x, const void *F, void *y,
+                          hipStream_t s);
 
 // setup kernels
 hipError_t launch_cell_slowness(int ndim, const int *n, const double *c, double *m,
                                 hipStream_t s);
+hipError_t launch_cell_mean(int ndim, const int *n, const double *v, double *cells,
+                            hipStream_t s);
 hipError_t launch_max_reduce(const double *x, int64_t N, double *partial, int nblk,
                              double *out, hipStream_t s);
 hipError_t launch_node_factors(const double *R, int64_t N, double omega, double lscale,
@@ -202,6 +212,12 @@ struct tdp_op {
     int nP = 0;
     double cS = 0, cM = 0, cw = 0, g = 0;
     tdp::Stencil<double> st_step{}, st_H{};
+    // cell damping (Sec. 5): Im H = omega sum_cells r_cell M_cell, integrator I_abd
+    int dform = TDP_DAMP_NODE;
+    double lam_im = 0, cos_th = 0;
+    double *rc = nullptr;                   // cell damping r_cell
+    tdp::Stencil<double> st_I{}, st_B{};    // Im H and (beta dt/(alpha omega)) Im H (mass classes)
+    void *u4 = nullptr;                     // third complex field of the I_abd loop
     tdp::Stencil<float> st_step32{};
     // device buffers
     double *m = nullptr;       // cell slowness

@@ -15,6 +15,9 @@ LIB_PATH = os.path.join(HERE, "libtdp.so")
 
 OK, ENOTCONV, EINVAL, ENOMEM, EHIP, ECFL = 0, 1, -1, -2, -3, -4
 F64, F32 = 0, 1
+# damping discretisation: "node" Im H = diag(omega R) (I_acd); "cell" Im H =
+# omega sum_cells r_cell M_cell, the non-diagonal damping of Sec. 5 (I_abd)
+DAMPING = {"node": 0, "cell": 1}
 
 SYMBOLS = ("tdp_op_create", "tdp_op_destroy", "tdp_op_query", "tdp_apply_H",
            "tdp_precond_apply", "tdp_precond_apply_complex", "tdp_gmres_solve", "tdp_grad_m", "tdp_op_set_tuning", "tdp_op_autotune",
@@ -47,14 +50,14 @@ class OpDesc(ctypes.Structure):
                 ("omega", ctypes.c_double), ("c", ctypes.c_void_p), ("R", ctypes.c_void_p),
                 ("stiff", ctypes.c_void_p), ("mass", ctypes.c_void_p),
                 ("steps_per_period", ctypes.c_int), ("prec", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("damping", ctypes.c_int)]
 
 
 class OpInfo(ctypes.Structure):
     _fields_ = [("omega_c", ctypes.c_double), ("dt", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("lam_bar", ctypes.c_double), ("n_P", ctypes.c_int), ("ndim", ctypes.c_int),
-                ("N", ctypes.c_int64)]
+                ("N", ctypes.c_int64), ("lam_im", ctypes.c_double)]
 
 
 class GmresCfg(ctypes.Structure):
@@ -159,7 +162,7 @@ class Operator:
     with spacing `h` (Dirichlet walls); c and R are FP64 tensors on the GPU."""
 
     def __init__(self, c, R, omega, h, prec=F64, steps_per_period=0, stiff=None, mass=None,
-                 scheme=None):
+                 scheme=None, damping="node"):
         import torch
         L = load()
         self.n = tuple(int(v) for v in c.shape)
@@ -191,6 +194,10 @@ class Operator:
                 setattr(desc, name, ctypes.cast(arr, ctypes.c_void_p))
         desc.steps_per_period = int(steps_per_period)
         desc.prec = int(prec)
+        if damping not in DAMPING:
+            raise ValueError(f"damping must be one of {sorted(DAMPING)}")
+        desc.damping = DAMPING[damping]
+        self.damping = damping
         desc.stream = _stream_ptr()
         self.prec = int(prec)
         h_ = ctypes.c_void_p()
@@ -201,6 +208,7 @@ class Operator:
         _check(L.tdp_op_query(self._h, ctypes.byref(info)), "tdp_op_query")
         self.omega_c, self.dt, self.alpha, self.beta = info.omega_c, info.dt, info.alpha, info.beta
         self.lam_bar, self.nP = info.lam_bar, info.n_P
+        self.lam_im = info.lam_im
 
     def close(self):
         if getattr(self, "_h", None):

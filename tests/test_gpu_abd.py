@@ -1,0 +1,111 @@
+"""GPU parity of the Sec. 5 path: cell damping Im H = omega sum_cells r_cell M_cell,
+I_abd (Def. 6) and S_T^abd (Def. 7), through the C ABI against the oracle
+(FP64 bar 1e-10), plus LU for a converged solve and the error paths."""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle
+from paper_2006_16861_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+Q1 = {2: ((2 / 3, -1 / 6, -1 / 3), (1 / 9, 1 / 18, 1 / 36)),
+      3: ((1 / 3, 0.0, -1 / 12, -1 / 12), (1 / 27, 1 / 54, 1 / 108, 1 / 216))}
+
+
+def note(msg):
+    print(f"[case] {msg}", file=sys.stderr, flush=True)
+
+
+def dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def problem(n, seed, rscale=2.0):
+    p = inputs.random_medium(n, seed=seed, width=3, r_scale=rscale)
+    rng = np.random.default_rng(seed + 11)
+    R = p.R + rng.uniform(0.0, 0.2 * p.omega, p.n)
+    return p, R
+
+
+def ops(p, R, tables=None):
+    from paper_2006_16861_amd import tdp
+    kw = {} if tables is None else {"stiff": tables[0], "mass": tables[1]}
+    g = tdp.Operator(dev(p.c), dev(R), p.omega, p.h, damping="cell", **kw)
+    o = oracle.Op(p.n, p.h, p.omega, p.c, R, damping="cell", **kw)
+    return g, o
+
+
+CASES = [((37, 150), None), ((64, 64), None), ((1, 9), None), ((45, 77), "q1"),
+         ((9, 11, 70), None), ((3, 1, 5), None), ((11, 13, 20), "q1")]
+
+
+@pytest.mark.parametrize("n,tab", CASES)
+def test_abd_parameters_H_and_precond(n, tab):
+    p, R = problem(n, 3)
+    note(f"abd {n} tables={tab}")
+    g, o = ops(p, R, Q1[len(n)] if tab else None)
+    assert g.nP == o.nP
+    for a, b in ((g.omega_c, o.omega_c), (g.dt, o.dt), (g.alpha, o.alpha), (g.beta, o.beta),
+                 (g.lam_bar, o.lam_bar)):
+        assert abs(a - b) <= 1e-12 * abs(b)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
+    assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
+    for T, rho in ((2, 0.25), (3, 0.0), (1, 0.75)):
+        Uo = o.precond(p.F, T, rho, variant=1)
+        assert rel(host(g.precond(dev(p.F), T, rho, variant=1)), Uo) <= TOL64
+    g.set_tuning(kernel=1, use_graph=0)
+    assert rel(host(g.precond(dev(p.F), 2, 0.25, variant=1)), o.precond(p.F, 2, 0.25, variant=1)) <= TOL64
+
+
+def test_abd_gmres_fixed_and_converged():
+    p, R = problem((40, 52), 5)
+    note("abd gmres")
+    g, o = ops(p, R)
+    Ug, ig = g.solve(dev(p.F), T=p.periods, restart=5, fixed_iters=9)
+    Uo, io = o.gmres(p.F, T=p.periods, restart=5, fixed_iters=9)
+    assert ig.iters == io["iters"] == 9
+    assert rel(host(Ug), Uo) <= TOL64
+    H = oracle.assemble_H(p.n, p.h, p.omega, p.c, R, damping="cell")
+    U = spla.spsolve(H.tocsc(), p.F.reshape(-1)).reshape(p.n)
+    Ug, ig = g.solve(dev(p.F), T=p.periods, tol=1e-11)
+    assert ig.status == 0
+    assert rel(host(Ug), U) <= 1e-8
+    assert rel(o.apply_H(host(Ug)), p.F) <= 1e-11 * (1 + 1e-9)
+
+
+def test_abd_gradient_and_error_paths():
+    import torch
+    from paper_2006_16861_amd import tdp
+    p, R = problem((30, 41), 6)
+    note("abd grad + errors")
+    g, o = ops(p, R)
+    rng = np.random.default_rng(7)
+    lam = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
+    U = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
+    assert rel(host(g.grad_m(dev(lam), dev(U))), o.grad_m(lam, U)) <= 1e-13
+    with pytest.raises(tdp.TdpError):
+        g.precond(dev(p.F), 2, 0.25, variant=0)        # Table 1 is the I_acd algorithm
+    with pytest.raises(tdp.TdpError):
+        tdp.Operator(dev(p.c), dev(R), p.omega, p.h, damping="cell", prec=tdp.F32)
+    with pytest.raises(tdp.TdpError):
+        tdp.Batch([g], [1])
+    with pytest.raises(tdp.TdpError):                  # n_P below the I_abd bound
+        tdp.Operator(dev(p.c), dev(R), p.omega, p.h, damping="cell", steps_per_period=g.nP - 4)
+    ok = tdp.Operator(dev(p.c), dev(R), p.omega, p.h, damping="cell", steps_per_period=g.nP + 8)
+    assert ok.nP == g.nP + 8
+    torch.cuda.synchronize()
