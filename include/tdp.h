@@ -218,16 +218,19 @@ int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
 /* Tuning of the recurrence sweep (no effect on results beyond rounding).
  *  kernel       0 auto, 1 one step per launch, 2 temporally blocked (2-D,
  *               Table 1 variant), 3 streamed along axis 0 (3-D, Table 1
- *               variant); inapplicable choices fall back to 1
+ *               variant), 4 streamed along axis 0 with two steps per launch
+ *               (3-D, Table 1 variant); inapplicable choices fall back to 1
  *  tb_depth     kernel 2: steps per launch, 1..16 (0 auto);
- *               kernel 3: planes per chunk (0 auto = 32)
+ *               kernels 3, 4: planes per chunk (0 auto = 32)
  *  use_graph    1 capture the step loop in a hipGraph and replay it
  *  tile         kernel 2 tile (rows x columns): 0 64x64 (8 rows per lane x
  *               8 waves), 1 64x64 (4 x 16 waves), 2 128x64 (FP32 only),
  *               3 32x64 (4 x 8 waves); 4..7 the same family with per-node
  *               coefficients in registers: 4 64x64 (4 x 16), 5 32x64 (4 x 8),
  *               6 64x64 (8 x 8), 7 32x64 (2 x 16); kernel 3: 0 8x64 columns (4 waves x 2
- *               rows each), 1 16x64 (4 waves x 4 rows), 2 16x64 (8 x 2)    */
+ *               rows each), 1 16x64 (4 waves x 4 rows), 2 16x64 (8 x 2);
+ *               kernel 4: the same three shapes for the first step, whose
+ *               one-node rim is recomputed (output 6x62 / 14x62 / 14x62)   */
 typedef struct {
     int kernel;
     int tb_depth;
@@ -239,7 +242,8 @@ int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t);
 
 /* Autotuner: times each sweep variant applicable to this op (one step per
  * launch; blocked tile shapes x depths 2, 3, 4, 6, 8 for the 2-D Table 1
- * loop; streamed column shapes x chunk lengths 16, 32, 64 in 3-D) over
+ * loop; streamed column shapes x chunk lengths 16, 32, 64 in 3-D, with one
+ * and two steps per launch) over
  * periods_T periods with HIP events on the op's stream, and makes
  * the fastest the op's tuning.  best (host, may be NULL) receives it; table
  * (host, may be NULL) receives up to cap rows of {kernel, tb_depth, tile,

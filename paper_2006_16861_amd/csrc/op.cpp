@@ -363,10 +363,10 @@ extern "C" int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t)
 {
     clear_error();
     if (!op || !t) TDP_FAIL(TDP_EINVAL, "NULL argument");
-    if (t->kernel < 0 || t->kernel > 3) TDP_FAIL(TDP_EINVAL, "kernel must be 0, 1, 2 or 3");
-    if (t->kernel == 3) {
+    if (t->kernel < 0 || t->kernel > 4) TDP_FAIL(TDP_EINVAL, "kernel must be in [0, 4]");
+    if (t->kernel == 3 || t->kernel == 4) {
         if (t->tb_depth < 0 || t->tb_depth > (1 << 20)) TDP_FAIL(TDP_EINVAL, "bad chunk length");
-        if (t->tile < 0 || t->tile > 2) TDP_FAIL(TDP_EINVAL, "tile must be 0, 1 or 2 for kernel 3");
+        if (t->tile < 0 || t->tile > 2) TDP_FAIL(TDP_EINVAL, "tile must be 0, 1 or 2 for kernels 3 and 4");
     } else {
         if (t->tb_depth < 0 || t->tb_depth > TDP_TB_KMAX) TDP_FAIL(TDP_EINVAL, "tb_depth must be in [0, 16]");
         if (t->tile < 0 || t->tile > 7) TDP_FAIL(TDP_EINVAL, "tile must be in [0, 7]");
@@ -454,12 +454,12 @@ static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth)
     if (op->dform == TDP_DAMP_CELL) kern = 1;    // I_abd: one step per launch
     if (kern == 0) kern = variant == 0 ? (op->ndim == 2 ? 2 : 3) : 1;
     if (kern == 2 && !(op->ndim == 2 && variant == 0)) kern = 1;
-    if (kern == 3 && !(op->ndim == 3 && variant == 0)) kern = 1;
+    if ((kern == 3 || kern == 4) && !(op->ndim == 3 && variant == 0)) kern = 1;
     if (kern == 2) {
         if (k == 0) k = 4;
         const int rows = tb2d_tile_rows(op->tune.tile, op->prec == TDP_F64);
         if (4 * k > rows || 4 * k > 64) k = rows / 8;   // keep at least half the tile exact
-    } else if (kern == 3) {
+    } else if (kern == 3 || kern == 4) {
         if (k == 0) k = 32;
     } else {
         k = 1;
@@ -528,11 +528,78 @@ static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, const void *
 // Issue the recurrence loop reading F (complex128, or float2 staged for FP32)
 // and writing U (complex128).  variant 0: Table 1 (real field, snapshot a
 // quarter period before the end gives Im U); variant 1: Definition 4.
+// Streamed 3-D loop with two steps per launch, ping-ponging between the field
+// pairs (u0, u1) and (v0, v1); an odd last step runs the one-step kernel in place.
+static int issue_steps_3d2(tdp_op *op, int T, double rho, int zc, const void *Fin, void *U)
+{
+    hipStream_t s = op->stream;
+    TDP_CHECK(ensure_tb_fields(op));
+    const std::vector<double> &tab = forcing_table(op, T, rho, 0);
+    const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - op->nP / 4;
+    const bool f64 = op->prec == TDP_F64;
+    const size_t fb = (f64 ? sizeof(double) : sizeof(float)) * op->N;
+    const int shape = op->tune.tile > 2 ? 1 : op->tune.tile;
+    void *cur = op->u0, *prev = op->u1, *ncur = op->v0, *nprev = op->v1;
+    TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
+    TDP_CHECK_HIP(launch_fill_zero(prev, fb, s));
+    double *Ud = (double *)U;
+    auto out_for = [&](int64_t j1) -> double * {      // destination of u_{j1}, if any
+        return j1 == jsnap ? Ud + 1 : (j1 == Ns ? Ud : nullptr);
+    };
+    Stream2Args a;
+    for (int k = 0; k < 3; ++k) a.n[k] = op->n[k];
+    a.sc = op->sc;
+    a.mc = op->mc;
+    a.zc = zc;
+    a.m = f64 ? (const void *)op->m : (const void *)op->m32;
+    a.dn = f64 ? (const void *)op->dn : (const void *)op->dn32;
+    a.F = Fin;
+    int64_t j = 0;
+    for (; j + 2 <= Ns; j += 2) {
+        a.u = cur;
+        a.up = prev;
+        a.u2out = ncur;
+        a.u1out = nprev;
+        a.fa[0] = tab[2 * j];
+        a.fb[0] = tab[2 * j + 1];
+        a.fa[1] = tab[2 * j + 2];
+        a.fb[1] = tab[2 * j + 3];
+        a.out1 = out_for(j + 1);
+        a.out2 = out_for(j + 2);
+        if (f64)
+            TDP_CHECK_HIP(launch_sweep3d_stream2_f64(a, op->st_step, shape, s));
+        else
+            TDP_CHECK_HIP(launch_sweep3d_stream2_f32(a, op->st_step32, shape, s));
+        std::swap(cur, ncur);
+        std::swap(prev, nprev);
+    }
+    if (j < Ns) {
+        SweepArgs b;
+        b.ndim = op->ndim;
+        for (int k = 0; k < 3; ++k) b.n[k] = op->n[k];
+        b.sc = op->sc;
+        b.mc = op->mc;
+        b.u = cur;
+        b.up = prev;
+        b.m = a.m;
+        b.dn = a.dn;
+        b.F = Fin;
+        b.out = out_for(j + 1);
+        if (f64)
+            TDP_CHECK_HIP(launch_sweep3d_stream_f64(b, op->st_step, tab[2 * j], tab[2 * j + 1], shape, zc, s));
+        else
+            TDP_CHECK_HIP(launch_sweep3d_stream_f32(b, op->st_step32, (float)tab[2 * j],
+                                                    (float)tab[2 * j + 1], shape, zc, s));
+    }
+    return TDP_OK;
+}
+
 static int issue_steps(tdp_op *op, int T, double rho, int variant, const void *Fin, void *U)
 {
     int kern, depth;
     sweep_plan(op, variant, &kern, &depth);
     if (kern == 2) return issue_steps_tb(op, T, rho, depth, Fin, U);
+    if (kern == 4) return issue_steps_3d2(op, T, rho, depth, Fin, U);
     const int shape3 = op->tune.tile > 2 ? 1 : op->tune.tile;
     hipStream_t s = op->stream;
     const std::vector<double> &tab = forcing_table(op, T, rho, variant);
@@ -603,7 +670,7 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
     {   // allocate before any stream capture: no allocation may happen inside it
         int kern, depth;
         sweep_plan(op, variant, &kern, &depth);
-        if (kern == 2) TDP_CHECK(ensure_tb_fields(op));
+        if (kern == 2 || kern == 4) TDP_CHECK(ensure_tb_fields(op));
     }
     hipStream_t s = op->stream;
     if (!op->tune.use_graph) {
@@ -689,6 +756,8 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
     if (op->ndim == 3 && variant == 0) {
         for (int shape = 0; shape < 3; ++shape)
             for (int zc : {16, 32, 64}) cand.push_back({3, zc, 1, shape});
+        for (int shape = 0; shape < 3; ++shape)
+            for (int zc : {16, 32, 64}) cand.push_back({4, zc, 1, shape});
     }
     const tdp_tuning saved = op->tune;
     void *tin = nullptr, *tout = nullptr;

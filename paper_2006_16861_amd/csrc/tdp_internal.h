@@ -124,6 +124,25 @@ hipError_t launch_sweep3d_stream_f64(const SweepArgs &a, const Stencil<double> &
 hipError_t launch_sweep3d_stream_f32(const SweepArgs &a, const Stencil<float> &st, float fa,
                                      float fb, int shape, int zc, hipStream_t s);
 
+// 3-D sweep streamed along axis 0, two steps per launch (sweep3d.hip):
+// (u, up) = (u_j, u_{j-1}) -> (u2out, u1out) = (u_{j+2}, u_{j+1}); outputs
+// distinct from the inputs; out1 / out2 (stride 2, may be null) receive
+// u_{j+1} / u_{j+2} (the snapshot or the final field).
+struct Stream2Args {
+    int n[3];
+    int sc, mc;
+    int zc;                  // planes per chunk
+    const void *u, *up;
+    void *u2out, *u1out;
+    const void *m, *dn, *F;
+    double fa[2], fb[2];     // forcing scalars of the two steps
+    double *out1, *out2;
+};
+hipError_t launch_sweep3d_stream2_f64(const Stream2Args &a, const Stencil<double> &st, int shape,
+                                      hipStream_t s);
+hipError_t launch_sweep3d_stream2_f32(const Stream2Args &a, const Stencil<float> &st, int shape,
+                                      hipStream_t s);
+
 // complex-linear variant: u, up are complex fields (re, im pairs of T); `out`
 // (if non-null) receives u_{j+1} as complex128.
 hipError_t launch_sweep_c_f64(const SweepArgs &a, const Stencil<double> &st, double fa,

@@ -263,7 +263,13 @@ def test_full_size_3d_one_period():
     assert g.nP == o.nP
     F = dev(p.F)
     U = host(g.precond(F, 1, 0.25))
-    assert rel(U, o.precond(p.F, 1, 0.25)) <= TOL64
+    Uo = o.precond(p.F, 1, 0.25)
+    assert rel(U, Uo) <= TOL64
+    for shape, zc in ((1, 32), (0, 64), (2, 16)):
+        g.set_tuning(kernel=4, tb_depth=zc, tile=shape)
+        U4 = host(g.precond(F, 1, 0.25))
+        assert rel(U4, Uo) <= TOL64 and rel(U4, U) <= 1e-13
+    g.set_tuning(kernel=0)
     rng = np.random.default_rng(4)
     x = (rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n))
     assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
@@ -340,24 +346,26 @@ Q1_2D = ((2 / 3, -1 / 6, -1 / 3), (1 / 9, 1 / 18, 1 / 36))
 Q1_3D = ((1 / 3, 0.0, -1 / 12, -1 / 12), (1 / 27, 1 / 54, 1 / 108, 1 / 216))
 
 
-@pytest.mark.parametrize("shape,zc", [(0, 16), (1, 7), (2, 32), (1, 64)])
-@pytest.mark.parametrize("n", [(9, 11, 70), (17, 5, 130), (40, 23, 9)])
-def test_precond_3d_streamed_f64(n, shape, zc):
+@pytest.mark.parametrize("kern", [3, 4])
+@pytest.mark.parametrize("shape,zc", [(0, 16), (1, 7), (2, 32), (1, 64), (0, 1)])
+@pytest.mark.parametrize("n", [(9, 11, 70), (17, 5, 130), (40, 23, 9), (1, 1, 3)])
+def test_precond_3d_streamed_f64(n, shape, zc, kern):
     p = inputs.random_medium(n, seed=21, width=2)
-    note(f"precond 3d streamed {n} shape={shape} zc={zc}")
+    note(f"precond 3d streamed kernel {kern} {n} shape={shape} zc={zc}")
     g, o = make_ops(p)
-    g.set_tuning(kernel=3, tb_depth=zc, tile=shape)
+    g.set_tuning(kernel=kern, tb_depth=zc, tile=shape)
     U = host(g.precond(dev(p.F), 2, 0.25))
     assert rel(U, o.precond(p.F, 2, 0.25)) <= TOL64
     g.set_tuning(kernel=1)
     assert rel(host(g.precond(dev(p.F), 2, 0.25)), U) <= 1e-13
 
 
-def test_precond_3d_streamed_f32():
+@pytest.mark.parametrize("kern,shape", [(3, 1), (4, 0), (4, 1), (4, 2)])
+def test_precond_3d_streamed_f32(kern, shape):
     p = inputs.random_medium((24, 30, 70), seed=22, width=3)
-    note("precond 3d streamed f32")
+    note(f"precond 3d streamed f32 kernel {kern} shape {shape}")
     g, o = make_ops(p, prec=1)
-    g.set_tuning(kernel=3, tb_depth=16, tile=1)
+    g.set_tuning(kernel=kern, tb_depth=16, tile=shape)
     U = host(g.precond(dev(p.F), 2, 0.25))
     assert rel(U, o.precond(p.F, 2, 0.25)) <= 1e-4
 
@@ -378,7 +386,7 @@ def test_general_cell_tables(ndim):
     x = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
     assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
     kernels = [(1, 0, 0), (2, 4, 0), (2, 3, 3), (2, 4, 4), (2, 3, 7)] if ndim == 2 else \
-        [(1, 0, 0), (3, 16, 1)]
+        [(1, 0, 0), (3, 16, 1), (4, 16, 1), (4, 9, 0)]
     Uo = o.precond(p.F, 2, 0.25)
     for kern, depth, tile in kernels:
         g.set_tuning(kernel=kern, tb_depth=depth, tile=tile)
@@ -411,7 +419,7 @@ def test_fd2_scheme_every_kernel(n):
     x = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
     assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
     kernels = [(1, 0, 0), (2, 8, 4), (2, 6, 5), (2, 3, 1), (2, 4, 3)] if ndim == 2 else \
-        [(1, 0, 0), (3, 16, 1), (3, 32, 2), (3, 7, 0)]
+        [(1, 0, 0), (3, 16, 1), (3, 32, 2), (3, 7, 0), (4, 16, 1), (4, 32, 2), (4, 7, 0)]
     Uo = o.precond(p.F, 2, 0.25)
     for kern, depth, tile in kernels:
         g.set_tuning(kernel=kern, tb_depth=depth, tile=tile)
