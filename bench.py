@@ -413,7 +413,8 @@ def main():
             apply_ms, step_ms = sweep_timing(op, F, T, args.rho, args.profile_sweeps, stream,
                                              args.variant)
             tun = op.get_tuning()
-            launches = Ns if tun["kernel"] != 2 else -(-Ns // tun["tb_depth"])
+            per = {2: tun["tb_depth"], 4: 2}.get(tun["kernel"], 1)
+            launches = -(-Ns // per)
             print(json.dumps({"mode": "profile", "workload": args.workload, "N": p.N,
                               "N_s": Ns, "tuning": tun, "launches_per_apply": launches,
                               "apply_ms": apply_ms, "us_per_step": step_ms * 1e3,
@@ -448,7 +449,7 @@ def main():
     bytes_per = words * (8 if prec == tdp.F64 else 4)
     tun = op.get_tuning()
     blocked = tun["kernel"] == 2
-    steps_per_launch = tun["tb_depth"] if blocked else 1
+    steps_per_launch = tun["tb_depth"] if blocked else (2 if tun["kernel"] == 4 else 1)
     launches = -(-Ns // steps_per_launch)
     launch_us = apply_ms * 1e3 / launches
     # algorithmic bytes of one launch: 7 words per node-step (u_j, u_{j-1}, u_{j+1},
@@ -463,6 +464,8 @@ def main():
                  f"depth={steps_per_launch} tile={tun['tile']}")
     elif tun["kernel"] == 3:
         kname = f"k_sweep3d_stream<{tname}> shape={tun['tile']} z-chunk={tun['tb_depth']}"
+    elif tun["kernel"] == 4:
+        kname = f"k_sweep3d_stream2<{tname}> shape={tun['tile']} z-chunk={tun['tb_depth']} (2 steps)"
     else:
         kname = f"k_sweep<{tname}> (one step per launch)"
     traffic = measured_traffic(args.workload, args.prec, args.variant, tun, args.damping)
