@@ -128,10 +128,12 @@ __global__ __launch_bounds__(256) void k_sweep(const T *__restrict__ u, T *__res
         return in ? u[i + ((int64_t)oz * ny + oy) * nx + ox] : T(0);
     };
     const T acc = eval_stencil<D, SC, MC>(U, w, st);
-    const auto f = F[i];
-    const T d = dn[i];
-    const T r = d * (acc + fa * f.x + fb * f.y) - (T(2) * d - T(1)) * up[i];
-    up[i] = r;
+    // per-node streams (read / written once): non-temporal, so that L2 keeps
+    // the u rows and cells that neighbouring workgroups re-read
+    const T fx = __builtin_nontemporal_load(&F[i].x), fy = __builtin_nontemporal_load(&F[i].y);
+    const T d = __builtin_nontemporal_load(dn + i);
+    const T r = d * (acc + fa * fx + fb * fy) - (T(2) * d - T(1)) * __builtin_nontemporal_load(up + i);
+    __builtin_nontemporal_store(r, up + i);
     if (out) out[2 * i] = (double)r;
 }
 
@@ -200,13 +202,15 @@ __global__ __launch_bounds__(256) void k_sweep_c(const C2<T> *__restrict__ u,
         return in ? u[i + ((int64_t)oz * ny + oy) * nx + ox] : C2<T>{T(0), T(0)};
     };
     const C2<T> acc = eval_stencil<D, SC, MC>(U, w, st);
-    const auto f = F[i];
-    const T d = dn[i], e = T(2) * d - T(1);
-    const C2<T> p = up[i];
+    const T fx = __builtin_nontemporal_load(&F[i].x), fy = __builtin_nontemporal_load(&F[i].y);
+    const auto f = typename V2<T>::type{fx, fy};
+    const T d = __builtin_nontemporal_load(dn + i), e = T(2) * d - T(1);
+    const C2<T> p = {__builtin_nontemporal_load(&up[i].x), __builtin_nontemporal_load(&up[i].y)};
     C2<T> r;
     r.x = d * (acc.x + fa * f.x - fb * f.y) - e * p.x;
     r.y = d * (acc.y + fa * f.y + fb * f.x) - e * p.y;
-    up[i] = r;
+    __builtin_nontemporal_store(r.x, &up[i].x);
+    __builtin_nontemporal_store(r.y, &up[i].y);
     if (out) out[i] = make_double2((double)r.x, (double)r.y);
 }
 

@@ -7,7 +7,9 @@
 // rotate through LDS, so every plane of u and of the cell slowness is fetched
 // from HBM about once per step (plus the in-plane halo) instead of being
 // re-read for each of its 19 or 27 uses.  u_{j-1}, the damping factor and F are
-// read once per node straight from HBM.  Workgroups are ordered so each XCD
+// read once per node straight from HBM, and u_{j+1} written once, with
+// non-temporal loads / stores so that they do not evict the u and cell planes
+// whose halos neighbouring workgroups re-read from L2.  Workgroups are ordered so each XCD
 // gets a contiguous range of tiles (in-plane halo re-reads hit its L2).
 #include <hip/hip_runtime.h>
 
@@ -138,11 +140,10 @@ __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream(
             nup[q] = nd[q] = nfr[q] = nfi[q] = T(0);
             if (gy < ny && gx < nx && p < ze) {
                 const int64_t i = p * plane + (int64_t)gy * nx + gx;
-                nup[q] = up[i];
-                nd[q] = dn[i];
-                const auto f = F[i];
-                nfr[q] = f.x;
-                nfi[q] = f.y;
+                nup[q] = __builtin_nontemporal_load(up + i);
+                nd[q] = __builtin_nontemporal_load(dn + i);
+                nfr[q] = __builtin_nontemporal_load(&F[i].x);
+                nfi[q] = __builtin_nontemporal_load(&F[i].y);
             }
         }
     };
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream(
                 const T r =
                     cd[q] * (acc + fa * cfr[q] + fb * cfi[q]) - (T(2) * cd[q] - T(1)) * cup[q];
                 const int64_t i = z * plane + (int64_t)gy * nx + gx;
-                up[i] = r;
+                __builtin_nontemporal_store(r, up + i);
                 if (out) out[2 * i] = (double)r;
             }
         }
@@ -302,11 +303,10 @@ __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream2(
             num[q] = nd[q] = nfr[q] = nfi[q] = T(0);
             if (xin && (unsigned)gy < (unsigned)ny && (unsigned)p < (unsigned)nz) {
                 const int64_t i = p * plane + (int64_t)gy * nx + gx;
-                num[q] = up[i];
-                nd[q] = dn[i];
-                const auto f = F[i];
-                nfr[q] = f.x;
-                nfi[q] = f.y;
+                num[q] = __builtin_nontemporal_load(up + i);
+                nd[q] = __builtin_nontemporal_load(dn + i);
+                nfr[q] = __builtin_nontemporal_load(&F[i].x);
+                nfi[q] = __builtin_nontemporal_load(&F[i].y);
             }
         }
     };
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream2(
                 v = cd[q] * (acc + fa1 * cfr[q] + fb1 * cfi[q]) - (T(2) * cd[q] - T(1)) * cum[q];
                 if (a >= zb && a < ze && tx >= 1 && tx < 63 && ry >= 1 && ry < RT - 1) {
                     const int64_t i = a * plane + (int64_t)gy * nx + gx;
-                    u1o[i] = v;
+                    __builtin_nontemporal_store(v, u1o + i);
                     if (out1) out1[2 * i] = (double)v;
                 }
             }
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream2(
                     const T uc = u0c[(ry + 1) * EX + tx + 1];
                     const T v = pd[q] * (acc + fa2 * pfr[q] + fb2 * pfi[q]) - (T(2) * pd[q] - T(1)) * uc;
                     const int64_t i = b * plane + (int64_t)gy * nx + gx;
-                    u2o[i] = v;
+                    __builtin_nontemporal_store(v, u2o + i);
                     if (out2) out2[2 * i] = (double)v;
                 }
             }
