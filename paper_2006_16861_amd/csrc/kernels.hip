@@ -107,7 +107,7 @@ __device__ __forceinline__ void load_cells(const T *__restrict__ m, int z, int y
 //   u_{j+1} = d (S[u_j] + fa Re F + fb Im F) - (2d - 1) u_{j-1},
 // S[.] the stencil with the step constants (it equals (2 - K) u), d = 1/(1+l/2).
 // u_{j+1} overwrites u_{j-1} in place.
-template <int D, int SC, int MC, typename T>
+template <int D, int SC, int MC, typename T, bool NT>
 __global__ __launch_bounds__(256) void k_sweep(const T *__restrict__ u, T *__restrict__ up,
                                                const T *__restrict__ m,
                                                const T *__restrict__ dn,
@@ -128,12 +128,11 @@ __global__ __launch_bounds__(256) void k_sweep(const T *__restrict__ u, T *__res
         return in ? u[i + ((int64_t)oz * ny + oy) * nx + ox] : T(0);
     };
     const T acc = eval_stencil<D, SC, MC>(U, w, st);
-    // per-node streams (read / written once): non-temporal, so that L2 keeps
-    // the u rows and cells that neighbouring workgroups re-read
-    const T fx = __builtin_nontemporal_load(&F[i].x), fy = __builtin_nontemporal_load(&F[i].y);
-    const T d = __builtin_nontemporal_load(dn + i);
-    const T r = d * (acc + fa * fx + fb * fy) - (T(2) * d - T(1)) * __builtin_nontemporal_load(up + i);
-    __builtin_nontemporal_store(r, up + i);
+    // per-node streams (read / written once per step; see stream_nt)
+    const T fx = ldnt<NT>(&F[i].x), fy = ldnt<NT>(&F[i].y);
+    const T d = ldnt<NT>(dn + i);
+    const T r = d * (acc + fa * fx + fb * fy) - (T(2) * d - T(1)) * ldnt<NT>(up + i);
+    stnt<NT>(r, up + i);
     if (out) out[2 * i] = (double)r;
 }
 
@@ -151,8 +150,14 @@ static hipError_t launch_sweep_t(const SweepArgs &a, const Stencil<T> &st, T fa,
     const T *m = (const T *)a.m;
     const T *dn = (const T *)a.dn;
     const auto *F = (const typename V2<T>::type *)a.F;
-#define TDP_SWEEP(D, SC, MC) \
-    hipLaunchKernelGGL((k_sweep<D, SC, MC, T>), grd, blk, 0, s, u, up, m, dn, F, nz, ny, nx, st, fa, fb, a.out)
+    const bool nt = stream_nt((int64_t)7 * sizeof(T) * nz * ny * nx);
+#define TDP_SWEEP(D, SC, MC)                                                                           \
+    do {                                                                                            \
+        if (nt)                                                                                     \
+            hipLaunchKernelGGL((k_sweep<D, SC, MC, T, true>), grd, blk, 0, s, u, up, m, dn, F, nz, ny, nx, st, fa, fb, a.out);  \
+        else                                                                                        \
+            hipLaunchKernelGGL((k_sweep<D, SC, MC, T, false>), grd, blk, 0, s, u, up, m, dn, F, nz, ny, nx, st, fa, fb, a.out); \
+    } while (0)
     if (a.ndim == 2) {
         if (a.sc <= 3 && a.mc <= 2) TDP_SWEEP(2, 3, 2);
         else TDP_SWEEP(2, 3, 3);
@@ -180,7 +185,7 @@ hipError_t launch_sweep_f32(const SweepArgs &a, const Stencil<float> &st, float 
 // complex-linear variant (Definition 4): complex field u driven by the complex
 // forcing g chi_j e^{i phi_j} F; (fa, fb) = g chi_j (cos phi_j, sin phi_j).
 //   u_{j+1} = d (S[u_j] + (fa + i fb) F) - (2d - 1) u_{j-1}
-template <int D, int SC, int MC, typename T>
+template <int D, int SC, int MC, typename T, bool NT>
 __global__ __launch_bounds__(256) void k_sweep_c(const C2<T> *__restrict__ u,
                                                  C2<T> *__restrict__ up,
                                                  const T *__restrict__ m,
@@ -202,15 +207,15 @@ __global__ __launch_bounds__(256) void k_sweep_c(const C2<T> *__restrict__ u,
         return in ? u[i + ((int64_t)oz * ny + oy) * nx + ox] : C2<T>{T(0), T(0)};
     };
     const C2<T> acc = eval_stencil<D, SC, MC>(U, w, st);
-    const T fx = __builtin_nontemporal_load(&F[i].x), fy = __builtin_nontemporal_load(&F[i].y);
+    const T fx = ldnt<NT>(&F[i].x), fy = ldnt<NT>(&F[i].y);
     const auto f = typename V2<T>::type{fx, fy};
-    const T d = __builtin_nontemporal_load(dn + i), e = T(2) * d - T(1);
-    const C2<T> p = {__builtin_nontemporal_load(&up[i].x), __builtin_nontemporal_load(&up[i].y)};
+    const T d = ldnt<NT>(dn + i), e = T(2) * d - T(1);
+    const C2<T> p = {ldnt<NT>(&up[i].x), ldnt<NT>(&up[i].y)};
     C2<T> r;
     r.x = d * (acc.x + fa * f.x - fb * f.y) - e * p.x;
     r.y = d * (acc.y + fa * f.y + fb * f.x) - e * p.y;
-    __builtin_nontemporal_store(r.x, &up[i].x);
-    __builtin_nontemporal_store(r.y, &up[i].y);
+    stnt<NT>(r.x, &up[i].x);
+    stnt<NT>(r.y, &up[i].y);
     if (out) out[i] = make_double2((double)r.x, (double)r.y);
 }
 
@@ -229,8 +234,14 @@ static hipError_t launch_sweep_c_t(const SweepArgs &a, const Stencil<T> &st, T f
     const T *dn = (const T *)a.dn;
     const auto *F = (const typename V2<T>::type *)a.F;
     double2 *out = (double2 *)a.out;
-#define TDP_SWEEPC(D, SC, MC) \
-    hipLaunchKernelGGL((k_sweep_c<D, SC, MC, T>), grd, blk, 0, s, u, up, m, dn, F, nz, ny, nx, st, fa, fb, out)
+    const bool nt = stream_nt((int64_t)10 * sizeof(T) * nz * ny * nx);
+#define TDP_SWEEPC(D, SC, MC)                                                                          \
+    do {                                                                                            \
+        if (nt)                                                                                     \
+            hipLaunchKernelGGL((k_sweep_c<D, SC, MC, T, true>), grd, blk, 0, s, u, up, m, dn, F, nz, ny, nx, st, fa, fb, out);  \
+        else                                                                                        \
+            hipLaunchKernelGGL((k_sweep_c<D, SC, MC, T, false>), grd, blk, 0, s, u, up, m, dn, F, nz, ny, nx, st, fa, fb, out); \
+    } while (0)
     if (a.ndim == 2) {
         if (a.sc <= 3 && a.mc <= 2) TDP_SWEEPC(2, 3, 2);
         else TDP_SWEEPC(2, 3, 3);
@@ -263,7 +274,7 @@ hipError_t launch_sweep_c_f32(const SweepArgs &a, const Stencil<float> &st, floa
 // stA the I_acd step stencil (2 - (dt^2/alpha) A) over the cell slowness, stB_r
 // the mass-class stencil of (beta dt/(alpha omega)) Im H over the cell damping.
 // u_{n-1} is read at the neighbours too, so u_{n+1} goes to a third field.
-template <int D, int SC, int MC>
+template <int D, int SC, int MC, bool NT>
 __global__ __launch_bounds__(256) void k_sweep_abd(const C2<double> *__restrict__ u,
                                                    const C2<double> *__restrict__ um,
                                                    C2<double> *__restrict__ uo,
@@ -297,12 +308,13 @@ __global__ __launch_bounds__(256) void k_sweep_abd(const C2<double> *__restrict_
     };
     const C2<double> acc = eval_stencil<D, SC, MC>(U, wm, stA);
     const C2<double> dmp = eval_stencil<D, 1, MC>(W, wr, stB);
-    const double2 f = F[i];
+    const double fx = ldnt<NT>(&F[i].x), fy = ldnt<NT>(&F[i].y);
     const C2<double> p = um[i];
     C2<double> r;
-    r.x = acc.x + dmp.x - p.x + fa * f.x - fb * f.y;
-    r.y = acc.y + dmp.y - p.y + fa * f.y + fb * f.x;
-    uo[i] = r;
+    r.x = acc.x + dmp.x - p.x + fa * fx - fb * fy;
+    r.y = acc.y + dmp.y - p.y + fa * fy + fb * fx;
+    stnt<NT>(r.x, &uo[i].x);
+    stnt<NT>(r.y, &uo[i].y);
     if (out) out[i] = make_double2(r.x, r.y);
 }
 
@@ -321,8 +333,14 @@ hipError_t launch_sweep_abd(const SweepArgs &a, void *uout, const double *rc,
     const double *m = (const double *)a.m;
     const double2 *F = (const double2 *)a.F;
     double2 *out = (double2 *)a.out;
-#define TDP_SWEEPB(D, SC, MC) \
-    hipLaunchKernelGGL((k_sweep_abd<D, SC, MC>), grd, blk, 0, s, u, um, uo, m, rc, F, nz, ny, nx, stA, stB, cth, fa, fb, out)
+    const bool nt = stream_nt((int64_t)80 * nz * ny * nx);
+#define TDP_SWEEPB(D, SC, MC)                                                                          \
+    do {                                                                                            \
+        if (nt)                                                                                     \
+            hipLaunchKernelGGL((k_sweep_abd<D, SC, MC, true>), grd, blk, 0, s, u, um, uo, m, rc, F, nz, ny, nx, stA, stB, cth, fa, fb, out);  \
+        else                                                                                        \
+            hipLaunchKernelGGL((k_sweep_abd<D, SC, MC, false>), grd, blk, 0, s, u, um, uo, m, rc, F, nz, ny, nx, stA, stB, cth, fa, fb, out); \
+    } while (0)
     if (a.ndim == 2) {
         if (a.sc <= 3 && a.mc <= 2) TDP_SWEEPB(2, 3, 2);
         else TDP_SWEEPB(2, 3, 3);
@@ -338,7 +356,7 @@ hipError_t launch_sweep_abd(const SweepArgs &a, void *uout, const double *rc,
 // complex H-apply: y = H x or y = F - H x, H = stencil + i diag(rw)
 // With the cell damping (CD), Im H = omega sum_cells r_cell M_cell is the
 // mass-class stencil stI over the cell damping rc instead of diag(rw).
-template <int D, int SC, int MC, bool CD>
+template <int D, int SC, int MC, bool CD, bool NT>
 __global__ __launch_bounds__(256) void k_apply_H(const double *__restrict__ m,
                                                  const double *__restrict__ rw,
                                                  const double *__restrict__ rc,
@@ -381,11 +399,11 @@ __global__ __launch_bounds__(256) void k_apply_H(const double *__restrict__ m,
         o.y = hi + r * xc.x;
     }
     if (F) {
-        const double2 f = F[i];
-        o.x = f.x - o.x;
-        o.y = f.y - o.y;
+        o.x = ldnt<NT>(&F[i].x) - o.x;
+        o.y = ldnt<NT>(&F[i].y) - o.y;
     }
-    y_out[i] = o;
+    stnt<NT>(o.x, &y_out[i].x);
+    stnt<NT>(o.y, &y_out[i].y);
 }
 
 hipError_t launch_apply_H(int ndim, const int *n, int sc, int mc, const double *m,
@@ -401,8 +419,14 @@ hipError_t launch_apply_H(int ndim, const int *n, int sc, int mc, const double *
     const double2 *xv = (const double2 *)x;
     const double2 *Fv = (const double2 *)F;
     double2 *yv = (double2 *)y;
-#define TDP_HAPPLY(D, SC, MC, CD) \
-    hipLaunchKernelGGL((k_apply_H<D, SC, MC, CD>), grd, blk, 0, s, m, rw, rc, st, stI, xv, Fv, yv, nz, ny, nx)
+    const bool nt = stream_nt((int64_t)56 * nz * ny * nx);
+#define TDP_HAPPLY(D, SC, MC, CD)                                                                      \
+    do {                                                                                            \
+        if (nt)                                                                                     \
+            hipLaunchKernelGGL((k_apply_H<D, SC, MC, CD, true>), grd, blk, 0, s, m, rw, rc, st, stI, xv, Fv, yv, nz, ny, nx);  \
+        else                                                                                        \
+            hipLaunchKernelGGL((k_apply_H<D, SC, MC, CD, false>), grd, blk, 0, s, m, rw, rc, st, stI, xv, Fv, yv, nz, ny, nx); \
+    } while (0)
 #define TDP_HAPPLY2(D, SC, MC) \
     do { if (rc) TDP_HAPPLY(D, SC, MC, true); else TDP_HAPPLY(D, SC, MC, false); } while (0)
     if (ndim == 2) {

@@ -7,9 +7,8 @@
 // rotate through LDS, so every plane of u and of the cell slowness is fetched
 // from HBM about once per step (plus the in-plane halo) instead of being
 // re-read for each of its 19 or 27 uses.  u_{j-1}, the damping factor and F are
-// read once per node straight from HBM, and u_{j+1} written once, with
-// non-temporal loads / stores so that they do not evict the u and cell planes
-// whose halos neighbouring workgroups re-read from L2.  Workgroups are ordered so each XCD
+// read once per node straight from HBM, and u_{j+1} written once (non-temporal
+// when the step's working set exceeds the MALL, see stream_nt).  Workgroups are ordered so each XCD
 // gets a contiguous range of tiles (in-plane halo re-reads hit its L2).
 #include <hip/hip_runtime.h>
 
@@ -65,7 +64,7 @@ __device__ __forceinline__ T stencil27(const LoadU &U, const T *w, const Stencil
     return r;
 }
 
-template <typename T, int SC, int MC, int TY, int RY>
+template <typename T, int SC, int MC, int TY, int RY, bool NTS>
 __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream(
     const T *__restrict__ u, T *__restrict__ up, const T *__restrict__ m,
     const T *__restrict__ dn, const typename V2s<T>::type *__restrict__ F, int nz, int ny,
@@ -140,10 +139,10 @@ __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream(
             nup[q] = nd[q] = nfr[q] = nfi[q] = T(0);
             if (gy < ny && gx < nx && p < ze) {
                 const int64_t i = p * plane + (int64_t)gy * nx + gx;
-                nup[q] = __builtin_nontemporal_load(up + i);
-                nd[q] = __builtin_nontemporal_load(dn + i);
-                nfr[q] = __builtin_nontemporal_load(&F[i].x);
-                nfi[q] = __builtin_nontemporal_load(&F[i].y);
+                nup[q] = ldnt<NTS>(up + i);
+                nd[q] = ldnt<NTS>(dn + i);
+                nfr[q] = ldnt<NTS>(&F[i].x);
+                nfi[q] = ldnt<NTS>(&F[i].y);
             }
         }
     };
@@ -200,7 +199,7 @@ __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream(
                 const T r =
                     cd[q] * (acc + fa * cfr[q] + fb * cfi[q]) - (T(2) * cd[q] - T(1)) * cup[q];
                 const int64_t i = z * plane + (int64_t)gy * nx + gx;
-                __builtin_nontemporal_store(r, up + i);
+                stnt<NTS>(r, up + i);
                 if (out) out[2 * i] = (double)r;
             }
         }
@@ -222,7 +221,7 @@ __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream(
 // ahead and kept one iteration longer for level 2.  Per node and launch this
 // reads u_j, u_{j-1}, m, d, F once and writes u_{j+1}, u_{j+2}: about 4 words
 // per node-step instead of 7.  Outputs must not alias the inputs.
-template <typename T, int SC, int MC, int TY, int RY>
+template <typename T, int SC, int MC, int TY, int RY, bool NTS>
 __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream2(
     const T *__restrict__ u, const T *__restrict__ up, T *__restrict__ u2o,
     T *__restrict__ u1o, const T *__restrict__ m, const T *__restrict__ dn,
@@ -303,10 +302,10 @@ __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream2(
             num[q] = nd[q] = nfr[q] = nfi[q] = T(0);
             if (xin && (unsigned)gy < (unsigned)ny && (unsigned)p < (unsigned)nz) {
                 const int64_t i = p * plane + (int64_t)gy * nx + gx;
-                num[q] = __builtin_nontemporal_load(up + i);
-                nd[q] = __builtin_nontemporal_load(dn + i);
-                nfr[q] = __builtin_nontemporal_load(&F[i].x);
-                nfi[q] = __builtin_nontemporal_load(&F[i].y);
+                num[q] = ldnt<NTS>(up + i);
+                nd[q] = ldnt<NTS>(dn + i);
+                nfr[q] = ldnt<NTS>(&F[i].x);
+                nfi[q] = ldnt<NTS>(&F[i].y);
             }
         }
     };
@@ -367,7 +366,7 @@ __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream2(
                 v = cd[q] * (acc + fa1 * cfr[q] + fb1 * cfi[q]) - (T(2) * cd[q] - T(1)) * cum[q];
                 if (a >= zb && a < ze && tx >= 1 && tx < 63 && ry >= 1 && ry < RT - 1) {
                     const int64_t i = a * plane + (int64_t)gy * nx + gx;
-                    __builtin_nontemporal_store(v, u1o + i);
+                    stnt<NTS>(v, u1o + i);
                     if (out1) out1[2 * i] = (double)v;
                 }
             }
@@ -400,7 +399,7 @@ __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream2(
                     const T uc = u0c[(ry + 1) * EX + tx + 1];
                     const T v = pd[q] * (acc + fa2 * pfr[q] + fb2 * pfi[q]) - (T(2) * pd[q] - T(1)) * uc;
                     const int64_t i = b * plane + (int64_t)gy * nx + gx;
-                    __builtin_nontemporal_store(v, u2o + i);
+                    stnt<NTS>(v, u2o + i);
                     if (out2) out2[2 * i] = (double)v;
                 }
             }
@@ -435,14 +434,19 @@ static hipError_t launch_stream2_t(const Stream2Args &a, const Stencil<T> &st, h
     const T *m = (const T *)a.m, *dn = (const T *)a.dn;
     const auto *F = (const typename V2s<T>::type *)a.F;
     const T fa1 = (T)a.fa[0], fb1 = (T)a.fb[0], fa2 = (T)a.fa[1], fb2 = (T)a.fb[1];
-    if (a.sc <= 3 && a.mc <= 2)
-        hipLaunchKernelGGL((k_sweep3d_stream2<T, 3, 2, TY, RY>), grd, blk, 0, s, u, up, u2o, u1o, m,
-                           dn, F, nz, ny, nx, st, fa1, fb1, fa2, fb2, a.out1, a.out2, zc, tiles_x,
-                           tiles_y, ntiles, per_xcd);
-    else
-        hipLaunchKernelGGL((k_sweep3d_stream2<T, 4, 4, TY, RY>), grd, blk, 0, s, u, up, u2o, u1o, m,
-                           dn, F, nz, ny, nx, st, fa1, fb1, fa2, fb2, a.out1, a.out2, zc, tiles_x,
-                           tiles_y, ntiles, per_xcd);
+    const bool nt = stream_nt((int64_t)7 * sizeof(T) * nz * ny * nx);
+#define TDP_S2(SC, MC, NTS)                                                                           \
+    hipLaunchKernelGGL((k_sweep3d_stream2<T, SC, MC, TY, RY, NTS>), grd, blk, 0, s, u, up, u2o, u1o, m, \
+                       dn, F, nz, ny, nx, st, fa1, fb1, fa2, fb2, a.out1, a.out2, zc, tiles_x,        \
+                       tiles_y, ntiles, per_xcd)
+    if (a.sc <= 3 && a.mc <= 2) {
+        if (nt) TDP_S2(3, 2, true);
+        else TDP_S2(3, 2, false);
+    } else {
+        if (nt) TDP_S2(4, 4, true);
+        else TDP_S2(4, 4, false);
+    }
+#undef TDP_S2
     return hipGetLastError();
 }
 
@@ -482,12 +486,18 @@ static hipError_t launch_stream_t(const SweepArgs &a, const Stencil<T> &st, T fa
     T *up = (T *)a.up;
     const T *m = (const T *)a.m, *dn = (const T *)a.dn;
     const auto *F = (const typename V2s<T>::type *)a.F;
-    if (a.sc <= 3 && a.mc <= 2)
-        hipLaunchKernelGGL((k_sweep3d_stream<T, 3, 2, TY, RY>), grd, blk, 0, s, u, up, m, dn, F,
-                           nz, ny, nx, st, fa, fb, a.out, zc, tiles_x, tiles_y, ntiles, per_xcd);
-    else
-        hipLaunchKernelGGL((k_sweep3d_stream<T, 4, 4, TY, RY>), grd, blk, 0, s, u, up, m, dn, F,
-                           nz, ny, nx, st, fa, fb, a.out, zc, tiles_x, tiles_y, ntiles, per_xcd);
+    const bool nt = stream_nt((int64_t)7 * sizeof(T) * nz * ny * nx);
+#define TDP_S1(SC, MC, NTS)                                                                       \
+    hipLaunchKernelGGL((k_sweep3d_stream<T, SC, MC, TY, RY, NTS>), grd, blk, 0, s, u, up, m, dn, F, \
+                       nz, ny, nx, st, fa, fb, a.out, zc, tiles_x, tiles_y, ntiles, per_xcd)
+    if (a.sc <= 3 && a.mc <= 2) {
+        if (nt) TDP_S1(3, 2, true);
+        else TDP_S1(3, 2, false);
+    } else {
+        if (nt) TDP_S1(4, 4, true);
+        else TDP_S1(4, 4, false);
+    }
+#undef TDP_S1
     return hipGetLastError();
 }
 

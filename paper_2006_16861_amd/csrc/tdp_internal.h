@@ -46,6 +46,31 @@ struct Stencil {
     T m[4];
 };
 
+// Per-node streams (u_{j-1}, damping factor, F, the new field) are read or
+// written once per step.  When a step's working set exceeds the 256 MB MALL
+// they go non-temporal, so that L2 keeps the rows and planes that neighbouring
+// workgroups re-read; when it fits, the normal policy keeps them cached for the
+// next step.
+// The choice is a template parameter of the kernels (a run-time select between
+// the two load forms would be merged into one plain load).
+inline bool stream_nt(int64_t bytes) { return bytes > ((int64_t)192 << 20); }
+template <bool NT, typename T>
+__device__ __forceinline__ T ldnt(const T *p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void stnt(T v, T *p)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 // Launch geometry / variant choice for the sweep.
 struct SweepCfg {
     int kernel = 1;       // 1 one step per launch, 2 temporally blocked
