@@ -25,7 +25,7 @@ def test_header_declares_core_entry_points():
 def test_library_exports_every_declared_symbol():
     from paper_2006_16861_amd import tdp
     if not os.path.exists(tdp.LIB_PATH):
-        pytest.fail("libtdp.so is not built (run __graft_entry__.build())")
+        pytest.fail("libtdp.so is not built (run python -m paper_2006_16861_amd.build)")
     lib = ctypes.CDLL(tdp.LIB_PATH)
     for s in declared_symbols():
         assert hasattr(lib, s), f"{s} declared in include/tdp.h but not exported"
