@@ -192,6 +192,8 @@ static int build_fields(tdp_batch *b, const int *T_op, double rho)
     return TDP_OK;
 }
 
+static const size_t kMaxBatchGraphs = 32;
+
 // One batched preconditioner application (Table 1) for the fields with
 // active[q] != 0: reads each field's pin, writes its pout.
 static int batch_precond(tdp_batch *b, const int *T_op, double rho, const std::vector<char> &active)
@@ -271,16 +273,32 @@ static int batch_precond(tdp_batch *b, const int *T_op, double rho, const std::v
             le = launch_sweep2d_tb_batch(bl, b->f64, s);
         }
         hipError_t ce = hipStreamEndCapture(s, &g);
-        if (le != hipSuccess) {
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (ce == hipSuccess) (void)hipGraphDestroy(g);
             (void)hipFree(dsched);
             TDP_CHECK_HIP(le);
+            TDP_CHECK_HIP(ce);
         }
-        TDP_CHECK_HIP(ce);
         hipGraphExec_t ge;
         hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (ie != hipSuccess) (void)hipFree(dsched);
         TDP_CHECK_HIP(ie);
+        // one graph per active set: as fields converge the sets change, so the
+        // cache is emptied when it would grow beyond kMaxBatchGraphs
+        if (b->graphs.size() >= kMaxBatchGraphs) {
+            const hipError_t se = hipStreamSynchronize(s);
+            for (auto &kv : b->graphs) {
+                (void)hipGraphExecDestroy(kv.second.first);
+                (void)hipFree(kv.second.second);
+            }
+            b->graphs.clear();
+            if (se != hipSuccess) {
+                (void)hipGraphExecDestroy(ge);
+                (void)hipFree(dsched);
+                TDP_CHECK_HIP(se);
+            }
+        }
         it = b->graphs.emplace(key, std::make_pair(ge, dsched)).first;
     }
     TDP_CHECK_HIP(hipGraphLaunch(it->second.first, s));

@@ -36,6 +36,10 @@ static void clear_error() { g_last_error.clear(); }
         return (code);             \
     } while (0)
 
+// Captured step loops kept per op (keyed by T, rho, variant and tuning); the
+// cache is emptied when it would grow beyond this.
+static const size_t kMaxGraphs = 16;
+
 // Classical fourth-order compact scheme in the cell form (entries by the
 // number of axes on which two corners of a cell differ).
 static const double kStiff2[3] = {5.0 / 6.0, -1.0 / 3.0, -1.0 / 6.0};
@@ -690,12 +694,21 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
         int rc = issue_steps(op, T, rho, variant, op->prec == TDP_F64 ? op->Fstage : op->Fst,
                              op->Ustage);
         hipError_t ce = hipStreamEndCapture(s, &g);
-        if (rc != TDP_OK) return rc;
+        if (rc != TDP_OK) {
+            if (ce == hipSuccess) (void)hipGraphDestroy(g);
+            return rc;
+        }
         TDP_CHECK_HIP(ce);
         hipGraphExec_t ge;
         hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         TDP_CHECK_HIP(ie);
+        // each graph holds N_s launch nodes: keep at most kMaxGraphs per op
+        if (op->graphs.size() >= kMaxGraphs) {
+            TDP_CHECK_HIP(hipStreamSynchronize(s));
+            for (auto &kv : op->graphs) (void)hipGraphExecDestroy(kv.second);
+            op->graphs.clear();
+        }
         it = op->graphs.emplace(key, ge).first;
     }
     if (op->prec == TDP_F64)

@@ -485,3 +485,20 @@ def test_gmres_short_T_matches_oracle(model, T):
     assert rel(o.apply_H(host(Ug)), p.F) <= 1e-6 * (1 + 1e-9)
     if ig.iters == io["iters"]:
         assert rel(host(Ug), Uo) <= 1e-8
+
+
+def test_graph_cache_beyond_its_cap():
+    """More (T, rho) pairs than the per-op cache of captured loops holds: the
+    cache is emptied and rebuilt, results stay identical to the oracle."""
+    p = inputs.random_medium((37, 150), seed=41, width=4)
+    note("graph cache: 24 captured loops on one op")
+    g, o = make_ops(p)
+    F = dev(p.F)
+    first = host(g.precond(F, 1, 0.25))
+    assert rel(first, o.precond(p.F, 1, 0.25)) <= TOL64
+    for T in range(2, 14):
+        for rho in (0.25, 0.5):
+            U = host(g.precond(F, T, rho))
+            if T in (7, 13):
+                assert rel(U, o.precond(p.F, T, rho)) <= TOL64
+    assert rel(host(g.precond(F, 1, 0.25)), first) <= 1e-15
