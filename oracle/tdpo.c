@@ -264,7 +264,7 @@ int tdpo_op_create(int ndim, const long *n, double h, double omega,
         } else if (nP < 0) {
             nP = -nP;
             if (nP % 4) { tdpo_op_destroy(op); return TDPO_EINVAL; }
-        } else if (nP % 4 != 0 || !abd_stable(2.0 * M_PI / nP, kmax2, lam_s, op->lam_im, NULL)) {
+        } else if (nP < 3 || !abd_stable(2.0 * M_PI / nP, kmax2, lam_s, op->lam_im, NULL)) {
             tdpo_op_destroy(op);
             return TDPO_ECFL;
         }
@@ -290,7 +290,7 @@ int tdpo_op_create(int ndim, const long *n, double h, double omega,
     } else if (nP < 0) {
         nP = -nP;   /* test hook: accept any n_P (multiple of 4) without the CFL check */
         if (nP % 4) { tdpo_op_destroy(op); return TDPO_EINVAL; }
-    } else if (nP % 4 != 0 || !((double)nP > nmin)) {
+    } else if (nP < 3 || !((double)nP > nmin)) {
         tdpo_op_destroy(op);
         return TDPO_ECFL;
     }
@@ -483,7 +483,11 @@ int tdpo_precond_apply(const tdpo_op *op, int T, double rho, const double comple
     if (rho > 1.0) return TDPO_EINVAL;
     long N = op->N;
     int nP = op->nP;
-    long Ns = (long)T * nP, jsnap = Ns - nP / 4;
+    /* the second sample lies q steps (phase phi = 2 pi q / n_P) before the end:
+     * u_{N_s - q} = cos(phi) Re U + sin(phi) Im U, so Im U comes from a 2x2 solve
+     * with Re U = u_{N_s}; for 4 | n_P, q = n_P/4 and Im U = u_{N_s - q} (Table 1) */
+    int q = nP % 4 == 0 ? nP / 4 : (nP + 2) / 4;
+    long Ns = (long)T * nP, jsnap = Ns - q;
     double *um = calloc(N, sizeof(double)), *u = calloc(N, sizeof(double));
     double *up = malloc(sizeof(double) * N), *f = malloc(sizeof(double) * N);
     double *snap = malloc(sizeof(double) * N);
@@ -499,7 +503,12 @@ int tdpo_precond_apply(const tdpo_op *op, int T, double rho, const double comple
         double *t = um; um = u; u = up; up = t;     /* now u = u_{j+1} */
         if (j + 1 == jsnap) memcpy(snap, u, sizeof(double) * N);
     }
-    for (long b = 0; b < N; ++b) U[b] = u[b] + I * snap[b];
+    if (nP % 4 == 0) {
+        for (long b = 0; b < N; ++b) U[b] = u[b] + I * snap[b];
+    } else {
+        double phi = 2.0 * M_PI * q / nP, c = cos(phi), s = sin(phi);
+        for (long b = 0; b < N; ++b) U[b] = u[b] + I * ((snap[b] - c * u[b]) / s);
+    }
     free(um); free(u); free(up); free(f); free(snap);
     return TDPO_OK;
 }

@@ -17,8 +17,11 @@ enum { TDPO_OK = 0, TDPO_ENOTCONV = 1, TDPO_EINVAL = -1, TDPO_ENOMEM = -2, TDPO_
 
 typedef struct tdpo_op tdpo_op;
 
-/* nP == 0: automatic; nP > 0: checked against the CFL bound; nP < 0: test
- * hook, |nP| used without the CFL check (to exhibit instability).
+/* nP == 0: automatic (smallest multiple of 4 above the CFL bound); nP > 0:
+ * any n_P >= 3 above the bound (Table 1 then samples the field a phase
+ * 2 pi q/n_P before the end, q = round(n_P/4), and solves a 2x2 system for
+ * Im U); nP < 0: test hook, |nP| (a multiple of 4) used without the CFL
+ * check (to exhibit instability).
  * dform 0: Im H = diag(omega R), integrator I_acd (Def. 2);
  * dform 1: Im H = omega sum_cells r_cell M_cell (r_cell = corner mean of R),
  *          integrator I_abd (Sec. 5, Def. 6), S_T^abd (Def. 7). */

@@ -223,14 +223,23 @@ def scalar_precond(kv, lv, g, nP, T, rho, a, variant=0):
 
     if variant:     # Definition 4: complex forcing, S_T F = u_{N_s}
         return u_at(Ns, cplx=True)
-    return u_at(Ns) + 1j * u_at(Ns - nP // 4)
+    if nP % 4 == 0:
+        return u_at(Ns) + 1j * u_at(Ns - nP // 4)
+    # two samples q steps apart; a time-harmonic field Re(U e^{i w t}) at
+    # phases 0 and -phi: least squares over (Re U, Im U) of the 2 samples
+    q = (nP + 2) // 4
+    phi = 2 * math.pi * q / nP
+    A = np.array([[1.0, 0.0], [math.cos(phi), math.sin(phi)]])
+    x = np.linalg.lstsq(A, np.array([u_at(Ns), u_at(Ns - q)]), rcond=None)[0]
+    return x[0] + 1j * x[1]
 
 
+@pytest.mark.parametrize("nP", [0, 10, 11])
 @pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("n,p,rval", [((7, 6), (2, 3), 0.0), ((7, 6), (1, 1), 0.3),
                                        ((4, 3, 5), (1, 2, 3), 0.2)])
-def test_precond_on_eigenvector_matches_green_function(n, p, rval, variant):
-    op, h, omega, c, R = const_op(n, cval=1.1, rval=rval)
+def test_precond_on_eigenvector_matches_green_function(n, p, rval, variant, nP):
+    op, h, omega, c, R = const_op(n, cval=1.1, rval=rval, nP=nP)
     e = sine_mode(n, p)
     theta = [math.pi * pa / (na + 1) for na, pa in zip(n, p)]
     S, M = compact_symbols(theta)
@@ -277,6 +286,37 @@ def test_precond_converges_to_inverse(variant):
         errs.append(np.linalg.norm(PF - U) / np.linalg.norm(U))
     assert all(b < a for a, b in zip(errs, errs[1:])), errs
     assert errs[-1] < 1e-8, errs
+
+
+@pytest.mark.parametrize("nP", [10, 11, 13])
+def test_general_steps_per_period_converges_to_inverse(nP):
+    """Table 1 with 4 not dividing n_P (Sec. 2.3): the two samples lie a phase
+    2 pi q/n_P apart, and Im U from the 2x2 solve still gives S_T F -> H^-1 F.
+    At 8 points per wavelength the CFL bound is 9.58, so n_P = 10 is allowed."""
+    n = (10, 9)
+    op, h, omega, c, R = const_op(n, cval=1.0, rval=0.5, ppw=8.0, nP=nP)
+    assert op.nP == nP
+    rng = np.random.default_rng(9)
+    F = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    H = oracle.assemble_H(n, h, omega, c, R)
+    U = spla.spsolve(H.tocsc(), F.reshape(-1)).reshape(n)
+    errs = []
+    for T in [2, 4, 8, 16, 32]:
+        PF = op.precond(F, T, 0.25, variant=0)
+        errs.append(np.linalg.norm(PF - U) / np.linalg.norm(U))
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-8, errs
+
+
+def test_general_steps_per_period_cfl_checks():
+    """A given n_P must be >= 3 and strictly above the CFL bound (9.58 at
+    8 points per wavelength); the default stays the next multiple of 4."""
+    assert const_op((8, 8), ppw=8.0)[0].nP == 12
+    assert const_op((8, 8), ppw=8.0, nP=10)[0].nP == 10
+    for bad in (9, 2):
+        with pytest.raises(oracle.OracleError) as e:
+            const_op((8, 8), ppw=8.0, nP=bad)
+        assert e.value.code == oracle.ECFL
 
 
 # ---------------------------------------------------------------- GMRES
