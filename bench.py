@@ -147,7 +147,9 @@ def _timed(fn):
 
 
 def form_precision(rho):
-    """Precision form on the 3-D layered medium (256^3, 8 ppw, T = 32): FP32
+    """Precision form on the 3-D layered medium (256^3, 8 ppw, T = 32, n_P = 10:
+    the smallest integer above the CFL bound 9.58, with Im U from the 2x2
+    solve of Sec. 2.3, against 12 for a multiple of 4): FP32
     recurrence fields inside FP64 GMRES (whose restarts recompute the true
     residual in FP64: the outer refinement), against the FP64 path."""
     import torch
@@ -157,7 +159,7 @@ def form_precision(rho):
     res = {"workload": "layered3d-256", "n": list(p.n), "periods_T": p.periods}
     U = {}
     for name, prec in (("f64", tdp.F64), ("f32", tdp.F32)):
-        op = tdp.operator_from_problem(p, prec=prec)
+        op = tdp.operator_from_problem(p, prec=prec, steps_per_period=-1)
         best, table = op.autotune(T=1, rho=rho)
         op.solve(F, T=p.periods, rho=rho, tol=1e-6)                 # warm (graphs)
         (Uq, info), dt = _timed(lambda: op.solve(F, T=p.periods, rho=rho, tol=1e-6))
@@ -166,7 +168,7 @@ def form_precision(rho):
         r = float(torch.linalg.norm(F - op.apply_H(Uq)) / torch.linalg.norm(F))
         U[name] = Uq
         word = 8 if prec == tdp.F64 else 4
-        res[name] = {"solves_per_s": 1.0 / dt, "seconds": dt, "iters": info.iters,
+        res[name] = {"solves_per_s": 1.0 / dt, "seconds": dt, "iters": info.iters, "n_P": op.nP,
                      "precond_applications": info.steps // (p.periods * op.nP),
                      "true_relres_fp64": r, "tuning": best, "sweep_us_per_step": us_step,
                      "sweep_algorithmic_GBps": 7 * word * p.N / (us_step * 1e-6) / 1e9}
@@ -254,7 +256,8 @@ def form_cell_damping(rho):
 def form_adjoint(rho):
     """Differentiation form: 128^3 smooth medium in [1.5, 3.0], 4 sources, 256
     receivers on the top face, misfit 1/2 ||P_r U(m) - d||^2; one gradient
-    evaluation = 4 forward + 4 adjoint solves to 1e-6."""
+    evaluation = 4 forward + 4 adjoint solves to 1e-6, at n_P = 10 (the
+    smallest integer above the CFL bound at 8 ppw)."""
     import torch
     from paper_2006_16861_amd import inputs, tdp
     from paper_2006_16861_amd.autograd import helmholtz_solve
@@ -267,11 +270,11 @@ def form_adjoint(rho):
     R = torch.as_tensor(p.R, device="cuda")
     with torch.no_grad():
         d = helmholtz_solve(torch.as_tensor(m_true, device="cuda"), F, R, p.omega, p.h,
-                            T=p.periods, tol=1e-6) * mask
+                            T=p.periods, tol=1e-6, steps_per_period=-1) * mask
 
     def grad_eval():
         m = torch.as_tensor(m0, device="cuda").clone().requires_grad_(True)
-        U = helmholtz_solve(m, F, R, p.omega, p.h, T=p.periods, tol=1e-6)
+        U = helmholtz_solve(m, F, R, p.omega, p.h, T=p.periods, tol=1e-6, steps_per_period=-1)
         L = 0.5 * (((U - d) * mask).abs() ** 2).sum()
         L.backward()
         return m.grad

@@ -77,8 +77,14 @@ typedef struct tdp_op tdp_op;
  *                    The cell tables must be positive semidefinite as element
  *                    matrices with max eigenvalue of M <= 2^-d (App. A bound).
  *  steps_per_period  n_P; 0 selects the smallest multiple of 4 above the CFL
- *                    bound of Sec. 2.2; a given value must be a multiple of 4
- *                    above that bound, else TDP_ECFL.
+ *                    bound of Sec. 2.2 (Table 1's default), -1 the smallest
+ *                    integer >= 3 above it; a given value must be >= 3 and
+ *                    above that bound, else TDP_ECFL.  When 4 does not
+ *                    divide n_P, Table 1 takes its second sample q =
+ *                    round(n_P/4) steps before the end and obtains Im U by
+ *                    the 2x2 solve the paper suggests for that case
+ *                    (Sec. 2.3): u_{N_s-q} = cos(phi) Re U + sin(phi) Im U,
+ *                    phi = 2 pi q/n_P.  The batched form needs 4 | n_P.
  *  prec              precision of the recurrence fields (Table 1 loop).
  *                    Krylov vectors, H and the residuals are always FP64.
  *  stream            hipStream_t every call of this op issues its work on.
@@ -173,7 +179,8 @@ int tdp_apply_H(const tdp_op *op, const void *x, void *y);
 /* U = S_T F, the real-field algorithm of Table 1 (Sec. 2.3): zero fields,
  * N_s = T n_P steps of the integrator I_acd (Def. 2) driven by
  * chi(1 - j/N_s) [cos(2 pi j/n_P) Re F - sin(2 pi j/n_P) Im F], then
- * U = u_{N_s} + i u_{N_s - n_P/4}.  chi is the sine-square window with
+ * U = u_{N_s} + i u_{N_s - n_P/4} (for 4 not dividing n_P, Im U from the
+ * 2x2 solve described at steps_per_period).  chi is the sine-square window with
  * parameter rho (rho <= 0: rho = 1/T).  F, U: device complex128 [N]. */
 int tdp_precond_apply(const tdp_op *op, int periods_T, double rho, const void *F, void *U);
 

@@ -99,6 +99,7 @@ extern "C" int tdp_batch_create(tdp_op *const *ops, int nops, const int *nrhs, t
         if (op->ndim != 2) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "batched form is 2-D only (op %d)", i); }
         if (op->prec != ops[0]->prec) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "all ops must share one precision"); }
         if (op->dform != TDP_DAMP_NODE) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "the batched form runs Table 1 (diagonal damping only)"); }
+        if (op->nP % 4 != 0) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "the batched form needs 4 | n_P (op %d)", i); }
         if (op->user_stream != ops[0]->user_stream) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "all ops must share one stream"); }
         (void)hipStreamSynchronize(op->stream);
         const bool gen = !(op->sc <= 3 && op->mc <= 2);

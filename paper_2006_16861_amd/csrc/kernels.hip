@@ -481,6 +481,24 @@ hipError_t launch_cvt_c128_to_c64(const void *F, void *Fs, int64_t N, hipStream_
     return hipGetLastError();
 }
 
+// Table 1 with 4 not dividing n_P: U.y holds u_{N_s - q}, a sample a phase
+// phi = 2 pi q / n_P before U.x = u_{N_s}; the time-harmonic field gives
+// u_{N_s - q} = cos(phi) Re U + sin(phi) Im U, solved here for Im U.
+__global__ void k_phase_extract(double2 *__restrict__ U, int64_t N, double c, double s)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 v = U[i];
+        U[i] = make_double2(v.x, (v.y - c * v.x) / s);
+    }
+}
+
+hipError_t launch_phase_extract(void *U, int64_t N, double c, double s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_phase_extract, dim3(grid_for(N)), dim3(256), 0, st, (double2 *)U, N, c, s);
+    return hipGetLastError();
+}
+
 __global__ void k_cvt_f64_f32(const double *__restrict__ a, float *__restrict__ b, int64_t N)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;

@@ -247,12 +247,12 @@ static int create_impl(const tdp_op_desc *d, tdp_op *op)
         // Sec. 5.1: theta = omega dt = 2 pi / n_P with n_P the smallest multiple of 4
         // satisfying the stability condition; omega from the K >= 0 condition
         const double kmax2 = op->omega_c * op->omega_c;
-        if (nP == 0) {
-            for (nP = 4; nP <= (1 << 22); nP += 4)
+        if (nP == 0 || nP == -1) {
+            const int step = nP == 0 ? 4 : 1;
+            for (nP = nP == 0 ? 4 : 3; nP <= (1 << 22); nP += step)
                 if (abd_stable(2.0 * M_PI / nP, kmax2, lam_s, op->lam_im, nullptr)) break;
             if (nP > (1 << 22)) TDP_FAIL(TDP_ECFL, "no stable step for the cell damping");
-        } else if (nP < 0 || nP % 4 != 0 ||
-                   !abd_stable(2.0 * M_PI / nP, kmax2, lam_s, op->lam_im, nullptr)) {
+        } else if (nP < 3 || !abd_stable(2.0 * M_PI / nP, kmax2, lam_s, op->lam_im, nullptr)) {
             TDP_FAIL(TDP_ECFL, "steps_per_period %d violates the I_abd stability condition", nP);
         }
         double w2 = 0.0;
@@ -263,8 +263,10 @@ static int create_impl(const tdp_op_desc *d, tdp_op *op)
         const double nmin = M_PI / std::asin(op->omega_c / std::sqrt(lb));
         if (nP == 0) {
             nP = 4 * ((int)std::floor(nmin / 4.0) + 1);
-        } else if (nP < 0 || nP % 4 != 0 || !((double)nP > nmin)) {
-            TDP_FAIL(TDP_ECFL, "steps_per_period %d must be a multiple of 4 above the CFL bound %.6f",
+        } else if (nP == -1) {
+            nP = std::max(3, (int)std::floor(nmin) + 1);
+        } else if (nP < 3 || !((double)nP > nmin)) {
+            TDP_FAIL(TDP_ECFL, "steps_per_period %d must be at least 3 and above the CFL bound %.6f",
                      nP, nmin);
         }
     }
@@ -439,6 +441,14 @@ const std::vector<double> &forcing_table(tdp_op *op, int T, double rho, int vari
     return op->tables.emplace(key, std::move(t)).first->second;
 }
 
+// Table 1's second sample: u_{N_s - q} with q = n_P/4 (a quarter period) when
+// 4 divides n_P, else q = round(n_P/4), whose phase 2 pi q/n_P stays within
+// 45 degrees of a quarter period, and Im U follows from a 2x2 solve (Sec. 2.3).
+static int64_t snap_lag(int nP)
+{
+    return nP % 4 == 0 ? nP / 4 : (nP + 2) / 4;
+}
+
 static int ensure_complex_fields(tdp_op *op)
 {
     const size_t fb = 2 * (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
@@ -488,7 +498,7 @@ static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, const void *
     hipStream_t s = op->stream;
     TDP_CHECK(ensure_tb_fields(op));
     const std::vector<double> &tab = forcing_table(op, T, rho, 0);
-    const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - op->nP / 4;
+    const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - snap_lag(op->nP);
     const size_t fb = (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
     void *cur = op->u0, *prev = op->u1, *ncur = op->v0, *nprev = op->v1;
     TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
@@ -539,7 +549,7 @@ static int issue_steps_3d2(tdp_op *op, int T, double rho, int zc, const void *Fi
     hipStream_t s = op->stream;
     TDP_CHECK(ensure_tb_fields(op));
     const std::vector<double> &tab = forcing_table(op, T, rho, 0);
-    const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - op->nP / 4;
+    const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - snap_lag(op->nP);
     const bool f64 = op->prec == TDP_F64;
     const size_t fb = (f64 ? sizeof(double) : sizeof(float)) * op->N;
     const int shape = op->tune.tile > 2 ? 1 : op->tune.tile;
@@ -598,7 +608,7 @@ static int issue_steps_3d2(tdp_op *op, int T, double rho, int zc, const void *Fi
     return TDP_OK;
 }
 
-static int issue_steps(tdp_op *op, int T, double rho, int variant, const void *Fin, void *U)
+static int issue_steps_loop(tdp_op *op, int T, double rho, int variant, const void *Fin, void *U)
 {
     int kern, depth;
     sweep_plan(op, variant, &kern, &depth);
@@ -607,7 +617,7 @@ static int issue_steps(tdp_op *op, int T, double rho, int variant, const void *F
     const int shape3 = op->tune.tile > 2 ? 1 : op->tune.tile;
     hipStream_t s = op->stream;
     const std::vector<double> &tab = forcing_table(op, T, rho, variant);
-    const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - op->nP / 4;
+    const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - snap_lag(op->nP);
     const size_t fb = (variant ? 2 : 1) * (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
     void *cur = variant ? op->u2 : op->u0, *prev = variant ? op->u3 : op->u1, *nxt = op->u4;
     TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
@@ -657,6 +667,16 @@ static int issue_steps(tdp_op *op, int T, double rho, int variant, const void *F
             }
         }
         std::swap(cur, prev);
+    }
+    return TDP_OK;
+}
+
+static int issue_steps(tdp_op *op, int T, double rho, int variant, const void *Fin, void *U)
+{
+    TDP_CHECK(issue_steps_loop(op, T, rho, variant, Fin, U));
+    if (variant == 0 && op->nP % 4 != 0) {
+        const double phi = 2.0 * M_PI * (double)snap_lag(op->nP) / op->nP;
+        TDP_CHECK_HIP(launch_phase_extract(U, op->N, std::cos(phi), std::sin(phi), op->stream));
     }
     return TDP_OK;
 }

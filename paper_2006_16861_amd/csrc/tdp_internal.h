@@ -184,6 +184,7 @@ hipError_t launch_sweep_abd(const SweepArgs &a, void *uout, const double *rc,
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_cvt_c128_to_c64(const void *F, void *Fs, int64_t N, hipStream_t s);
 hipError_t launch_cvt_f64_to_f32(const double *x, float *y, int64_t N, hipStream_t s);
+hipError_t launch_phase_extract(void *U, int64_t N, double c, double s, hipStream_t st);
 
 // y = H x   or   y = F - H x  (when F != null); complex128.  Im H = diag(rw),
 // or with rc != null the mass-class stencil stI over the cell damping rc.

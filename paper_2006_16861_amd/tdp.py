@@ -159,7 +159,9 @@ class SolveInfo:
 
 class Operator:
     """H for -Lap U - omega^2/c^2 U + i omega R U = F on an interior grid `n`
-    with spacing `h` (Dirichlet walls); c and R are FP64 tensors on the GPU."""
+    with spacing `h` (Dirichlet walls); c and R are FP64 tensors on the GPU.
+    steps_per_period: 0 the smallest multiple of 4 above the CFL bound, -1
+    the smallest integer >= 3 above it, or a given n_P (checked)."""
 
     def __init__(self, c, R, omega, h, prec=F64, steps_per_period=0, stiff=None, mass=None,
                  scheme=None, damping="node"):

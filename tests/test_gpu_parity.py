@@ -502,3 +502,53 @@ def test_graph_cache_beyond_its_cap():
             if T in (7, 13):
                 assert rel(U, o.precond(p.F, T, rho)) <= TOL64
     assert rel(host(g.precond(F, 1, 0.25)), first) <= 1e-15
+
+
+@pytest.mark.parametrize("n", [(70, 131), (13, 17, 70)])
+def test_general_steps_per_period_every_kernel(n):
+    """n_P not a multiple of 4 (Sec. 2.3's 2x2 extraction of Im U):
+    steps_per_period = -1 picks the smallest integer above the CFL bound,
+    and every sweep kernel, with and without graph capture, in FP64 and FP32,
+    matches the oracle run with the same n_P; so does fixed-iteration GMRES."""
+    from paper_2006_16861_amd import tdp
+    p = inputs.random_medium(n, seed=33, width=3)
+    note(f"general n_P {n}")
+    g = tdp.Operator(dev(p.c), dev(p.R), p.omega, p.h, steps_per_period=-1)
+    assert g.nP % 4 != 0
+    with pytest.raises(oracle.OracleError):
+        oracle.Op.from_problem(p, nP=g.nP - 1)
+    kernels = [(1, 0, 0), (2, 8, 4), (2, 6, 5), (2, 3, 1)] if len(n) == 2 else \
+        [(1, 0, 0), (3, 16, 1), (3, 7, 0), (4, 16, 1), (4, 7, 2)]
+    for nP in (g.nP, g.nP + 1, g.nP + 3):
+        if nP % 4 == 0:
+            continue
+        o = oracle.Op.from_problem(p, nP=nP)
+        gn = g if nP == g.nP else tdp.Operator(dev(p.c), dev(p.R), p.omega, p.h, steps_per_period=nP)
+        assert gn.nP == o.nP == nP and abs(gn.dt - o.dt) <= 1e-14 * o.dt
+        for T in (2, 3):
+            Uo = o.precond(p.F, T, 0.25)
+            for kern, depth, tile in kernels:
+                for graph in (1, 0):
+                    gn.set_tuning(kernel=kern, tb_depth=depth, tile=tile, use_graph=graph)
+                    U = host(gn.precond(dev(p.F), T, 0.25))
+                    assert rel(U, Uo) <= TOL64, (nP, T, kern, depth, tile, graph)
+            gn.set_tuning(kernel=0)
+            Uc = host(gn.precond(dev(p.F), T, 0.25, variant=1))
+            assert rel(Uc, o.precond(p.F, T, 0.25, variant=1)) <= TOL64
+    g32 = tdp.Operator(dev(p.c), dev(p.R), p.omega, p.h, steps_per_period=-1, prec=tdp.F32)
+    assert g32.nP == g.nP
+    o = oracle.Op.from_problem(p, nP=g.nP)
+    assert rel(host(g32.precond(dev(p.F), 2, 0.25)), o.precond(p.F, 2, 0.25)) <= 1e-4
+    Ug, ig = g.solve(dev(p.F), T=p.periods, restart=6, fixed_iters=10)
+    Uo, io = o.gmres(p.F, T=p.periods, restart=6, fixed_iters=10)
+    assert ig.iters == io["iters"] == 10
+    assert rel(host(Ug), Uo) <= TOL64
+
+
+def test_general_steps_per_period_rejected_by_the_batch():
+    from paper_2006_16861_amd import tdp
+    p = inputs.random_medium((40, 50), seed=34, width=3)
+    g = tdp.Operator(dev(p.c), dev(p.R), p.omega, p.h, steps_per_period=-1)
+    assert g.nP % 4 != 0
+    with pytest.raises(tdp.TdpError):
+        tdp.Batch([g], [1])
