@@ -83,10 +83,45 @@ def sweep_timing(op, F, T, rho, reps, stream, variant=0):
     return ms, ms / (T * op.nP)
 
 
-def cpu_baseline(p, T, rho, napply, target_s=12.0):
+_ONE_THREAD = """
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import bench, oracle
+p = bench.make_problem(sys.argv[2])
+op = oracle.Op.from_problem(p)
+t = time.perf_counter()
+op.precond(p.F, 1, float(sys.argv[3]))
+print(json.dumps({"ms_per_step": (time.perf_counter() - t) / op.nP * 1e3}))
+"""
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_one_thread(workload, rho):
+    """Oracle steps on one host thread (a separate process with
+    OMP_NUM_THREADS=1): one period of recurrence steps on the full grid."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _ONE_THREAD, ROOT, workload, str(rho)],
+                       capture_output=True, text=True, env=env, timeout=300)
+    if r.returncode != 0:
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])["ms_per_step"]
+
+
+def cpu_baseline(p, T, rho, napply, target_s=12.0, workload=None):
     """The oracle (plain C, OpenMP) on the host cores: time one H-apply and a
     bounded number of recurrence steps, scale to napply preconditioner
-    applications (+ H-applies) per solve."""
+    applications (+ H-applies) per solve.  Also one period of steps on a
+    single thread, for the per-core rate."""
     import numpy as np
     import oracle
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -104,10 +139,18 @@ def cpu_baseline(p, T, rho, napply, target_s=12.0):
     tT = time.perf_counter() - t
     per_step = tT / (Ts * op.nP)
     t_solve = napply * (per_step * T * op.nP + tH)
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"{Ts * op.nP} recurrence steps + 1 H-apply on the full grid "
-                      f"({per_step * 1e3:.2f} ms/step), scaled to {napply} preconditioner "
-                      f"applications of {T * op.nP} steps per solve"}
+    out = {"value": 1.0 / t_solve, "unit": "solves/s", "cores": cores, "kind": "oracle",
+           "sample": f"{Ts * op.nP} recurrence steps + 1 H-apply on the full grid "
+                     f"({per_step * 1e3:.2f} ms/step), scaled to {napply} preconditioner "
+                     f"applications of {T * op.nP} steps per solve",
+           "cpu_model": cpu_model(), "ms_per_step": per_step * 1e3}
+    if workload is not None:
+        one = cpu_one_thread(workload, rho)
+        if one is not None:
+            out["one_thread_ms_per_step"] = one
+            # the H-applies (< 1% of a solve) left out
+            out["one_thread_solves_per_s_steps_only"] = 1.0 / (napply * one * 1e-3 * T * op.nP)
+    return out
 
 
 def stream_probe(nbytes=2 << 30, reps=5):
@@ -286,6 +329,102 @@ def form_adjoint(rho):
             "solves_per_s": 8.0 / dt, "seconds": dt, "grad_norm": float(torch.linalg.norm(g))}
 
 
+XGMI_LINK_GBS = 153.0           # one MI355X xGMI link, one direction, published
+
+
+def study_shard(ngpu=8, rho=0.25):
+    """One GPU's share of a slab decomposition along axis 0 over `ngpu` GPUs:
+    the sweep at the slab's real shape (its interior plus the halo planes the
+    kernel needs), against 1/ngpu of the full-grid step, and the halo each step
+    (or block of k steps) would exchange with each neighbour: bytes, the time
+    of one device copy of it (the staging cost, if a staging buffer is used;
+    slabs along axis 0 have contiguous faces, so none is needed) and its time on
+    one xGMI link at the published rate.  Nothing here moves data between GPUs."""
+    import torch
+    from paper_2006_16861_amd import inputs, tdp
+    out = {"study": "shard", "gpus_modelled": ngpu, "xgmi_link_GBps": XGMI_LINK_GBS}
+
+    def slab_op(p, lo, hi, prec, spp):
+        sl = slice(lo, hi)
+        c = torch.as_tensor(np.ascontiguousarray(p.c[sl]), device="cuda")
+        R = torch.as_tensor(np.ascontiguousarray(p.R[sl]), device="cuda")
+        F = torch.as_tensor(np.ascontiguousarray(p.F[sl]), device="cuda")
+        op = tdp.Operator(c, R, p.omega, p.h, prec=prec, steps_per_period=spp)
+        op._keep = (c, R)
+        return op, F
+
+    def step_us(op, F, T):
+        best, _ = op.autotune(T=1, rho=rho)
+        ms, step_ms = sweep_timing(op, F, T, rho, 3, torch.cuda.current_stream())
+        return step_ms * 1e3, best
+
+    def copy_us(nbytes):
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b.copy_(a)
+        e0.record()
+        for _ in range(20):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 20 * 1e3
+
+    # 3-D: layered3d-256, slabs of 256/ngpu planes, one halo plane per side for
+    # the one-step kernels, two for the two-step kernel
+    p = inputs.layered3d(256)
+    own = p.n[0] // ngpu
+    lo = p.n[0] // 2 - own // 2
+    res3 = {"workload": "layered3d-256", "slab_planes": own}
+    for name, prec in (("f64", tdp.F64), ("f32", tdp.F32)):
+        word = 8 if prec == tdp.F64 else 4
+        full_op, Ff = slab_op(p, 0, p.n[0], prec, -1)
+        full_us, full_best = step_us(full_op, Ff, p.periods)
+        del full_op, Ff
+        torch.cuda.empty_cache()
+        r = {"full_grid_us_per_step": full_us, "full_grid_tuning": full_best}
+        for halo in (1, 2):
+            op, F = slab_op(p, lo - halo, lo + own + halo, prec, -1)
+            us, best = step_us(op, F, p.periods)
+            r[f"halo{halo}"] = {"grid": list(op.n), "us_per_step": us, "tuning": best,
+                                "vs_ideal": (full_us / ngpu) / us}
+            del op, F
+            torch.cuda.empty_cache()
+        face = p.n[1] * p.n[2] * word
+        r["face_bytes"] = face
+        r["face_copy_us"] = copy_us(face)
+        r["face_xgmi_us"] = face / (XGMI_LINK_GBS * 1e3)
+        res3[name] = r
+        log(f"shard 3-D {name}: full {full_us:.1f} us/step, slab {r['halo1']['us_per_step']:.1f} "
+            f"us/step, face {face >> 10} KiB ({r['face_xgmi_us']:.2f} us on one link)")
+    out["3d"] = res3
+
+    # 2-D: smooth2d-1024, slabs of 1024/ngpu rows; the blocked kernel of depth k
+    # needs k halo rows per side and one exchange every k steps
+    p = inputs.smooth2d(1024)
+    own = p.n[0] // ngpu
+    lo = p.n[0] // 2 - own // 2
+    full_op, Ff = slab_op(p, 0, p.n[0], tdp.F64, 0)
+    full_us, full_best = step_us(full_op, Ff, p.periods)
+    del full_op, Ff
+    res2 = {"workload": "smooth2d-1024", "slab_rows": own, "full_grid_us_per_step": full_us,
+            "full_grid_tuning": full_best}
+    for k in (4, 8):
+        op, F = slab_op(p, lo - k, lo + own + k, tdp.F64, 0)
+        op.set_tuning(kernel=2, tb_depth=k, tile=5)
+        ms, step_ms = sweep_timing(op, F, p.periods, rho, 3, torch.cuda.current_stream())
+        face = k * p.n[1] * 8
+        res2[f"depth{k}"] = {"grid": list(op.n), "us_per_step": step_ms * 1e3,
+                             "vs_ideal": (full_us / ngpu) / (step_ms * 1e3),
+                             "face_bytes_per_exchange": face,
+                             "face_xgmi_us": face / (XGMI_LINK_GBS * 1e3),
+                             "compute_us_between_exchanges": k * step_ms * 1e3}
+        del op, F
+    out["2d"] = res2
+    log(f"shard 2-D: full {full_us:.2f} us/step; slab {res2['depth8']['us_per_step']:.2f} us/step")
+    print(json.dumps(out), flush=True)
+
+
 def study_convergence(model, Ts=(10, 20, 40, 80, 160, 320), rhos=(0.0, 0.25, 0.5, 0.75),
                       gmres_Ts=(5, 10, 20, 40, 80), ref_tol=1e-12):
     """Sec. 4.1's convergence studies on the constant model and the resonant disc
@@ -362,14 +501,18 @@ def main():
     ap.add_argument("--profile-sweeps", type=int, default=0,
                     help="profiling mode: one 256 MiB device copy (counter calibration), then "
                          "this many preconditioner applications, then exit")
-    ap.add_argument("--study", choices=["convergence"], default=None,
-                    help="run Sec. 4.1's convergence study on the constant and resonant "
-                         "models instead of the benchmark")
+    ap.add_argument("--study", choices=["convergence", "shard"], default=None,
+                    help="convergence: Sec. 4.1's convergence study on the constant and "
+                         "resonant models; shard: the sweep at one GPU's slab of an 8-GPU "
+                         "decomposition, with its halo sizes (instead of the benchmark)")
     ap.add_argument("--study-model", type=int, default=320,
                     help="model size (nodes per axis, without the damping layers)")
     args = ap.parse_args()
-    if args.study:
+    if args.study == "convergence":
         study_convergence(args.study_model)
+        return
+    if args.study == "shard":
+        study_shard()
         return
     if args.damping == "cell" and args.variant != 1:
         raise SystemExit("--damping cell runs S_T^abd: pass --variant 1")
@@ -516,7 +659,7 @@ def main():
         out["forms"] = forms
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(p, T, args.rho, int(napply))
+        out["cpu_baseline"] = cpu_baseline(p, T, args.rho, int(napply), workload=args.workload)
         log(f"cpu baseline {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 

@@ -552,3 +552,25 @@ def test_general_steps_per_period_rejected_by_the_batch():
     assert g.nP % 4 != 0
     with pytest.raises(tdp.TdpError):
         tdp.Batch([g], [1])
+
+
+@pytest.mark.parametrize("n,mode", [((40, 33), (3, 5)), ((12, 9, 17), (2, 1, 4))])
+def test_gmres_complex_variant_one_iteration_on_eigenvector(n, mode):
+    """Def. 4 on a sine mode of a constant medium with uniform damping: GMRES is
+    exact after one iteration on the GPU as in the oracle (U = F / lambda)."""
+    from paper_2006_16861_amd import tdp
+    h = 1.0 / (max(n) + 1)
+    omega = inputs.omega_for_ppw(1.1, h, 8.0)
+    c = np.full(n, 1.1)
+    R = np.full(n, 0.3 * omega)
+    grids = np.meshgrid(*[np.sin(math.pi * pa * (np.arange(na) + 1) / (na + 1))
+                          for na, pa in zip(n, mode)], indexing="ij")
+    F = np.prod(grids, axis=0) * (0.6 - 0.8j)
+    note(f"one-iteration GMRES on a sine mode {n}")
+    g = tdp.Operator(dev(c), dev(R), omega, h)
+    o = oracle.Op(n, h, omega, c, R)
+    Ug, ig = g.solve(dev(F), T=3, tol=1e-12, variant=1)
+    Uo, io = o.gmres(F, T=3, tol=1e-12, variant=1)
+    assert ig.status == 0 and ig.iters == io["iters"] == 1
+    assert rel(host(Ug), Uo) <= TOL64
+    assert rel(o.apply_H(host(Ug)), F) <= 1e-11

@@ -336,6 +336,25 @@ def test_gmres_matches_lu(n, variant):
     assert err < 1e-8
 
 
+@pytest.mark.parametrize("n,mode", [((9, 7), (2, 3)), ((5, 4, 6), (1, 2, 2))])
+def test_gmres_complex_variant_one_iteration_on_eigenvector(n, mode):
+    """Constant medium and uniform damping: a sine mode e is an eigenvector of
+    H and of the complex-linear Def. 4 map, so P H e is parallel to e and GMRES
+    is exact after one iteration (U = F / lambda with lambda the closed-form
+    eigenvalue). The real-linear Table 1 map is not: one iteration leaves a
+    residual."""
+    op, h, omega, c, R = const_op(n, cval=1.1, rval=0.3)
+    F = sine_mode(n, mode) * (0.6 - 0.8j)
+    theta = [math.pi * pa / (na + 1) for na, pa in zip(n, mode)]
+    S, M = compact_symbols(theta)
+    lam = S / h ** 2 - (omega / 1.1) ** 2 * M + 1j * omega * R.flat[0]
+    U, res = op.gmres(F, T=3, tol=1e-12, variant=1)
+    assert res["status"] == oracle.OK and res["iters"] == 1
+    assert np.linalg.norm(U - F / lam) <= 1e-11 * np.linalg.norm(F / lam)
+    _, res0 = op.gmres(F, T=3, variant=0, fixed_iters=1)
+    assert res0["relres"] > 1e-6
+
+
 def test_gmres_givens_estimates_monotone_within_cycle():
     p = inputs.random_medium((12, 12), seed=8, width=2)
     op = oracle.Op.from_problem(p)
