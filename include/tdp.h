@@ -59,7 +59,11 @@ typedef struct tdp_op tdp_op;
 /* Operator description (Sec. 2.2: the preconditioner's parameters follow from
  * H alone).
  *  ndim              2 or 3
- *  n[0..ndim-1]      interior nodes per axis (>= 1); n[ndim..2] ignored
+ *  n[0..ndim-1]      interior nodes per axis (>= 1, <= 2^20); n[ndim..2]
+ *                    ignored.  The node-per-thread kernels launch 4 rows of
+ *                    axis ndim-2 and one plane of axis 0 (3-D) per block row,
+ *                    so 2-D n[0] <= 262139 and 3-D n[0] <= 65534,
+ *                    n[1] <= 262139 (else TDP_EINVAL); N <= 2^36.
  *  h                 grid spacing (> 0)
  *  omega             physical angular frequency (> 0)
  *  c                 device, [N] wave speed at the nodes (> 0)

@@ -152,6 +152,17 @@ static int create_impl(const tdp_op_desc *d, tdp_op *op)
         op->Nc *= d->n[a] + 1;
     }
     if (op->N > (int64_t)1 << 36) TDP_FAIL(TDP_EINVAL, "grid too large");
+    // launch grids of the node (and cell) per thread kernels: blocks of 4 rows
+    // along axis ndim-2 and one (cell) plane of axis 0 in 3-D per grid row,
+    // at most 65535 blocks along grid y and z
+    {
+        const int64_t ylen = d->n[d->ndim - 2] + 1;
+        if ((ylen + 3) / 4 > 65535)
+            TDP_FAIL(TDP_EINVAL, "n[%d] = %lld exceeds 262139", d->ndim - 2,
+                     (long long)d->n[d->ndim - 2]);
+        if (d->ndim == 3 && d->n[0] + 1 > 65535)
+            TDP_FAIL(TDP_EINVAL, "n[0] = %lld exceeds 65534 in 3-D", (long long)d->n[0]);
+    }
     op->h = d->h;
     op->omega = d->omega;
     op->prec = d->prec;
@@ -778,7 +789,7 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
     cand.push_back({1, 0, 1, 0});
     if (op->ndim == 2 && variant == 0) {
         const int tiles[] = {0, 1, 2, 3, 4, 5, 6, 7};
-        const int depths[] = {2, 3, 4, 6, 8};
+        const int depths[] = {2, 3, 4, 6, 8, 10, 12, 16};
         for (int tile : tiles) {
             if (tile == 2 && op->prec == TDP_F64) continue;
             const int rows = tb2d_tile_rows(tile, op->prec == TDP_F64);

@@ -285,7 +285,7 @@ TB_CASES = [
 
 
 @pytest.mark.parametrize("tile", [0, 1, 3, 4, 5, 6, 7])
-@pytest.mark.parametrize("depth", [1, 3, 4, 5, 8])
+@pytest.mark.parametrize("depth", [1, 3, 4, 5, 8, 12, 16])
 @pytest.mark.parametrize("name,mk", TB_CASES)
 def test_precond_blocked_f64(name, mk, depth, tile):
     p = mk()
@@ -574,3 +574,34 @@ def test_gmres_complex_variant_one_iteration_on_eigenvector(n, mode):
     assert ig.status == 0 and ig.iters == io["iters"] == 1
     assert rel(host(Ug), Uo) <= TOL64
     assert rel(o.apply_H(host(Ug)), F) <= 1e-11
+
+
+@pytest.mark.parametrize("n,kernels", [
+    ((262139, 2), [(1, 0, 0), (2, 8, 5), (2, 4, 4)]),
+    ((65534, 2, 3), [(1, 0, 0), (3, 32, 1), (4, 16, 0)]),
+])
+def test_maximum_axis_lengths(n, kernels):
+    """The longest axes the launch grids allow (2-D n[0] = 262139, 3-D
+    n[0] = 65534): parameters, H, every sweep kernel and Def. 4 match the
+    oracle; one more node along that axis is refused with TDP_EINVAL."""
+    from paper_2006_16861_amd import tdp
+    torch = _torch()
+    p = inputs.random_medium(n, seed=35, width=1)
+    note(f"maximum axis lengths {n}")
+    g, o = make_ops(p)
+    assert g.nP == o.nP and abs(g.omega_c - o.omega_c) <= 1e-14 * o.omega_c
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
+    assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
+    Uo = o.precond(p.F, 1, 0.25)
+    for kern, depth, tile in kernels:
+        g.set_tuning(kernel=kern, tb_depth=depth, tile=tile)
+        assert rel(host(g.precond(dev(p.F), 1, 0.25)), Uo) <= TOL64, (kern, depth, tile)
+    g.set_tuning(kernel=0)
+    assert rel(host(g.precond(dev(p.F), 1, 0.25, variant=1)),
+               o.precond(p.F, 1, 0.25, variant=1)) <= TOL64
+    big = (n[0] + 1,) + n[1:]
+    c = torch.ones(big, dtype=torch.float64, device="cuda")
+    with pytest.raises(tdp.TdpError) as ei:
+        tdp.Operator(c, None, 10.0, 1.0 / (max(big) + 1))
+    assert ei.value.code == tdp.EINVAL
