@@ -51,3 +51,62 @@ def test_create_rejects_bad_arguments_before_touching_device():
     d.h = -1.0
     assert L.tdp_op_create(ctypes.byref(d), ctypes.byref(h)) == tdp.EINVAL
     assert L.tdp_op_destroy(None) == tdp.OK
+
+
+def _desc(ndim, n, **kw):
+    from paper_2006_16861_amd import tdp
+    d = tdp.OpDesc()
+    d.ndim = ndim
+    for a in range(3):
+        d.n[a] = n[a] if a < len(n) else 1
+    d.h, d.omega = 0.01, 10.0
+    buf = (ctypes.c_double * 1)(1.0)          # never read: every check below fails first
+    d.c = ctypes.cast(buf, ctypes.c_void_p)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d, buf
+
+
+@pytest.mark.parametrize("ndim,n,msg", [
+    (2, (262140, 2), "262139"),
+    (3, (65535, 2, 2), "65534"),
+    (3, (8, 262140, 2), "262139"),
+    (2, (0, 8), "out of range"),
+    (3, (8, 8, (1 << 20) + 1), "out of range"),
+    (3, (4096, 4096, 1 << 20), "too large"),
+])
+def test_create_rejects_grids_beyond_the_launch_limits(ndim, n, msg):
+    """Axis lengths the node-per-thread launch grids cannot cover, and grids
+    beyond 2^36 nodes, are refused before any device call."""
+    from paper_2006_16861_amd import tdp
+    L = tdp.load()
+    d, _keep = _desc(ndim, n)
+    h = ctypes.c_void_p()
+    assert L.tdp_op_create(ctypes.byref(d), ctypes.byref(h)) == tdp.EINVAL
+    assert msg in tdp.last_error()
+
+
+def test_create_rejects_bad_modes_and_tables():
+    from paper_2006_16861_amd import tdp
+    L = tdp.load()
+    h = ctypes.c_void_p()
+    cases = [({"prec": 5}, "prec"), ({"damping": 7}, "damping"),
+             ({"damping": 1, "prec": tdp.F32}, "FP64 only")]
+    for kw, msg in cases:
+        d, _keep = _desc(2, (8, 8), **kw)
+        assert L.tdp_op_create(ctypes.byref(d), ctypes.byref(h)) == tdp.EINVAL, kw
+        assert msg in tdp.last_error(), (kw, tdp.last_error())
+    # App. A conditions on the cell tables (checked on the host)
+    for stiff, mass, msg in [((-1.0, 0.0, 0.0), None, "not PSD"),
+                             (None, (1.0, 0.0, 0.0), "2^-d"),
+                             ((0.0, 0.0, 0.0), None, "zero"),
+                             ((float("nan"), 0.0, 0.0), None, "non-finite")]:
+        d, _keep = _desc(2, (8, 8))
+        arrs = []
+        for name, tab in (("stiff", stiff), ("mass", mass)):
+            if tab is not None:
+                arr = (ctypes.c_double * 3)(*tab)
+                arrs.append(arr)
+                setattr(d, name, ctypes.cast(arr, ctypes.c_void_p))
+        assert L.tdp_op_create(ctypes.byref(d), ctypes.byref(h)) == tdp.EINVAL, msg
+        assert msg in tdp.last_error(), (msg, tdp.last_error())
