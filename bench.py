@@ -203,7 +203,7 @@ def form_precision(rho):
     U = {}
     for name, prec in (("f64", tdp.F64), ("f32", tdp.F32)):
         op = tdp.operator_from_problem(p, prec=prec, steps_per_period=-1)
-        best, table = op.autotune(T=1, rho=rho)
+        best, table = op.autotune(T=4, rho=rho)
         op.solve(F, T=p.periods, rho=rho, tol=1e-6)                 # warm (graphs)
         (Uq, info), dt = _timed(lambda: op.solve(F, T=p.periods, rho=rho, tol=1e-6))
         _, step_ms = sweep_timing(op, F, p.periods, rho, 1, torch.cuda.current_stream())
@@ -354,7 +354,7 @@ def study_shard(ngpu=8, rho=0.25):
         return op, F
 
     def step_us(op, F, T):
-        best, _ = op.autotune(T=1, rho=rho)
+        best, _ = op.autotune(T=4, rho=rho)
         ms, step_ms = sweep_timing(op, F, T, rho, 3, torch.cuda.current_stream())
         return step_ms * 1e3, best
 

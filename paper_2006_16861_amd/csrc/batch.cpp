@@ -172,7 +172,7 @@ static int build_fields(tdp_batch *b, const int *T_op, double rho)
         x.ny = op->n[0];
         x.nx = op->n[1];
         x.Ns = T_op[fl.op] * op->nP;
-        x.jsnap = x.Ns - op->nP / 4;
+        x.jsnap = x.Ns - op->nP / 4;      // 4 | n_P (checked at creation)
         x.m = (const T *)(b->f64 ? (const void *)op->m : (const void *)op->m32);
         x.dn = (const T *)(b->f64 ? (const void *)op->dn : (const void *)op->dn32);
         x.F = b->f64 ? fl.pin : fl.Fst;

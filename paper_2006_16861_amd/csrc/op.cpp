@@ -256,7 +256,8 @@ static int create_impl(const tdp_op_desc *d, tdp_op *op)
         TDP_CHECK_HIP(hipStreamSynchronize(s));
         op->lam_im = op->omega * rmax;
         // Sec. 5.1: theta = omega dt = 2 pi / n_P with n_P the smallest multiple of 4
-        // satisfying the stability condition; omega from the K >= 0 condition
+        // (steps_per_period = -1: the smallest integer >= 3) satisfying the
+        // stability condition; omega from the K >= 0 condition
         const double kmax2 = op->omega_c * op->omega_c;
         if (nP == 0 || nP == -1) {
             const int step = nP == 0 ? 4 : 1;
@@ -550,9 +551,6 @@ static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, const void *
     return TDP_OK;
 }
 
-// Issue the recurrence loop reading F (complex128, or float2 staged for FP32)
-// and writing U (complex128).  variant 0: Table 1 (real field, snapshot a
-// quarter period before the end gives Im U); variant 1: Definition 4.
 // Streamed 3-D loop with two steps per launch, ping-ponging between the field
 // pairs (u0, u1) and (v0, v1); an odd last step runs the one-step kernel in place.
 static int issue_steps_3d2(tdp_op *op, int T, double rho, int zc, const void *Fin, void *U)
@@ -619,6 +617,10 @@ static int issue_steps_3d2(tdp_op *op, int T, double rho, int zc, const void *Fi
     return TDP_OK;
 }
 
+// Issue the recurrence loop reading F (complex128, or float2 staged for FP32)
+// and writing U (complex128).  variant 0: Table 1 (real field; u_{N_s} to
+// Re U and the sample u_{N_s - q} to Im U, see snap_lag); variant 1:
+// Definition 4.
 static int issue_steps_loop(tdp_op *op, int T, double rho, int variant, const void *Fin, void *U)
 {
     int kern, depth;
