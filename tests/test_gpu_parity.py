@@ -229,9 +229,10 @@ def test_gmres_applications_match_oracle():
 
 # ---------------------------------------------------------------- full-size workloads
 def test_full_size_2d_one_period_and_H():
-    """1024^2 smooth medium (the benchmark workload) in the benchmark's launch
-    configuration: one period of the recurrence (12 launches over every tile and
-    the ragged edges) and the H-apply against the oracle."""
+    """1024^2 smooth medium (the benchmark workload): one period of the
+    recurrence over every tile and the ragged edges, in the configuration the
+    autotuner picks for the benchmark and in the blocked depth-8 32 x 64 tile it
+    has picked on every run so far, and the H-apply, against the oracle."""
     p = inputs.smooth2d(1024)
     note("full-size smooth2d-1024: P F with T=1, H-apply")
     g, o = make_ops(p)
@@ -239,10 +240,13 @@ def test_full_size_2d_one_period_and_H():
     rng = np.random.default_rng(3)
     x = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
     assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
-    U = host(g.precond(F, 1, 0.25))
-    assert rel(U, o.precond(p.F, 1, 0.25)) <= TOL64
-    U = host(g.precond(dev(x), 1, 0.25))
-    assert rel(U, o.precond(x, 1, 0.25)) <= TOL64
+    UoF, Uox = o.precond(p.F, 1, 0.25), o.precond(x, 1, 0.25)
+    best, _ = g.autotune(T=4)
+    note(f"  autotuned {best}")
+    for tun in (best, {"kernel": 2, "tb_depth": 8, "tile": 5, "use_graph": 1}):
+        g.set_tuning(**tun)
+        assert rel(host(g.precond(F, 1, 0.25)), UoF) <= TOL64, tun
+        assert rel(host(g.precond(dev(x), 1, 0.25)), Uox) <= TOL64, tun
 
 
 def test_full_size_2d_solve_residual_checked_by_oracle():
@@ -273,6 +277,26 @@ def test_full_size_3d_one_period():
     rng = np.random.default_rng(4)
     x = (rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n))
     assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
+
+
+def test_full_size_3d_precision_form_configuration():
+    """layered3d-256 as the precision form runs it: n_P = 10 (the smallest
+    integer above the CFL bound, Im U from the 2x2 solve), autotuned sweeps in
+    FP64 and FP32, one period against the oracle."""
+    from paper_2006_16861_amd import tdp
+    p = inputs.layered3d(256)
+    note("full-size layered3d-256 at n_P = 10: FP64 and FP32, autotuned")
+    F = dev(p.F)
+    Uo = None
+    for prec, tol in ((tdp.F64, TOL64), (tdp.F32, 1e-4)):
+        g = tdp.operator_from_problem(p, prec=prec, steps_per_period=-1)
+        assert g.nP == 10
+        if Uo is None:
+            Uo = oracle.Op.from_problem(p, nP=g.nP).precond(p.F, 1, 0.25)
+        best, _ = g.autotune(T=4)
+        note(f"  prec {prec} autotuned {best}")
+        assert rel(host(g.precond(F, 1, 0.25)), Uo) <= tol
+        del g
 
 
 # ---------------------------------------------------------------- temporally blocked sweep
