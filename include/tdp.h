@@ -252,8 +252,8 @@ typedef struct {
 int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t);
 
 /* Autotuner: times each sweep variant applicable to this op (one step per
- * launch; blocked tile shapes x depths 2, 3, 4, 6, 8 for the 2-D Table 1
- * loop; streamed column shapes x chunk lengths 16, 32, 64 in 3-D, with one
+ * launch; blocked tile shapes x depths 2, 3, 4, 6, 8, 10, 12, 16 (4 x depth
+ * at most the tile's rows) for the 2-D Table 1 loop; streamed column shapes x chunk lengths 16, 32, 64 in 3-D, with one
  * and two steps per launch) over
  * periods_T periods with HIP events on the op's stream, and makes
  * the fastest the op's tuning.  best (host, may be NULL) receives it; table
@@ -272,7 +272,8 @@ int tdp_op_get_tuning(const tdp_op *op, tdp_tuning *t);
  * by k steps per launch of the blocked sweep, each with its own medium,
  * forcing table and step count, and is replayed from one hipGraph; GMRES runs
  * per field in lockstep and takes the same decisions as tdp_gmres_solve.
- * The batch keeps pointers to the ops: they must outlive it. */
+ * The batch keeps pointers to the ops: they must outlive it.  Ops with the
+ * cell damping, or whose n_P is not a multiple of 4, are refused (TDP_EINVAL). */
 typedef struct tdp_batch tdp_batch;
 
 int tdp_batch_create(tdp_op *const *ops, int nops, const int *nrhs, tdp_batch **out);
