@@ -88,7 +88,7 @@ typedef struct tdp_op tdp_op;
  *                    round(n_P/4) steps before the end and obtains Im U by
  *                    the 2x2 solve the paper suggests for that case
  *                    (Sec. 2.3): u_{N_s-q} = cos(phi) Re U + sin(phi) Im U,
- *                    phi = 2 pi q/n_P.  The batched form needs 4 | n_P.
+ *                    phi = 2 pi q/n_P.
  *  prec              precision of the recurrence fields (Table 1 loop).
  *                    Krylov vectors, H and the residuals are always FP64.
  *  stream            hipStream_t every call of this op issues its work on.
@@ -273,7 +273,7 @@ int tdp_op_get_tuning(const tdp_op *op, tdp_tuning *t);
  * forcing table and step count, and is replayed from one hipGraph; GMRES runs
  * per field in lockstep and takes the same decisions as tdp_gmres_solve.
  * The batch keeps pointers to the ops: they must outlive it.  Ops with the
- * cell damping, or whose n_P is not a multiple of 4, are refused (TDP_EINVAL). */
+ * cell damping are refused (TDP_EINVAL). */
 typedef struct tdp_batch tdp_batch;
 
 int tdp_batch_create(tdp_op *const *ops, int nops, const int *nrhs, tdp_batch **out);

@@ -99,7 +99,6 @@ extern "C" int tdp_batch_create(tdp_op *const *ops, int nops, const int *nrhs, t
         if (op->ndim != 2) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "batched form is 2-D only (op %d)", i); }
         if (op->prec != ops[0]->prec) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "all ops must share one precision"); }
         if (op->dform != TDP_DAMP_NODE) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "the batched form runs Table 1 (diagonal damping only)"); }
-        if (op->nP % 4 != 0) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "the batched form needs 4 | n_P (op %d)", i); }
         if (op->user_stream != ops[0]->user_stream) { free_batch(b); TDP_BFAIL(TDP_EINVAL, "all ops must share one stream"); }
         (void)hipStreamSynchronize(op->stream);
         const bool gen = !(op->sc <= 3 && op->mc <= 2);
@@ -172,7 +171,7 @@ static int build_fields(tdp_batch *b, const int *T_op, double rho)
         x.ny = op->n[0];
         x.nx = op->n[1];
         x.Ns = T_op[fl.op] * op->nP;
-        x.jsnap = x.Ns - op->nP / 4;      // 4 | n_P (checked at creation)
+        x.jsnap = x.Ns - snap_lag(op->nP);
         x.m = (const T *)(b->f64 ? (const void *)op->m : (const void *)op->m32);
         x.dn = (const T *)(b->f64 ? (const void *)op->dn : (const void *)op->dn32);
         x.F = b->f64 ? fl.pin : fl.Fst;
@@ -272,6 +271,13 @@ static int batch_precond(tdp_batch *b, const int *T_op, double rho, const std::v
             bl.shape = b->shape;
             bl.general = b->general;
             le = launch_sweep2d_tb_batch(bl, b->f64, s);
+        }
+        // Table 1 with 4 not dividing n_P: Im U from the two samples (2x2 solve)
+        for (int q : act) {
+            const tdp_op *op = b->ops[b->f[q].op];
+            if (le != hipSuccess || op->nP % 4 == 0) continue;
+            const double phi = 2.0 * M_PI * (double)snap_lag(op->nP) / op->nP;
+            le = launch_phase_extract(b->f[q].pout, b->f[q].N, std::cos(phi), std::sin(phi), s);
         }
         hipError_t ce = hipStreamEndCapture(s, &g);
         if (le != hipSuccess || ce != hipSuccess) {

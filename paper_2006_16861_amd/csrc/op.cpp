@@ -456,7 +456,7 @@ const std::vector<double> &forcing_table(tdp_op *op, int T, double rho, int vari
 // Table 1's second sample: u_{N_s - q} with q = n_P/4 (a quarter period) when
 // 4 divides n_P, else q = round(n_P/4), whose phase 2 pi q/n_P stays within
 // 45 degrees of a quarter period, and Im U follows from a 2x2 solve (Sec. 2.3).
-static int64_t snap_lag(int nP)
+int64_t snap_lag(int nP)
 {
     return nP % 4 == 0 ? nP / 4 : (nP + 2) / 4;
 }

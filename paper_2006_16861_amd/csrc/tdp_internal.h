@@ -240,6 +240,7 @@ struct StreamJoin {
 struct tdp_op;
 // host helpers shared by op.cpp and batch.cpp
 const std::vector<double> &forcing_table(tdp_op *op, int T, double rho, int variant);
+int64_t snap_lag(int nP);   // Table 1's second sample lies snap_lag(n_P) steps before the end
 int apply_H_impl(const tdp_op *op, const void *x, const void *F, void *y);
 
 // The opaque operator.

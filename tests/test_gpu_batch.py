@@ -145,3 +145,36 @@ def test_batch_autotune_keeps_results_exact():
         for k in range(r):
             assert rel(Us[q].cpu().numpy(), o.precond(Fs[q], T[i])) <= 1e-10
             q += 1
+
+
+def test_batch_with_general_steps_per_period():
+    """Fields whose n_P is not a multiple of 4 (n_P = 10 and 11, next to a
+    field with the default n_P = 12) in one batch: each matches the oracle run
+    with its n_P, for the batched preconditioner and fixed-iteration GMRES."""
+    from paper_2006_16861_amd import tdp
+    probs = [inputs.random_medium((40, 50), seed=34, width=3),
+             inputs.random_medium((37, 150), seed=1, width=4), inputs.const2d()]
+    spp = [-1, 11, 0]
+    ops = [tdp.operator_from_problem(p, steps_per_period=v) for p, v in zip(probs, spp)]
+    assert [o.nP for o in ops] == [10, 11, 12]
+    note("batch with n_P = 10, 11, 12")
+    b = tdp.Batch(ops, [1, 2, 1])
+    rng = np.random.default_rng(8)
+    Fs = [probs[0].F, probs[1].F, rng.standard_normal(probs[1].n) + 1j * rng.standard_normal(probs[1].n),
+          probs[2].F]
+    fo = [0, 1, 1, 2]
+    orc = [oracle.Op.from_problem(p, nP=o.nP) for p, o in zip(probs, ops)]
+    for depth, tile in ((8, 4), (4, 5)):
+        b.set_tuning(depth, tile)
+        T = [3, 2, 4]
+        Us = b.precond([dev(F) for F in Fs], T)
+        for q, F in enumerate(Fs):
+            i = fo[q]
+            assert rel(Us[q].cpu().numpy(), orc[i].precond(F, T[i])) <= 1e-10, (q, depth, tile)
+    T = [p.periods for p in probs]
+    Us, infos, rc = b.solve([dev(F) for F in Fs], T, restart=4, fixed_iters=6)
+    for q, F in enumerate(Fs):
+        i = fo[q]
+        Uo, io = orc[i].gmres(F, T[i], restart=4, fixed_iters=6)
+        assert infos[q].iters == 6
+        assert rel(Us[q].cpu().numpy(), Uo) <= 1e-10, q

@@ -569,13 +569,6 @@ def test_general_steps_per_period_every_kernel(n):
     assert rel(host(Ug), Uo) <= TOL64
 
 
-def test_general_steps_per_period_rejected_by_the_batch():
-    from paper_2006_16861_amd import tdp
-    p = inputs.random_medium((40, 50), seed=34, width=3)
-    g = tdp.Operator(dev(p.c), dev(p.R), p.omega, p.h, steps_per_period=-1)
-    assert g.nP % 4 != 0
-    with pytest.raises(tdp.TdpError):
-        tdp.Batch([g], [1])
 
 
 @pytest.mark.parametrize("n,mode", [((40, 33), (3, 5)), ((12, 9, 17), (2, 1, 4))])
