@@ -279,6 +279,29 @@ def test_full_size_3d_one_period():
     assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
 
 
+def test_full_size_3d_f32_solve_residual_checked_by_oracle():
+    """The precision form's solve (layered3d-256, FP32 fields, FP64 GMRES,
+    n_P = 10, tol 1e-6): its true residual, recomputed by the oracle's FP64 H,
+    meets the tolerance, and the solution agrees with the FP64 GPU solve to
+    the level the tolerance allows."""
+    from paper_2006_16861_amd import tdp
+    p = inputs.layered3d(256)
+    note("full-size layered3d-256 FP32 solve to 1e-6, residual by the oracle")
+    F = dev(p.F)
+    U = {}
+    for prec in (tdp.F32, tdp.F64):
+        g = tdp.operator_from_problem(p, prec=prec, steps_per_period=-1)
+        Ug, ig = g.solve(F, T=p.periods, tol=1e-6)
+        assert ig.status == 0
+        U[prec] = host(Ug)
+        del g, Ug
+    o = oracle.Op.from_problem(p, nP=10)
+    r = rel(o.apply_H(U[tdp.F32]), p.F)
+    note(f"  oracle-checked relres {r:.3e}")
+    assert r <= 1e-6 * (1 + 1e-9)
+    assert rel(U[tdp.F32], U[tdp.F64]) <= 1e-5
+
+
 def test_full_size_3d_precision_form_configuration():
     """layered3d-256 as the precision form runs it: n_P = 10 (the smallest
     integer above the CFL bound, Im U from the 2x2 solve), autotuned sweeps in
