@@ -135,7 +135,8 @@ typedef struct {
  * P = S_T of Table 1).
  *  restart      Krylov dimension m per cycle (>= 1)
  *  max_iters    limit on preconditioned operator applications (>= 1)
- *  periods_T    T, periods per preconditioner application (N_s = T n_P)
+ *  periods_T    T, periods per preconditioner application (N_s = T n_P
+ *               <= 2^24 in every entry point, else TDP_EINVAL)
  *  rho          window parameter in (0, 1]; <= 0 means rho = 1/T
  *  tol          target for the true relative residual ||F - H U|| / ||F||
  *  x0_given     1: U holds the initial guess on entry; 0: start from 0
@@ -233,7 +234,8 @@ int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
  *               (3-D, Table 1 variant); inapplicable choices fall back to 1
  *  tb_depth     kernel 2: steps per launch, 1..16 (0 auto);
  *               kernels 3, 4: planes per chunk (0 auto = 32)
- *  use_graph    1 capture the step loop in a hipGraph and replay it
+ *  use_graph    1 capture the step loop in a hipGraph and replay it (loops
+ *               of more than 2^17 launches are issued directly)
  *  tile         kernel 2 tile (rows x columns): 0 64x64 (8 rows per lane x
  *               8 waves), 1 64x64 (4 x 16 waves), 2 128x64 (FP32 only),
  *               3 32x64 (4 x 8 waves); 4..7 the same family with per-node
@@ -270,7 +272,8 @@ int tdp_op_get_tuning(const tdp_op *op, tdp_tuning *t);
  * solved together.  Field q enumerates (op 0, rhs 0..nrhs[0]-1), (op 1, ...).
  * One batched preconditioner application (Table 1) advances every live field
  * by k steps per launch of the blocked sweep, each with its own medium,
- * forcing table and step count, and is replayed from one hipGraph; GMRES runs
+ * forcing table and step count, and is replayed from one hipGraph (at most
+ * 2^17 launches, i.e. max N_s <= 2^17 k, else TDP_EINVAL); GMRES runs
  * per field in lockstep and takes the same decisions as tdp_gmres_solve.
  * The batch keeps pointers to the ops: they must outlive it.  Ops with the
  * cell damping are refused (TDP_EINVAL). */

@@ -194,6 +194,17 @@ static int build_fields(tdp_batch *b, const int *T_op, double rho)
 
 static const size_t kMaxBatchGraphs = 32;
 
+// periods per op: >= 1, and N_s = T n_P within TDP_MAX_STEPS
+static int check_periods(const tdp_batch *b, const int *periods_T)
+{
+    for (size_t i = 0; i < b->ops.size(); ++i) {
+        if (periods_T[i] < 1) TDP_BFAIL(TDP_EINVAL, "periods_T[%zu] < 1", i);
+        if ((int64_t)periods_T[i] * b->ops[i]->nP > TDP_MAX_STEPS)
+            TDP_BFAIL(TDP_EINVAL, "periods_T[%zu] n_P exceeds 2^24 steps", i);
+    }
+    return TDP_OK;
+}
+
 // One batched preconditioner application (Table 1) for the fields with
 // active[q] != 0: reads each field's pin, writes its pout.
 static int batch_precond(tdp_batch *b, const int *T_op, double rho, const std::vector<char> &active)
@@ -201,6 +212,9 @@ static int batch_precond(tdp_batch *b, const int *T_op, double rho, const std::v
     hipStream_t s = b->s;
     std::vector<int> Tv(T_op, T_op + b->ops.size());
     if (Tv != b->tkey || rho != b->rho_key) {
+        // cached applications may still be running on the stream: wait before
+        // their graphs and schedules are released
+        if (!b->graphs.empty()) TDP_CHECK_HIP(hipStreamSynchronize(s));
         for (auto &kv : b->graphs) {
             (void)hipGraphExecDestroy(kv.second.first);
             (void)hipFree(kv.second.second);
@@ -225,6 +239,8 @@ static int batch_precond(tdp_batch *b, const int *T_op, double rho, const std::v
                 maxNs = std::max(maxNs, T_op[b->f[q].op] * op->nP);
             }
         const int nl = (maxNs + b->K - 1) / b->K;
+        if (nl > TDP_MAX_GRAPH_LAUNCHES)     // the application is one captured graph
+            TDP_BFAIL(TDP_EINVAL, "%d launches per batched application exceed 2^17 (lower periods_T)", nl);
         std::vector<int> host;       // per launch: list then prefix
         std::vector<std::tuple<int, int, int, int>> launches;   // (list off, prefix off, n, tiles)
         for (int L = 0; L < nl; ++L) {
@@ -317,8 +333,7 @@ extern "C" int tdp_batch_precond(tdp_batch *b, const int *periods_T, double rho,
 {
     if (!b || !periods_T || !F || !U) TDP_BFAIL(TDP_EINVAL, "NULL argument");
     if (rho > 1.0) TDP_BFAIL(TDP_EINVAL, "rho must be <= 1");
-    for (size_t i = 0; i < b->ops.size(); ++i)
-        if (periods_T[i] < 1) TDP_BFAIL(TDP_EINVAL, "periods_T[%zu] < 1", i);
+    TDP_CHECK(check_periods(b, periods_T));
     StreamJoin join(b->ops[0]->user_stream, b->s, b->ops[0]->ev);
     std::vector<char> active(b->f.size(), 1);
     for (size_t q = 0; q < b->f.size(); ++q) {
@@ -337,6 +352,8 @@ extern "C" int tdp_batch_autotune(tdp_batch *b, const int *periods_T, double rho
                                   int cap)
 {
     if (!b || !periods_T) TDP_BFAIL(TDP_EINVAL, "NULL argument");
+    if (rho > 1.0) TDP_BFAIL(TDP_EINVAL, "rho must be <= 1");
+    TDP_CHECK(check_periods(b, periods_T));
     StreamJoin join(b->ops[0]->user_stream, b->s, b->ops[0]->ev);
     std::vector<char> active(b->f.size(), 1);
     for (auto &fl : b->f) TDP_CHECK_HIP(launch_fill_zero(fl.pin, 16 * fl.N, b->s));
@@ -380,6 +397,11 @@ extern "C" int tdp_batch_autotune(tdp_batch *b, const int *periods_T, double rho
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    const hipError_t se = hipStreamSynchronize(b->s);   // no timed graph may still run
+    if (se != hipSuccess && rc == TDP_OK) {
+        ::tdp::set_error("HIP error: %s", hipGetErrorString(se));
+        rc = TDP_EHIP;
+    }
     for (auto &kv : b->graphs) {
         (void)hipGraphExecDestroy(kv.second.first);
         (void)hipFree(kv.second.second);
@@ -455,8 +477,7 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
     if (cfg->max_iters < 1 || !(cfg->tol > 0.0) || cfg->rho > 1.0)
         TDP_BFAIL(TDP_EINVAL, "bad GMRES configuration");
     if (cfg->variant != 0) TDP_BFAIL(TDP_EINVAL, "the batched form uses the Table 1 preconditioner");
-    for (size_t i = 0; i < b->ops.size(); ++i)
-        if (periods_T[i] < 1) TDP_BFAIL(TDP_EINVAL, "periods_T[%zu] < 1", i);
+    TDP_CHECK(check_periods(b, periods_T));
     const size_t nf = b->f.size();
     for (size_t q = 0; q < nf; ++q)
         if (!F[q] || !U[q] || F[q] == U[q]) TDP_BFAIL(TDP_EINVAL, "bad F/U pointer for field %zu", q);

@@ -702,15 +702,21 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
     if (variant != 0 && variant != 1) TDP_FAIL(TDP_EINVAL, "variant must be 0 or 1");
     if (op->dform == TDP_DAMP_CELL && variant == 0)
         TDP_FAIL(TDP_EINVAL, "Table 1 runs I_acd: with the cell damping use the complex form (S_T^abd)");
-    if ((int64_t)T * op->nP > ((int64_t)1 << 31)) TDP_FAIL(TDP_EINVAL, "too many steps");
+    const int64_t Ns = (int64_t)T * op->nP;
+    if (Ns > TDP_MAX_STEPS)
+        TDP_FAIL(TDP_EINVAL, "N_s = periods_T n_P = %lld exceeds 2^24", (long long)Ns);
     if (variant) TDP_CHECK(ensure_complex_fields(op));
+    int64_t launches;
     {   // allocate before any stream capture: no allocation may happen inside it
         int kern, depth;
         sweep_plan(op, variant, &kern, &depth);
         if (kern == 2 || kern == 4) TDP_CHECK(ensure_tb_fields(op));
+        launches = kern == 2 ? (Ns + depth - 1) / depth : (kern == 4 ? (Ns + 1) / 2 : Ns);
     }
     hipStream_t s = op->stream;
-    if (!op->tune.use_graph) {
+    // a graph holds one kernel node per launch: very long loops are issued
+    // directly instead of being captured
+    if (!op->tune.use_graph || launches > TDP_MAX_GRAPH_LAUNCHES) {
         const void *Fin = F;
         if (op->prec == TDP_F32) {
             TDP_CHECK_HIP(launch_cvt_c128_to_c64(F, op->Fst, op->N, s));

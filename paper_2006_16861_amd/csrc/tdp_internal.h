@@ -98,6 +98,8 @@ hipError_t launch_sweep_f32(const SweepArgs &a, const Stencil<float> &st, float 
 
 // Temporally blocked 2-D sweep (sweep_tb.hip): one launch = k steps.
 #define TDP_TB_KMAX 16
+#define TDP_MAX_STEPS ((int64_t)1 << 24)   // recurrence steps per application
+#define TDP_MAX_GRAPH_LAUNCHES (1 << 17)     // kernel launches captured in one graph
 struct TBCoef {
     int k;                   // steps in this launch (1..TDP_TB_KMAX, < tile half-size)
     int out_step[2];         // 1-based step whose result goes to out[i] (0: none)

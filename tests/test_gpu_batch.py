@@ -178,3 +178,20 @@ def test_batch_with_general_steps_per_period():
         Uo, io = orc[i].gmres(F, T[i], restart=4, fixed_iters=6)
         assert infos[q].iters == 6
         assert rel(Us[q].cpu().numpy(), Uo) <= 1e-10, q
+
+
+def test_batch_argument_errors():
+    from paper_2006_16861_amd import tdp
+    probs, nrhs, ops, Fs = small_batch()
+    b = tdp.Batch(ops, nrhs)
+    F = [dev(F) for F in Fs]
+    b.set_tuning(8, 4)
+    # T < 1; N_s beyond 2^24; a captured application beyond 2^17 launches of 8 steps
+    for T in ([0, 1, 1], [1, (1 << 24) // ops[1].nP + 1, 1], [1, (8 << 17) // ops[1].nP + 1, 1]):
+        with pytest.raises(tdp.TdpError) as ei:
+            b.precond(F, T)
+        assert ei.value.code == tdp.EINVAL
+        with pytest.raises(tdp.TdpError):
+            b.solve(F, T, fixed_iters=1)
+        with pytest.raises(tdp.TdpError):
+            b.autotune(T)

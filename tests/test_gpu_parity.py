@@ -162,6 +162,9 @@ def test_zero_rhs_and_errors():
     assert ei.value.code == tdp.ECFL
     with pytest.raises(tdp.TdpError):
         g.precond(dev(p.F), 0)
+    with pytest.raises(tdp.TdpError) as ei:          # N_s beyond 2^24
+        g.precond(dev(p.F), (1 << 24) // g.nP + 1)
+    assert ei.value.code == tdp.EINVAL and "2^24" in str(ei.value)
     _, info = g.solve(dev(p.F), T=1, tol=1e-12, max_iters=1)
     assert info.status == tdp.ENOTCONV and info.iters == 1
 
@@ -645,3 +648,15 @@ def test_maximum_axis_lengths(n, kernels):
     with pytest.raises(tdp.TdpError) as ei:
         tdp.Operator(c, None, 10.0, 1.0 / (max(big) + 1))
     assert ei.value.code == tdp.EINVAL
+
+
+def test_long_loop_issued_without_capture():
+    """More than 2^17 launches in one application: the loop is issued directly
+    instead of being captured into a graph, and still matches the oracle."""
+    p = inputs.const2d(n=16, width=3)
+    g, o = make_ops(p)
+    T = (1 << 17) // g.nP + 1
+    note(f"long loop: T = {T}, {T * g.nP} one-step launches")
+    g.set_tuning(kernel=1, use_graph=1)
+    U = host(g.precond(dev(p.F), T, 0.25))
+    assert rel(U, o.precond(p.F, T, 0.25)) <= TOL64
