@@ -694,7 +694,11 @@ static int issue_steps(tdp_op *op, int T, double rho, int variant, const void *F
     return TDP_OK;
 }
 
-static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *F, void *U)
+// direct: F and U are buffers owned by the op (GMRES work vectors), so the
+// loop may be captured on them; otherwise a captured loop works on the
+// staging buffers, with copies of F in and U out around the replay.
+static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *F, void *U,
+                        bool direct = false)
 {
     if (T < 1) TDP_FAIL(TDP_EINVAL, "periods_T must be >= 1");
     if (rho <= 0.0) rho = 1.0 / T;
@@ -724,14 +728,29 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
         }
         return issue_steps(op, T, rho, variant, Fin, U);
     }
-    // captured loop: reads op->Fstage (F64) / op->Fst (F32), writes op->Ustage
-    auto key = std::make_tuple(T, rho, variant, op->tune.kernel, op->tune.tb_depth, op->tune.tile);
+    // captured loop: on F and U themselves (direct), else reading op->Fstage
+    // (F64) / op->Fst (F32) and writing op->Ustage
+    auto key = std::make_tuple(T, rho, variant, op->tune.kernel, op->tune.tb_depth, op->tune.tile,
+                               direct ? F : nullptr, direct ? (const void *)U : nullptr);
     auto it = op->graphs.find(key);
     if (it == op->graphs.end()) {
         hipGraph_t g;
         TDP_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        int rc = issue_steps(op, T, rho, variant, op->prec == TDP_F64 ? op->Fstage : op->Fst,
+        int rc = TDP_OK;
+        if (direct) {
+            if (op->prec == TDP_F32) {
+                const hipError_t e = launch_cvt_c128_to_c64(F, op->Fst, op->N, s);
+                if (e != hipSuccess) {
+                    set_error("launch_cvt_c128_to_c64 failed: %s", hipGetErrorString(e));
+                    rc = TDP_EHIP;
+                }
+            }
+            if (rc == TDP_OK)
+                rc = issue_steps(op, T, rho, variant, op->prec == TDP_F64 ? F : op->Fst, U);
+        } else {
+            rc = issue_steps(op, T, rho, variant, op->prec == TDP_F64 ? op->Fstage : op->Fst,
                              op->Ustage);
+        }
         hipError_t ce = hipStreamEndCapture(s, &g);
         if (rc != TDP_OK) {
             if (ce == hipSuccess) (void)hipGraphDestroy(g);
@@ -749,6 +768,10 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
             op->graphs.clear();
         }
         it = op->graphs.emplace(key, ge).first;
+    }
+    if (direct) {
+        TDP_CHECK_HIP(hipGraphLaunch(it->second, s));
+        return TDP_OK;
     }
     if (op->prec == TDP_F64)
         TDP_CHECK_HIP(hipMemcpyAsync(op->Fstage, F, 16 * op->N, hipMemcpyDeviceToDevice, s));
@@ -1013,7 +1036,7 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
             break;
         }
         if (its >= limit) break;
-        TDP_CHECK(precond_impl(op, T, rho, variant, op->rv, col(0)));
+        TDP_CHECK(precond_impl(op, T, rho, variant, op->rv, col(0), true));
         ++napply;
         double z2;
         TDP_CHECK(norm2_host(op, col(0), &z2));
@@ -1029,7 +1052,7 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
         bool converged = false;           // smallest true residual (0: the start)
         for (int i = 0; i < m && its < limit; ++i) {
             TDP_CHECK(apply_H_impl(op, col(i), nullptr, op->tv));
-            TDP_CHECK(precond_impl(op, T, rho, variant, op->tv, op->wv));
+            TDP_CHECK(precond_impl(op, T, rho, variant, op->tv, op->wv, true));
             ++napply;
             ++its;
             // classical Gram-Schmidt, two passes

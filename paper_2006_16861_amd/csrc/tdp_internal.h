@@ -289,7 +289,10 @@ struct tdp_op {
     // forcing tables per (T, rho)
     std::map<std::tuple<int, double, int>, std::vector<double>> tables;
     // captured step loops, keyed by (T, rho, variant, kernel, depth, tile)
-    std::map<std::tuple<int, double, int, int, int, int>, hipGraphExec_t> graphs;
+    // captured loops by (T, rho, variant, kernel, depth, tile, F, U); F = U =
+    // nullptr for loops on the staging buffers
+    std::map<std::tuple<int, double, int, int, int, int, const void *, const void *>,
+             hipGraphExec_t> graphs;
     tdp_tuning tune{0, 0, 1, 0};
     // stream join with the caller, staging buffers of the captured loop
     hipStream_t user_stream = nullptr;
