@@ -637,6 +637,8 @@ def main():
                    "gmres_iters": infos[-1].iters, "gmres_restarts": infos[-1].restarts,
                    "precond_applications": int(napply),
                    "true_relres": relres, "setup_ms": setup_ms,
+                   "solve_ms": [round(i.ms_total, 3) for i in infos],
+                   "solve_ms_median": float(np.median([i.ms_total for i in infos])),
                    "kernel": op.get_tuning(), "parallelism": "single-gpu"},
         "recurrence_GBps": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
