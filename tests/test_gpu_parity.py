@@ -660,3 +660,50 @@ def test_long_loop_issued_without_capture():
     g.set_tuning(kernel=1, use_graph=1)
     U = host(g.precond(dev(p.F), T, 0.25))
     assert rel(U, o.precond(p.F, T, 0.25)) <= TOL64
+
+
+def test_two_ops_on_two_streams_from_two_threads():
+    """Two operators bound to two torch streams, driven from two host threads
+    at once (preconditioner and fixed-iteration GMRES): no state is shared, and
+    each result matches the oracle; an error on one thread is reported on that
+    thread only."""
+    import threading
+    from paper_2006_16861_amd import tdp
+    torch = _torch()
+    probs = [inputs.random_medium((37, 150), seed=51, width=4),
+             inputs.random_medium((9, 11, 70), seed=52, width=2)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    ops = []
+    for p, st in zip(probs, streams):
+        with torch.cuda.stream(st):
+            ops.append(tdp.operator_from_problem(p))
+    torch.cuda.synchronize()
+    note("two ops, two streams, two threads")
+    out, errs = [None, None], [None, None]
+
+    def work(k):
+        try:
+            with torch.cuda.stream(streams[k]):
+                F = dev(probs[k].F)
+                U1 = host(ops[k].precond(F, 2, 0.25))
+                Ug, ig = ops[k].solve(F, T=probs[k].periods, restart=5, fixed_iters=8)
+                if k == 1:
+                    with pytest.raises(tdp.TdpError):
+                        ops[k].precond(F, 0)
+                    errs[k] = tdp.last_error()
+                out[k] = (U1, host(Ug))
+        except Exception as e:          # reported below on the main thread
+            errs[k] = e
+
+    th = [threading.Thread(target=work, args=(k,)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not isinstance(errs[0], Exception) and errs[0] is None, errs[0]
+    assert isinstance(errs[1], str) and "periods_T" in errs[1], errs[1]
+    for k, p in enumerate(probs):
+        o = oracle.Op.from_problem(p)
+        assert rel(out[k][0], o.precond(p.F, 2, 0.25)) <= TOL64
+        Uo, _ = o.gmres(p.F, T=p.periods, restart=5, fixed_iters=8)
+        assert rel(out[k][1], Uo) <= TOL64
