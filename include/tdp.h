@@ -240,7 +240,8 @@ int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
  *               8 waves), 1 64x64 (4 x 16 waves), 2 128x64 (FP32 only),
  *               3 32x64 (4 x 8 waves); 4..7 the same family with per-node
  *               coefficients in registers: 4 64x64 (4 x 16), 5 32x64 (4 x 8),
- *               6 64x64 (8 x 8), 7 32x64 (2 x 16); kernel 3: 0 8x64 columns (4 waves x 2
+ *               6 64x64 (8 x 8), 7 32x64 (2 x 16), 8 128x64 (8 x 16, FP32 only);
+ *               kernel 3: 0 8x64 columns (4 waves x 2
  *               rows each), 1 16x64 (4 waves x 4 rows), 2 16x64 (8 x 2);
  *               kernel 4: the same three shapes for the first step, whose
  *               one-node rim is recomputed (output 6x62 / 14x62 / 14x62)   */

@@ -139,7 +139,7 @@ extern "C" int tdp_batch_set_tuning(tdp_batch *b, int depth, int tile)
 {
     if (!b) TDP_BFAIL(TDP_EINVAL, "NULL batch");
     if (depth < 1 || depth > 15) TDP_BFAIL(TDP_EINVAL, "depth must be in [1, 15]");
-    if (tile < 0 || tile > 7 || (tile == 2 && b->f64)) TDP_BFAIL(TDP_EINVAL, "bad tile");
+    if (tile < 0 || tile > 8 || ((tile == 2 || tile == 8) && b->f64)) TDP_BFAIL(TDP_EINVAL, "bad tile");
     const int rows = tb2d_tile_rows(tile, b->f64);
     if (4 * depth > rows) TDP_BFAIL(TDP_EINVAL, "depth too large for the tile");
     b->K = depth;
@@ -364,8 +364,8 @@ extern "C" int tdp_batch_autotune(tdp_batch *b, const int *periods_T, double rho
     TDP_CHECK_HIP(hipEventCreate(&e0));
     TDP_CHECK_HIP(hipEventCreate(&e1));
     int rc = TDP_OK;
-    for (int shape = 0; shape < 8 && rc == TDP_OK; ++shape) {
-        if (shape == 2 && b->f64) continue;
+    for (int shape = 0; shape < 9 && rc == TDP_OK; ++shape) {
+        if ((shape == 2 || shape == 8) && b->f64) continue;
         const int rows = tb2d_tile_rows(shape, b->f64);
         for (int K : {4, 6, 8}) {
             if (4 * K > rows) continue;

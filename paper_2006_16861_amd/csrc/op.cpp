@@ -387,9 +387,10 @@ extern "C" int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t)
         if (t->tile < 0 || t->tile > 2) TDP_FAIL(TDP_EINVAL, "tile must be 0, 1 or 2 for kernels 3 and 4");
     } else {
         if (t->tb_depth < 0 || t->tb_depth > TDP_TB_KMAX) TDP_FAIL(TDP_EINVAL, "tb_depth must be in [0, 16]");
-        if (t->tile < 0 || t->tile > 7) TDP_FAIL(TDP_EINVAL, "tile must be in [0, 7]");
-        if (t->kernel == 2 && t->tile == 2 && op->prec == TDP_F64)
-            TDP_FAIL(TDP_EINVAL, "tile 2 is FP32 only");
+        if (t->tile < 0 || t->tile > 8) TDP_FAIL(TDP_EINVAL, "tile must be in [0, 8]");
+        if ((t->kernel == 0 || t->kernel == 2) && (t->tile == 2 || t->tile == 8) &&
+            op->prec == TDP_F64)
+            TDP_FAIL(TDP_EINVAL, "tiles 2 and 8 are FP32 only");
     }
     op->tune = *t;
     return TDP_OK;
@@ -819,10 +820,10 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
     std::vector<tdp_tuning> cand;
     cand.push_back({1, 0, 1, 0});
     if (op->ndim == 2 && variant == 0) {
-        const int tiles[] = {0, 1, 2, 3, 4, 5, 6, 7};
+        const int tiles[] = {0, 1, 2, 3, 4, 5, 6, 7, 8};
         const int depths[] = {2, 3, 4, 6, 8, 10, 12, 16};
         for (int tile : tiles) {
-            if (tile == 2 && op->prec == TDP_F64) continue;
+            if ((tile == 2 || tile == 8) && op->prec == TDP_F64) continue;
             const int rows = tb2d_tile_rows(tile, op->prec == TDP_F64);
             for (int k : depths)
                 if (4 * k <= rows && 4 * k <= 64) cand.push_back({2, k, 1, tile});

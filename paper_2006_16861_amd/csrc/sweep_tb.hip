@@ -465,6 +465,7 @@ hipError_t launch_sweep2d_tb_batch(const TBBatchLaunch &L, bool f64, hipStream_t
         case 1: case 4: return launch_tb_batch_t<double, 4, 16>(L, s);
         case 3: case 5: return launch_tb_batch_t<double, 4, 8>(L, s);
         case 7: return launch_tb_batch_t<double, 2, 16>(L, s);
+        case 2: case 8: return hipErrorInvalidValue;  // FP32-only shapes
         default: return launch_tb_batch_t<double, 8, 8>(L, s);
         }
     }
@@ -473,6 +474,7 @@ hipError_t launch_sweep2d_tb_batch(const TBBatchLaunch &L, bool f64, hipStream_t
     case 2: return launch_tb_batch_t<float, 8, 16>(L, s);
     case 3: case 5: return launch_tb_batch_t<float, 4, 8>(L, s);
     case 7: return launch_tb_batch_t<float, 2, 16>(L, s);
+    case 8: return launch_tb_batch_t<float, 8, 16>(L, s);
     default: return launch_tb_batch_t<float, 8, 8>(L, s);
     }
 }
@@ -491,11 +493,12 @@ int tb2d_tiles(int shape, int K, int ny, int nx)
 //   1: 4 x 16 -> 64 x 64, 1024 threads    5: 4 x 8  -> 32 x 64, 512 threads
 //   2: 8 x 16 -> 128 x 64 (FP32 only)     6: 8 x 8  -> 64 x 64, 512 threads
 //   3: 4 x 8  -> 32 x 64, 512 threads     7: 2 x 16 -> 32 x 64, 1024 threads
+//   8: 8 x 16 -> 128 x 64 with per-node coefficients (FP32 only)
 int tb2d_tile_rows(int shape, bool f64)
 {
     (void)f64;
     switch (shape) {
-    case 2: return 128;
+    case 2: case 8: return 128;
     case 3: case 5: case 7: return 32;
     default: return 64;
     }
@@ -510,6 +513,7 @@ hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hip
     case 5: return launch_tb2_t<double, 4, 8>(a, st, s);
     case 6: return launch_tb2_t<double, 8, 8>(a, st, s);
     case 7: return launch_tb2_t<double, 2, 16>(a, st, s);
+    case 2: case 8: return hipErrorInvalidValue;     // FP32-only shapes
     default: return launch_tb_t<double, 8, 8>(a, st, s);
     }
 }
@@ -524,6 +528,7 @@ hipError_t launch_sweep2d_tb_f32(const TBArgs &a, const Stencil<float> &st, hipS
     case 5: return launch_tb2_t<float, 4, 8>(a, st, s);
     case 6: return launch_tb2_t<float, 8, 8>(a, st, s);
     case 7: return launch_tb2_t<float, 2, 16>(a, st, s);
+    case 8: return launch_tb2_t<float, 8, 16>(a, st, s);
     default: return launch_tb_t<float, 8, 8>(a, st, s);
     }
 }

@@ -195,3 +195,30 @@ def test_batch_argument_errors():
             b.solve(F, T, fixed_iters=1)
         with pytest.raises(tdp.TdpError):
             b.autotune(T)
+
+
+def test_batch_f32_tall_tile():
+    """The FP32-only 128 x 64 tile with per-node coefficients (tile 8) in the
+    batched sweep matches the oracle and the one-step FP32 path; FP64 batches
+    refuse it."""
+    from paper_2006_16861_amd import tdp
+    probs, nrhs, ops, Fs = small_batch(prec=1)
+    note("batch f32 tile 8")
+    b = tdp.Batch(ops, nrhs)
+    T = [3, 2, 4]
+    for depth in (8, 12):
+        b.set_tuning(depth, 8)
+        Us = b.precond([dev(F) for F in Fs], T)
+        q = 0
+        for i, (p, r) in enumerate(zip(probs, nrhs)):
+            o = oracle.Op.from_problem(p)
+            ops[i].set_tuning(kernel=1)
+            for k in range(r):
+                got = Us[q].cpu().numpy()
+                assert rel(got, o.precond(Fs[q], T[i])) <= 1e-4
+                assert rel(got, ops[i].precond(dev(Fs[q]), T[i]).cpu().numpy()) <= 1e-5
+                q += 1
+    probs64, nrhs64, ops64, _ = small_batch()
+    b64 = tdp.Batch(ops64, nrhs64)
+    with pytest.raises(tdp.TdpError):
+        b64.set_tuning(8, 8)

@@ -353,7 +353,7 @@ def test_precond_blocked_f64(name, mk, depth, tile):
     assert rel(U, U1) <= 1e-13
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 def test_precond_blocked_f32(tile):
     p = inputs.random_medium((150, 200), seed=18, width=6)
     note(f"precond blocked f32 150x200 tile={tile}")
