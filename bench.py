@@ -638,6 +638,7 @@ def main():
                    "precond_applications": int(napply),
                    "true_relres": relres, "setup_ms": setup_ms,
                    "solve_ms": [round(i.ms_total, 3) for i in infos],
+                   "precond_ms": [round(i.ms_precond, 3) for i in infos],
                    "solve_ms_median": float(np.median([i.ms_total for i in infos])),
                    "kernel": op.get_tuning(), "parallelism": "single-gpu"},
         "recurrence_GBps": achieved,

@@ -152,7 +152,9 @@ typedef struct {
     int variant;
 } tdp_gmres_cfg;
 
-/* GMRES report (host struct).  history (host, may be NULL) receives the
+/* GMRES report (host struct).  With TDP_LOG=1 in the environment the solve
+ * also prints one line per cycle and a summary to stderr.  history (host,
+ * may be NULL) receives the
  * Givens estimate of ||P r|| / ||P r_0|| after each iteration, up to
  * history_cap entries.  switched = 1 when a tolerance-mode solve with
  * variant 0 rejected a cycle and continued with variant 1 (see
@@ -165,6 +167,9 @@ typedef struct {
     double *history;
     int history_cap, history_len;
     int switched;
+    double ms_precond;       /* GPU time of the preconditioner applications
+                                (HIP events on the op's stream; 0 in the
+                                batched form)                            */
 } tdp_gmres_info;
 
 /* Create an operator: validates the description, copies c and R, computes

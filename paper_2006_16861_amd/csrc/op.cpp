@@ -8,6 +8,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -108,6 +109,8 @@ static int free_op(tdp_op *op)
 {
     if (!op) return TDP_OK;
     if (op->ev) (void)hipEventDestroy(op->ev);
+    for (hipEvent_t e : op->tev)
+        if (e) (void)hipEventDestroy(e);
     (void)hipFree(op->Fstage);
     (void)hipFree(op->Ustage);
     (void)hipFree(op->gcell);
@@ -976,9 +979,33 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
     if (cfg->rho > 1.0) TDP_FAIL(TDP_EINVAL, "rho must be <= 1");
     if (cfg->variant != 0 && cfg->variant != 1) TDP_FAIL(TDP_EINVAL, "variant must be 0 or 1");
     TDP_CHECK(ensure_krylov(op, m));
+    for (hipEvent_t &e : op->tev)
+        if (!e) TDP_CHECK_HIP(hipEventCreate(&e));
     hipStream_t s = op->stream;
     const int64_t N = op->N;
     const int T = cfg->periods_T;
+    // TDP_LOG=1 in the environment: one stderr line per cycle
+    static const bool log_cycles = [] {
+        const char *v = std::getenv("TDP_LOG");
+        return v && v[0] == '1';
+    }();
+    double ms_precond = 0.0;
+    // preconditioner application on the op's stream, bracketed by timing
+    // events; the elapsed time is read after the stream's next synchronisation
+    bool timed_pending = false;
+    auto precond_timed = [&](const void *x, void *y, int var) -> int {
+        TDP_CHECK_HIP(hipEventRecord(op->tev[0], s));
+        TDP_CHECK(precond_impl(op, T, cfg->rho, var, x, y, true));
+        TDP_CHECK_HIP(hipEventRecord(op->tev[1], s));
+        timed_pending = true;
+        return TDP_OK;
+    };
+    auto collect_time = [&]() {      // after a synchronisation of s
+        if (!timed_pending) return;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, op->tev[0], op->tev[1]) == hipSuccess) ms_precond += ms;
+        timed_pending = false;
+    };
     const double rho = cfg->rho;
     const bool tolmode = cfg->fixed_iters <= 0;
     const int limit = tolmode ? cfg->max_iters : cfg->fixed_iters;
@@ -1037,10 +1064,11 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
             break;
         }
         if (its >= limit) break;
-        TDP_CHECK(precond_impl(op, T, rho, variant, op->rv, col(0), true));
+        TDP_CHECK(precond_timed(op->rv, col(0), variant));
         ++napply;
         double z2;
         TDP_CHECK(norm2_host(op, col(0), &z2));
+        collect_time();
         const double beta0 = std::sqrt(z2);
         if (pnorm0 < 0.0) pnorm0 = beta0;
         if (beta0 == 0.0) break;
@@ -1053,7 +1081,7 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
         bool converged = false;           // smallest true residual (0: the start)
         for (int i = 0; i < m && its < limit; ++i) {
             TDP_CHECK(apply_H_impl(op, col(i), nullptr, op->tv));
-            TDP_CHECK(precond_impl(op, T, rho, variant, op->tv, op->wv, true));
+            TDP_CHECK(precond_timed(op->tv, op->wv, variant));
             ++napply;
             ++its;
             // classical Gram-Schmidt, two passes
@@ -1066,6 +1094,7 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
             TDP_CHECK_HIP(hipMemcpyAsync(op->hres, op->dcoef, sizeof(double) * (4 * (m + 1) + 2),
                                          hipMemcpyDeviceToHost, s));
             TDP_CHECK_HIP(hipStreamSynchronize(s));
+            collect_time();
             const double *h1 = op->hres, *h2 = op->hres + 2 * (m + 1);
             for (int k = 0; k <= i; ++k)
                 HM(k, i) = cplx(h1[2 * k] + h2[2 * k], h1[2 * k + 1] + h2[2 * k + 1]);
@@ -1137,6 +1166,12 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
                 TDP_CHECK(update(U, U, best_k));
             }
             rel = best_rel;
+            if (log_cycles)
+                std::fprintf(stderr,
+                             "tdp gmres: cycle %d its %d variant %d kept %d/%d true relres %.3e "
+                             "(start %.3e) est %.3e%s\n",
+                             restarts, its, variant, best_k, k_used, best_rel, rel_start, est,
+                             best_k == 0 && k_used > 0 ? " rejected" : "");
             if (best_k == 0 && k_used > 0) {      // Table 1 cycle rejected:
                 variant = 1;                      // continue with Definition 4
                 switched = 1;
@@ -1159,6 +1194,13 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
         if (its >= limit) break;
     }
     TDP_CHECK_HIP(hipStreamSynchronize(s));
+    collect_time();
+    if (log_cycles)
+        std::fprintf(stderr, "tdp gmres: %s after %d iterations, %d cycles, true relres %.3e, "
+                             "%.1f ms (preconditioner %.1f ms)\n",
+                     status == TDP_OK ? "done" : "not converged", its, restarts, rel,
+                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(),
+                     ms_precond);
     if (info) {
         info->iters = its;
         info->restarts = restarts;
@@ -1169,6 +1211,7 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
         info->switched = switched;
         info->ms_total =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        info->ms_precond = ms_precond;
     }
     return status;
 }

@@ -298,6 +298,7 @@ struct tdp_op {
     hipStream_t user_stream = nullptr;
     bool own_stream = false;
     hipEvent_t ev = nullptr;
+    hipEvent_t tev[2] = {nullptr, nullptr};   // timing of the preconditioner in GMRES
     void *Fstage = nullptr;    // complex128 input of the captured loop (FP64)
     void *Ustage = nullptr;    // complex128 output of the captured loop
     double *gcell = nullptr;   // per-cell gradient scratch

@@ -72,7 +72,8 @@ class GmresInfo(ctypes.Structure):
                 ("relres_true", ctypes.c_double), ("relres_prec", ctypes.c_double),
                 ("steps", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int),
-                ("history_len", ctypes.c_int), ("switched", ctypes.c_int)]
+                ("history_len", ctypes.c_int), ("switched", ctypes.c_int),
+                ("ms_precond", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -155,6 +156,7 @@ class SolveInfo:
     ms_total: float
     history: list
     switched: int = 0      # 1: a rejected cycle moved the solve to the complex-linear variant
+    ms_precond: float = 0.0   # GPU time of the preconditioner applications
 
 
 class Operator:
@@ -254,7 +256,7 @@ class Operator:
                     "tdp_gmres_solve")
         return U, SolveInfo(rc, info.iters, info.restarts, info.relres_true, info.relres_prec,
                             info.steps, info.ms_total, list(hist[: info.history_len]),
-                            info.switched)
+                            info.switched, info.ms_precond)
 
     def grad_m(self, lam, U, out=None):
         import torch

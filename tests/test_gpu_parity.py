@@ -707,3 +707,27 @@ def test_two_ops_on_two_streams_from_two_threads():
         assert rel(out[k][0], o.precond(p.F, 2, 0.25)) <= TOL64
         Uo, _ = o.gmres(p.F, T=p.periods, restart=5, fixed_iters=8)
         assert rel(out[k][1], Uo) <= TOL64
+
+
+def test_gmres_phase_time_and_cycle_log():
+    """The report's preconditioner time is positive and below the wall time;
+    with TDP_LOG=1 a solve prints one line per cycle and a summary."""
+    import os
+    import subprocess
+    p = inputs.const2d()
+    g, _ = make_ops(p)
+    _, info = g.solve(dev(p.F), T=p.periods, tol=1e-8)
+    assert 0.0 < info.ms_precond <= info.ms_total
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import torch\n"
+            "from paper_2006_16861_amd import tdp, inputs\n"
+            "p = inputs.const2d()\n"
+            "op = tdp.operator_from_problem(p)\n"
+            "U, info = op.solve(torch.as_tensor(p.F, device='cuda'), T=p.periods, tol=1e-8, restart=4)\n"
+            "print(info.restarts)\n") % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, TDP_LOG="1"))
+    assert r.returncode == 0, r.stderr[-2000:]
+    cycles = [l for l in r.stderr.splitlines() if l.startswith("tdp gmres: cycle")]
+    assert len(cycles) == int(r.stdout.strip().splitlines()[-1]) and len(cycles) >= 2
+    assert any(l.startswith("tdp gmres: done after") for l in r.stderr.splitlines())
