@@ -504,12 +504,14 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
         S.y.assign(m, 0.0);
         S.ybest.assign(m, 0.0);
         S.cs.assign(m, 0.0);
-        if (!cfg->x0_given) TDP_CHECK_HIP(launch_fill_zero(U[q], 16 * b->f[q].N, s));
         TDP_CHECK(norm2_async(q, F[q], b->f[q].dco));
         TDP_CHECK_HIP(hipMemcpyAsync(hb + q * hs, b->f[q].dco, sizeof(double), hipMemcpyDeviceToHost, s));
     }
     TDP_CHECK_HIP(hipStreamSynchronize(s));
+    for (size_t q = 0; q < nf; ++q)     // refused before any output is written
+        if (!std::isfinite(std::sqrt(hb[q * hs]))) TDP_BFAIL(TDP_EINVAL, "F[%zu] holds NaN or Inf", q);
     for (size_t q = 0; q < nf; ++q) {
+        if (!cfg->x0_given) TDP_CHECK_HIP(launch_fill_zero(U[q], 16 * b->f[q].N, s));
         st[q].bnorm = std::sqrt(hb[q * hs]);
         if (st[q].bnorm == 0.0) {
             TDP_CHECK_HIP(launch_fill_zero(U[q], 16 * b->f[q].N, s));
@@ -584,6 +586,8 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
             needP[q] = 0;
             if (S.ph == NEED_RES) {
                 S.rel = std::sqrt(hb[q * hs]) / S.bnorm;
+                if (!std::isfinite(S.rel) && S.its == 0 && S.restarts == 0)
+                    TDP_BFAIL(TDP_EINVAL, "non-finite residual of field %zu: U holds NaN or Inf", q);
                 if (tolmode && S.rel <= cfg->tol) {
                     S.status = TDP_OK;
                     S.ph = DONE;

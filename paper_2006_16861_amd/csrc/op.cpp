@@ -1017,10 +1017,11 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
     double *dn2 = op->dcoef + 4 * (m + 1);  // ||w||^2
     double *dy = op->dcoef + 4 * (m + 1) + 2;
 
-    if (!cfg->x0_given) TDP_CHECK_HIP(launch_fill_zero(U, 16 * N, s));
     double b2;
     TDP_CHECK(norm2_host(op, F, &b2));
     const double bnorm = std::sqrt(b2);
+    if (!std::isfinite(bnorm)) TDP_FAIL(TDP_EINVAL, "F holds NaN or Inf");   // nothing written
+    if (!cfg->x0_given) TDP_CHECK_HIP(launch_fill_zero(U, 16 * N, s));
     int its = 0, restarts = 0, nhist = 0, status = TDP_ENOTCONV;
     int variant = op->dform == TDP_DAMP_CELL ? 1 : cfg->variant, switched = 0;
     int64_t napply = 0;
@@ -1059,6 +1060,8 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
         TDP_CHECK(apply_H_impl(op, U, F, op->rv));   // r = F - H U
         TDP_CHECK(norm2_host(op, op->rv, &r2));
         rel = std::sqrt(r2) / bnorm;
+        if (!std::isfinite(rel) && its == 0 && restarts == 0)   // U is still the caller's x0
+            TDP_FAIL(TDP_EINVAL, "non-finite residual: the initial U holds NaN or Inf");
         if (tolmode && rel <= cfg->tol) {
             status = TDP_OK;
             break;

@@ -195,6 +195,11 @@ def test_batch_argument_errors():
             b.solve(F, T, fixed_iters=1)
         with pytest.raises(tdp.TdpError):
             b.autotune(T)
+    Fbad = [f.clone() for f in F]
+    Fbad[2][3, 3] = float("nan")
+    with pytest.raises(tdp.TdpError) as ei:         # refused at once, not iterated
+        b.solve(Fbad, [2, 2, 2], tol=1e-6)
+    assert ei.value.code == tdp.EINVAL and "NaN" in str(ei.value)
 
 
 def test_batch_f32_tall_tile():

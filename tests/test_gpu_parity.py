@@ -167,6 +167,16 @@ def test_zero_rhs_and_errors():
     assert ei.value.code == tdp.EINVAL and "2^24" in str(ei.value)
     _, info = g.solve(dev(p.F), T=1, tol=1e-12, max_iters=1)
     assert info.status == tdp.ENOTCONV and info.iters == 1
+    Fbad = p.F.copy()
+    Fbad[4, 5] = np.nan
+    with pytest.raises(tdp.TdpError) as ei:        # refused at once, not iterated
+        g.solve(dev(Fbad), T=2, tol=1e-6)
+    assert ei.value.code == tdp.EINVAL and "NaN" in str(ei.value)
+    U0 = np.zeros(p.n, complex)
+    U0[2, 2] = np.inf
+    with pytest.raises(tdp.TdpError) as ei:
+        g.solve(dev(p.F), T=2, tol=1e-6, x0=dev(U0))
+    assert ei.value.code == tdp.EINVAL
 
 
 def test_precond_f32_close_to_oracle():
