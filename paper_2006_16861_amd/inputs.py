@@ -250,21 +250,24 @@ def random_medium(n, seed: int, cmin: float = 1.0, cmax: float = 2.0,
 
 
 def _model2d(name, model: int, width: int, ppw: float, c_of_xy, src_xy) -> Problem:
-    """A model on the unit square sampled at h = 1/(model+1), with damping
-    layers of `width` nodes added outside it (as in Sec. 4.1), so the grid has
-    model + 2 width nodes per axis.  c_of_xy(x, y) gives the speed at model
-    coordinates (nodes in the layers take the speed of the nearest model node);
-    the point source sits at model coordinates src_xy."""
+    """A model on the unit square, `model` nodes per axis at the cell centres
+    (k + 1/2) h, h = 1/model, so that k = omega/c = 2 pi model/ppw for c = 1
+    (Sec. 4.1 prints k = 335.1 for its 320 x 320 constant model at 6 points
+    per wavelength); damping layers of `width` nodes are added outside it (as
+    in Sec. 4.1), so the grid has model + 2 width nodes per axis.  c_of_xy(x, y)
+    gives the speed at model coordinates (nodes in the layers take the speed of
+    the nearest model node); the point source sits at the model node nearest
+    to src_xy."""
     n = model + 2 * width
     shape = (n, n)
-    h = 1.0 / (model + 1)
+    h = 1.0 / model
     idx = np.clip(np.arange(n) - width, 0, model - 1)
-    xs = (idx + 1) * h
+    xs = (idx + 0.5) * h
     X, Y = np.meshgrid(xs, xs, indexing="ij")
     c = np.ascontiguousarray(c_of_xy(X, Y), dtype=np.float64)
     omega = omega_for_ppw(float(c.min()), h, ppw)
     R = damping_profile(shape, width, 2.0 * omega)
-    src = tuple(width + int(round(v / h)) - 1 for v in src_xy)
+    src = tuple(width + min(model - 1, max(0, int(math.floor(v / h)))) for v in src_xy)
     F = point_source(shape, src)
     return Problem(name, shape, h, omega, c, R, F, periods_for((model, model), ppw), ppw,
                    width, {"model": model, "src": src})

@@ -1,0 +1,42 @@
+"""Values the paper prints (tests/golden/, each file citing its passage)
+against the oracle and the input recipe (CPU)."""
+import math
+import os
+
+import pytest
+
+import oracle
+from paper_2006_16861_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _records(name):
+    out = []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.split("#", 1)[0].split()
+        if line:
+            out.append({line[i]: float(line[i + 1]) for i in range(0, len(line), 2)})
+    return out
+
+
+def test_sec4_1_steps_per_period():
+    """6 points per wavelength -> 8 steps per period, from the oracle's CFL
+    choice on the constant model (a small model: n_P depends only on the
+    points per wavelength)."""
+    rec = [r for r in _records("sec4_1_constant_model.txt") if "steps_per_period" in r][0]
+    p = inputs.open2d(model=48, width=8, ppw=rec["ppw"])
+    assert oracle.Op.from_problem(p).nP == int(rec["steps_per_period"])
+
+
+@pytest.mark.parametrize("model", [320, 640])
+def test_sec4_1_wavenumber_of_the_constant_model(model):
+    """k = omega/c of the study's constant model against the printed value.
+    2 pi 320/6 = 335.10 matches 335.1; 2 pi 640/6 = 670.21 is printed as
+    670.1, so the bound is the printed value's last digit plus that slip
+    (0.02%)."""
+    rec = [r for r in _records("sec4_1_constant_model.txt") if r.get("model") == model][0]
+    p = inputs.open2d(model=model, width=32, ppw=6.0)
+    k = p.omega / float(p.c.min())
+    assert abs(k - rec["k"]) <= 2e-4 * rec["k"], (k, rec["k"])
+    assert abs(k - 2 * math.pi * model / 6) <= 1e-9 * k
