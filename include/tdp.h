@@ -238,7 +238,8 @@ int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
  *               variant), 4 streamed along axis 0 with two steps per launch
  *               (3-D, Table 1 variant); inapplicable choices fall back to 1
  *  tb_depth     kernel 2: steps per launch, 1..16 (0 auto);
- *               kernels 3, 4: planes per chunk (0 auto = 32)
+ *               kernels 3, 4: planes per chunk (0 auto: 32, halved down
+ *               to 8 until the launch has about 8192 waves)
  *  use_graph    1 capture the step loop in a hipGraph and replay it (loops
  *               of more than 2^17 launches are issued directly)
  *  tile         kernel 2 tile (rows x columns): 0 64x64 (8 rows per lane x

@@ -490,7 +490,18 @@ static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth)
         const int rows = tb2d_tile_rows(op->tune.tile, op->prec == TDP_F64);
         if (4 * k > rows || 4 * k > 64) k = rows / 8;   // keep at least half the tile exact
     } else if (kern == 3 || kern == 4) {
-        if (k == 0) k = 32;
+        if (k == 0) {
+            // default chunk length: halve from 32 (down to 8) until the launch
+            // has about 8192 waves, so that small grids still fill the chip
+            // (128^3: 8 planes, 2x faster than 32; 256^3: 16)
+            const int shape = op->tune.tile > 2 ? 1 : op->tune.tile;
+            const int rows = kern == 3 ? (shape == 0 ? 8 : 16) : (shape == 0 ? 6 : 14);
+            const int cols = kern == 3 ? 64 : 62;
+            const int waves = shape == 2 ? 8 : 4;
+            const int64_t txy = (int64_t)((op->n[2] + cols - 1) / cols) * ((op->n[1] + rows - 1) / rows);
+            k = 32;
+            while (k > 8 && txy * ((op->n[0] + k - 1) / k) * waves < 8192) k /= 2;
+        }
     } else {
         k = 1;
     }
@@ -834,9 +845,9 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
     }
     if (op->ndim == 3 && variant == 0) {
         for (int shape = 0; shape < 3; ++shape)
-            for (int zc : {16, 32, 64}) cand.push_back({3, zc, 1, shape});
+            for (int zc : {4, 8, 16, 32, 64}) cand.push_back({3, zc, 1, shape});
         for (int shape = 0; shape < 3; ++shape)
-            for (int zc : {16, 32, 64}) cand.push_back({4, zc, 1, shape});
+            for (int zc : {4, 8, 16, 32, 64}) cand.push_back({4, zc, 1, shape});
     }
     const tdp_tuning saved = op->tune;
     void *tin = nullptr, *tout = nullptr;
