@@ -233,7 +233,10 @@ int tdp_gmres_solve(const tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, v
 int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
 
 /* Tuning of the recurrence sweep (no effect on results beyond rounding).
- *  kernel       0 auto, 1 one step per launch, 2 temporally blocked (2-D,
+ *  kernel       0 auto (kernel, depth and tile chosen by the library: the
+ *               blocked 2-D sweep on tile 5 (FP64) or 8 (FP32) at depth 8, the
+ *               streamed 3-D sweep on tile 0; tb_depth and tile ignored),
+ *               1 one step per launch, 2 temporally blocked (2-D,
  *               Table 1 variant), 3 streamed along axis 0 (3-D, Table 1
  *               variant), 4 streamed along axis 0 with two steps per launch
  *               (3-D, Table 1 variant); inapplicable choices fall back to 1

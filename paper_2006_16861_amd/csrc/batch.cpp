@@ -109,7 +109,7 @@ extern "C" int tdp_batch_create(tdp_op *const *ops, int nops, const int *nrhs, t
     }
     b->f64 = ops[0]->prec == TDP_F64;
     b->s = ops[0]->stream;
-    b->shape = 4;
+    b->shape = b->f64 ? 4 : 8;    // FP32: the 128 x 64 tile
     b->K = 8;
     const size_t es = b->f64 ? sizeof(double) : sizeof(float);
     for (int i = 0; i < nops; ++i) {

@@ -475,29 +475,35 @@ static int ensure_complex_fields(tdp_op *op)
     return TDP_OK;
 }
 
-// Which sweep kernel and depth the loop uses: 1 one step per launch, 2 the
-// blocked 2-D kernel (k steps per launch), 3 the streamed 3-D kernel (depth =
-// planes per chunk).
-static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth)
+// Which sweep kernel, depth and tile the loop uses: 1 one step per launch, 2
+// the blocked 2-D kernel (k steps per launch), 3 / 4 the streamed 3-D kernels
+// (depth = planes per chunk).  kernel 0 chooses all three: the blocked 2-D
+// sweep on the 32 x 64 tile (FP64) or the 128 x 64 tile (FP32) at depth 8,
+// the streamed 3-D sweep on 8 x 64 columns, with the chunk below.
+static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth, int *tile)
 {
-    int kern = op->tune.kernel, k = op->tune.tb_depth;
+    int kern = op->tune.kernel, k = op->tune.tb_depth, t = op->tune.tile;
+    if (kern == 0) {
+        kern = variant == 0 ? (op->ndim == 2 ? 2 : 3) : 1;
+        k = kern == 2 ? 8 : 0;
+        t = kern == 2 ? (op->prec == TDP_F64 ? 5 : 8) : 0;
+    }
     if (op->dform == TDP_DAMP_CELL) kern = 1;    // I_abd: one step per launch
-    if (kern == 0) kern = variant == 0 ? (op->ndim == 2 ? 2 : 3) : 1;
     if (kern == 2 && !(op->ndim == 2 && variant == 0)) kern = 1;
     if ((kern == 3 || kern == 4) && !(op->ndim == 3 && variant == 0)) kern = 1;
     if (kern == 2) {
         if (k == 0) k = 4;
-        const int rows = tb2d_tile_rows(op->tune.tile, op->prec == TDP_F64);
+        const int rows = tb2d_tile_rows(t, op->prec == TDP_F64);
         if (4 * k > rows || 4 * k > 64) k = rows / 8;   // keep at least half the tile exact
     } else if (kern == 3 || kern == 4) {
+        if (t > 2) t = 1;
         if (k == 0) {
             // default chunk length: halve from 32 (down to 8) until the launch
             // has about 8192 waves, so that small grids still fill the chip
             // (128^3: 8 planes, 2x faster than 32; 256^3: 16)
-            const int shape = op->tune.tile > 2 ? 1 : op->tune.tile;
-            const int rows = kern == 3 ? (shape == 0 ? 8 : 16) : (shape == 0 ? 6 : 14);
+            const int rows = kern == 3 ? (t == 0 ? 8 : 16) : (t == 0 ? 6 : 14);
             const int cols = kern == 3 ? 64 : 62;
-            const int waves = shape == 2 ? 8 : 4;
+            const int waves = t == 2 ? 8 : 4;
             const int64_t txy = (int64_t)((op->n[2] + cols - 1) / cols) * ((op->n[1] + rows - 1) / rows);
             k = 32;
             while (k > 8 && txy * ((op->n[0] + k - 1) / k) * waves < 8192) k /= 2;
@@ -507,6 +513,7 @@ static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth)
     }
     *kernel = kern;
     *depth = k;
+    *tile = t;
 }
 
 static int ensure_tb_fields(tdp_op *op)
@@ -520,7 +527,8 @@ static int ensure_tb_fields(tdp_op *op)
 
 // Blocked loop: launches of k steps, ping-ponging between the field pairs
 // (u0, u1) and (v0, v1).
-static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, const void *Fin, void *U)
+static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, int tile, const void *Fin,
+                          void *U)
 {
     hipStream_t s = op->stream;
     TDP_CHECK(ensure_tb_fields(op));
@@ -535,7 +543,7 @@ static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, const void *
     a.nx = op->n[1];
     a.sc = op->sc;
     a.mc = op->mc;
-    a.shape = op->tune.tile;
+    a.shape = tile;
     a.m = op->prec == TDP_F64 ? (const void *)op->m : (const void *)op->m32;
     a.dn = op->prec == TDP_F64 ? (const void *)op->dn : (const void *)op->dn32;
     a.F = Fin;
@@ -568,7 +576,8 @@ static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, const void *
 
 // Streamed 3-D loop with two steps per launch, ping-ponging between the field
 // pairs (u0, u1) and (v0, v1); an odd last step runs the one-step kernel in place.
-static int issue_steps_3d2(tdp_op *op, int T, double rho, int zc, const void *Fin, void *U)
+static int issue_steps_3d2(tdp_op *op, int T, double rho, int zc, int shape, const void *Fin,
+                           void *U)
 {
     hipStream_t s = op->stream;
     TDP_CHECK(ensure_tb_fields(op));
@@ -576,7 +585,6 @@ static int issue_steps_3d2(tdp_op *op, int T, double rho, int zc, const void *Fi
     const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - snap_lag(op->nP);
     const bool f64 = op->prec == TDP_F64;
     const size_t fb = (f64 ? sizeof(double) : sizeof(float)) * op->N;
-    const int shape = op->tune.tile > 2 ? 1 : op->tune.tile;
     void *cur = op->u0, *prev = op->u1, *ncur = op->v0, *nprev = op->v1;
     TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
     TDP_CHECK_HIP(launch_fill_zero(prev, fb, s));
@@ -638,11 +646,11 @@ static int issue_steps_3d2(tdp_op *op, int T, double rho, int zc, const void *Fi
 // Definition 4.
 static int issue_steps_loop(tdp_op *op, int T, double rho, int variant, const void *Fin, void *U)
 {
-    int kern, depth;
-    sweep_plan(op, variant, &kern, &depth);
-    if (kern == 2) return issue_steps_tb(op, T, rho, depth, Fin, U);
-    if (kern == 4) return issue_steps_3d2(op, T, rho, depth, Fin, U);
-    const int shape3 = op->tune.tile > 2 ? 1 : op->tune.tile;
+    int kern, depth, tile;
+    sweep_plan(op, variant, &kern, &depth, &tile);
+    if (kern == 2) return issue_steps_tb(op, T, rho, depth, tile, Fin, U);
+    if (kern == 4) return issue_steps_3d2(op, T, rho, depth, tile, Fin, U);
+    const int shape3 = tile;
     hipStream_t s = op->stream;
     const std::vector<double> &tab = forcing_table(op, T, rho, variant);
     const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - snap_lag(op->nP);
@@ -727,8 +735,8 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
     if (variant) TDP_CHECK(ensure_complex_fields(op));
     int64_t launches;
     {   // allocate before any stream capture: no allocation may happen inside it
-        int kern, depth;
-        sweep_plan(op, variant, &kern, &depth);
+        int kern, depth, tile;
+        sweep_plan(op, variant, &kern, &depth, &tile);
         if (kern == 2 || kern == 4) TDP_CHECK(ensure_tb_fields(op));
         launches = kern == 2 ? (Ns + depth - 1) / depth : (kern == 4 ? (Ns + 1) / 2 : Ns);
     }
