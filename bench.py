@@ -639,6 +639,8 @@ def main():
                    "true_relres": relres, "setup_ms": setup_ms,
                    "solve_ms": [round(i.ms_total, 3) for i in infos],
                    "precond_ms": [round(i.ms_precond, 3) for i in infos],
+                   "H_ms": [round(i.ms_H, 3) for i in infos],
+                   "arnoldi_ms": [round(i.ms_arnoldi, 3) for i in infos],
                    "solve_ms_median": float(np.median([i.ms_total for i in infos])),
                    "kernel": op.get_tuning(), "parallelism": "single-gpu"},
         "recurrence_GBps": achieved,

@@ -167,9 +167,11 @@ typedef struct {
     double *history;
     int history_cap, history_len;
     int switched;
-    double ms_precond;       /* GPU time of the preconditioner applications
-                                (HIP events on the op's stream; 0 in the
-                                batched form)                            */
+    double ms_precond;       /* GPU time of the preconditioner applications,
+                                of the H-applies and of the Gram-Schmidt
+                                kernels (HIP events on the op's stream; 0
+                                in the batched form)                     */
+    double ms_H, ms_arnoldi;
 } tdp_gmres_info;
 
 /* Create an operator: validates the description, copies c and R, computes

@@ -769,7 +769,7 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
             inf.steps = S.napply * (int64_t)periods_T[b->f[q].op] * b->ops[b->f[q].op]->nP;
             inf.history_len = S.nhist < inf.history_cap ? S.nhist : inf.history_cap;
             inf.ms_total = ms;
-            inf.ms_precond = 0.0;          // not timed per field in the batched form
+            inf.ms_precond = inf.ms_H = inf.ms_arnoldi = 0.0;   // not timed per field here
         }
     }
     return worst;

@@ -1008,22 +1008,35 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
         const char *v = std::getenv("TDP_LOG");
         return v && v[0] == '1';
     }();
-    double ms_precond = 0.0;
-    // preconditioner application on the op's stream, bracketed by timing
-    // events; the elapsed time is read after the stream's next synchronisation
-    bool timed_pending = false;
-    auto precond_timed = [&](const void *x, void *y, int var) -> int {
-        TDP_CHECK_HIP(hipEventRecord(op->tev[0], s));
-        TDP_CHECK(precond_impl(op, T, cfg->rho, var, x, y, true));
-        TDP_CHECK_HIP(hipEventRecord(op->tev[1], s));
-        timed_pending = true;
+    // phase timing: GPU time of the preconditioner applications (0), the
+    // H-applies (1) and the Gram-Schmidt kernels (2), from event pairs on the
+    // op's stream read after its next synchronisation (each phase is recorded
+    // at most once between two synchronisations)
+    double ms_phase[3] = {0.0, 0.0, 0.0};
+    bool pending[3] = {false, false, false};
+    auto mark = [&](int ph, int end) -> int {
+        TDP_CHECK_HIP(hipEventRecord(op->tev[2 * ph + end], s));
+        if (end) pending[ph] = true;
         return TDP_OK;
     };
-    auto collect_time = [&]() {      // after a synchronisation of s
-        if (!timed_pending) return;
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, op->tev[0], op->tev[1]) == hipSuccess) ms_precond += ms;
-        timed_pending = false;
+    auto collect_time = [&]() {
+        for (int ph = 0; ph < 3; ++ph) {
+            if (!pending[ph]) continue;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, op->tev[2 * ph], op->tev[2 * ph + 1]) == hipSuccess)
+                ms_phase[ph] += ms;
+            pending[ph] = false;
+        }
+    };
+    auto precond_timed = [&](const void *x, void *y, int var) -> int {
+        TDP_CHECK(mark(0, 0));
+        TDP_CHECK(precond_impl(op, T, cfg->rho, var, x, y, true));
+        return mark(0, 1);
+    };
+    auto apply_H_timed = [&](const void *x, const void *Fr, void *y) -> int {
+        TDP_CHECK(mark(1, 0));
+        TDP_CHECK(apply_H_impl(op, x, Fr, y));
+        return mark(1, 1);
     };
     const double rho = cfg->rho;
     const bool tolmode = cfg->fixed_iters <= 0;
@@ -1076,8 +1089,9 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
     }
     while (status != TDP_OK) {
         double r2;
-        TDP_CHECK(apply_H_impl(op, U, F, op->rv));   // r = F - H U
+        TDP_CHECK(apply_H_timed(U, F, op->rv));   // r = F - H U
         TDP_CHECK(norm2_host(op, op->rv, &r2));
+        collect_time();
         rel = std::sqrt(r2) / bnorm;
         if (!std::isfinite(rel) && its == 0 && restarts == 0)   // U is still the caller's x0
             TDP_FAIL(TDP_EINVAL, "non-finite residual: the initial U holds NaN or Inf");
@@ -1102,17 +1116,19 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
         int k_used = 0, best_k = 0;       // best_k: the cycle's candidate with the
         bool converged = false;           // smallest true residual (0: the start)
         for (int i = 0; i < m && its < limit; ++i) {
-            TDP_CHECK(apply_H_impl(op, col(i), nullptr, op->tv));
+            TDP_CHECK(apply_H_timed(col(i), nullptr, op->tv));
             TDP_CHECK(precond_timed(op->tv, op->wv, variant));
             ++napply;
             ++its;
             // classical Gram-Schmidt, two passes
+            TDP_CHECK(mark(2, 0));
             TDP_CHECK_HIP(launch_mdot(op->V, N, i + 1, op->wv, N, op->red, nblk, d1, s));
             TDP_CHECK_HIP(launch_maxpy(op->wv, op->V, N, i + 1, d1, -1.0, N, s));
             TDP_CHECK_HIP(launch_mdot(op->V, N, i + 1, op->wv, N, op->red, nblk, d2, s));
             TDP_CHECK_HIP(launch_maxpy(op->wv, op->V, N, i + 1, d2, -1.0, N, s));
             TDP_CHECK_HIP(launch_mdot(op->wv, N, 1, op->wv, N, op->red, nblk, dn2, s));
             TDP_CHECK_HIP(launch_scale_by_invnorm(col(i + 1), op->wv, dn2, N, s));
+            TDP_CHECK(mark(2, 1));
             TDP_CHECK_HIP(hipMemcpyAsync(op->hres, op->dcoef, sizeof(double) * (4 * (m + 1) + 2),
                                          hipMemcpyDeviceToHost, s));
             TDP_CHECK_HIP(hipStreamSynchronize(s));
@@ -1150,8 +1166,9 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
             if (tolmode) {
                 solve_y(k_used);
                 TDP_CHECK(update(op->xv, U, k_used));
-                TDP_CHECK(apply_H_impl(op, op->xv, F, op->rv));
+                TDP_CHECK(apply_H_timed(op->xv, F, op->rv));
                 TDP_CHECK(norm2_host(op, op->rv, &r2));
+                collect_time();
                 const double relt = std::sqrt(r2) / bnorm;
                 rel_last = relt;
                 if (relt < best_rel) {
@@ -1207,8 +1224,9 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
             break;
         }
         if (!tolmode && its >= limit) {
-            TDP_CHECK(apply_H_impl(op, U, F, op->rv));
+            TDP_CHECK(apply_H_timed(U, F, op->rv));
             TDP_CHECK(norm2_host(op, op->rv, &r2));
+            collect_time();
             rel = std::sqrt(r2) / bnorm;
             status = TDP_OK;
             break;
@@ -1222,7 +1240,7 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
                              "%.1f ms (preconditioner %.1f ms)\n",
                      status == TDP_OK ? "done" : "not converged", its, restarts, rel,
                      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(),
-                     ms_precond);
+                     ms_phase[0]);
     if (info) {
         info->iters = its;
         info->restarts = restarts;
@@ -1233,7 +1251,9 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
         info->switched = switched;
         info->ms_total =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        info->ms_precond = ms_precond;
+        info->ms_precond = ms_phase[0];
+        info->ms_H = ms_phase[1];
+        info->ms_arnoldi = ms_phase[2];
     }
     return status;
 }

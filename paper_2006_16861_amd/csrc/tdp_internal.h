@@ -298,7 +298,7 @@ struct tdp_op {
     hipStream_t user_stream = nullptr;
     bool own_stream = false;
     hipEvent_t ev = nullptr;
-    hipEvent_t tev[2] = {nullptr, nullptr};   // timing of the preconditioner in GMRES
+    hipEvent_t tev[6] = {};    // GMRES phase timing: (start, end) per phase
     void *Fstage = nullptr;    // complex128 input of the captured loop (FP64)
     void *Ustage = nullptr;    // complex128 output of the captured loop
     double *gcell = nullptr;   // per-cell gradient scratch

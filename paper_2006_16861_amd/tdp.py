@@ -73,7 +73,8 @@ class GmresInfo(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int),
                 ("history_len", ctypes.c_int), ("switched", ctypes.c_int),
-                ("ms_precond", ctypes.c_double)]
+                ("ms_precond", ctypes.c_double), ("ms_H", ctypes.c_double),
+                ("ms_arnoldi", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -157,6 +158,8 @@ class SolveInfo:
     history: list
     switched: int = 0      # 1: a rejected cycle moved the solve to the complex-linear variant
     ms_precond: float = 0.0   # GPU time of the preconditioner applications
+    ms_H: float = 0.0         # ... of the H-applies
+    ms_arnoldi: float = 0.0   # ... of the Gram-Schmidt kernels
 
 
 class Operator:
@@ -256,7 +259,7 @@ class Operator:
                     "tdp_gmres_solve")
         return U, SolveInfo(rc, info.iters, info.restarts, info.relres_true, info.relres_prec,
                             info.steps, info.ms_total, list(hist[: info.history_len]),
-                            info.switched, info.ms_precond)
+                            info.switched, info.ms_precond, info.ms_H, info.ms_arnoldi)
 
     def grad_m(self, lam, U, out=None):
         import torch

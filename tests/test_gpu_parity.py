@@ -728,6 +728,8 @@ def test_gmres_phase_time_and_cycle_log():
     g, _ = make_ops(p)
     _, info = g.solve(dev(p.F), T=p.periods, tol=1e-8)
     assert 0.0 < info.ms_precond <= info.ms_total
+    assert 0.0 < info.ms_H and 0.0 < info.ms_arnoldi
+    assert info.ms_precond + info.ms_H + info.ms_arnoldi <= info.ms_total
     code = ("import sys; sys.path.insert(0, %r)\n"
             "import torch\n"
             "from paper_2006_16861_amd import tdp, inputs\n"
