@@ -276,24 +276,32 @@ def form_batched(rho):
 def form_cell_damping(rho):
     """Sec. 5 path on the headline workload: smooth2d-1024 with the cell
     (non-diagonal) damping Im H = omega sum_cells r_cell M_cell, preconditioned
-    by S_T^abd (I_abd), FP64, to a true relative residual of 1e-6.  The sweep
-    moves 10 words per node-step (u_n, u_{n-1} and F complex, the two cell
-    arrays, u_{n+1} complex)."""
+    by S_T^abd (I_abd), to a true relative residual of 1e-6, with FP64 and with
+    FP32 recurrence fields (GMRES, H and the residuals in FP64 either way).  The
+    sweep moves 10 words per node-step (u_n, u_{n-1} and F complex, the two
+    cell arrays, u_{n+1} complex)."""
     import torch
     from paper_2006_16861_amd import inputs, tdp
     p = inputs.smooth2d(1024)
-    op = tdp.operator_from_problem(p, damping="cell")
     F = torch.as_tensor(p.F, device="cuda")
-    op.solve(F, T=p.periods, rho=rho, tol=1e-6)                     # warm (graph)
-    (U, info), dt = _timed(lambda: op.solve(F, T=p.periods, rho=rho, tol=1e-6))
-    r = float(torch.linalg.norm(F - op.apply_H(U)) / torch.linalg.norm(F))
-    _, step_ms = sweep_timing(op, F, p.periods, rho, 1, torch.cuda.current_stream(), variant=1)
-    us = step_ms * 1e3
-    log(f"form cell damping: {dt:.3f} s, iters {info.iters}, relres {r:.2e}, {us:.2f} us/step")
-    return {"workload": "smooth2d-1024, cell damping (Sec. 5, I_abd)", "n_P": op.nP,
-            "omega_c": op.omega_c, "solves_per_s": 1.0 / dt, "seconds": dt, "iters": info.iters,
-            "precond_applications": info.steps // (p.periods * op.nP), "true_relres": r,
-            "sweep_us_per_step": us, "sweep_algorithmic_GBps": 10 * 8 * p.N / (us * 1e-6) / 1e9}
+    res = {"workload": "smooth2d-1024, cell damping (Sec. 5, I_abd)"}
+    for name, prec in (("f64", tdp.F64), ("f32", tdp.F32)):
+        op = tdp.operator_from_problem(p, damping="cell", prec=prec)
+        op.solve(F, T=p.periods, rho=rho, tol=1e-6)                     # warm (graph)
+        (U, info), dt = _timed(lambda: op.solve(F, T=p.periods, rho=rho, tol=1e-6))
+        r = float(torch.linalg.norm(F - op.apply_H(U)) / torch.linalg.norm(F))
+        _, step_ms = sweep_timing(op, F, p.periods, rho, 1, torch.cuda.current_stream(), variant=1)
+        us = step_ms * 1e3
+        word = 8 if prec == tdp.F64 else 4
+        log(f"form cell damping {name}: {dt:.3f} s, iters {info.iters}, relres {r:.2e}, "
+            f"{us:.2f} us/step")
+        res[name] = {"n_P": op.nP, "omega_c": op.omega_c, "solves_per_s": 1.0 / dt,
+                     "seconds": dt, "iters": info.iters,
+                     "precond_applications": info.steps // (p.periods * op.nP), "true_relres": r,
+                     "sweep_us_per_step": us,
+                     "sweep_algorithmic_GBps": 10 * word * p.N / (us * 1e-6) / 1e9}
+        del op
+    return res
 
 
 def form_adjoint(rho):

@@ -100,7 +100,7 @@ typedef struct tdp_op tdp_op;
  *                    dt and n_P follow Sec. 5.1 (omega_c^2 = k_max^2 +
  *                    (beta/theta)(1 - cos theta) lam_im, theta = omega_c dt =
  *                    2 pi/n_P the largest for which 4I - K - 2L > 0 holds on
- *                    the bounds); FP64 only; preconditioning is S_T^abd
+ *                    the bounds); FP64 or FP32 fields; preconditioning is S_T^abd
  *                    (tdp_precond_apply returns TDP_EINVAL, GMRES uses the
  *                    complex-linear map whatever its variant); not batched. */
 typedef struct {

@@ -274,72 +274,73 @@ hipError_t launch_sweep_c_f32(const SweepArgs &a, const Stencil<float> &st, floa
 // stA the I_acd step stencil (2 - (dt^2/alpha) A) over the cell slowness, stB_r
 // the mass-class stencil of (beta dt/(alpha omega)) Im H over the cell damping.
 // u_{n-1} is read at the neighbours too, so u_{n+1} goes to a third field.
-template <int D, int SC, int MC, bool NT>
-__global__ __launch_bounds__(256) void k_sweep_abd(const C2<double> *__restrict__ u,
-                                                   const C2<double> *__restrict__ um,
-                                                   C2<double> *__restrict__ uo,
-                                                   const double *__restrict__ m,
-                                                   const double *__restrict__ rc,
-                                                   const double2 *__restrict__ F, int nz,
-                                                   int ny, int nx, Stencil<double> stA,
-                                                   Stencil<double> stB, double cth, double fa,
-                                                   double fb, double2 *__restrict__ out)
+template <int D, int SC, int MC, typename T, bool NT>
+__global__ __launch_bounds__(256) void k_sweep_abd(const C2<T> *__restrict__ u,
+                                                   const C2<T> *__restrict__ um,
+                                                   C2<T> *__restrict__ uo,
+                                                   const T *__restrict__ m,
+                                                   const T *__restrict__ rc,
+                                                   const typename V2<T>::type *__restrict__ F,
+                                                   int nz, int ny, int nx, Stencil<T> stA,
+                                                   Stencil<T> stB, T cth, T fa, T fb,
+                                                   double2 *__restrict__ out)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z;
     if (x >= nx || y >= ny) return;
     const int64_t i = ((int64_t)z * ny + y) * nx + x;
-    double wm[1 << D], wr[1 << D];
+    T wm[1 << D], wr[1 << D];
     load_cells<D>(m, z, y, x, ny, nx, wm);
     load_cells<D>(rc, z, y, x, ny, nx, wr);
     auto inside = [&](int oz, int oy, int ox) -> bool {
         return (unsigned)(y + oy) < (unsigned)ny && (unsigned)(x + ox) < (unsigned)nx &&
                (D == 2 || (unsigned)(z + oz) < (unsigned)nz);
     };
-    auto U = [&](int oz, int oy, int ox) -> C2<double> {
-        return inside(oz, oy, ox) ? u[i + ((int64_t)oz * ny + oy) * nx + ox] : C2<double>{0.0, 0.0};
+    auto U = [&](int oz, int oy, int ox) -> C2<T> {
+        return inside(oz, oy, ox) ? u[i + ((int64_t)oz * ny + oy) * nx + ox] : C2<T>{T(0), T(0)};
     };
-    auto W = [&](int oz, int oy, int ox) -> C2<double> {
-        if (!inside(oz, oy, ox)) return C2<double>{0.0, 0.0};
+    auto W = [&](int oz, int oy, int ox) -> C2<T> {
+        if (!inside(oz, oy, ox)) return C2<T>{T(0), T(0)};
         const int64_t j = i + ((int64_t)oz * ny + oy) * nx + ox;
-        const C2<double> a = um[j], b = u[j];
-        return C2<double>{a.x - cth * b.x, a.y - cth * b.y};
+        const C2<T> a = um[j], b = u[j];
+        return C2<T>{a.x - cth * b.x, a.y - cth * b.y};
     };
-    const C2<double> acc = eval_stencil<D, SC, MC>(U, wm, stA);
-    const C2<double> dmp = eval_stencil<D, 1, MC>(W, wr, stB);
-    const double fx = ldnt<NT>(&F[i].x), fy = ldnt<NT>(&F[i].y);
-    const C2<double> p = um[i];
-    C2<double> r;
+    const C2<T> acc = eval_stencil<D, SC, MC>(U, wm, stA);
+    const C2<T> dmp = eval_stencil<D, 1, MC>(W, wr, stB);
+    const T fx = ldnt<NT>(&F[i].x), fy = ldnt<NT>(&F[i].y);
+    const C2<T> p = um[i];
+    C2<T> r;
     r.x = acc.x + dmp.x - p.x + fa * fx - fb * fy;
     r.y = acc.y + dmp.y - p.y + fa * fy + fb * fx;
     stnt<NT>(r.x, &uo[i].x);
     stnt<NT>(r.y, &uo[i].y);
-    if (out) out[i] = make_double2(r.x, r.y);
+    if (out) out[i] = make_double2((double)r.x, (double)r.y);
 }
 
-hipError_t launch_sweep_abd(const SweepArgs &a, void *uout, const double *rc,
-                            const Stencil<double> &stA, const Stencil<double> &stB, double cth,
-                            double fa, double fb, hipStream_t s)
+template <typename T>
+static hipError_t launch_sweep_abd_t(const SweepArgs &a, void *uout, const T *rc,
+                                     const Stencil<T> &stA, const Stencil<T> &stB, T cth, T fa,
+                                     T fb, hipStream_t s)
 {
     const int nz = a.ndim == 3 ? a.n[0] : 1;
     const int ny = a.ndim == 3 ? a.n[1] : a.n[0];
     const int nx = a.ndim == 3 ? a.n[2] : a.n[1];
     dim3 blk(64, 4, 1);
     dim3 grd((nx + 63) / 64, (ny + 3) / 4, nz);
-    const C2<double> *u = (const C2<double> *)a.u;
-    const C2<double> *um = (const C2<double> *)a.up;
-    C2<double> *uo = (C2<double> *)uout;
-    const double *m = (const double *)a.m;
-    const double2 *F = (const double2 *)a.F;
+    const C2<T> *u = (const C2<T> *)a.u;
+    const C2<T> *um = (const C2<T> *)a.up;
+    C2<T> *uo = (C2<T> *)uout;
+    const T *m = (const T *)a.m;
+    const auto *F = (const typename V2<T>::type *)a.F;
     double2 *out = (double2 *)a.out;
-    const bool nt = stream_nt((int64_t)80 * nz * ny * nx);
+    const bool nt = stream_nt((int64_t)10 * sizeof(T) * nz * ny * nx);
 #define TDP_SWEEPB(D, SC, MC)                                                                          \
     do {                                                                                            \
         if (nt)                                                                                     \
-            hipLaunchKernelGGL((k_sweep_abd<D, SC, MC, true>), grd, blk, 0, s, u, um, uo, m, rc, F, nz, ny, nx, stA, stB, cth, fa, fb, out);  \
+            hipLaunchKernelGGL((k_sweep_abd<D, SC, MC, T, true>), grd, blk, 0, s, u, um, uo, m, rc, F, nz, ny, nx, stA, stB, cth, fa, fb, out);  \
         else                                                                                        \
-            hipLaunchKernelGGL((k_sweep_abd<D, SC, MC, false>), grd, blk, 0, s, u, um, uo, m, rc, F, nz, ny, nx, stA, stB, cth, fa, fb, out); \
+            hipLaunchKernelGGL((k_sweep_abd<D, SC, MC, T, false>), grd, blk, 0, s, u, um, uo, m, rc, F, nz, ny, nx, stA, stB, cth, fa, fb, out); \
     } while (0)
     if (a.ndim == 2) {
         if (a.sc <= 3 && a.mc <= 2) TDP_SWEEPB(2, 3, 2);
@@ -350,6 +351,20 @@ hipError_t launch_sweep_abd(const SweepArgs &a, void *uout, const double *rc,
     }
 #undef TDP_SWEEPB
     return hipGetLastError();
+}
+
+hipError_t launch_sweep_abd_f64(const SweepArgs &a, void *uout, const double *rc,
+                                const Stencil<double> &stA, const Stencil<double> &stB,
+                                double cth, double fa, double fb, hipStream_t s)
+{
+    return launch_sweep_abd_t<double>(a, uout, rc, stA, stB, cth, fa, fb, s);
+}
+
+hipError_t launch_sweep_abd_f32(const SweepArgs &a, void *uout, const float *rc,
+                                const Stencil<float> &stA, const Stencil<float> &stB, float cth,
+                                float fa, float fb, hipStream_t s)
+{
+    return launch_sweep_abd_t<float>(a, uout, rc, stA, stB, cth, fa, fb, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -115,7 +115,7 @@ static int free_op(tdp_op *op)
     (void)hipFree(op->Ustage);
     (void)hipFree(op->gcell);
     for (auto &kv : op->graphs) (void)hipGraphExecDestroy(kv.second);
-    void *bufs[] = {op->m, op->rw, op->dn, op->m32, op->dn32, op->u0, op->u1, op->u2, op->v0, op->v1,
+    void *bufs[] = {op->m, op->rw, op->dn, op->m32, op->dn32, op->rc32, op->u0, op->u1, op->u2, op->v0, op->v1,
                     op->u3, op->u4, op->rc, op->Fst, op->scratch, op->V, op->wv, op->tv, op->rv,
                     op->xv, op->red, op->dcoef};
     for (void *b : bufs) (void)hipFree(b);
@@ -141,8 +141,6 @@ static int create_impl(const tdp_op_desc *d, tdp_op *op)
     if (d->prec != TDP_F64 && d->prec != TDP_F32) TDP_FAIL(TDP_EINVAL, "prec must be TDP_F64 or TDP_F32");
     if (d->damping != TDP_DAMP_NODE && d->damping != TDP_DAMP_CELL)
         TDP_FAIL(TDP_EINVAL, "damping must be TDP_DAMP_NODE or TDP_DAMP_CELL");
-    if (d->damping == TDP_DAMP_CELL && d->prec != TDP_F64)
-        TDP_FAIL(TDP_EINVAL, "the cell damping (I_abd) path is FP64 only");
     op->dform = d->damping;
     op->ndim = d->ndim;
     op->N = 1;
@@ -322,9 +320,12 @@ static int create_impl(const tdp_op_desc *d, tdp_op *op)
         op->st_B.m[k] = lb * op->omega * mk;
     }
     op->st_step32.c0 = (float)op->st_step.c0;
+    op->st_B32.c0 = (float)op->st_B.c0;
     for (int k = 0; k < 4; ++k) {
         op->st_step32.s[k] = (float)op->st_step.s[k];
         op->st_step32.m[k] = (float)op->st_step.m[k];
+        op->st_B32.s[k] = (float)op->st_B.s[k];
+        op->st_B32.m[k] = (float)op->st_B.m[k];
     }
 
     TDP_CHECK_HIP(launch_node_factors(d->R, op->N, op->omega, lscale, op->rw, op->dn, s));
@@ -339,6 +340,11 @@ static int create_impl(const tdp_op_desc *d, tdp_op *op)
             TDP_FAIL(TDP_ENOMEM, "device allocation of FP32 arrays failed");
         TDP_CHECK_HIP(launch_cvt_f64_to_f32(op->m, op->m32, op->Nc, s));
         TDP_CHECK_HIP(launch_cvt_f64_to_f32(op->dn, op->dn32, op->N, s));
+        if (op->dform == TDP_DAMP_CELL) {
+            if (hipMalloc(&op->rc32, sizeof(float) * op->Nc) != hipSuccess)
+                TDP_FAIL(TDP_ENOMEM, "device allocation of FP32 arrays failed");
+            TDP_CHECK_HIP(launch_cvt_f64_to_f32(op->rc, op->rc32, op->Nc, s));
+        }
     }
     if (hipMalloc(&op->Fstage, 16 * op->N) != hipSuccess || hipMalloc(&op->Ustage, 16 * op->N) != hipSuccess)
         TDP_FAIL(TDP_ENOMEM, "device allocation of staging buffers failed");
@@ -674,8 +680,12 @@ static int issue_steps_loop(tdp_op *op, int T, double rho, int variant, const vo
         if (op->dform == TDP_DAMP_CELL) {
             // I_abd reads u_{n-1} at the neighbours: three fields rotate
             a.out = (j + 1 == Ns) ? Ud : nullptr;
-            TDP_CHECK_HIP(launch_sweep_abd(a, nxt, op->rc, op->st_step, op->st_B, op->cos_th, fa,
-                                           fbv, s));
+            if (op->prec == TDP_F64)
+                TDP_CHECK_HIP(launch_sweep_abd_f64(a, nxt, op->rc, op->st_step, op->st_B,
+                                                   op->cos_th, fa, fbv, s));
+            else
+                TDP_CHECK_HIP(launch_sweep_abd_f32(a, nxt, op->rc32, op->st_step32, op->st_B32,
+                                                   (float)op->cos_th, (float)fa, (float)fbv, s));
             void *t = prev;
             prev = cur;
             cur = nxt;

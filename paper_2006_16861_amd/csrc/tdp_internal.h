@@ -179,9 +179,12 @@ hipError_t launch_sweep_c_f32(const SweepArgs &a, const Stencil<float> &st, floa
 
 // I_abd step on complex fields (Sec. 5): a.u = u_n, a.up = u_{n-1} (read only),
 // u_{n+1} -> uout; rc the cell damping; stB the mass-class stencil of L/ImH.
-hipError_t launch_sweep_abd(const SweepArgs &a, void *uout, const double *rc,
-                            const Stencil<double> &stA, const Stencil<double> &stB, double cth,
-                            double fa, double fb, hipStream_t s);
+hipError_t launch_sweep_abd_f64(const SweepArgs &a, void *uout, const double *rc,
+                                const Stencil<double> &stA, const Stencil<double> &stB,
+                                double cth, double fa, double fb, hipStream_t s);
+hipError_t launch_sweep_abd_f32(const SweepArgs &a, void *uout, const float *rc,
+                                const Stencil<float> &stA, const Stencil<float> &stB, float cth,
+                                float fa, float fb, hipStream_t s);
 
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_cvt_c128_to_c64(const void *F, void *Fs, int64_t N, hipStream_t s);
@@ -265,6 +268,8 @@ struct tdp_op {
     double lam_im = 0, cos_th = 0;
     double *rc = nullptr;                   // cell damping r_cell
     tdp::Stencil<double> st_I{}, st_B{};    // Im H and (beta dt/(alpha omega)) Im H (mass classes)
+    tdp::Stencil<float> st_B32{};
+    float *rc32 = nullptr;                  // FP32 copy of the cell damping
     void *u4 = nullptr;                     // third complex field of the I_abd loop
     tdp::Stencil<float> st_step32{};
     // device buffers

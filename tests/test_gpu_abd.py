@@ -101,11 +101,29 @@ def test_abd_gradient_and_error_paths():
     with pytest.raises(tdp.TdpError):
         g.precond(dev(p.F), 2, 0.25, variant=0)        # Table 1 is the I_acd algorithm
     with pytest.raises(tdp.TdpError):
-        tdp.Operator(dev(p.c), dev(R), p.omega, p.h, damping="cell", prec=tdp.F32)
-    with pytest.raises(tdp.TdpError):
         tdp.Batch([g], [1])
     with pytest.raises(tdp.TdpError):                  # n_P below the I_abd bound
         tdp.Operator(dev(p.c), dev(R), p.omega, p.h, damping="cell", steps_per_period=g.nP - 4)
     ok = tdp.Operator(dev(p.c), dev(R), p.omega, p.h, damping="cell", steps_per_period=g.nP + 8)
     assert ok.nP == g.nP + 8
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n", [(37, 150), (9, 11, 70)])
+def test_abd_f32_fields(n):
+    """FP32 recurrence fields with the cell damping (the precision form of the
+    Sec. 5 path): S_T^abd close to the FP64 oracle, and GMRES, which keeps H and
+    the residuals in FP64, reaches 1e-8 checked by the oracle's H."""
+    from paper_2006_16861_amd import tdp
+    p, R = problem(n, 8)
+    note(f"abd f32 {n}")
+    g = tdp.Operator(dev(p.c), dev(R), p.omega, p.h, damping="cell", prec=tdp.F32)
+    o = oracle.Op(p.n, p.h, p.omega, p.c, R, damping="cell")
+    assert g.nP == o.nP
+    for graph in (1, 0):
+        g.set_tuning(kernel=0, use_graph=graph)
+        U = host(g.precond(dev(p.F), 2, 0.25, variant=1))
+        assert rel(U, o.precond(p.F, 2, 0.25, variant=1)) <= 1e-4
+    Ug, ig = g.solve(dev(p.F), T=p.periods, tol=1e-8)
+    assert ig.status == 0
+    assert rel(o.apply_H(host(Ug)), p.F) <= 1e-8 * (1 + 1e-9)
