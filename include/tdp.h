@@ -199,7 +199,10 @@ int tdp_precond_apply(const tdp_op *op, int periods_T, double rho, const void *F
 /* U = S_T F by Definition 4 (Sec. 2.3) as stated: the integrator I_acd on a
  * complex field driven by chi(1 - j/N_s) e^{i 2 pi j/n_P} F from zero fields,
  * U = e^{-i 2 pi T} u_{N_s} = u_{N_s}.  Complex-linear, unlike Table 1 whose
- * output is only real-linear; costs 10 instead of 7 words per node-step.
+ * output is only real-linear.  The recurrence has real coefficients, so the
+ * real and imaginary parts run as two real passes of the blocked (2-D) or
+ * streamed (3-D) kernels; with tdp_tuning.kernel = 1 as one complex pass
+ * (10 instead of 7 words per node-step).
  * With TDP_DAMP_CELL this is S_T^abd (Sec. 5, Def. 7): the same forcing
  * driving I_abd (Def. 6), 10 words per node-step (u_{n-1} is read with its
  * neighbours, so u_{n+1} goes to a third field).

@@ -457,8 +457,13 @@ const std::vector<double> &forcing_table(tdp_op *op, int T, double rho, int vari
     for (int64_t j = 0; j < Ns; ++j) {
         const double chi = window(1.0 - (double)j / (double)Ns, rho);
         const double ph = 2.0 * M_PI * (double)j / op->nP;
-        t[2 * j] = op->g * chi * std::cos(ph);
-        t[2 * j + 1] = (variant ? 1.0 : -1.0) * op->g * chi * std::sin(ph);
+        if (variant == 2) {          // imaginary part of Definition 4's forcing
+            t[2 * j] = op->g * chi * std::sin(ph);
+            t[2 * j + 1] = op->g * chi * std::cos(ph);
+        } else {
+            t[2 * j] = op->g * chi * std::cos(ph);
+            t[2 * j + 1] = (variant ? 1.0 : -1.0) * op->g * chi * std::sin(ph);
+        }
     }
     return op->tables.emplace(key, std::move(t)).first->second;
 }
@@ -489,14 +494,15 @@ static int ensure_complex_fields(tdp_op *op)
 static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth, int *tile)
 {
     int kern = op->tune.kernel, k = op->tune.tb_depth, t = op->tune.tile;
+    (void)variant;    // Definition 4 runs the same kernels as two real passes
     if (kern == 0) {
-        kern = variant == 0 ? (op->ndim == 2 ? 2 : 3) : 1;
+        kern = op->ndim == 2 ? 2 : 3;
         k = kern == 2 ? 8 : 0;
         t = kern == 2 ? (op->prec == TDP_F64 ? 5 : 8) : 0;
     }
     if (op->dform == TDP_DAMP_CELL) kern = 1;    // I_abd: one step per launch
-    if (kern == 2 && !(op->ndim == 2 && variant == 0)) kern = 1;
-    if ((kern == 3 || kern == 4) && !(op->ndim == 3 && variant == 0)) kern = 1;
+    if (kern == 2 && op->ndim != 2) kern = 1;
+    if ((kern == 3 || kern == 4) && op->ndim != 3) kern = 1;
     if (kern == 2) {
         if (k == 0) k = 4;
         const int rows = tb2d_tile_rows(t, op->prec == TDP_F64);
@@ -533,13 +539,16 @@ static int ensure_tb_fields(tdp_op *op)
 
 // Blocked loop: launches of k steps, ping-ponging between the field pairs
 // (u0, u1) and (v0, v1).
+// Real-field loops (Table 1's recurrence with the forcing table `tabv`): the
+// final field goes to out_final and, when out_snap is given, the sample
+// u_{N_s - q} to out_snap (stride-2 doubles inside a complex128 array).
 static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, int tile, const void *Fin,
-                          void *U)
+                          int tabv, double *out_final, double *out_snap)
 {
     hipStream_t s = op->stream;
     TDP_CHECK(ensure_tb_fields(op));
-    const std::vector<double> &tab = forcing_table(op, T, rho, 0);
-    const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - snap_lag(op->nP);
+    const std::vector<double> &tab = forcing_table(op, T, rho, tabv);
+    const int64_t Ns = (int64_t)T * op->nP, jsnap = out_snap ? Ns - snap_lag(op->nP) : -1;
     const size_t fb = (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
     void *cur = op->u0, *prev = op->u1, *ncur = op->v0, *nprev = op->v1;
     TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
@@ -553,7 +562,6 @@ static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, int tile, co
     a.m = op->prec == TDP_F64 ? (const void *)op->m : (const void *)op->m32;
     a.dn = op->prec == TDP_F64 ? (const void *)op->dn : (const void *)op->dn32;
     a.F = Fin;
-    double *Ud = (double *)U;
     for (int64_t j0 = 0; j0 < Ns; j0 += depth) {
         const int k = (int)std::min<int64_t>(depth, Ns - j0);
         a.u_in = cur;
@@ -567,9 +575,9 @@ static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, int tile, co
         }
         // step q (1-based) of this launch produces u_{j0+q}
         a.cf.out_step[0] = (jsnap > j0 && jsnap <= j0 + k) ? (int)(jsnap - j0) : 0;
-        a.cf.out[0] = Ud + 1;
+        a.cf.out[0] = out_snap;
         a.cf.out_step[1] = (Ns > j0 && Ns <= j0 + k) ? (int)(Ns - j0) : 0;
-        a.cf.out[1] = Ud;
+        a.cf.out[1] = out_final;
         if (op->prec == TDP_F64)
             TDP_CHECK_HIP(launch_sweep2d_tb_f64(a, op->st_step, s));
         else
@@ -583,20 +591,19 @@ static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, int tile, co
 // Streamed 3-D loop with two steps per launch, ping-ponging between the field
 // pairs (u0, u1) and (v0, v1); an odd last step runs the one-step kernel in place.
 static int issue_steps_3d2(tdp_op *op, int T, double rho, int zc, int shape, const void *Fin,
-                           void *U)
+                           int tabv, double *out_final, double *out_snap)
 {
     hipStream_t s = op->stream;
     TDP_CHECK(ensure_tb_fields(op));
-    const std::vector<double> &tab = forcing_table(op, T, rho, 0);
-    const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - snap_lag(op->nP);
+    const std::vector<double> &tab = forcing_table(op, T, rho, tabv);
+    const int64_t Ns = (int64_t)T * op->nP, jsnap = out_snap ? Ns - snap_lag(op->nP) : -1;
     const bool f64 = op->prec == TDP_F64;
     const size_t fb = (f64 ? sizeof(double) : sizeof(float)) * op->N;
     void *cur = op->u0, *prev = op->u1, *ncur = op->v0, *nprev = op->v1;
     TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
     TDP_CHECK_HIP(launch_fill_zero(prev, fb, s));
-    double *Ud = (double *)U;
     auto out_for = [&](int64_t j1) -> double * {      // destination of u_{j1}, if any
-        return j1 == jsnap ? Ud + 1 : (j1 == Ns ? Ud : nullptr);
+        return j1 == jsnap ? out_snap : (j1 == Ns ? out_final : nullptr);
     };
     Stream2Args a;
     for (int k = 0; k < 3; ++k) a.n[k] = op->n[k];
@@ -646,22 +653,16 @@ static int issue_steps_3d2(tdp_op *op, int T, double rho, int zc, int shape, con
     return TDP_OK;
 }
 
-// Issue the recurrence loop reading F (complex128, or float2 staged for FP32)
-// and writing U (complex128).  variant 0: Table 1 (real field; u_{N_s} to
-// Re U and the sample u_{N_s - q} to Im U, see snap_lag); variant 1:
-// Definition 4.
-static int issue_steps_loop(tdp_op *op, int T, double rho, int variant, const void *Fin, void *U)
+// One step per launch on a real field (kernel 1, or kernel 3 in 3-D),
+// u0/u1 swapped in place.
+static int issue_steps_real1(tdp_op *op, int T, double rho, int kern, int depth, int shape3,
+                             const void *Fin, int tabv, double *out_final, double *out_snap)
 {
-    int kern, depth, tile;
-    sweep_plan(op, variant, &kern, &depth, &tile);
-    if (kern == 2) return issue_steps_tb(op, T, rho, depth, tile, Fin, U);
-    if (kern == 4) return issue_steps_3d2(op, T, rho, depth, tile, Fin, U);
-    const int shape3 = tile;
     hipStream_t s = op->stream;
-    const std::vector<double> &tab = forcing_table(op, T, rho, variant);
-    const int64_t Ns = (int64_t)T * op->nP, jsnap = Ns - snap_lag(op->nP);
-    const size_t fb = (variant ? 2 : 1) * (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
-    void *cur = variant ? op->u2 : op->u0, *prev = variant ? op->u3 : op->u1, *nxt = op->u4;
+    const std::vector<double> &tab = forcing_table(op, T, rho, tabv);
+    const int64_t Ns = (int64_t)T * op->nP, jsnap = out_snap ? Ns - snap_lag(op->nP) : -1;
+    const size_t fb = (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
+    void *cur = op->u0, *prev = op->u1;
     TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
     TDP_CHECK_HIP(launch_fill_zero(prev, fb, s));
     SweepArgs a;
@@ -672,14 +673,72 @@ static int issue_steps_loop(tdp_op *op, int T, double rho, int variant, const vo
     a.F = Fin;
     a.m = op->prec == TDP_F64 ? (const void *)op->m : (const void *)op->m32;
     a.dn = op->prec == TDP_F64 ? (const void *)op->dn : (const void *)op->dn32;
-    double *Ud = (double *)U;
     for (int64_t j = 0; j < Ns; ++j) {
         a.u = cur;
         a.up = prev;
         const double fa = tab[2 * j], fbv = tab[2 * j + 1];
+        a.out = (j + 1 == jsnap) ? out_snap : (j + 1 == Ns ? out_final : nullptr);
+        if (kern == 3) {
+            if (op->prec == TDP_F64)
+                TDP_CHECK_HIP(launch_sweep3d_stream_f64(a, op->st_step, fa, fbv, shape3, depth, s));
+            else
+                TDP_CHECK_HIP(launch_sweep3d_stream_f32(a, op->st_step32, (float)fa, (float)fbv,
+                                                        shape3, depth, s));
+        } else if (op->prec == TDP_F64) {
+            TDP_CHECK_HIP(launch_sweep_f64(a, op->st_step, fa, fbv, s));
+        } else {
+            TDP_CHECK_HIP(launch_sweep_f32(a, op->st_step32, (float)fa, (float)fbv, s));
+        }
+        std::swap(cur, prev);
+    }
+    return TDP_OK;
+}
+
+// Issue the recurrence loop reading F (complex128, or float2 staged for FP32)
+// and writing U (complex128).  variant 0: Table 1 (real field; u_{N_s} to
+// Re U and the sample u_{N_s - q} to Im U, see snap_lag).  variant 1:
+// Definition 4.  Its recurrence has real coefficients, so the real and
+// imaginary parts of the complex field are two real recurrences driven by the
+// real and imaginary parts of the forcing: with the blocked or streamed
+// kernels they run as two real passes (tables 0 and 2), with kernel 1 as one
+// complex pass.  The cell damping runs I_abd on the complex field.
+static int issue_steps_loop(tdp_op *op, int T, double rho, int variant, const void *Fin, void *U)
+{
+    int kern, depth, tile;
+    sweep_plan(op, variant, &kern, &depth, &tile);
+    double *Ud = (double *)U;
+    auto real_pass = [&](int tabv, double *fin, double *snap) -> int {
+        if (kern == 2) return issue_steps_tb(op, T, rho, depth, tile, Fin, tabv, fin, snap);
+        if (kern == 4) return issue_steps_3d2(op, T, rho, depth, tile, Fin, tabv, fin, snap);
+        return issue_steps_real1(op, T, rho, kern, depth, tile, Fin, tabv, fin, snap);
+    };
+    if (variant == 0) return real_pass(0, Ud, Ud + 1);
+    if (op->dform == TDP_DAMP_NODE && kern != 1) {
+        TDP_CHECK(real_pass(0, Ud, nullptr));
+        return real_pass(2, Ud + 1, nullptr);
+    }
+    hipStream_t s = op->stream;
+    const std::vector<double> &tab = forcing_table(op, T, rho, variant);
+    const int64_t Ns = (int64_t)T * op->nP;
+    const size_t fb = 2 * (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
+    void *cur = op->u2, *prev = op->u3, *nxt = op->u4;
+    TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
+    TDP_CHECK_HIP(launch_fill_zero(prev, fb, s));
+    SweepArgs a;
+    a.ndim = op->ndim;
+    for (int k = 0; k < 3; ++k) a.n[k] = op->n[k];
+    a.sc = op->sc;
+    a.mc = op->mc;
+    a.F = Fin;
+    a.m = op->prec == TDP_F64 ? (const void *)op->m : (const void *)op->m32;
+    a.dn = op->prec == TDP_F64 ? (const void *)op->dn : (const void *)op->dn32;
+    for (int64_t j = 0; j < Ns; ++j) {
+        a.u = cur;
+        a.up = prev;
+        const double fa = tab[2 * j], fbv = tab[2 * j + 1];
+        a.out = (j + 1 == Ns) ? Ud : nullptr;
         if (op->dform == TDP_DAMP_CELL) {
             // I_abd reads u_{n-1} at the neighbours: three fields rotate
-            a.out = (j + 1 == Ns) ? Ud : nullptr;
             if (op->prec == TDP_F64)
                 TDP_CHECK_HIP(launch_sweep_abd_f64(a, nxt, op->rc, op->st_step, op->st_B,
                                                    op->cos_th, fa, fbv, s));
@@ -692,26 +751,10 @@ static int issue_steps_loop(tdp_op *op, int T, double rho, int variant, const vo
             nxt = t;
             continue;
         }
-        if (variant) {
-            a.out = (j + 1 == Ns) ? Ud : nullptr;
-            if (op->prec == TDP_F64)
-                TDP_CHECK_HIP(launch_sweep_c_f64(a, op->st_step, fa, fbv, s));
-            else
-                TDP_CHECK_HIP(launch_sweep_c_f32(a, op->st_step32, (float)fa, (float)fbv, s));
-        } else {
-            a.out = (j + 1 == jsnap) ? Ud + 1 : (j + 1 == Ns ? Ud : nullptr);
-            if (kern == 3) {
-                if (op->prec == TDP_F64)
-                    TDP_CHECK_HIP(launch_sweep3d_stream_f64(a, op->st_step, fa, fbv, shape3, depth, s));
-                else
-                    TDP_CHECK_HIP(launch_sweep3d_stream_f32(a, op->st_step32, (float)fa,
-                                                            (float)fbv, shape3, depth, s));
-            } else if (op->prec == TDP_F64) {
-                TDP_CHECK_HIP(launch_sweep_f64(a, op->st_step, fa, fbv, s));
-            } else {
-                TDP_CHECK_HIP(launch_sweep_f32(a, op->st_step32, (float)fa, (float)fbv, s));
-            }
-        }
+        if (op->prec == TDP_F64)
+            TDP_CHECK_HIP(launch_sweep_c_f64(a, op->st_step, fa, fbv, s));
+        else
+            TDP_CHECK_HIP(launch_sweep_c_f32(a, op->st_step32, (float)fa, (float)fbv, s));
         std::swap(cur, prev);
     }
     return TDP_OK;
@@ -749,6 +792,7 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
         sweep_plan(op, variant, &kern, &depth, &tile);
         if (kern == 2 || kern == 4) TDP_CHECK(ensure_tb_fields(op));
         launches = kern == 2 ? (Ns + depth - 1) / depth : (kern == 4 ? (Ns + 1) / 2 : Ns);
+        if (variant == 1 && kern != 1) launches *= 2;     // two real passes
     }
     hipStream_t s = op->stream;
     // a graph holds one kernel node per launch: very long loops are issued
@@ -851,7 +895,7 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
     hipStream_t s = op->stream;
     std::vector<tdp_tuning> cand;
     cand.push_back({1, 0, 1, 0});
-    if (op->ndim == 2 && variant == 0) {
+    if (op->ndim == 2 && op->dform == TDP_DAMP_NODE) {
         const int tiles[] = {0, 1, 2, 3, 4, 5, 6, 7, 8};
         const int depths[] = {2, 3, 4, 6, 8, 10, 12, 16};
         for (int tile : tiles) {
@@ -861,7 +905,7 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
                 if (4 * k <= rows && 4 * k <= 64) cand.push_back({2, k, 1, tile});
         }
     }
-    if (op->ndim == 3 && variant == 0) {
+    if (op->ndim == 3 && op->dform == TDP_DAMP_NODE) {
         for (int shape = 0; shape < 3; ++shape)
             for (int zc : {4, 8, 16, 32, 64}) cand.push_back({3, zc, 1, shape});
         for (int shape = 0; shape < 3; ++shape)

@@ -205,14 +205,24 @@ def test_gmres_f32_reaches_tolerance():
 # ---------------------------------------------------------------- Definition 4 variant
 @pytest.mark.parametrize("name,mk", [CASES[0], CASES[1], CASES[3], CASES[4]])
 def test_precond_complex_variant(name, mk):
+    """Definition 4 as one complex pass (kernel 1) and as two real passes of
+    the blocked (2-D) or streamed (3-D) kernels, against the oracle's complex
+    recurrence."""
+    from paper_2006_16861_amd import tdp
     p = mk()
     note(f"precond complex variant {name}")
     g, o = make_ops(p)
     T = min(p.periods, 4)
-    for graph in (0, 1):
-        g.set_tuning(kernel=1, use_graph=graph)
-        U = host(g.precond(dev(p.F), T, 0.25, variant=1))
-        assert rel(U, o.precond(p.F, T, 0.25, variant=1)) <= TOL64
+    Uo = o.precond(p.F, T, 0.25, variant=1)
+    kernels = [(1, 0, 0), (0, 0, 0)] + ([(2, 8, 5), (2, 4, 1), (2, 3, 7)] if len(p.n) == 2 else
+                                        [(3, 8, 0), (3, 16, 2), (4, 7, 1)])
+    for kern, depth, tile in kernels:
+        for graph in (0, 1):
+            g.set_tuning(kernel=kern, tb_depth=depth, tile=tile, use_graph=graph)
+            U = host(g.precond(dev(p.F), T, 0.25, variant=1))
+            assert rel(U, Uo) <= TOL64, (kern, depth, tile, graph)
+    g32 = tdp.operator_from_problem(p, prec=tdp.F32)
+    assert rel(host(g32.precond(dev(p.F), T, 0.25, variant=1)), Uo) <= 1e-4
 
 
 def test_gmres_complex_variant_fixed_and_converged():
