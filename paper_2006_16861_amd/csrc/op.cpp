@@ -1092,7 +1092,6 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
         TDP_CHECK(apply_H_impl(op, x, Fr, y));
         return mark(1, 1);
     };
-    const double rho = cfg->rho;
     const bool tolmode = cfg->fixed_iters <= 0;
     const int limit = tolmode ? cfg->max_iters : cfg->fixed_iters;
     const int nblk = blas_nblocks(N);
