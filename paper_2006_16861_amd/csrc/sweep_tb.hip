@@ -161,12 +161,104 @@ __device__ __forceinline__ void tb_tile(T *__restrict__ ul, T *__restrict__ cl,
     }
 }
 
+// Cross-lane neighbours of a row held one node per lane (lane = tile column):
+// the value of the lane to the left (x-1) or right (x+1), 0 past the wave's
+// ends, which is the tile's zero pad.  DPP wave shifts by one lane (VALU
+// moves; no LDS traffic).
+__device__ __forceinline__ int dpp_from_left(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
+}
+__device__ __forceinline__ int dpp_from_right(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
+}
+__device__ __forceinline__ float lane_west(float v)
+{
+    return __int_as_float(dpp_from_left(__float_as_int(v)));
+}
+__device__ __forceinline__ float lane_east(float v)
+{
+    return __int_as_float(dpp_from_right(__float_as_int(v)));
+}
+__device__ __forceinline__ double lane_west(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)dpp_from_left((int)b);
+    const unsigned hi = (unsigned)dpp_from_left((int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double lane_east(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)dpp_from_right((int)b);
+    const unsigned hi = (unsigned)dpp_from_right((int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Second form of the tile update: the cell-mass sums do not change in time,
 // so each lane folds them once per launch into per-node stencil coefficients
-// held in registers (centre, W, E, S, N; corners too for a general mass
-// table) and keeps no cells in LDS; each lane then reads its column of R+2
-// rows at x-1, x, x+1 from LDS once per step and reuses it for its R nodes.
-// The exact-region, Dirichlet and output rules are those of tb_tile.
+// held in registers (centre, W, E, S, N; the corners too when they are not
+// zero), each already multiplied by the node's damping factor d, so that a
+// step is
+//   u_{j+1} = sum_q c_q u_j(q) + fa d Re F + fb d Im F + (1 - 2d) u_{j-1}.
+// Each wave owns R consecutive tile rows and keeps u_j and u_{j-1} of its
+// nodes in registers (u_{j+1} overwrites u_{j-1}; the two arrays swap roles
+// every step).  The x-neighbours come from the adjacent lanes by DPP shifts,
+// and only the wave's first and last rows go through LDS, where the waves
+// above and below read them (two LDS copies, one barrier per step).  No cells
+// are kept in LDS.
+// After s+1 steps only rows s+1 .. EY-2-s still feed the exact region, so a
+// wave whose rows all lie outside that window skips the step (its stale rows
+// are never read again).  The exact-region, Dirichlet and output rules are
+// those of tb_tile.
+template <typename T, int SC, int MC, int R, int NCO, int US>
+__device__ __forceinline__ void tb2_step(const T *__restrict__ cur, T *__restrict__ nxt, int rs,
+                                         int rn, const T (&co)[R][NCO], const T (&fr)[R],
+                                         const T (&fi)[R], const T (&e)[R], const T (&a)[R],
+                                         T (&b)[R], T fas, T fbs)
+{
+    constexpr bool CORNER = MC > 2 || SC > 2;
+    // rows r0-1 .. r0+R at x-1, x, x+1: the two halo rows from LDS, the own
+    // rows from registers and the neighbouring lanes
+    T cw[R + 2], cc[R + 2], ce[R + 2];
+    cw[0] = cur[rs - 1];
+    cc[0] = cur[rs];
+    ce[0] = cur[rs + 1];
+    cw[R + 1] = cur[rn - 1];
+    cc[R + 1] = cur[rn];
+    ce[R + 1] = cur[rn + 1];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        cc[i + 1] = a[i];
+        cw[i + 1] = lane_west(a[i]);
+        ce[i + 1] = lane_east(a[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        // node row r0+i: centre cc[i+1], S cc[i], N cc[i+2]
+        T acc = co[i][0] * cc[i + 1];
+        acc += co[i][1] * cw[i + 1];
+        acc += co[i][2] * ce[i + 1];
+        acc += co[i][3] * cc[i];
+        acc += co[i][4] * cc[i + 2];
+        if (MC > 2) {
+            acc += co[i][5] * cw[i];
+            acc += co[i][6] * ce[i];
+            acc += co[i][7] * cw[i + 2];
+            acc += co[i][8] * ce[i + 2];
+        } else if (CORNER) {
+            acc += co[i][5] * ((cw[i] + ce[i]) + (cw[i + 2] + ce[i + 2]));
+        }
+        acc += fas * fr[i];
+        acc += fbs * fi[i];
+        b[i] = acc + e[i] * b[i];
+    }
+    // the wave's first and last rows for its neighbours' next step
+    nxt[rs + US] = b[0];
+    nxt[rn - US] = b[R - 1];
+}
+
 template <typename T, int SC, int MC, int R, int W>
 __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict__ u_in,
                                          const T *__restrict__ up_in, T *__restrict__ u_out,
@@ -179,18 +271,21 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
 {
     constexpr int EX = 64, EY = R * W;
     constexpr int US = EX + 2;
-    constexpr int NCO = MC > 2 ? 9 : 5;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int UB = (EY + 2) * US;
+    constexpr int NCO = MC > 2 ? 9 : (SC > 2 ? 6 : 5);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r0 = wv * R;
     const int gx = gx0 + lane;
     const bool xin = (unsigned)gx < (unsigned)nx;
 
     // per-node coefficients from the cells around each node (storage rows
-    // gy0+r0 .. gy0+r0+R, columns gx and gx+1)
+    // gy0+r0 .. gy0+r0+R, columns gx and gx+1), times d
     T co[R][NCO];
-    T uc[R], uprev[R], d[R], fr[R], fi[R];
+    T fr[R], fi[R], e[R];
+    T u0[R], u1[R];   // u_j and u_{j-1} of the wave's nodes
     {
-        T ca[R + 1], cb[R + 1];
+        T ca[R + 1], cb[R + 1], d[R];
 #pragma unroll
         for (int i = 0; i <= R; ++i) {
             const int sy = gy0 + r0 + i;
@@ -199,17 +294,17 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
             ca[i] = (rok && (unsigned)gx <= (unsigned)nx) ? m[base + gx] : T(0);
             cb[i] = (rok && (unsigned)(gx + 1) <= (unsigned)nx) ? m[base + gx + 1] : T(0);
         }
-        // the node data of all R rows are requested before any of it is used or
-        // stored to LDS, so the tile load is a single memory round trip
+        // the node data of all R rows are requested before any of it is used,
+        // so the tile load is a single memory round trip
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const int gy = gy0 + r0 + i;
             const bool in = xin && (unsigned)gy < (unsigned)ny;
             const int64_t g = (int64_t)gy * nx + gx;
-            uc[i] = uprev[i] = d[i] = fr[i] = fi[i] = T(0);
+            u0[i] = u1[i] = d[i] = fr[i] = fi[i] = T(0);
             if (in) {
-                uc[i] = u_in[g];
-                uprev[i] = up_in[g];
+                u0[i] = u_in[g];
+                u1[i] = up_in[g];
                 d[i] = dn[g];
                 const auto f = F[g];
                 fr[i] = f.x;
@@ -219,22 +314,28 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const T mSW = ca[i], mSE = cb[i], mNW = ca[i + 1], mNE = cb[i + 1];
-            co[i][0] = st.c0 + st.m[0] * ((mSW + mSE) + (mNW + mNE));
-            co[i][1] = st.s[1] + st.m[1] * (mSW + mNW);   // W
-            co[i][2] = st.s[1] + st.m[1] * (mSE + mNE);   // E
-            co[i][3] = st.s[1] + st.m[1] * (mSW + mSE);   // S
-            co[i][4] = st.s[1] + st.m[1] * (mNW + mNE);   // N
+            const T dd = d[i];
+            co[i][0] = dd * (st.c0 + st.m[0] * ((mSW + mSE) + (mNW + mNE)));
+            co[i][1] = dd * (st.s[1] + st.m[1] * (mSW + mNW));   // W
+            co[i][2] = dd * (st.s[1] + st.m[1] * (mSE + mNE));   // E
+            co[i][3] = dd * (st.s[1] + st.m[1] * (mSW + mSE));   // S
+            co[i][4] = dd * (st.s[1] + st.m[1] * (mNW + mNE));   // N
             if (MC > 2) {
-                co[i][5] = st.s[2] + st.m[2] * mSW;
-                co[i][6] = st.s[2] + st.m[2] * mSE;
-                co[i][7] = st.s[2] + st.m[2] * mNW;
-                co[i][8] = st.s[2] + st.m[2] * mNE;
+                co[i][5] = dd * (st.s[2] + st.m[2] * mSW);
+                co[i][6] = dd * (st.s[2] + st.m[2] * mSE);
+                co[i][7] = dd * (st.s[2] + st.m[2] * mNW);
+                co[i][8] = dd * (st.s[2] + st.m[2] * mNE);
+            } else if (SC > 2) {
+                co[i][5] = dd * st.s[2];   // the four corners share one weight
             }
+            fr[i] *= dd;
+            fi[i] *= dd;
+            e[i] = T(1) - T(2) * dd;
         }
     }
-    // two LDS copies of the tile (step s reads copy s&1 and writes the other, so one
-    // barrier per step suffices); zero the pads of both
-    constexpr int UB = (EY + 2) * US;
+    // LDS copy c holds, at row r+1, tile row r of level c (mod 2) for the
+    // first and last row of every wave; row 0, row EY+1 and the first and
+    // last column of both copies are the zero pad
     for (int t = threadIdx.x; t < US; t += 64 * W) {
         ul[t] = ul[UB + t] = T(0);
         ul[(EY + 1) * US + t] = ul[UB + (EY + 1) * US + t] = T(0);
@@ -243,44 +344,13 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
         ul[t * US] = ul[UB + t * US] = T(0);
         ul[t * US + EX + 1] = ul[UB + t * US + EX + 1] = T(0);
     }
-#pragma unroll
-    for (int i = 0; i < R; ++i) ul[(r0 + i + 1) * US + lane + 1] = uc[i];
+    ul[(r0 + 1) * US + lane + 1] = u0[0];
+    ul[(r0 + R) * US + lane + 1] = u0[R - 1];
     __syncthreads();
 
-    T unew[R];
-    for (int s = 0; s < k; ++s) {
-        const T fas = (T)fa[s * fstride], fbs = (T)fb[s * fstride];
-        const T *cur = ul + (s & 1) * UB;
-        T *nxt = ul + ((s + 1) & 1) * UB;
-        T cw[R + 2], cc[R + 2], ce[R + 2];   // LDS rows r0-1 .. r0+R at x-1, x, x+1
-#pragma unroll
-        for (int i = 0; i < R + 2; ++i) {
-            const T *p = &cur[(r0 + i) * US + lane + 1];
-            cw[i] = p[-1];
-            cc[i] = p[0];
-            ce[i] = p[1];
-        }
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            // node row r0+i: centre cc[i+1], S cc[i], N cc[i+2]
-            T acc = co[i][0] * cc[i + 1];
-            acc += co[i][1] * cw[i + 1];
-            acc += co[i][2] * ce[i + 1];
-            acc += co[i][3] * cc[i];
-            acc += co[i][4] * cc[i + 2];
-            if (MC > 2) {
-                acc += co[i][5] * cw[i];
-                acc += co[i][6] * ce[i];
-                acc += co[i][7] * cw[i + 2];
-                acc += co[i][8] * ce[i + 2];
-            } else if (SC > 2) {
-                acc += st.s[2] * ((cw[i] + ce[i]) + (cw[i + 2] + ce[i + 2]));
-            }
-            unew[i] = d[i] * (acc + fas * fr[i] + fbs * fi[i]) - (T(2) * d[i] - T(1)) * uprev[i];
-            uprev[i] = cc[i + 1];
-        }
-#pragma unroll
-        for (int i = 0; i < R; ++i) nxt[(r0 + i + 1) * US + lane + 1] = unew[i];
+    // LDS offsets of the halo rows r0-1 (south) and r0+R (north) at column x
+    const int rs = r0 * US + lane + 1, rn = (r0 + R + 1) * US + lane + 1;
+    auto snapshot = [&](int s, const T(&v)[R]) {
         if (s + 1 == out_step[0] || s + 1 == out_step[1]) {
             double *o = (s + 1 == out_step[0]) ? out[0] : out[1];
 #pragma unroll
@@ -289,11 +359,29 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
                 const int gy = gy0 + r;
                 if (r >= halo && r < EY - halo && lane >= halo && lane < EX - halo && xin &&
                     (unsigned)gy < (unsigned)ny)
-                    o[2 * ((int64_t)gy * nx + gx)] = (double)unew[i];
+                    o[2 * ((int64_t)gy * nx + gx)] = (double)v[i];
             }
+        }
+    };
+    // rows whose new value is still read by a later step or written out
+    auto active = [&](int s) { return r0 + R > s + 1 && r0 < EY - 1 - s; };
+    for (int s = 0; s < k; s += 2) {
+        if (active(s)) {
+            tb2_step<T, SC, MC, R, NCO, US>(ul, ul + UB, rs, rn, co, fr, fi, e, u0, u1,
+                                        (T)fa[s * fstride], (T)fb[s * fstride]);
+            snapshot(s, u1);
+        }
+        __syncthreads();
+        if (s + 1 == k) break;
+        if (active(s + 1)) {
+            tb2_step<T, SC, MC, R, NCO, US>(ul + UB, ul, rs, rn, co, fr, fi, e, u1, u0,
+                                        (T)fa[(s + 1) * fstride], (T)fb[(s + 1) * fstride]);
+            snapshot(s + 1, u0);
         }
         __syncthreads();
     }
+    // every output row lies in a wave that ran every step: level k is in u1
+    // for odd k, in u0 for even k
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const int r = r0 + i;
@@ -301,14 +389,17 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
         if (r >= halo && r < EY - halo && lane >= halo && lane < EX - halo && xin &&
             (unsigned)gy < (unsigned)ny) {
             const int64_t g = (int64_t)gy * nx + gx;
-            u_out[g] = unew[i];
-            up_out[g] = uprev[i];
+            u_out[g] = (k & 1) ? u1[i] : u0[i];
+            up_out[g] = (k & 1) ? u0[i] : u1[i];
         }
     }
 }
 
+// Tiles of 32 rows are sized for two workgroups per CU: ask for the
+// 128-VGPR budget that four waves per SIMD allow.
 template <typename T, int SC, int MC, int R, int W>
-__global__ __launch_bounds__(64 * W) void k_sweep2d_tb2(
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(R * W <= 32 ? 4 : 1)))
+void k_sweep2d_tb2(
     const T *__restrict__ u_in, const T *__restrict__ up_in, T *__restrict__ u_out,
     T *__restrict__ up_out, const T *__restrict__ m, const T *__restrict__ dn,
     const typename V2t<T>::type *__restrict__ F, int ny, int nx, Stencil<T> st, TBCoef cf,
@@ -350,7 +441,8 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_tb(
 // Batched form: one launch advances every field of the work list by up to K
 // steps; workgroup -> (field, tile) through the per-launch tile prefix sums.
 template <typename T, int SC, int MC, int R, int W, bool V2F>
-__global__ __launch_bounds__(64 * W) void k_sweep2d_tb_batch(
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(R * W <= 32 ? 4 : 1)))
+void k_sweep2d_tb_batch(
     const BFieldT<T> *__restrict__ fields, const int *__restrict__ list,
     const int *__restrict__ prefix, int nlist, int j0, int K, int parity, int ntiles,
     int per_xcd)
