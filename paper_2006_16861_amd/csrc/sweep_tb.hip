@@ -286,13 +286,14 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
     T u0[R], u1[R];   // u_j and u_{j-1} of the wave's nodes
     {
         T ca[R + 1], cb[R + 1], d[R];
+        // row offsets are wave-uniform (scalar); only the column is per lane
 #pragma unroll
         for (int i = 0; i <= R; ++i) {
             const int sy = gy0 + r0 + i;
             const bool rok = (unsigned)sy <= (unsigned)ny;
-            const int64_t base = (int64_t)sy * (nx + 1);
-            ca[i] = (rok && (unsigned)gx <= (unsigned)nx) ? m[base + gx] : T(0);
-            cb[i] = (rok && (unsigned)(gx + 1) <= (unsigned)nx) ? m[base + gx + 1] : T(0);
+            const T *mrow = m + (int64_t)sy * (nx + 1);
+            ca[i] = (rok && (unsigned)gx <= (unsigned)nx) ? mrow[gx] : T(0);
+            cb[i] = (rok && (unsigned)(gx + 1) <= (unsigned)nx) ? mrow[gx + 1] : T(0);
         }
         // the node data of all R rows are requested before any of it is used,
         // so the tile load is a single memory round trip
@@ -300,13 +301,13 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
         for (int i = 0; i < R; ++i) {
             const int gy = gy0 + r0 + i;
             const bool in = xin && (unsigned)gy < (unsigned)ny;
-            const int64_t g = (int64_t)gy * nx + gx;
+            const int64_t row = (int64_t)gy * nx;
             u0[i] = u1[i] = d[i] = fr[i] = fi[i] = T(0);
             if (in) {
-                u0[i] = u_in[g];
-                u1[i] = up_in[g];
-                d[i] = dn[g];
-                const auto f = F[g];
+                u0[i] = (u_in + row)[gx];
+                u1[i] = (up_in + row)[gx];
+                d[i] = (dn + row)[gx];
+                const auto f = (F + row)[gx];
                 fr[i] = f.x;
                 fi[i] = f.y;
             }
@@ -350,6 +351,7 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
 
     // LDS offsets of the halo rows r0-1 (south) and r0+R (north) at column x
     const int rs = r0 * US + lane + 1, rn = (r0 + R + 1) * US + lane + 1;
+    const bool xout = lane >= halo && lane < EX - halo && xin;
     auto snapshot = [&](int s, const T(&v)[R]) {
         if (s + 1 == out_step[0] || s + 1 == out_step[1]) {
             double *o = (s + 1 == out_step[0]) ? out[0] : out[1];
@@ -357,9 +359,8 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
             for (int i = 0; i < R; ++i) {
                 const int r = r0 + i;
                 const int gy = gy0 + r;
-                if (r >= halo && r < EY - halo && lane >= halo && lane < EX - halo && xin &&
-                    (unsigned)gy < (unsigned)ny)
-                    o[2 * ((int64_t)gy * nx + gx)] = (double)v[i];
+                if (r >= halo && r < EY - halo && (unsigned)gy < (unsigned)ny && xout)
+                    (o + 2 * (int64_t)gy * nx)[2 * gx] = (double)v[i];
             }
         }
     };
@@ -386,11 +387,10 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
     for (int i = 0; i < R; ++i) {
         const int r = r0 + i;
         const int gy = gy0 + r;
-        if (r >= halo && r < EY - halo && lane >= halo && lane < EX - halo && xin &&
-            (unsigned)gy < (unsigned)ny) {
-            const int64_t g = (int64_t)gy * nx + gx;
-            u_out[g] = (k & 1) ? u1[i] : u0[i];
-            up_out[g] = (k & 1) ? u0[i] : u1[i];
+        if (r >= halo && r < EY - halo && (unsigned)gy < (unsigned)ny && xout) {
+            const int64_t row = (int64_t)gy * nx;
+            (u_out + row)[gx] = (k & 1) ? u1[i] : u0[i];
+            (up_out + row)[gx] = (k & 1) ? u0[i] : u1[i];
         }
     }
 }
