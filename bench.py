@@ -277,9 +277,10 @@ def form_cell_damping(rho):
     """Sec. 5 path on the headline workload: smooth2d-1024 with the cell
     (non-diagonal) damping Im H = omega sum_cells r_cell M_cell, preconditioned
     by S_T^abd (I_abd), to a true relative residual of 1e-6, with FP64 and with
-    FP32 recurrence fields (GMRES, H and the residuals in FP64 either way).  The
-    sweep moves 10 words per node-step (u_n, u_{n-1} and F complex, the two
-    cell arrays, u_{n+1} complex)."""
+    FP32 recurrence fields (GMRES, H and the residuals in FP64 either way), on
+    the autotuner's sweep (blocked 2-D I_abd or one step per launch).  Rates use
+    10 words per complex node-step (u_n, u_{n-1} and F complex, the two cell
+    arrays, u_{n+1} complex)."""
     import torch
     from paper_2006_16861_amd import inputs, tdp
     p = inputs.smooth2d(1024)
@@ -287,6 +288,7 @@ def form_cell_damping(rho):
     res = {"workload": "smooth2d-1024, cell damping (Sec. 5, I_abd)"}
     for name, prec in (("f64", tdp.F64), ("f32", tdp.F32)):
         op = tdp.operator_from_problem(p, damping="cell", prec=prec)
+        op.autotune(T=4, rho=rho, variant=1)
         op.solve(F, T=p.periods, rho=rho, tol=1e-6)                     # warm (graph)
         (U, info), dt = _timed(lambda: op.solve(F, T=p.periods, rho=rho, tol=1e-6))
         r = float(torch.linalg.norm(F - op.apply_H(U)) / torch.linalg.norm(F))
@@ -298,7 +300,7 @@ def form_cell_damping(rho):
         res[name] = {"n_P": op.nP, "omega_c": op.omega_c, "solves_per_s": 1.0 / dt,
                      "seconds": dt, "iters": info.iters,
                      "precond_applications": info.steps // (p.periods * op.nP), "true_relres": r,
-                     "sweep_us_per_step": us,
+                     "sweep_us_per_step": us, "tuning": op.get_tuning(),
                      "sweep_algorithmic_GBps": 10 * word * p.N / (us * 1e-6) / 1e9}
         del op
     return res

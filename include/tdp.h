@@ -204,8 +204,12 @@ int tdp_precond_apply(const tdp_op *op, int periods_T, double rho, const void *F
  * streamed (3-D) kernels; with tdp_tuning.kernel = 1 as one complex pass
  * (10 instead of 7 words per node-step).
  * With TDP_DAMP_CELL this is S_T^abd (Sec. 5, Def. 7): the same forcing
- * driving I_abd (Def. 6), 10 words per node-step (u_{n-1} is read with its
- * neighbours, so u_{n+1} goes to a third field).
+ * driving I_abd (Def. 6).  Its recurrence has real coefficients too: in 2-D
+ * (mass tables without corner entries) it runs as two real passes of the
+ * blocked I_abd kernel (k steps per launch), else, and with
+ * tdp_tuning.kernel = 1, on the complex field one step per launch (10 words
+ * per node-step; u_{n-1} is read with its neighbours, so u_{n+1} goes to a
+ * third field).
  * F, U: device complex128 [N]. */
 int tdp_precond_apply_complex(const tdp_op *op, int periods_T, double rho, const void *F,
                               void *U);
@@ -239,10 +243,12 @@ int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
 
 /* Tuning of the recurrence sweep (no effect on results beyond rounding).
  *  kernel       0 auto (kernel, depth and tile chosen by the library: the
- *               blocked 2-D sweep on tile 5 (FP64) or 8 (FP32) at depth 8, the
- *               streamed 3-D sweep on tile 0; tb_depth and tile ignored),
- *               1 one step per launch, 2 temporally blocked (2-D,
- *               Table 1 variant), 3 streamed along axis 0 (3-D, Table 1
+ *               blocked 2-D sweep on tile 5 (FP64) or 8 (FP32) at depth 8, with
+ *               the cell damping on tile 7 (FP64) or 5 (FP32); the streamed
+ *               3-D sweep on tile 0; tb_depth and tile ignored),
+ *               1 one step per launch, 2 temporally blocked (2-D; with the
+ *               cell damping, tiles 5 and 7 in FP64 and 4..7 in FP32, mass
+ *               tables without corner entries), 3 streamed along axis 0 (3-D, Table 1
  *               variant), 4 streamed along axis 0 with two steps per launch
  *               (3-D, Table 1 variant); inapplicable choices fall back to 1
  *  tb_depth     kernel 2: steps per launch, 1..16 (0 auto);
@@ -270,8 +276,9 @@ int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t);
 
 /* Autotuner: times each sweep variant applicable to this op (one step per
  * launch; blocked tile shapes x depths 2, 3, 4, 6, 8, 10, 12, 16 (4 x depth
- * at most the tile's rows) for the 2-D Table 1 loop; streamed column shapes x chunk lengths 16, 32, 64 in 3-D, with one
- * and two steps per launch) over
+ * at most the tile's rows) for the 2-D Table 1 loop; the blocked I_abd tiles
+ * x depths 2, 3, 4, 6, 8 with the 2-D cell damping; streamed column shapes x
+ * chunk lengths 4, 8, 16, 32, 64 in 3-D, with one and two steps per launch) over
  * periods_T periods with HIP events on the op's stream, and makes
  * the fastest the op's tuning.  best (host, may be NULL) receives it; table
  * (host, may be NULL) receives up to cap rows of {kernel, tb_depth, tile,

@@ -495,12 +495,18 @@ static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth, i
 {
     int kern = op->tune.kernel, k = op->tune.tb_depth, t = op->tune.tile;
     (void)variant;    // Definition 4 runs the same kernels as two real passes
+    const bool f64 = op->prec == TDP_F64;
     if (kern == 0) {
         kern = op->ndim == 2 ? 2 : 3;
         k = kern == 2 ? 8 : 0;
-        t = kern == 2 ? (op->prec == TDP_F64 ? 5 : 8) : 0;
+        t = kern == 2 ? (f64 ? 5 : 8) : 0;
+        if (op->dform == TDP_DAMP_CELL) t = f64 ? 7 : 5;
     }
-    if (op->dform == TDP_DAMP_CELL) kern = 1;    // I_abd: one step per launch
+    // I_abd: the blocked 2-D kernel on the tiles that hold its per-node state
+    // (mass tables without corner entries), else one step per launch
+    if (op->dform == TDP_DAMP_CELL &&
+        !(kern == 2 && op->ndim == 2 && op->mc <= 2 && abd_tile_ok(t, f64)))
+        kern = 1;
     if (kern == 2 && op->ndim != 2) kern = 1;
     if ((kern == 3 || kern == 4) && op->ndim != 3) kern = 1;
     if (kern == 2) {
@@ -543,7 +549,7 @@ static int ensure_tb_fields(tdp_op *op)
 // final field goes to out_final and, when out_snap is given, the sample
 // u_{N_s - q} to out_snap (stride-2 doubles inside a complex128 array).
 static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, int tile, const void *Fin,
-                          int tabv, double *out_final, double *out_snap)
+                          int tabv, double *out_final, double *out_snap, bool abd = false)
 {
     hipStream_t s = op->stream;
     TDP_CHECK(ensure_tb_fields(op));
@@ -562,6 +568,10 @@ static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, int tile, co
     a.m = op->prec == TDP_F64 ? (const void *)op->m : (const void *)op->m32;
     a.dn = op->prec == TDP_F64 ? (const void *)op->dn : (const void *)op->dn32;
     a.F = Fin;
+    if (abd) {
+        a.rc = op->prec == TDP_F64 ? (const void *)op->rc : (const void *)op->rc32;
+        a.cth = op->cos_th;
+    }
     for (int64_t j0 = 0; j0 < Ns; j0 += depth) {
         const int k = (int)std::min<int64_t>(depth, Ns - j0);
         a.u_in = cur;
@@ -578,7 +588,11 @@ static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, int tile, co
         a.cf.out[0] = out_snap;
         a.cf.out_step[1] = (Ns > j0 && Ns <= j0 + k) ? (int)(Ns - j0) : 0;
         a.cf.out[1] = out_final;
-        if (op->prec == TDP_F64)
+        if (abd && op->prec == TDP_F64)
+            TDP_CHECK_HIP(launch_sweep2d_abd_tb_f64(a, op->st_step, op->st_B, s));
+        else if (abd)
+            TDP_CHECK_HIP(launch_sweep2d_abd_tb_f32(a, op->st_step32, op->st_B32, s));
+        else if (op->prec == TDP_F64)
             TDP_CHECK_HIP(launch_sweep2d_tb_f64(a, op->st_step, s));
         else
             TDP_CHECK_HIP(launch_sweep2d_tb_f32(a, op->st_step32, s));
@@ -701,7 +715,9 @@ static int issue_steps_real1(tdp_op *op, int T, double rho, int kern, int depth,
 // imaginary parts of the complex field are two real recurrences driven by the
 // real and imaginary parts of the forcing: with the blocked or streamed
 // kernels they run as two real passes (tables 0 and 2), with kernel 1 as one
-// complex pass.  The cell damping runs I_abd on the complex field.
+// complex pass.  The cell damping runs I_abd, whose recurrence has real
+// coefficients too: two real passes of the blocked 2-D kernel (tables 0 and
+// 2 again), or the complex field with kernel 1.
 static int issue_steps_loop(tdp_op *op, int T, double rho, int variant, const void *Fin, void *U)
 {
     int kern, depth, tile;
@@ -712,6 +728,10 @@ static int issue_steps_loop(tdp_op *op, int T, double rho, int variant, const vo
         if (kern == 4) return issue_steps_3d2(op, T, rho, depth, tile, Fin, tabv, fin, snap);
         return issue_steps_real1(op, T, rho, kern, depth, tile, Fin, tabv, fin, snap);
     };
+    if (op->dform == TDP_DAMP_CELL && kern == 2) {
+        TDP_CHECK(issue_steps_tb(op, T, rho, depth, tile, Fin, 0, Ud, nullptr, true));
+        return issue_steps_tb(op, T, rho, depth, tile, Fin, 2, Ud + 1, nullptr, true);
+    }
     if (variant == 0) return real_pass(0, Ud, Ud + 1);
     if (op->dform == TDP_DAMP_NODE && kern != 1) {
         TDP_CHECK(real_pass(0, Ud, nullptr));
@@ -890,7 +910,7 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
     if (!op) TDP_FAIL(TDP_EINVAL, "NULL argument");
     if (periods_T < 1) TDP_FAIL(TDP_EINVAL, "periods_T must be >= 1");
     if (variant != 0 && variant != 1) TDP_FAIL(TDP_EINVAL, "variant must be 0 or 1");
-    if (op->dform == TDP_DAMP_CELL) variant = 1;      // S_T^abd: one-step kernel only
+    if (op->dform == TDP_DAMP_CELL) variant = 1;      // S_T^abd: the complex form
     StreamJoin join(op->user_stream, op->stream, op->ev);
     hipStream_t s = op->stream;
     std::vector<tdp_tuning> cand;
@@ -903,6 +923,14 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
             const int rows = tb2d_tile_rows(tile, op->prec == TDP_F64);
             for (int k : depths)
                 if (4 * k <= rows && 4 * k <= 64) cand.push_back({2, k, 1, tile});
+        }
+    }
+    if (op->ndim == 2 && op->dform == TDP_DAMP_CELL && op->mc <= 2) {
+        for (int tile = 4; tile <= 7; ++tile) {
+            if (!abd_tile_ok(tile, op->prec == TDP_F64)) continue;
+            const int rows = tb2d_tile_rows(tile, op->prec == TDP_F64);
+            for (int k : {2, 3, 4, 6, 8})
+                if (4 * k <= rows) cand.push_back({2, k, 1, tile});
         }
     }
     if (op->ndim == 3 && op->dform == TDP_DAMP_NODE) {

@@ -483,6 +483,247 @@ void k_sweep2d_tb_batch(
                                  out_step, out);
 }
 
+// Frequency-adapted backward-differences damped leapfrog I_abd (Sec. 5) with
+// the cell damping, blocked like tb_tile2, on one real part of the complex
+// field of S_T^abd.  Its recurrence has real coefficients,
+//   x_{n+1} = A[x_n] + B[x_{n-1} - cos(theta) x_n] - x_{n-1} + fa Re F + fb Im F,
+// with A the I_acd step stencil over the cell slowness and B the damping
+// stencil (mass classes only) over the cell damping, so the real and
+// imaginary parts of the field are two such recurrences: forcing scalars
+// (fa, -fb) and (fb, fa) of the complex forcing (fa + i fb) F.  B reads
+// w = x_{n-1} - cos(theta) x_n at the neighbours, so every wave passes the
+// first and last rows of both x_n and w through LDS; the x-neighbours of both
+// come from DPP.  A step still reaches one node, so the exact region, the
+// window of rows a wave must update and the output rules are those of
+// tb_tile2.  Mass tables with corner entries are not covered here.
+template <typename T, int R, int US>
+__device__ __forceinline__ void abd_step(const T *__restrict__ xc, const T *__restrict__ wc,
+                                         T *__restrict__ xn, T *__restrict__ wn, int rs, int rn,
+                                         const T (&ca)[R][6], const T (&cb)[R][5],
+                                         const T (&fr)[R], const T (&fi)[R], T cth,
+                                         const T (&a)[R], T (&b)[R], T fas, T fbs)
+{
+    // x at rows r0-1 .. r0+R and x-1, x, x+1; w at rows r0-1 .. r0+R and x
+    T xw[R + 2], xx[R + 2], xe[R + 2], ww[R + 2];
+    xw[0] = xc[rs - 1];
+    xx[0] = xc[rs];
+    xe[0] = xc[rs + 1];
+    ww[0] = wc[rs];
+    xw[R + 1] = xc[rn - 1];
+    xx[R + 1] = xc[rn];
+    xe[R + 1] = xc[rn + 1];
+    ww[R + 1] = wc[rn];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        xx[i + 1] = a[i];
+        xw[i + 1] = lane_west(a[i]);
+        xe[i + 1] = lane_east(a[i]);
+        ww[i + 1] = b[i] - cth * a[i];
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        T acc = ca[i][0] * xx[i + 1];
+        acc += ca[i][1] * xw[i + 1];
+        acc += ca[i][2] * xe[i + 1];
+        acc += ca[i][3] * xx[i];
+        acc += ca[i][4] * xx[i + 2];
+        acc += ca[i][5] * ((xw[i] + xe[i]) + (xw[i + 2] + xe[i + 2]));
+        acc += cb[i][0] * ww[i + 1];
+        acc += cb[i][1] * lane_west(ww[i + 1]);
+        acc += cb[i][2] * lane_east(ww[i + 1]);
+        acc += cb[i][3] * ww[i];
+        acc += cb[i][4] * ww[i + 2];
+        acc += fas * fr[i];
+        acc += fbs * fi[i];
+        b[i] = acc - b[i];
+    }
+    // the wave's first and last rows of x_{n+1} and w_{n+1} = x_n - cos(theta) x_{n+1}
+    xn[rs + US] = b[0];
+    xn[rn - US] = b[R - 1];
+    wn[rs + US] = a[0] - cth * b[0];
+    wn[rn - US] = a[R - 1] - cth * b[R - 1];
+}
+
+template <typename T, int R, int W>
+__device__ __forceinline__ void tb_tile_abd(T *__restrict__ ul, const T *__restrict__ u_in,
+                                            const T *__restrict__ up_in, T *__restrict__ u_out,
+                                            T *__restrict__ up_out, const T *__restrict__ m,
+                                            const T *__restrict__ rc,
+                                            const typename V2t<T>::type *__restrict__ F, int ny,
+                                            int nx, const Stencil<T> &sa, const Stencil<T> &sb,
+                                            T cth, int k, int halo, int gy0, int gx0,
+                                            const double *fa, const double *fb,
+                                            const int *out_step, double *const *out)
+{
+    constexpr int EX = 64, EY = R * W;
+    constexpr int US = EX + 2;
+    constexpr int UB = (EY + 2) * US;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r0 = wv * R;
+    const int gx = gx0 + lane;
+    const bool xin = (unsigned)gx < (unsigned)nx;
+
+    // per-node coefficients of A (over the slowness; centre, W, E, S, N and
+    // the corner weight) and B (over the damping; centre, W, E, S, N) from the
+    // four cells around each node.  They are zero at nodes outside the domain,
+    // which then stay 0 (Dirichlet): I_abd has no damping factor d that would
+    // zero their update as in tb_tile2.
+    T ca[R][6], cb[R][5];
+    T fr[R], fi[R];
+    T u0[R], u1[R];   // x_n and x_{n-1} of the wave's nodes
+    {
+        T ma[R + 1], mb[R + 1], ra[R + 1], rb[R + 1];
+        T on[R];
+#pragma unroll
+        for (int i = 0; i <= R; ++i) {
+            const int sy = gy0 + r0 + i;
+            const bool rok = (unsigned)sy <= (unsigned)ny;
+            const int64_t row = (int64_t)sy * (nx + 1);
+            const bool ok0 = rok && (unsigned)gx <= (unsigned)nx;
+            const bool ok1 = rok && (unsigned)(gx + 1) <= (unsigned)nx;
+            ma[i] = ok0 ? (m + row)[gx] : T(0);
+            mb[i] = ok1 ? (m + row)[gx + 1] : T(0);
+            ra[i] = ok0 ? (rc + row)[gx] : T(0);
+            rb[i] = ok1 ? (rc + row)[gx + 1] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int gy = gy0 + r0 + i;
+            const bool in = xin && (unsigned)gy < (unsigned)ny;
+            const int64_t row = (int64_t)gy * nx;
+            u0[i] = u1[i] = fr[i] = fi[i] = T(0);
+            on[i] = in ? T(1) : T(0);
+            if (in) {
+                u0[i] = (u_in + row)[gx];
+                u1[i] = (up_in + row)[gx];
+                const auto f = (F + row)[gx];
+                fr[i] = f.x;
+                fi[i] = f.y;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            {
+                const T SW = ma[i], SE = mb[i], NW = ma[i + 1], NE = mb[i + 1];
+                ca[i][0] = on[i] * (sa.c0 + sa.m[0] * ((SW + SE) + (NW + NE)));
+                ca[i][1] = on[i] * (sa.s[1] + sa.m[1] * (SW + NW));
+                ca[i][2] = on[i] * (sa.s[1] + sa.m[1] * (SE + NE));
+                ca[i][3] = on[i] * (sa.s[1] + sa.m[1] * (SW + SE));
+                ca[i][4] = on[i] * (sa.s[1] + sa.m[1] * (NW + NE));
+                ca[i][5] = on[i] * sa.s[2];
+            }
+            {
+                const T SW = ra[i], SE = rb[i], NW = ra[i + 1], NE = rb[i + 1];
+                cb[i][0] = on[i] * (sb.c0 + sb.m[0] * ((SW + SE) + (NW + NE)));
+                cb[i][1] = on[i] * sb.m[1] * (SW + NW);
+                cb[i][2] = on[i] * sb.m[1] * (SE + NE);
+                cb[i][3] = on[i] * sb.m[1] * (SW + SE);
+                cb[i][4] = on[i] * sb.m[1] * (NW + NE);
+            }
+        }
+    }
+    // LDS: x copies 0 and 1, then w copies 0 and 1; copy c holds level c (mod
+    // 2) of the first and last row of every wave at row r+1; the pads are zero
+    for (int t = threadIdx.x; t < US; t += 64 * W)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            ul[c * UB + t] = T(0);
+            ul[c * UB + (EY + 1) * US + t] = T(0);
+        }
+    for (int t = threadIdx.x; t < EY + 2; t += 64 * W)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            ul[c * UB + t * US] = T(0);
+            ul[c * UB + t * US + EX + 1] = T(0);
+        }
+    ul[(r0 + 1) * US + lane + 1] = u0[0];
+    ul[(r0 + R) * US + lane + 1] = u0[R - 1];
+    ul[2 * UB + (r0 + 1) * US + lane + 1] = u1[0] - cth * u0[0];
+    ul[2 * UB + (r0 + R) * US + lane + 1] = u1[R - 1] - cth * u0[R - 1];
+    __syncthreads();
+
+    const int rs = r0 * US + lane + 1, rn = (r0 + R + 1) * US + lane + 1;
+    const bool xout = lane >= halo && lane < EX - halo && xin;
+    auto snapshot = [&](int s, const T(&v)[R]) {
+        if (s + 1 == out_step[0] || s + 1 == out_step[1]) {
+            double *o = (s + 1 == out_step[0]) ? out[0] : out[1];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int r = r0 + i;
+                const int gy = gy0 + r;
+                if (r >= halo && r < EY - halo && (unsigned)gy < (unsigned)ny && xout)
+                    (o + 2 * (int64_t)gy * nx)[2 * gx] = (double)v[i];
+            }
+        }
+    };
+    auto active = [&](int s) { return r0 + R > s + 1 && r0 < EY - 1 - s; };
+    T *x0 = ul, *x1 = ul + UB, *w0 = ul + 2 * UB, *w1 = ul + 3 * UB;
+    for (int s = 0; s < k; s += 2) {
+        if (active(s)) {
+            abd_step<T, R, US>(x0, w0, x1, w1, rs, rn, ca, cb, fr, fi, cth, u0, u1,
+                               (T)fa[s], (T)fb[s]);
+            snapshot(s, u1);
+        }
+        __syncthreads();
+        if (s + 1 == k) break;
+        if (active(s + 1)) {
+            abd_step<T, R, US>(x1, w1, x0, w0, rs, rn, ca, cb, fr, fi, cth, u1, u0,
+                               (T)fa[s + 1], (T)fb[s + 1]);
+            snapshot(s + 1, u0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int r = r0 + i;
+        const int gy = gy0 + r;
+        if (r >= halo && r < EY - halo && (unsigned)gy < (unsigned)ny && xout) {
+            const int64_t row = (int64_t)gy * nx;
+            (u_out + row)[gx] = (k & 1) ? u1[i] : u0[i];
+            (up_out + row)[gx] = (k & 1) ? u0[i] : u1[i];
+        }
+    }
+}
+
+template <typename T, int R, int W>
+__global__ __launch_bounds__(64 * W) void k_sweep2d_abd_tb(const T *__restrict__ u_in, const T *__restrict__ up_in,
+                      T *__restrict__ u_out, T *__restrict__ up_out, const T *__restrict__ m,
+                      const T *__restrict__ rc, const typename V2t<T>::type *__restrict__ F,
+                      int ny, int nx, Stencil<T> sa, Stencil<T> sb, T cth, TBCoef cf,
+                      int tiles_x, int ntiles, int per_xcd)
+{
+    constexpr int EX = 64, EY = R * W;
+    __shared__ T ul[4 * (EY + 2) * (EX + 2)];
+    const int id = blockIdx.x;
+    const int tile = (id % 8) * per_xcd + id / 8;
+    if (tile >= ntiles) return;
+    const int k = cf.k;
+    const int OX = EX - 2 * k, OY = EY - 2 * k;
+    const int ty = tile / tiles_x, tx = tile % tiles_x;
+    tb_tile_abd<T, R, W>(ul, u_in, up_in, u_out, up_out, m, rc, F, ny, nx, sa, sb, cth, k, k,
+                         ty * OY - k, tx * OX - k, cf.fa, cf.fb, cf.out_step, cf.out);
+}
+
+template <typename T, int R, int W>
+static hipError_t launch_abd_tb_t(const TBArgs &a, const Stencil<T> &sa, const Stencil<T> &sb,
+                                  hipStream_t s)
+{
+    constexpr int EX = 64, EY = R * W;
+    const int k = a.cf.k;
+    const int OX = EX - 2 * k, OY = EY - 2 * k;
+    if (k < 1 || k > TDP_TB_KMAX || OX < 1 || OY < 1) return hipErrorInvalidValue;
+    const int tiles_x = (a.nx + OX - 1) / OX, tiles_y = (a.ny + OY - 1) / OY;
+    const int ntiles = tiles_x * tiles_y;
+    const int per_xcd = (ntiles + 7) / 8;
+    hipLaunchKernelGGL((k_sweep2d_abd_tb<T, R, W>), dim3(8 * per_xcd), dim3(64 * W), 0, s,
+                       (const T *)a.u_in, (const T *)a.up_in, (T *)a.u_out, (T *)a.up_out,
+                       (const T *)a.m, (const T *)a.rc,
+                       (const typename V2t<T>::type *)a.F, a.ny, a.nx, sa, sb, (T)a.cth, a.cf,
+                       tiles_x, ntiles, per_xcd);
+    return hipGetLastError();
+}
+
 template <typename T, int R, int W>
 static hipError_t launch_tb2_t(const TBArgs &a, const Stencil<T> &st, hipStream_t s)
 {
@@ -596,6 +837,11 @@ int tb2d_tile_rows(int shape, bool f64)
     }
 }
 
+bool abd_tile_ok(int shape, bool f64)
+{
+    return f64 ? (shape == 5 || shape == 7) : (shape >= 4 && shape <= 7);
+}
+
 hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hipStream_t s)
 {
     switch (a.shape) {
@@ -607,6 +853,33 @@ hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hip
     case 7: return launch_tb2_t<double, 2, 16>(a, st, s);
     case 2: case 8: return hipErrorInvalidValue;     // FP32-only shapes
     default: return launch_tb_t<double, 8, 8>(a, st, s);
+    }
+}
+
+// I_abd: shapes 4..7 as for tb_tile2 in FP32, 5 and 7 in FP64 (its 12 words
+// of per-node state do not fit the register file in the others); mass tables
+// with corner entries are refused (the one-step kernel runs them)
+hipError_t launch_sweep2d_abd_tb_f64(const TBArgs &a, const Stencil<double> &sa,
+                                     const Stencil<double> &sb, hipStream_t s)
+{
+    if (a.sc > 3 || a.mc > 2) return hipErrorInvalidValue;
+    switch (a.shape) {
+    case 5: return launch_abd_tb_t<double, 4, 8>(a, sa, sb, s);
+    case 7: return launch_abd_tb_t<double, 2, 16>(a, sa, sb, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep2d_abd_tb_f32(const TBArgs &a, const Stencil<float> &sa,
+                                     const Stencil<float> &sb, hipStream_t s)
+{
+    if (a.sc > 3 || a.mc > 2) return hipErrorInvalidValue;
+    switch (a.shape) {
+    case 4: return launch_abd_tb_t<float, 4, 16>(a, sa, sb, s);
+    case 5: return launch_abd_tb_t<float, 4, 8>(a, sa, sb, s);
+    case 6: return launch_abd_tb_t<float, 8, 8>(a, sa, sb, s);
+    case 7: return launch_abd_tb_t<float, 2, 16>(a, sa, sb, s);
+    default: return hipErrorInvalidValue;
     }
 }
 

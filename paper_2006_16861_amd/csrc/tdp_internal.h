@@ -114,6 +114,8 @@ struct TBArgs {
     const void *u_in, *up_in;    // u_j, u_{j-1}
     void *u_out, *up_out;        // u_{j+k}, u_{j+k-1}  (distinct from the inputs)
     const void *m, *dn, *F;
+    const void *rc = nullptr;    // cell damping (I_abd form only)
+    double cth = 0.0;            // cos(omega_c dt) (I_abd form only)
     TBCoef cf;
 };
 // Batched blocked sweep: per-field descriptor (device array).  Buffers a0/a1
@@ -141,7 +143,14 @@ int tb2d_tiles(int shape, int K, int ny, int nx);
 
 hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hipStream_t s);
 hipError_t launch_sweep2d_tb_f32(const TBArgs &a, const Stencil<float> &st, hipStream_t s);
+// blocked I_abd on one real part of the complex field (shapes 4..8, mass
+// tables without corner entries)
+hipError_t launch_sweep2d_abd_tb_f64(const TBArgs &a, const Stencil<double> &sa,
+                                     const Stencil<double> &sb, hipStream_t s);
+hipError_t launch_sweep2d_abd_tb_f32(const TBArgs &a, const Stencil<float> &sa,
+                                     const Stencil<float> &sb, hipStream_t s);
 int tb2d_tile_rows(int shape, bool f64);
+bool abd_tile_ok(int shape, bool f64);    // tile shapes of the blocked I_abd kernel
 
 // 3-D sweep streamed along axis 0 (sweep3d.hip), one step per launch.
 // shape 0/1/2: 8 x 64 (4 waves x 2 rows), 16 x 64 (4 waves x 4 rows), 16 x 64

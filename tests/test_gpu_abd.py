@@ -127,3 +127,63 @@ def test_abd_f32_fields(n):
     Ug, ig = g.solve(dev(p.F), T=p.periods, tol=1e-8)
     assert ig.status == 0
     assert rel(o.apply_H(host(Ug)), p.F) <= 1e-8 * (1 + 1e-9)
+
+
+ABD_GRIDS = [(37, 150), (130, 77), (1, 9), (5, 200), (64, 64)]
+
+
+@pytest.mark.parametrize("n", ABD_GRIDS)
+def test_abd_blocked_tiles_and_depths(n):
+    """The blocked I_abd kernel (two real passes of k steps per launch) on every
+    FP64 tile shape it takes, depths 1..8 (odd, and not dividing N_s), graph
+    on and off, against the oracle's S_T^abd; grids of one row, ragged, and
+    spanning several tiles."""
+    p, R = problem(n, 12)
+    g, o = ops(p, R)
+    for T, rho in ((2, 0.25), (1, 0.75)):
+        Uo = o.precond(p.F, T, rho, variant=1)
+        for tile in (5, 7):
+            for depth in (1, 3, 8):
+                for graph in (1, 0):
+                    note(f"abd blocked {n} T={T} tile={tile} depth={depth} graph={graph}")
+                    g.set_tuning(kernel=2, tb_depth=depth, tile=tile, use_graph=graph)
+                    assert rel(host(g.precond(dev(p.F), T, rho, variant=1)), Uo) <= TOL64
+
+
+def test_abd_blocked_fallbacks_and_f32_tiles():
+    """Tiles the blocked I_abd kernel does not take, and mass tables with corner
+    entries, run the one-step kernel (same result); FP32 fields on every FP32
+    tile shape stay within FP32 accuracy of the FP64 oracle."""
+    from paper_2006_16861_amd import tdp
+    p, R = problem((70, 130), 13)
+    g, o = ops(p, R)
+    Uo = o.precond(p.F, 2, 0.25, variant=1)
+    for tile in (0, 4, 6):
+        note(f"abd blocked fallback tile={tile}")
+        g.set_tuning(kernel=2, tb_depth=4, tile=tile, use_graph=1)
+        assert rel(host(g.precond(dev(p.F), 2, 0.25, variant=1)), Uo) <= TOL64
+    gq, oq = ops(p, R, Q1[2])
+    note("abd blocked fallback corner mass")
+    gq.set_tuning(kernel=2, tb_depth=4, tile=7, use_graph=1)
+    assert rel(host(gq.precond(dev(p.F), 2, 0.25, variant=1)),
+               oq.precond(p.F, 2, 0.25, variant=1)) <= TOL64
+    g32 = tdp.Operator(dev(p.c), dev(R), p.omega, p.h, damping="cell", prec=tdp.F32)
+    for tile in (4, 5, 6, 7):
+        note(f"abd blocked f32 tile={tile}")
+        g32.set_tuning(kernel=2, tb_depth=6, tile=tile, use_graph=1)
+        assert rel(host(g32.precond(dev(p.F), 2, 0.25, variant=1)), Uo) <= 1e-4
+
+
+def test_abd_autotune_picks_a_candidate():
+    """The autotuner's table for the cell damping lists the one-step kernel and
+    the blocked tiles, and the op keeps a listed candidate that still matches
+    the oracle."""
+    p, R = problem((96, 160), 14)
+    g, o = ops(p, R)
+    note("abd autotune")
+    best, rows = g.autotune(T=1)
+    kinds = {(int(r[0]), int(r[2])) for r in rows}
+    assert (1, 0) in kinds and (2, 5) in kinds and (2, 7) in kinds
+    assert (best["kernel"], best["tile"]) in kinds
+    assert rel(host(g.precond(dev(p.F), 2, 0.25, variant=1)),
+               o.precond(p.F, 2, 0.25, variant=1)) <= TOL64
