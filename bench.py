@@ -571,6 +571,8 @@ def main():
             tun = op.get_tuning()
             per = {2: tun["tb_depth"], 4: 2}.get(tun["kernel"], 1)
             launches = -(-Ns // per)
+            if args.variant == 1 and tun["kernel"] != 1:
+                launches *= 2                    # two real passes
             print(json.dumps({"mode": "profile", "workload": args.workload, "N": p.N,
                               "N_s": Ns, "tuning": tun, "launches_per_apply": launches,
                               "apply_ms": apply_ms, "us_per_step": step_ms * 1e3,
