@@ -275,7 +275,7 @@ typedef struct {
 int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t);
 
 /* Autotuner: times each sweep variant applicable to this op (one step per
- * launch; blocked tile shapes x depths 2, 3, 4, 6, 8, 10, 12, 16 (4 x depth
+ * launch; blocked tile shapes x depths 2-10, 12, 16 (4 x depth
  * at most the tile's rows) for the 2-D Table 1 loop; the blocked I_abd tiles
  * x depths 2, 3, 4, 6, 8 with the 2-D cell damping; streamed column shapes x
  * chunk lengths 4, 8, 16, 32, 64 in 3-D, with one and two steps per launch) over

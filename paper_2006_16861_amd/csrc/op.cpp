@@ -917,7 +917,7 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
     cand.push_back({1, 0, 1, 0});
     if (op->ndim == 2 && op->dform == TDP_DAMP_NODE) {
         const int tiles[] = {0, 1, 2, 3, 4, 5, 6, 7, 8};
-        const int depths[] = {2, 3, 4, 6, 8, 10, 12, 16};
+        const int depths[] = {2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16};
         for (int tile : tiles) {
             if ((tile == 2 || tile == 8) && op->prec == TDP_F64) continue;
             const int rows = tb2d_tile_rows(tile, op->prec == TDP_F64);

@@ -275,7 +275,7 @@ class Operator:
     def autotune(self, T=4, rho=0.25, variant=0):
         """Time the sweep variants and keep the fastest; returns (best, table)
         with table rows (kernel, tb_depth, tile, us_per_step)."""
-        cap = 64
+        cap = 128
         tab = (ctypes.c_double * (4 * cap))()
         best = Tuning()
         n = _check(load().tdp_op_autotune(self._h, int(T), float(rho), int(variant),
@@ -333,7 +333,7 @@ class Batch:
     def autotune(self, T, rho=0.25):
         """Time the batched sweep variants, keep the fastest; returns rows
         (depth, tile, ms per application)."""
-        cap = 64
+        cap = 128
         tab = (ctypes.c_double * (3 * cap))()
         Tv = (ctypes.c_int * len(self.ops))(*[int(t) for t in T])
         n = _check(load().tdp_batch_autotune(self._h, ctypes.cast(Tv, ctypes.c_void_p), float(rho),
