@@ -661,6 +661,13 @@ def main():
                      "kernel": kname, "bytes_per_node_step": bytes_per,
                      "nodes_per_launch": p.N, "steps_per_launch": Ns / launches,
                      "avg_launch_us": launch_us,
+                     # HBM bytes actually moved per launch (the counters) over the
+                     # same launch time; with temporal blocking the algorithmic
+                     # rate exceeds the HBM peak and the step loop, not HBM,
+                     # sets the launch time
+                     "traffic_GBps": (traffic / (launch_us * 1e-6) / 1e9) if traffic else None,
+                     "traffic_frac": (traffic / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+                     if traffic else None,
                      "measured_ceiling_GBps": ceiling,
                      "alu": {"flops_per_node_step": FLOPS_PER_NODE_STEP,
                              "achieved_TFLOPs": FLOPS_PER_NODE_STEP * p.N * Ns / (apply_ms * 1e-3) / 1e12,
