@@ -609,14 +609,24 @@ def main():
     blocked = tun["kernel"] == 2
     steps_per_launch = tun["tb_depth"] if blocked else (2 if tun["kernel"] == 4 else 1)
     launches = -(-Ns // steps_per_launch)
-    launch_us = apply_ms * 1e3 / launches
+    if args.variant == 1 and tun["kernel"] != 1:
+        launches *= 2                            # Def. 4 and I_abd: two real passes
+    napply = infos[-1].steps // Ns
+    # average launch duration over the timed solves: the GPU time of their
+    # preconditioner applications (HIP events on the op's stream around each
+    # application) over the launches they made; the standalone application
+    # (with its staging copies) is reported beside it
+    launch_us = float(np.median([i.ms_precond for i in infos])) * 1e3 / (napply * launches)
+    standalone_launch_us = apply_ms * 1e3 / launches
     # algorithmic bytes of one launch: 7 words per node-step (u_j, u_{j-1}, u_{j+1},
     # m, damping, Re F, Im F) x N nodes x the steps the launch advances
     achieved = p.N * bytes_per * (Ns / launches) / (launch_us * 1e-6) / 1e9
-    napply = infos[-1].steps // Ns
     tname = "double" if prec == tdp.F64 else "float"
-    if args.damping == "cell":
-        kname = "k_sweep_abd<double> (I_abd, one step per launch)"
+    if args.damping == "cell" and tun["kernel"] == 2:
+        kname = (f"k_sweep2d_abd_tb<{tname}> depth={steps_per_launch} tile={tun['tile']} "
+                 "(I_abd, two real passes)")
+    elif args.damping == "cell":
+        kname = f"k_sweep_abd<{tname}> (I_abd, one step per launch)"
     elif tun["kernel"] == 2:
         kname = (f"k_sweep2d_{'tb2' if tun['tile'] >= 4 else 'tb'}<{tname}> "
                  f"depth={steps_per_launch} tile={tun['tile']}")
@@ -661,6 +671,9 @@ def main():
                      "kernel": kname, "bytes_per_node_step": bytes_per,
                      "nodes_per_launch": p.N, "steps_per_launch": Ns / launches,
                      "avg_launch_us": launch_us,
+                     "avg_launch_us_source": "HIP events around the preconditioner "
+                                             "applications of the timed solves",
+                     "standalone_launch_us": standalone_launch_us,
                      # HBM bytes actually moved per launch (the counters) over the
                      # same launch time; with temporal blocking the algorithmic
                      # rate exceeds the HBM peak and the step loop, not HBM,
