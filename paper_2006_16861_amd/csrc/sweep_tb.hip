@@ -1,16 +1,21 @@
-// Temporally blocked 2-D recurrence sweep (Table 1 loop, integrator I_acd of
-// Def. 2): one launch advances the real field by k <= TB_KMAX steps.
+// Temporally blocked 2-D recurrence sweeps: one launch advances a real field
+// by k <= TB_KMAX steps.
 //
 // Each workgroup owns an extended tile of EY x EX nodes (EX = 64 = one wave
-// across x, EY = R rows per lane x W waves).  It loads u_j into LDS, the cell
-// slowness of the tile into LDS, and keeps u_{j-1}, the damping factor and
-// the right-hand side of its R nodes in registers.  Every step updates the
-// whole tile from LDS; values within s nodes of the tile edge are wrong after
-// s steps (their neighbours outside the tile are taken as 0), so after k steps
-// the inner (EY - 2k) x (EX - 2k) nodes are exact and are the ones written
-// back.  Nodes outside the domain carry d = 0, F = 0, u = 0 and stay 0
+// across x, EY = R rows per lane x W waves).  Values within s nodes of the
+// tile edge are wrong after s steps (their neighbours outside the tile are
+// taken as 0), so after k steps the inner (EY - 2k) x (EX - 2k) nodes are
+// exact and are the ones written back.  Nodes outside the domain stay 0
 // (Dirichlet).  HBM traffic per node-step falls from 7 words to about
-// (5 (EY EX) / (out area) + cells + 2) / k words.
+// (6 (EY EX) / (out area) + 2) / k words.  Three tile updates live here:
+//  - tb_tile (shapes 0..3): u_j and the cell slowness of the tile in LDS;
+//    u_{j-1}, the damping factor and the right-hand side in registers
+//    (Table 1 loop, I_acd of Def. 2);
+//  - tb_tile2 (shapes 4..8, the default): per-node coefficients and the rows
+//    of u_j, u_{j-1} in registers, x-neighbours by DPP, only each wave's edge
+//    rows through LDS (same integrator);
+//  - tb_tile_abd: the same register form for I_abd (Sec. 5, cell damping) on
+//    one real part of the complex field.
 //
 // Workgroups are mapped XCD-aware: the hardware deals consecutive workgroup
 // ids round-robin to the 8 XCDs, so id -> tile is remapped to give each XCD a
