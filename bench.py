@@ -494,6 +494,9 @@ def main():
     ap.add_argument("--rho", type=float, default=0.25)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--scheme", choices=["compact", "fd2"], default="compact",
+                    help="fd2: the second-order 5-/7-point scheme of Sec. 3.1 instead of the "
+                         "compact fourth-order one")
     ap.add_argument("--damping", choices=["node", "cell"], default="node",
                     help="cell: the non-diagonal damping of Sec. 5 (I_abd; needs --variant 1)")
     ap.add_argument("--variant", type=int, default=0,
@@ -542,7 +545,8 @@ def main():
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         t = time.perf_counter()
-        op = tdp.operator_from_problem(p, prec=prec, damping=args.damping)
+        op = tdp.operator_from_problem(p, prec=prec, damping=args.damping,
+                                       scheme=None if args.scheme == "compact" else args.scheme)
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t) * 1e3
         tune_table = []
@@ -636,7 +640,9 @@ def main():
         kname = f"k_sweep3d_stream2<{tname}> shape={tun['tile']} z-chunk={tun['tb_depth']} (2 steps)"
     else:
         kname = f"k_sweep<{tname}> (one step per launch)"
-    traffic = measured_traffic(args.workload, args.prec, args.variant, tun, args.damping)
+    # the counters were taken with the compact scheme
+    traffic = (measured_traffic(args.workload, args.prec, args.variant, tun, args.damping)
+               if args.scheme == "compact" else None)
     ceiling = stream_probe()
     log(f"stream probe: copy {ceiling['copy']:.0f} GB/s, triad {ceiling['triad']:.0f} GB/s")
     log(f"precond apply {apply_ms:.3f} ms, {step_ms * 1e3:.2f} us/step, {achieved:.1f} GB/s algorithmic")
@@ -653,7 +659,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == tdp.F64 else "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": list(p.n), "h": p.h, "omega": p.omega,
+        "config": {"workload": args.workload, "scheme": args.scheme, "n": list(p.n), "h": p.h,
+                   "omega": p.omega,
                    "ppw": p.ppw, "damping_width": p.width, "periods_T": T, "n_P": op.nP,
                    "N_s": Ns, "rho": args.rho, "variant": args.variant, "restart": args.restart, "tol": args.tol,
                    "gmres_iters": infos[-1].iters, "gmres_restarts": infos[-1].restarts,
