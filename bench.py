@@ -494,6 +494,9 @@ def main():
     ap.add_argument("--rho", type=float, default=0.25)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--steps-per-period", type=int, default=0,
+                    help="n_P: 0 the smallest multiple of 4 above the CFL bound (Table 1), "
+                         "-1 the smallest integer >= 3 above it (Im U by the 2x2 solve)")
     ap.add_argument("--scheme", choices=["compact", "fd2"], default="compact",
                     help="fd2: the second-order 5-/7-point scheme of Sec. 3.1 instead of the "
                          "compact fourth-order one")
@@ -546,7 +549,8 @@ def main():
     with torch.cuda.stream(stream):
         t = time.perf_counter()
         op = tdp.operator_from_problem(p, prec=prec, damping=args.damping,
-                                       scheme=None if args.scheme == "compact" else args.scheme)
+                                       scheme=None if args.scheme == "compact" else args.scheme,
+                                       steps_per_period=args.steps_per_period)
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t) * 1e3
         tune_table = []
@@ -642,7 +646,7 @@ def main():
         kname = f"k_sweep<{tname}> (one step per launch)"
     # the counters were taken with the compact scheme
     traffic = (measured_traffic(args.workload, args.prec, args.variant, tun, args.damping)
-               if args.scheme == "compact" else None)
+               if args.scheme == "compact" and args.steps_per_period == 0 else None)
     ceiling = stream_probe()
     log(f"stream probe: copy {ceiling['copy']:.0f} GB/s, triad {ceiling['triad']:.0f} GB/s")
     log(f"precond apply {apply_ms:.3f} ms, {step_ms * 1e3:.2f} us/step, {achieved:.1f} GB/s algorithmic")
