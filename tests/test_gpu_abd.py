@@ -187,3 +187,17 @@ def test_abd_autotune_picks_a_candidate():
     assert (best["kernel"], best["tile"]) in kinds
     assert rel(host(g.precond(dev(p.F), 2, 0.25, variant=1)),
                o.precond(p.F, 2, 0.25, variant=1)) <= TOL64
+
+
+def test_abd_blocked_degenerate_damping():
+    """Degenerate cell damping: R = 0 everywhere (B vanishes, only the
+    constant centre term of the damping stencil is left) and R nonzero on a
+    single node; the blocked two-pass I_abd against the oracle."""
+    p, R = problem((50, 90), 21)
+    for name, RR in (("zero", np.zeros_like(R)), ("one node", np.where(np.arange(R.size).reshape(R.shape) == 2000, 3.0 * p.omega, 0.0))):
+        g, o = ops(p, RR)
+        Uo = o.precond(p.F, 2, 0.25, variant=1)
+        for tile in (5, 7):
+            note(f"abd blocked degenerate damping {name} tile={tile}")
+            g.set_tuning(kernel=2, tb_depth=8, tile=tile)
+            assert rel(host(g.precond(dev(p.F), 2, 0.25, variant=1)), Uo) <= TOL64
