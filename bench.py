@@ -494,6 +494,9 @@ def main():
     ap.add_argument("--rho", type=float, default=0.25)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--periods", type=int, default=0,
+                    help="T, periods per preconditioner application (0: the workload's, "
+                         "about the model size in wavelengths)")
     ap.add_argument("--steps-per-period", type=int, default=0,
                     help="n_P: 0 the smallest multiple of 4 above the CFL bound (Table 1), "
                          "-1 the smallest integer >= 3 above it (Im U by the 2x2 solve)")
@@ -566,7 +569,7 @@ def main():
         else:
             op.set_tuning(kernel=args.kernel, tb_depth=args.tb_depth, tile=args.tile,
                           use_graph=0 if args.no_graph else 1)
-        T = p.periods
+        T = args.periods if args.periods > 0 else p.periods
         Ns = T * op.nP
         F = torch.as_tensor(p.F, device="cuda")
         if args.profile_sweeps:
