@@ -37,3 +37,19 @@ def test_bench_json_line():
         assert k in rf, k
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
     assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) <= 1e-12
+
+
+def test_traffic_table_is_consistent():
+    """profiles/traffic.json: every entry's bytes per launch is its scaled
+    FETCH_SIZE + WRITE_SIZE (KiB), and names a committed profile summary."""
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+        table = json.load(f)
+    assert table
+    for key, e in table.items():
+        want = e["fetch_kib"] * 1024 * e["fetch_scale"] + e["write_kib"] * 1024 * e["write_scale"]
+        # the KiB figures are stored to 0.1 KiB
+        assert abs(e["bytes_per_launch"] - want) <= 0.05 * 1024 * (e["fetch_scale"] + e["write_scale"]), key
+        assert os.path.exists(os.path.join(ROOT, "profiles", e["profile"])), key
+        workload, prec, variant, kern, depth, tile = key.split("|")[:6]
+        assert prec in ("f64", "f32") and variant in ("v0", "v1"), key
+        assert kern.startswith("k") and depth.startswith("d") and tile.startswith("t"), key
