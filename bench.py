@@ -274,7 +274,7 @@ def form_batched(rho):
 
 
 def form_cell_damping(rho):
-    """Sec. 5 path on the headline workload: smooth2d-1024 with the cell
+    """Sec. 6 path on the headline workload: smooth2d-1024 with the cell
     (non-diagonal) damping Im H = omega sum_cells r_cell M_cell, preconditioned
     by S_T^abd (I_abd), to a true relative residual of 1e-6, with FP64 and with
     FP32 recurrence fields (GMRES, H and the residuals in FP64 either way), on
@@ -285,7 +285,7 @@ def form_cell_damping(rho):
     from paper_2006_16861_amd import inputs, tdp
     p = inputs.smooth2d(1024)
     F = torch.as_tensor(p.F, device="cuda")
-    res = {"workload": "smooth2d-1024, cell damping (Sec. 5, I_abd)"}
+    res = {"workload": "smooth2d-1024, cell damping (Sec. 6, I_abd)"}
     for name, prec in (("f64", tdp.F64), ("f32", tdp.F32)):
         op = tdp.operator_from_problem(p, damping="cell", prec=prec)
         op.autotune(T=4, rho=rho, variant=1)
@@ -437,7 +437,7 @@ def study_shard(ngpu=8, rho=0.25):
 
 def study_convergence(model, Ts=(10, 20, 40, 80, 160, 320), rhos=(0.0, 0.25, 0.5, 0.75),
                       gmres_Ts=(5, 10, 20, 40, 80), ref_tol=1e-12):
-    """Sec. 4.1's convergence studies on the constant model and the resonant disc
+    """Sec. 5.1's convergence studies on the constant model and the resonant disc
     model (6 points per wavelength, 8 steps per period, 32-node damping layers):
     (a) the relative error of S_T F against H^-1 F as T grows, for each taper rho
         (rho = 0: the forcing ramps up over one period);
@@ -504,7 +504,7 @@ def main():
                     help="fd2: the second-order 5-/7-point scheme of Sec. 3.1 instead of the "
                          "compact fourth-order one")
     ap.add_argument("--damping", choices=["node", "cell"], default="node",
-                    help="cell: the non-diagonal damping of Sec. 5 (I_abd; needs --variant 1)")
+                    help="cell: the non-diagonal damping of Sec. 6 (I_abd; needs --variant 1)")
     ap.add_argument("--variant", type=int, default=0,
                     help="0: Table 1 real-field preconditioner, 1: Definition 4 complex field")
     ap.add_argument("--kernel", type=int, default=0)
@@ -521,7 +521,7 @@ def main():
                     help="profiling mode: one 256 MiB device copy (counter calibration), then "
                          "this many preconditioner applications, then exit")
     ap.add_argument("--study", choices=["convergence", "shard"], default=None,
-                    help="convergence: Sec. 4.1's convergence study on the constant and "
+                    help="convergence: Sec. 5.1's convergence study on the constant and "
                          "resonant models; shard: the sweep at one GPU's slab of an 8-GPU "
                          "decomposition, with its halo sizes (instead of the benchmark)")
     ap.add_argument("--study-model", type=int, default=320,

@@ -11,7 +11,7 @@
  * couples its corners b, g with h^-2 S[Delta] - omega^2 m_cell M[Delta],
  * Delta = number of axes on which b and g differ, m_cell the mean of 1/c^2
  * over the cell's corners (corners outside the box take the nearest interior
- * node).  Im H = diag(omega R), or with the cell damping of Sec. 5
+ * node).  Im H = diag(omega R), or with the cell damping of Sec. 6
  * (tdp_op_desc.damping = TDP_DAMP_CELL) Im H = omega sum_cells r_cell M[Delta],
  * r_cell the mean of R over the cell's corners.
  *
@@ -51,7 +51,7 @@ typedef enum { TDP_F64 = 0, TDP_F32 = 1 } tdp_prec;
 /* Damping discretisation and the integrator it selects.
  *  TDP_DAMP_NODE  Im H = diag(omega R): I_acd (Def. 2), Table 1 / Def. 4.
  *  TDP_DAMP_CELL  Im H = omega sum_cells r_cell M[Delta], not diagonal: the
- *                 explicit I_abd of Sec. 5 (Def. 6) and S_T^abd (Def. 7). */
+ *                 explicit I_abd of Sec. 6 (Def. 6) and S_T^abd (Def. 7). */
 typedef enum { TDP_DAMP_NODE = 0, TDP_DAMP_CELL = 1 } tdp_damping;
 
 typedef struct tdp_op tdp_op;
@@ -97,7 +97,7 @@ typedef struct tdp_op tdp_op;
  *                    each call's entry / exit (the step loop is captured
  *                    into a graph, which the default stream cannot hold).
  *  damping           tdp_damping (0 = TDP_DAMP_NODE).  TDP_DAMP_CELL: omega_c,
- *                    dt and n_P follow Sec. 5.1 (omega_c^2 = k_max^2 +
+ *                    dt and n_P follow Sec. 6.1 (omega_c^2 = k_max^2 +
  *                    (beta/theta)(1 - cos theta) lam_im, theta = omega_c dt =
  *                    2 pi/n_P the largest for which 4I - K - 2L > 0 holds on
  *                    the bounds); FP64 or FP32 fields; preconditioning is S_T^abd
@@ -203,7 +203,7 @@ int tdp_precond_apply(const tdp_op *op, int periods_T, double rho, const void *F
  * real and imaginary parts run as two real passes of the blocked (2-D) or
  * streamed (3-D) kernels; with tdp_tuning.kernel = 1 as one complex pass
  * (10 instead of 7 words per node-step).
- * With TDP_DAMP_CELL this is S_T^abd (Sec. 5, Def. 7): the same forcing
+ * With TDP_DAMP_CELL this is S_T^abd (Sec. 6, Def. 7): the same forcing
  * driving I_abd (Def. 6).  Its recurrence has real coefficients too: in 2-D
  * (mass tables without corner entries) it runs as two real passes of the
  * blocked I_abd kernel (k steps per launch), else, and with

@@ -226,7 +226,7 @@ def assemble_H(n, h, omega, c, R=None, stiff=None, mass=None, damping="diagonal"
     Each cell (lower corner alpha, alpha_a in -1..n_a-1) adds the (2^d x 2^d)
     element matrix h^-2 S[Delta] - omega^2 m_cell M[Delta] over its interior
     corners (App. A); Im H = diag(omega R), or with damping="cell" the element
-    matrices i omega r_cell M[Delta], r_cell the corner mean of R (Sec. 5)."""
+    matrices i omega r_cell M[Delta], r_cell the corner mean of R (Sec. 6)."""
     import itertools
     import scipy.sparse as sp
     n = tuple(int(v) for v in n)

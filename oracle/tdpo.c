@@ -145,7 +145,7 @@ static double stiffness_symbol(const tdpo_op *op, const double *theta)
     return s;
 }
 
-/* Sec. 5.1's stability condition 4I - K - 2L > 0 for I_abd with
+/* Sec. 6.1's stability condition 4I - K - 2L > 0 for I_abd with
  * theta = omega dt, using the bounds lam_s >= lambda_max(Re H) (stiffness part)
  * and lam_im >= lambda_max(Im H):
  *   (theta^2/alpha)(lam_s/omega^2 + 1) + (theta beta/alpha)(1 + cos theta) lam_im/omega^2 < 4,
@@ -254,7 +254,7 @@ int tdpo_op_create(int ndim, const long *n, double h, double omega,
         if (s > smax) smax = s;
     }
     if (dform == 1) {
-        /* Sec. 5.1: n_P = 2 pi / theta, the smallest multiple of 4 for which the
+        /* Sec. 6.1: n_P = 2 pi / theta, the smallest multiple of 4 for which the
          * stability condition holds; omega from the K >= 0 condition */
         double kmax2 = op->omega_c * op->omega_c, lam_s = smax / (h * h), w2 = 0.0;
         if (nP == 0) {
@@ -360,7 +360,7 @@ static double reH_row(const tdpo_op *op, const double *x, long b)
 }
 
 /* (Im H x)_b for the cell damping (dform 1): omega sum over cells a containing
- * b, over corners g of a, of r_a M_{Delta(b,g)} x_g (Sec. 5: non-diagonal B);
+ * b, over corners g of a, of r_a M_{Delta(b,g)} x_g (Sec. 6: non-diagonal B);
  * omega R_b x_b for the diagonal damping. */
 static double imH_row(const tdpo_op *op, const double *x, long b)
 {
@@ -474,7 +474,7 @@ double tdpo_window(double s, double rho)
 }
 
 /* Table 1: U = S_T F with real fields.  rho <= 0 means "ramp over one
- * period" (Sec. 4.1), i.e. rho = 1/T. */
+ * period" (Sec. 5.1), i.e. rho = 1/T. */
 int tdpo_precond_apply(const tdpo_op *op, int T, double rho, const double complex *F,
                        double complex *U)
 {

@@ -24,7 +24,7 @@ typedef struct tdpo_op tdpo_op;
  * check (to exhibit instability).
  * dform 0: Im H = diag(omega R), integrator I_acd (Def. 2);
  * dform 1: Im H = omega sum_cells r_cell M_cell (r_cell = corner mean of R),
- *          integrator I_abd (Sec. 5, Def. 6), S_T^abd (Def. 7). */
+ *          integrator I_abd (Sec. 6, Def. 6), S_T^abd (Def. 7). */
 int tdpo_op_create(int ndim, const long *n, double h, double omega, const double *c,
                    const double *R, const double *stiff, const double *mass, int nP,
                    int dform, tdpo_op **out);

@@ -266,7 +266,7 @@ hipError_t launch_sweep_c_f32(const SweepArgs &a, const Stencil<float> &st, floa
 }
 
 // ---------------------------------------------------------------------------
-// frequency adapted backward-differences damped leapfrog I_abd (Sec. 5, Def. 6)
+// frequency adapted backward-differences damped leapfrog I_abd (Sec. 6, Def. 6)
 // on the complex field of S_T^abd (Def. 7), for the cell damping
 // Im H = omega sum_cells r_cell M_cell:
 //   u_{n+1} = (2 - K - L) u_n - (I - L) u_{n-1} + g f_n

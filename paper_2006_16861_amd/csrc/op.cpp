@@ -82,7 +82,7 @@ static void table_spectrum(int d, const double *T, double *lo, double *hi)
     }
 }
 
-// Sec. 5.1: stability of I_abd at theta = omega dt with the bounds lam_s >=
+// Sec. 6.1: stability of I_abd at theta = omega dt with the bounds lam_s >=
 // lambda_max of the stiffness part of Re H and lam_im >= lambda_max(Im H):
 // omega^2 = kmax2 + (beta/theta)(1 - cos theta) lam_im makes K >= 0, and
 // 4I - K - 2L > 0 holds when
@@ -256,7 +256,7 @@ static int create_impl(const tdp_op_desc *d, tdp_op *op)
         TDP_CHECK_HIP(hipMemcpyAsync(&rmax, op->scratch + nblk, sizeof(double), hipMemcpyDeviceToHost, s));
         TDP_CHECK_HIP(hipStreamSynchronize(s));
         op->lam_im = op->omega * rmax;
-        // Sec. 5.1: theta = omega dt = 2 pi / n_P with n_P the smallest multiple of 4
+        // Sec. 6.1: theta = omega dt = 2 pi / n_P with n_P the smallest multiple of 4
         // (steps_per_period = -1: the smallest integer >= 3) satisfying the
         // stability condition; omega from the K >= 0 condition
         const double kmax2 = op->omega_c * op->omega_c;
@@ -311,7 +311,7 @@ static int create_impl(const tdp_op_desc *d, tdp_op *op)
         op->st_H.m[k] = -op->omega * op->omega * mk;
     }
     // Im H (cell damping) and (beta dt / (alpha omega_c)) Im H as mass-class
-    // stencils over r_cell (Sec. 5: L = (beta dt/alpha) B, B = Im H / omega_c)
+    // stencils over r_cell (Sec. 6: L = (beta dt/alpha) B, B = Im H / omega_c)
     op->cos_th = std::cos(th);
     const double lb = op->beta * op->dt / op->alpha / op->omega_c;
     for (int k = 0; k < 4; ++k) {

@@ -14,7 +14,7 @@
 //  - tb_tile2 (shapes 4..8, the default): per-node coefficients and the rows
 //    of u_j, u_{j-1} in registers, x-neighbours by DPP, only each wave's edge
 //    rows through LDS (same integrator);
-//  - tb_tile_abd: the same register form for I_abd (Sec. 5, cell damping) on
+//  - tb_tile_abd: the same register form for I_abd (Sec. 6, cell damping) on
 //    one real part of the complex field.
 //
 // Workgroups are mapped XCD-aware: the hardware deals consecutive workgroup
@@ -488,7 +488,7 @@ void k_sweep2d_tb_batch(
                                  out_step, out);
 }
 
-// Frequency-adapted backward-differences damped leapfrog I_abd (Sec. 5) with
+// Frequency-adapted backward-differences damped leapfrog I_abd (Sec. 6) with
 // the cell damping, blocked like tb_tile2, on one real part of the complex
 // field of S_T^abd.  Its recurrence has real coefficients,
 //   x_{n+1} = A[x_n] + B[x_{n-1} - cos(theta) x_n] - x_{n-1} + fa Re F + fb Im F,

@@ -186,7 +186,7 @@ hipError_t launch_sweep_c_f64(const SweepArgs &a, const Stencil<double> &st, dou
 hipError_t launch_sweep_c_f32(const SweepArgs &a, const Stencil<float> &st, float fa, float fb,
                               hipStream_t s);
 
-// I_abd step on complex fields (Sec. 5): a.u = u_n, a.up = u_{n-1} (read only),
+// I_abd step on complex fields (Sec. 6): a.u = u_n, a.up = u_{n-1} (read only),
 // u_{n+1} -> uout; rc the cell damping; stB the mass-class stencil of L/ImH.
 hipError_t launch_sweep_abd_f64(const SweepArgs &a, void *uout, const double *rc,
                                 const Stencil<double> &stA, const Stencil<double> &stB,
@@ -272,7 +272,7 @@ struct tdp_op {
     int nP = 0;
     double cS = 0, cM = 0, cw = 0, g = 0;
     tdp::Stencil<double> st_step{}, st_H{};
-    // cell damping (Sec. 5): Im H = omega sum_cells r_cell M_cell, integrator I_abd
+    // cell damping (Sec. 6): Im H = omega sum_cells r_cell M_cell, integrator I_abd
     int dform = TDP_DAMP_NODE;
     double lam_im = 0, cos_th = 0;
     double *rc = nullptr;                   // cell damping r_cell

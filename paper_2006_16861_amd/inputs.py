@@ -20,7 +20,7 @@ Workload recipe (the paper's own media are not available; these stand in):
                 24-cell layer, source at the centre.
   * "smooth3d"  n^3 (128^3), Gaussian sigma=8 field mapped to [1.5, 3.0].
 Damping profile (the paper adds absorbing layers of a fixed width around the
-model, Section 4.1): here the layer lies inside the grid, with per-axis depth
+model, Section 5.1): here the layer lies inside the grid, with per-axis depth
 delta_a(i) = max(0, w - min(i, n_a-1-i)), delta = max_a delta_a and
 R = R_max (delta/w)^2, R_max = 2 omega.
 """
@@ -252,9 +252,9 @@ def random_medium(n, seed: int, cmin: float = 1.0, cmax: float = 2.0,
 def _model2d(name, model: int, width: int, ppw: float, c_of_xy, src_xy) -> Problem:
     """A model on the unit square, `model` nodes per axis at the cell centres
     (k + 1/2) h, h = 1/model, so that k = omega/c = 2 pi model/ppw for c = 1
-    (Sec. 4.1 prints k = 335.1 for its 320 x 320 constant model at 6 points
+    (Sec. 5.1 prints k = 335.1 for its 320 x 320 constant model at 6 points
     per wavelength); damping layers of `width` nodes are added outside it (as
-    in Sec. 4.1), so the grid has model + 2 width nodes per axis.  c_of_xy(x, y)
+    in Sec. 5.1), so the grid has model + 2 width nodes per axis.  c_of_xy(x, y)
     gives the speed at model coordinates (nodes in the layers take the speed of
     the nearest model node); the point source sits at the model node nearest
     to src_xy."""
@@ -274,7 +274,7 @@ def _model2d(name, model: int, width: int, ppw: float, c_of_xy, src_xy) -> Probl
 
 
 def open2d(model: int = 320, width: int = 32, ppw: float = 6.0) -> Problem:
-    """Constant speed c = 1 on the unit square (the constant model of Sec. 4.1),
+    """Constant speed c = 1 on the unit square (the constant model of Sec. 5.1),
     point source at (0.5, 0.25)."""
     return _model2d("open2d", model, width, ppw, lambda X, Y: np.ones_like(X), (0.5, 0.25))
 
@@ -283,7 +283,7 @@ def disc2d(model: int = 320, width: int = 32, ppw: float = 6.0, c_out: float = 1
            c_in: float = 0.5, radius: float = 0.2) -> Problem:
     """Piecewise constant model with a slow disc (speed c_in inside radius
     `radius` around (0.5, 0.5), c_out outside): waves are trapped in the disc, a
-    resonant stand-in for Sec. 4.1's circular model.  Source at (0.5, 0.2),
+    resonant stand-in for Sec. 5.1's circular model.  Source at (0.5, 0.2),
     outside the disc."""
     def c_of(X, Y):
         inside = (X - 0.5) ** 2 + (Y - 0.5) ** 2 < radius ** 2

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libtdp.so")
 OK, ENOTCONV, EINVAL, ENOMEM, EHIP, ECFL = 0, 1, -1, -2, -3, -4
 F64, F32 = 0, 1
 # damping discretisation: "node" Im H = diag(omega R) (I_acd); "cell" Im H =
-# omega sum_cells r_cell M_cell, the non-diagonal damping of Sec. 5 (I_abd)
+# omega sum_cells r_cell M_cell, the non-diagonal damping of Sec. 6 (I_abd)
 DAMPING = {"node": 0, "cell": 1}
 
 SYMBOLS = ("tdp_op_create", "tdp_op_destroy", "tdp_op_query", "tdp_apply_H",

@@ -20,22 +20,22 @@ def _records(name):
     return out
 
 
-def test_sec4_1_steps_per_period():
+def test_sec5_1_steps_per_period():
     """6 points per wavelength -> 8 steps per period, from the oracle's CFL
     choice on the constant model (a small model: n_P depends only on the
     points per wavelength)."""
-    rec = [r for r in _records("sec4_1_constant_model.txt") if "steps_per_period" in r][0]
+    rec = [r for r in _records("sec5_1_constant_model.txt") if "steps_per_period" in r][0]
     p = inputs.open2d(model=48, width=8, ppw=rec["ppw"])
     assert oracle.Op.from_problem(p).nP == int(rec["steps_per_period"])
 
 
 @pytest.mark.parametrize("model", [320, 640])
-def test_sec4_1_wavenumber_of_the_constant_model(model):
+def test_sec5_1_wavenumber_of_the_constant_model(model):
     """k = omega/c of the study's constant model against the printed value.
     2 pi 320/6 = 335.10 matches 335.1; 2 pi 640/6 = 670.21 is printed as
     670.1, so the bound is the printed value's last digit plus that slip
     (0.02%)."""
-    rec = [r for r in _records("sec4_1_constant_model.txt") if r.get("model") == model][0]
+    rec = [r for r in _records("sec5_1_constant_model.txt") if r.get("model") == model][0]
     p = inputs.open2d(model=model, width=32, ppw=6.0)
     k = p.omega / float(p.c.min())
     assert abs(k - rec["k"]) <= 2e-4 * rec["k"], (k, rec["k"])

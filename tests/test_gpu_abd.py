@@ -1,4 +1,4 @@
-"""GPU parity of the Sec. 5 path: cell damping Im H = omega sum_cells r_cell M_cell,
+"""GPU parity of the Sec. 6 path: cell damping Im H = omega sum_cells r_cell M_cell,
 I_abd (Def. 6) and S_T^abd (Def. 7), through the C ABI against the oracle
 (FP64 bar 1e-10), plus LU for a converged solve and the error paths."""
 import sys
@@ -112,7 +112,7 @@ def test_abd_gradient_and_error_paths():
 @pytest.mark.parametrize("n", [(37, 150), (9, 11, 70)])
 def test_abd_f32_fields(n):
     """FP32 recurrence fields with the cell damping (the precision form of the
-    Sec. 5 path): S_T^abd close to the FP64 oracle, and GMRES, which keeps H and
+    Sec. 6 path): S_T^abd close to the FP64 oracle, and GMRES, which keeps H and
     the residuals in FP64, reaches 1e-8 checked by the oracle's H."""
     from paper_2006_16861_amd import tdp
     p, R = problem(n, 8)

@@ -1,4 +1,4 @@
-"""Sec. 4.1's convergence findings, reproduced on the constant model and the
+"""Sec. 5.1's convergence findings, reproduced on the constant model and the
 resonant disc model (160^2 model + 32-node damping layers, 6 points per
 wavelength, so 8 steps per period), against sparse LU of the independently
 assembled H:

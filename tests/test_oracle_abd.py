@@ -1,4 +1,4 @@
-"""Pins of the oracle's Sec. 5 path: cell ("consistent") damping
+"""Pins of the oracle's Sec. 6 path: cell ("consistent") damping
 Im H = omega sum_cells r_cell M_cell, the frequency adapted backward-differences
 damped leapfrog I_abd (Def. 6) and S_T^abd (Def. 7)."""
 import math
@@ -97,7 +97,7 @@ def stable(theta, kmax2, lam_s, lam_im):
 @pytest.mark.parametrize("n", [(8, 7), (4, 5, 3)])
 @pytest.mark.parametrize("rscale", [0.5, 2.0, 8.0])
 def test_abd_parameters_and_stability_conditions(n, rscale):
-    """Sec. 5.1: omega^2 = k_max^2 + (beta/theta)(1 - cos theta) lambda_max(Im H)
+    """Sec. 6.1: omega^2 = k_max^2 + (beta/theta)(1 - cos theta) lambda_max(Im H)
     makes K >= 0; n_P is the smallest multiple of 4 with 4I - K - 2L > 0 (from the
     bounds); L >= 0.  Checked with the dense K and L."""
     p, R = problem(n, 60, rscale)
@@ -140,7 +140,7 @@ def test_abd_harmonic_invariance(n):
 
 @pytest.mark.parametrize("n", [(12, 9), (5, 4, 6)])
 def test_abd_energy_identity_and_conservation(n):
-    """Sec. 5.2: E_bd(n+1/2) - E_bd(n-1/2) = -2 <u+ - u-, L (u+ - u-)> (<= 0 for
+    """Sec. 6.2: E_bd(n+1/2) - E_bd(n-1/2) = -2 <u+ - u-, L (u+ - u-)> (<= 0 for
     L >= 0), and E_bd is conserved without damping."""
     for rs in (2.0, 0.0):
         p, R = problem(n, 80)
@@ -197,7 +197,7 @@ def test_abd_precond_on_eigenvector_is_scalar_recurrence(ndim):
 
 
 def test_abd_converges_to_inverse_and_gmres_matches_lu():
-    """Sec. 5.2 (convergence theorem): S_T^abd F -> H^-1 F as T grows; GMRES
+    """Sec. 6.2 (convergence theorem): S_T^abd F -> H^-1 F as T grows; GMRES
     preconditioned by S_T^abd reaches the sparse-LU solution."""
     p, R = problem((14, 12), 90)
     R = R + 0.5 * p.omega                        # uniform floor: a spectral gap

@@ -117,7 +117,7 @@ def test_cfl_parameters_closed_form():
 
 
 def test_paper_steps_per_period_at_6ppw():
-    """Sec. 4.1: six points per wavelength resulted in eight steps per period."""
+    """Sec. 5.1: six points per wavelength resulted in eight steps per period."""
     op, *_ = const_op((64, 64), cval=1.0, ppw=6.0)
     assert op.nP == 8
     op, *_ = const_op((64, 64), cval=1.0, ppw=10.0)
