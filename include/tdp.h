@@ -196,6 +196,25 @@ int tdp_apply_H(const tdp_op *op, const void *x, void *y);
  * parameter rho (rho <= 0: rho = 1/T).  F, U: device complex128 [N]. */
 int tdp_precond_apply(const tdp_op *op, int periods_T, double rho, const void *F, void *U);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * U = S_T F as tdp_precond_apply (Table 1, same kernels and tuning), with the
+ * recurrence fields (and, for FP32 fields, the complex64 copy of F) in one
+ * static device array of TDP_NOALLOC_MAX_BYTES per GPU instead of buffers of
+ * the op.  The call allocates nothing (no hipMalloc, hipFree, graph
+ * instantiation or forcing-table cache); its launches are issued directly on
+ * the op's stream.  Needs 32 bytes per node with FP64 fields and 24 with FP32
+ * fields (each part rounded up to 256 bytes): FP64 grids up to 2^21 nodes.
+ * Larger grids return TDP_EINVAL before any work is issued.  Every call on
+ * one GPU uses that GPU's one array, and each call starts by zeroing the
+ * fields it uses: calls that overlap in time on one GPU (two streams, two
+ * ops, two host threads) race and give wrong results.  Ops with the cell
+ * damping return TDP_EINVAL, as tdp_precond_apply does.
+ * F, U: device complex128 [N], distinct. */
+#define TDP_NOALLOC_MAX_BYTES (64u << 20)
+int tdp_precond_apply_noalloc(const tdp_op *op, int periods_T, double rho, const void *F,
+                              void *U);
+
 /* U = S_T F by Definition 4 (Sec. 2.3) as stated: the integrator I_acd on a
  * complex field driven by chi(1 - j/N_s) e^{i 2 pi j/n_P} F from zero fields,
  * U = e^{-i 2 pi T} u_{N_s} = u_{N_s}.  Complex-linear, unlike Table 1 whose

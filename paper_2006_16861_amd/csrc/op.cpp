@@ -29,7 +29,7 @@ void set_error(const char *fmt, ...)
     g_last_error = buf;
 }
 
-static void clear_error() { g_last_error.clear(); }
+void clear_error() { g_last_error.clear(); }
 
 #define TDP_FAIL(code, ...)        \
     do {                           \
@@ -192,6 +192,8 @@ static int create_impl(const tdp_op_desc *d, tdp_op *op)
     for (int k = 0; k <= D; ++k)
         if (op->M[k] != 0.0) op->mc = k + 1;
 
+    TDP_CHECK_HIP(hipGetDevice(&op->device));
+    TDP_CHECK(noalloc_setup_device(op->device));
     op->user_stream = (hipStream_t)d->stream;
     if (op->user_stream) {
         op->stream = op->user_stream;
@@ -447,6 +449,20 @@ static double window(double s, double rho)
 //                           forcing fa Re F + fb Im F = g Re(chi_j e^{i phi_j} F);
 //   Definition 4 (complex): fa_j = g chi_j cos phi_j,  fb_j = g chi_j sin phi_j,
 //                           forcing (fa + i fb) F = g chi_j e^{i phi_j} F.
+void forcing_pair(const tdp_op *op, int64_t Ns, double rho, int variant, int64_t j, double *fa,
+                  double *fb)
+{
+    const double chi = window(1.0 - (double)j / (double)Ns, rho);
+    const double ph = 2.0 * M_PI * (double)j / op->nP;
+    if (variant == 2) {          // imaginary part of Definition 4's forcing
+        *fa = op->g * chi * std::sin(ph);
+        *fb = op->g * chi * std::cos(ph);
+    } else {
+        *fa = op->g * chi * std::cos(ph);
+        *fb = (variant ? 1.0 : -1.0) * op->g * chi * std::sin(ph);
+    }
+}
+
 const std::vector<double> &forcing_table(tdp_op *op, int T, double rho, int variant)
 {
     auto key = std::make_tuple(T, rho, variant);
@@ -454,18 +470,36 @@ const std::vector<double> &forcing_table(tdp_op *op, int T, double rho, int vari
     if (it != op->tables.end()) return it->second;
     const int64_t Ns = (int64_t)T * op->nP;
     std::vector<double> t(2 * Ns);
-    for (int64_t j = 0; j < Ns; ++j) {
-        const double chi = window(1.0 - (double)j / (double)Ns, rho);
-        const double ph = 2.0 * M_PI * (double)j / op->nP;
-        if (variant == 2) {          // imaginary part of Definition 4's forcing
-            t[2 * j] = op->g * chi * std::sin(ph);
-            t[2 * j + 1] = op->g * chi * std::cos(ph);
-        } else {
-            t[2 * j] = op->g * chi * std::cos(ph);
-            t[2 * j + 1] = (variant ? 1.0 : -1.0) * op->g * chi * std::sin(ph);
-        }
-    }
+    for (int64_t j = 0; j < Ns; ++j) forcing_pair(op, Ns, rho, variant, j, &t[2 * j], &t[2 * j + 1]);
     return op->tables.emplace(key, std::move(t)).first->second;
+}
+
+// Forcing scalars of one loop: read from the cached table, or (for the
+// allocation-free entry point) evaluated step by step with the same formula.
+struct ForcingSrc {
+    const double *tab = nullptr;
+    const tdp_op *op = nullptr;
+    int64_t Ns = 0;
+    double rho = 0;
+    int variant = 0;
+    double a(int64_t j) const { return tab ? tab[2 * j] : pair(j).first; }
+    double b(int64_t j) const { return tab ? tab[2 * j + 1] : pair(j).second; }
+    std::pair<double, double> pair(int64_t j) const
+    {
+        double fa, fb;
+        forcing_pair(op, Ns, rho, variant, j, &fa, &fb);
+        return {fa, fb};
+    }
+};
+static ForcingSrc forcing_src(tdp_op *op, int T, double rho, int variant, const LoopBufs &lb)
+{
+    ForcingSrc f;
+    f.op = op;
+    f.Ns = (int64_t)T * op->nP;
+    f.rho = rho;
+    f.variant = variant;
+    if (!lb.table_free) f.tab = forcing_table(op, T, rho, variant).data();
+    return f;
 }
 
 // Table 1's second sample: u_{N_s - q} with q = n_P/4 (a quarter period) when
@@ -548,15 +582,15 @@ static int ensure_tb_fields(tdp_op *op)
 // Real-field loops (Table 1's recurrence with the forcing table `tabv`): the
 // final field goes to out_final and, when out_snap is given, the sample
 // u_{N_s - q} to out_snap (stride-2 doubles inside a complex128 array).
-static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, int tile, const void *Fin,
-                          int tabv, double *out_final, double *out_snap, bool abd = false)
+static int issue_steps_tb(tdp_op *op, const LoopBufs &lb, int T, double rho, int depth, int tile,
+                          const void *Fin, int tabv, double *out_final, double *out_snap,
+                          bool abd = false)
 {
     hipStream_t s = op->stream;
-    TDP_CHECK(ensure_tb_fields(op));
-    const std::vector<double> &tab = forcing_table(op, T, rho, tabv);
+    const ForcingSrc tab = forcing_src(op, T, rho, tabv, lb);
     const int64_t Ns = (int64_t)T * op->nP, jsnap = out_snap ? Ns - snap_lag(op->nP) : -1;
     const size_t fb = (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
-    void *cur = op->u0, *prev = op->u1, *ncur = op->v0, *nprev = op->v1;
+    void *cur = lb.u0, *prev = lb.u1, *ncur = lb.v0, *nprev = lb.v1;
     TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
     TDP_CHECK_HIP(launch_fill_zero(prev, fb, s));
     TBArgs a;
@@ -580,8 +614,8 @@ static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, int tile, co
         a.up_out = nprev;
         a.cf.k = k;
         for (int q = 0; q < k; ++q) {
-            a.cf.fa[q] = tab[2 * (j0 + q)];
-            a.cf.fb[q] = tab[2 * (j0 + q) + 1];
+            a.cf.fa[q] = tab.a(j0 + q);
+            a.cf.fb[q] = tab.b(j0 + q);
         }
         // step q (1-based) of this launch produces u_{j0+q}
         a.cf.out_step[0] = (jsnap > j0 && jsnap <= j0 + k) ? (int)(jsnap - j0) : 0;
@@ -604,16 +638,15 @@ static int issue_steps_tb(tdp_op *op, int T, double rho, int depth, int tile, co
 
 // Streamed 3-D loop with two steps per launch, ping-ponging between the field
 // pairs (u0, u1) and (v0, v1); an odd last step runs the one-step kernel in place.
-static int issue_steps_3d2(tdp_op *op, int T, double rho, int zc, int shape, const void *Fin,
-                           int tabv, double *out_final, double *out_snap)
+static int issue_steps_3d2(tdp_op *op, const LoopBufs &lb, int T, double rho, int zc, int shape,
+                           const void *Fin, int tabv, double *out_final, double *out_snap)
 {
     hipStream_t s = op->stream;
-    TDP_CHECK(ensure_tb_fields(op));
-    const std::vector<double> &tab = forcing_table(op, T, rho, tabv);
+    const ForcingSrc tab = forcing_src(op, T, rho, tabv, lb);
     const int64_t Ns = (int64_t)T * op->nP, jsnap = out_snap ? Ns - snap_lag(op->nP) : -1;
     const bool f64 = op->prec == TDP_F64;
     const size_t fb = (f64 ? sizeof(double) : sizeof(float)) * op->N;
-    void *cur = op->u0, *prev = op->u1, *ncur = op->v0, *nprev = op->v1;
+    void *cur = lb.u0, *prev = lb.u1, *ncur = lb.v0, *nprev = lb.v1;
     TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
     TDP_CHECK_HIP(launch_fill_zero(prev, fb, s));
     auto out_for = [&](int64_t j1) -> double * {      // destination of u_{j1}, if any
@@ -633,10 +666,10 @@ static int issue_steps_3d2(tdp_op *op, int T, double rho, int zc, int shape, con
         a.up = prev;
         a.u2out = ncur;
         a.u1out = nprev;
-        a.fa[0] = tab[2 * j];
-        a.fb[0] = tab[2 * j + 1];
-        a.fa[1] = tab[2 * j + 2];
-        a.fb[1] = tab[2 * j + 3];
+        a.fa[0] = tab.a(j);
+        a.fb[0] = tab.b(j);
+        a.fa[1] = tab.a(j + 1);
+        a.fb[1] = tab.b(j + 1);
         a.out1 = out_for(j + 1);
         a.out2 = out_for(j + 2);
         if (f64)
@@ -659,24 +692,25 @@ static int issue_steps_3d2(tdp_op *op, int T, double rho, int zc, int shape, con
         b.F = Fin;
         b.out = out_for(j + 1);
         if (f64)
-            TDP_CHECK_HIP(launch_sweep3d_stream_f64(b, op->st_step, tab[2 * j], tab[2 * j + 1], shape, zc, s));
+            TDP_CHECK_HIP(launch_sweep3d_stream_f64(b, op->st_step, tab.a(j), tab.b(j), shape, zc, s));
         else
-            TDP_CHECK_HIP(launch_sweep3d_stream_f32(b, op->st_step32, (float)tab[2 * j],
-                                                    (float)tab[2 * j + 1], shape, zc, s));
+            TDP_CHECK_HIP(launch_sweep3d_stream_f32(b, op->st_step32, (float)tab.a(j),
+                                                    (float)tab.b(j), shape, zc, s));
     }
     return TDP_OK;
 }
 
 // One step per launch on a real field (kernel 1, or kernel 3 in 3-D),
 // u0/u1 swapped in place.
-static int issue_steps_real1(tdp_op *op, int T, double rho, int kern, int depth, int shape3,
-                             const void *Fin, int tabv, double *out_final, double *out_snap)
+static int issue_steps_real1(tdp_op *op, const LoopBufs &lb, int T, double rho, int kern,
+                             int depth, int shape3, const void *Fin, int tabv, double *out_final,
+                             double *out_snap)
 {
     hipStream_t s = op->stream;
-    const std::vector<double> &tab = forcing_table(op, T, rho, tabv);
+    const ForcingSrc tab = forcing_src(op, T, rho, tabv, lb);
     const int64_t Ns = (int64_t)T * op->nP, jsnap = out_snap ? Ns - snap_lag(op->nP) : -1;
     const size_t fb = (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
-    void *cur = op->u0, *prev = op->u1;
+    void *cur = lb.u0, *prev = lb.u1;
     TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
     TDP_CHECK_HIP(launch_fill_zero(prev, fb, s));
     SweepArgs a;
@@ -690,7 +724,7 @@ static int issue_steps_real1(tdp_op *op, int T, double rho, int kern, int depth,
     for (int64_t j = 0; j < Ns; ++j) {
         a.u = cur;
         a.up = prev;
-        const double fa = tab[2 * j], fbv = tab[2 * j + 1];
+        const double fa = tab.a(j), fbv = tab.b(j);
         a.out = (j + 1 == jsnap) ? out_snap : (j + 1 == Ns ? out_final : nullptr);
         if (kern == 3) {
             if (op->prec == TDP_F64)
@@ -718,19 +752,20 @@ static int issue_steps_real1(tdp_op *op, int T, double rho, int kern, int depth,
 // complex pass.  The cell damping runs I_abd, whose recurrence has real
 // coefficients too: two real passes of the blocked 2-D kernel (tables 0 and
 // 2 again), or the complex field with kernel 1.
-static int issue_steps_loop(tdp_op *op, int T, double rho, int variant, const void *Fin, void *U)
+static int issue_steps_loop(tdp_op *op, const LoopBufs &lb, int T, double rho, int variant,
+                            const void *Fin, void *U)
 {
     int kern, depth, tile;
     sweep_plan(op, variant, &kern, &depth, &tile);
     double *Ud = (double *)U;
     auto real_pass = [&](int tabv, double *fin, double *snap) -> int {
-        if (kern == 2) return issue_steps_tb(op, T, rho, depth, tile, Fin, tabv, fin, snap);
-        if (kern == 4) return issue_steps_3d2(op, T, rho, depth, tile, Fin, tabv, fin, snap);
-        return issue_steps_real1(op, T, rho, kern, depth, tile, Fin, tabv, fin, snap);
+        if (kern == 2) return issue_steps_tb(op, lb, T, rho, depth, tile, Fin, tabv, fin, snap);
+        if (kern == 4) return issue_steps_3d2(op, lb, T, rho, depth, tile, Fin, tabv, fin, snap);
+        return issue_steps_real1(op, lb, T, rho, kern, depth, tile, Fin, tabv, fin, snap);
     };
     if (op->dform == TDP_DAMP_CELL && kern == 2) {
-        TDP_CHECK(issue_steps_tb(op, T, rho, depth, tile, Fin, 0, Ud, nullptr, true));
-        return issue_steps_tb(op, T, rho, depth, tile, Fin, 2, Ud + 1, nullptr, true);
+        TDP_CHECK(issue_steps_tb(op, lb, T, rho, depth, tile, Fin, 0, Ud, nullptr, true));
+        return issue_steps_tb(op, lb, T, rho, depth, tile, Fin, 2, Ud + 1, nullptr, true);
     }
     if (variant == 0) return real_pass(0, Ud, Ud + 1);
     if (op->dform == TDP_DAMP_NODE && kern != 1) {
@@ -780,9 +815,10 @@ static int issue_steps_loop(tdp_op *op, int T, double rho, int variant, const vo
     return TDP_OK;
 }
 
-static int issue_steps(tdp_op *op, int T, double rho, int variant, const void *Fin, void *U)
+static int issue_steps(tdp_op *op, const LoopBufs &lb, int T, double rho, int variant,
+                       const void *Fin, void *U)
 {
-    TDP_CHECK(issue_steps_loop(op, T, rho, variant, Fin, U));
+    TDP_CHECK(issue_steps_loop(op, lb, T, rho, variant, Fin, U));
     if (variant == 0 && op->nP % 4 != 0) {
         const double phi = 2.0 * M_PI * (double)snap_lag(op->nP) / op->nP;
         TDP_CHECK_HIP(launch_phase_extract(U, op->N, std::cos(phi), std::sin(phi), op->stream));
@@ -814,6 +850,7 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
         launches = kern == 2 ? (Ns + depth - 1) / depth : (kern == 4 ? (Ns + 1) / 2 : Ns);
         if (variant == 1 && kern != 1) launches *= 2;     // two real passes
     }
+    const LoopBufs lb{op->u0, op->u1, op->v0, op->v1, false};
     hipStream_t s = op->stream;
     // a graph holds one kernel node per launch: very long loops are issued
     // directly instead of being captured
@@ -823,7 +860,7 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
             TDP_CHECK_HIP(launch_cvt_c128_to_c64(F, op->Fst, op->N, s));
             Fin = op->Fst;
         }
-        return issue_steps(op, T, rho, variant, Fin, U);
+        return issue_steps(op, lb, T, rho, variant, Fin, U);
     }
     // captured loop: on F and U themselves (direct), else reading op->Fstage
     // (F64) / op->Fst (F32) and writing op->Ustage
@@ -843,9 +880,9 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
                 }
             }
             if (rc == TDP_OK)
-                rc = issue_steps(op, T, rho, variant, op->prec == TDP_F64 ? F : op->Fst, U);
+                rc = issue_steps(op, lb, T, rho, variant, op->prec == TDP_F64 ? F : op->Fst, U);
         } else {
-            rc = issue_steps(op, T, rho, variant, op->prec == TDP_F64 ? op->Fstage : op->Fst,
+            rc = issue_steps(op, lb, T, rho, variant, op->prec == TDP_F64 ? op->Fstage : op->Fst,
                              op->Ustage);
         }
         hipError_t ce = hipStreamEndCapture(s, &g);
@@ -877,6 +914,27 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
     TDP_CHECK_HIP(hipGraphLaunch(it->second, s));
     TDP_CHECK_HIP(hipMemcpyAsync(U, op->Ustage, 16 * op->N, hipMemcpyDeviceToDevice, s));
     return TDP_OK;
+}
+
+int precond_noalloc_impl(tdp_op *op, int T, double rho, const void *F, void *U,
+                         const LoopBufs &bufs, void *f32_stage)
+{
+    if (T < 1) TDP_FAIL(TDP_EINVAL, "periods_T must be >= 1");
+    if (rho <= 0.0) rho = 1.0 / T;
+    if (rho > 1.0) TDP_FAIL(TDP_EINVAL, "rho must be <= 1");
+    if (op->dform == TDP_DAMP_CELL)
+        TDP_FAIL(TDP_EINVAL, "Table 1 runs I_acd: with the cell damping use the complex form (S_T^abd)");
+    const int64_t Ns = (int64_t)T * op->nP;
+    if (Ns > TDP_MAX_STEPS)
+        TDP_FAIL(TDP_EINVAL, "N_s = periods_T n_P = %lld exceeds 2^24", (long long)Ns);
+    const void *Fin = F;
+    if (op->prec == TDP_F32) {
+        TDP_CHECK_HIP(launch_cvt_c128_to_c64(F, f32_stage, op->N, op->stream));
+        Fin = f32_stage;
+    }
+    LoopBufs lb = bufs;
+    lb.table_free = true;
+    return issue_steps(op, lb, T, rho, 0, Fin, U);
 }
 
 static int precond_entry(const tdp_op *cop, int T, double rho, int variant, const void *F, void *U)

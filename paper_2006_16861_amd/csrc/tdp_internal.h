@@ -15,6 +15,7 @@
 namespace tdp {
 
 void set_error(const char *fmt, ...);
+void clear_error();
 
 #define TDP_CHECK_HIP(call)                                                              \
     do {                                                                                 \
@@ -70,6 +71,15 @@ __device__ __forceinline__ void stnt(T v, T *p)
     else
         *p = v;
 }
+
+// Recurrence fields of one preconditioner application: the pairs (u0, u1)
+// and, for the kernels that ping-pong (blocked 2-D, two-step 3-D), (v0, v1).
+// table_free: evaluate the forcing scalars step by step instead of reading
+// the op's cached table (the allocation-free entry point).
+struct LoopBufs {
+    void *u0, *u1, *v0, *v1;
+    bool table_free;
+};
 
 // Launch geometry / variant choice for the sweep.
 struct SweepCfg {
@@ -256,10 +266,19 @@ struct tdp_op;
 const std::vector<double> &forcing_table(tdp_op *op, int T, double rho, int variant);
 int64_t snap_lag(int nP);   // Table 1's second sample lies snap_lag(n_P) steps before the end
 int apply_H_impl(const tdp_op *op, const void *x, const void *F, void *y);
+// Table 1 on the fields `bufs` (4 planes of the op's field precision) with
+// F staged in `f32_stage` (N complex64, FP32 fields only), issued launch by
+// launch without graph capture, staging copies or forcing tables.
+int precond_noalloc_impl(tdp_op *op, int T, double rho, const void *F, void *U,
+                         const tdp::LoopBufs &bufs, void *f32_stage);
+// Device scratch of the allocation-free entry point (noalloc.hip): looked up
+// once per device at op creation, with that device current.
+int noalloc_setup_device(int dev);
 
 // The opaque operator.
 struct tdp_op {
     int ndim = 0;
+    int device = 0;          // HIP device current at creation
     int n[3] = {1, 1, 1};
     int64_t N = 0, Nc = 0;
     double h = 0, omega = 0;

@@ -20,7 +20,8 @@ F64, F32 = 0, 1
 DAMPING = {"node": 0, "cell": 1}
 
 SYMBOLS = ("tdp_op_create", "tdp_op_destroy", "tdp_op_query", "tdp_apply_H",
-           "tdp_precond_apply", "tdp_precond_apply_complex", "tdp_gmres_solve", "tdp_grad_m", "tdp_op_set_tuning", "tdp_op_autotune",
+           "tdp_precond_apply", "tdp_precond_apply_complex", "tdp_precond_apply_noalloc",
+           "tdp_gmres_solve", "tdp_grad_m", "tdp_op_set_tuning", "tdp_op_autotune",
            "tdp_op_get_tuning", "tdp_last_error", "tdp_batch_create", "tdp_batch_destroy",
            "tdp_batch_set_tuning", "tdp_batch_precond", "tdp_batch_solve", "tdp_batch_autotune")
 
@@ -100,6 +101,7 @@ def load(path: str = LIB_PATH):
     L.tdp_apply_H.argtypes = [P, P, P]
     L.tdp_precond_apply.argtypes = [P, I, D, P, P]
     L.tdp_precond_apply_complex.argtypes = [P, I, D, P, P]
+    L.tdp_precond_apply_noalloc.argtypes = [P, I, D, P, P]
     L.tdp_gmres_solve.argtypes = [P, ctypes.POINTER(GmresCfg), P, P, ctypes.POINTER(GmresInfo)]
     L.tdp_grad_m.argtypes = [P, P, P, P]
     L.tdp_op_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
@@ -242,6 +244,16 @@ class Operator:
         fn = load().tdp_precond_apply_complex if variant else load().tdp_precond_apply
         _check(fn(self._h, int(T), float(rho), self._cplx(F, "F"), self._cplx(out, "U")),
                "tdp_precond_apply")
+        return out
+
+    def precond_noalloc(self, F, T, rho=0.25, out=None):
+        """Table 1 preconditioner through the allocation-free entry point (the
+        recurrence fields live in the library's static device array)."""
+        import torch
+        out = torch.empty_like(F) if out is None else out
+        _check(load().tdp_precond_apply_noalloc(self._h, int(T), float(rho), self._cplx(F, "F"),
+                                                self._cplx(out, "U")),
+               "tdp_precond_apply_noalloc")
         return out
 
     def solve(self, F, T, rho=0.25, tol=1e-6, restart=30, max_iters=3000, fixed_iters=0,
