@@ -313,7 +313,12 @@ int tdp_op_get_tuning(const tdp_op *op, tdp_tuning *t);
  * solved together.  Field q enumerates (op 0, rhs 0..nrhs[0]-1), (op 1, ...).
  * One batched preconditioner application (Table 1) advances every live field
  * by k steps per launch of the blocked sweep, each with its own medium,
- * forcing table and step count, and is replayed from one hipGraph (at most
+ * forcing table and step count.  The live right-hand sides of one operator
+ * (two or more) go through the shared-medium tile: one workgroup advances a
+ * slab of several of them over one tile, loading the medium (cell slowness,
+ * damping) and folding its stencil coefficients once for the slab, so a
+ * node-step moves 5 + 2/slab words per right-hand side instead of 7.  The
+ * application is replayed from one hipGraph (at most
  * 2^17 launches, i.e. max N_s <= 2^17 k, else TDP_EINVAL); GMRES runs
  * per field in lockstep and takes the same decisions as tdp_gmres_solve.
  * The batch keeps pointers to the ops: they must outlive it.  Ops with the
@@ -323,14 +328,22 @@ typedef struct tdp_batch tdp_batch;
 int tdp_batch_create(tdp_op *const *ops, int nops, const int *nrhs, tdp_batch **out);
 int tdp_batch_destroy(tdp_batch *b);
 
-/* Steps per launch (1..15) and tile shape (as tdp_tuning.tile) of the batched
- * blocked sweep. */
-int tdp_batch_set_tuning(tdp_batch *b, int depth, int tile);
+/* Steps per launch (1..15), tile shape of single fields (as tdp_tuning.tile)
+ * and shared-medium tile of the batched blocked sweep.  medium_tile: -1 runs
+ * every field on its own tile; 0..2 select rows per lane x waves and
+ * right-hand sides per workgroup:
+ *   FP32 fields  0: 4 x 8, 4 (32 x 64 tile)   1: 4 x 16, 4 (64 x 64)   2: 2 x 16, 6 (32 x 64)
+ *   FP64 fields  0: 2 x 16, 3 (32 x 64)       1: 4 x 8, 2 (32 x 64)    2: 2 x 16, 2 (32 x 64)
+ * Default: depth 8, tile 8 (FP32) or 4 (FP64), medium tile 0.  4 x depth
+ * must not exceed either tile's rows (else TDP_EINVAL). */
+int tdp_batch_set_tuning(tdp_batch *b, int depth, int tile, int medium_tile);
 
 /* Autotuner of the batched sweep: times one batched application for every
- * tile shape x depth (4, 6, 8) and keeps the fastest.  table (host, may be
- * NULL) receives up to cap rows {depth, tile, milliseconds per application}.
- * Returns the number of candidates timed or a negative error. */
+ * depth (4, 6, 8) x single-field tile shape, then every shared-medium tile
+ * (and none) with that depth's best single-field tile, and keeps the
+ * fastest.  table (host, may be NULL) receives up to cap rows {depth, tile,
+ * medium_tile, milliseconds per application}.  Returns the number of
+ * candidates timed or a negative error. */
 int tdp_batch_autotune(tdp_batch *b, const int *periods_T, double rho, double *table, int cap);
 
 /* U[q] = S_T F[q] for every field (Table 1).  periods_T: host [nops];

@@ -1,8 +1,11 @@
 // Batched form: many right-hand sides on one medium and many independent 2-D
 // problems of uneven sizes advanced together.  Every k-step launch of the
-// batched blocked sweep covers all live fields (each with its own medium,
-// stencil constants, forcing table, step count and output), the whole step
-// schedule of one preconditioner application is captured in one hipGraph,
+// batched blocked sweeps covers all live fields (each with its own medium,
+// stencil constants, forcing table, step count and output): the live
+// right-hand sides of a medium go in slabs of several per workgroup through
+// the shared-medium tile (the medium is loaded and folded once per slab),
+// single fields through the per-field tile.  The whole step schedule of one
+// preconditioner application is captured in one hipGraph,
 // and restarted GMRES (Sec. 2.4) runs for every field in lockstep: one
 // batched preconditioner application per round, with each field following
 // exactly the decision sequence of a single solve.
@@ -52,6 +55,7 @@ struct tdp_batch {
     bool f64 = true, general = false;
     hipStream_t s = nullptr;
     int K = 8, shape = 1;
+    int mshape = 0;               // shared-medium tile (-1: every field on its own tile)
     // device copies of per-op forcing tables, keyed by (op, T, rho)
     std::map<std::tuple<int, int, double>, double *> dtab;
     void *dfields = nullptr;      // BFieldT<T>[] for the current (T, rho) set
@@ -135,15 +139,20 @@ extern "C" int tdp_batch_create(tdp_op *const *ops, int nops, const int *nrhs, t
     return TDP_OK;
 }
 
-extern "C" int tdp_batch_set_tuning(tdp_batch *b, int depth, int tile)
+extern "C" int tdp_batch_set_tuning(tdp_batch *b, int depth, int tile, int medium_tile)
 {
     if (!b) TDP_BFAIL(TDP_EINVAL, "NULL batch");
     if (depth < 1 || depth > 15) TDP_BFAIL(TDP_EINVAL, "depth must be in [1, 15]");
     if (tile < 0 || tile > 8 || ((tile == 2 || tile == 8) && b->f64)) TDP_BFAIL(TDP_EINVAL, "bad tile");
     const int rows = tb2d_tile_rows(tile, b->f64);
     if (4 * depth > rows) TDP_BFAIL(TDP_EINVAL, "depth too large for the tile");
+    if (medium_tile < -1 || (medium_tile >= 0 && mrhs_nr(medium_tile, b->f64) == 0))
+        TDP_BFAIL(TDP_EINVAL, "bad shared-medium tile");
+    if (medium_tile >= 0 && 4 * depth > mrhs_rows(medium_tile, b->f64))
+        TDP_BFAIL(TDP_EINVAL, "depth too large for the shared-medium tile");
     b->K = depth;
     b->shape = tile;
+    b->mshape = medium_tile;
     return TDP_OK;
 }
 
@@ -226,7 +235,8 @@ static int batch_precond(tdp_batch *b, const int *T_op, double rho, const std::v
         b->rho_key = rho;
     }
     std::string key(active.begin(), active.end());
-    key += "|" + std::to_string(b->K) + "|" + std::to_string(b->shape);
+    key += "|" + std::to_string(b->K) + "|" + std::to_string(b->shape) + "|" +
+           std::to_string(b->mshape);
     auto it = b->graphs.find(key);
     if (it == b->graphs.end()) {
         // schedule: launch L advances every active field with N_s > L*K
@@ -241,22 +251,52 @@ static int batch_precond(tdp_batch *b, const int *T_op, double rho, const std::v
         const int nl = (maxNs + b->K - 1) / b->K;
         if (nl > TDP_MAX_GRAPH_LAUNCHES)     // the application is one captured graph
             TDP_BFAIL(TDP_EINVAL, "%d launches per batched application exceed 2^17 (lower periods_T)", nl);
-        std::vector<int> host;       // per launch: list then prefix
-        std::vector<std::tuple<int, int, int, int>> launches;   // (list off, prefix off, n, tiles)
+        // per launch: the single fields (list + tile prefix) and the slabs of
+        // right-hand sides sharing a medium (NR field indices each + prefix)
+        struct Sched { int lo, po, n, tiles, so, sp, ns, stiles; };
+        const int NR = b->mshape >= 0 ? mrhs_nr(b->mshape, b->f64) : 0;
+        std::vector<int> host;
+        std::vector<Sched> launches;
         for (int L = 0; L < nl; ++L) {
-            std::vector<int> list, pre{0};
+            std::map<int, std::vector<int>> byop;     // live fields of each medium
             for (int q : act) {
                 const tdp_op *op = b->ops[b->f[q].op];
-                if (T_op[b->f[q].op] * op->nP > L * b->K) {
-                    list.push_back(q);
-                    pre.push_back(pre.back() + tb2d_tiles(b->shape, b->K, op->n[0], op->n[1]));
+                if (T_op[b->f[q].op] * op->nP > L * b->K) byop[b->f[q].op].push_back(q);
+            }
+            std::vector<int> list, pre{0}, slabs, spre{0};
+            for (const auto &kv : byop) {
+                const tdp_op *op = b->ops[kv.first];
+                const std::vector<int> &qs = kv.second;
+                if (NR >= 2 && qs.size() >= 2) {
+                    const int et = mrhs_rows(b->mshape, b->f64);
+                    const int OX = 64 - 2 * b->K, OY = et - 2 * b->K;
+                    const int tiles = ((op->n[1] + OX - 1) / OX) * ((op->n[0] + OY - 1) / OY);
+                    for (size_t a = 0; a < qs.size(); a += NR) {
+                        for (int r = 0; r < NR; ++r)
+                            slabs.push_back(a + r < qs.size() ? qs[a + r] : -1);
+                        spre.push_back(spre.back() + tiles);
+                    }
+                } else {
+                    for (int q : qs) {
+                        list.push_back(q);
+                        pre.push_back(pre.back() + tb2d_tiles(b->shape, b->K, op->n[0], op->n[1]));
+                    }
                 }
             }
-            const int lo = (int)host.size();
+            Sched sc;
+            sc.lo = (int)host.size();
             host.insert(host.end(), list.begin(), list.end());
-            const int po = (int)host.size();
+            sc.po = (int)host.size();
             host.insert(host.end(), pre.begin(), pre.end());
-            launches.emplace_back(lo, po, (int)list.size(), pre.back());
+            sc.n = (int)list.size();
+            sc.tiles = pre.back();
+            sc.so = (int)host.size();
+            host.insert(host.end(), slabs.begin(), slabs.end());
+            sc.sp = (int)host.size();
+            host.insert(host.end(), spre.begin(), spre.end());
+            sc.ns = (int)spre.size() - 1;
+            sc.stiles = spre.back();
+            launches.push_back(sc);
         }
         int *dsched = nullptr;
         if (hipMalloc(&dsched, sizeof(int) * std::max<size_t>(1, host.size())) != hipSuccess)
@@ -275,18 +315,35 @@ static int batch_precond(tdp_batch *b, const int *T_op, double rho, const std::v
             if (le == hipSuccess) le = launch_fill_zero(fl.a1, es * fl.N, s);
         }
         for (int L = 0; L < nl && le == hipSuccess; ++L) {
-            TBBatchLaunch bl;
-            bl.fields = b->dfields;
-            bl.list = dsched + std::get<0>(launches[L]);
-            bl.prefix = dsched + std::get<1>(launches[L]);
-            bl.nlist = std::get<2>(launches[L]);
-            bl.ntiles = std::get<3>(launches[L]);
-            bl.j0 = L * b->K;
-            bl.K = b->K;
-            bl.parity = L & 1;
-            bl.shape = b->shape;
-            bl.general = b->general;
-            le = launch_sweep2d_tb_batch(bl, b->f64, s);
+            const Sched &sc = launches[L];
+            if (sc.n > 0) {
+                TBBatchLaunch bl;
+                bl.fields = b->dfields;
+                bl.list = dsched + sc.lo;
+                bl.prefix = dsched + sc.po;
+                bl.nlist = sc.n;
+                bl.ntiles = sc.tiles;
+                bl.j0 = L * b->K;
+                bl.K = b->K;
+                bl.parity = L & 1;
+                bl.shape = b->shape;
+                bl.general = b->general;
+                le = launch_sweep2d_tb_batch(bl, b->f64, s);
+            }
+            if (sc.ns > 0 && le == hipSuccess) {
+                TBMrhsLaunch ml;
+                ml.fields = b->dfields;
+                ml.slabs = dsched + sc.so;
+                ml.prefix = dsched + sc.sp;
+                ml.nslab = sc.ns;
+                ml.ntiles = sc.stiles;
+                ml.j0 = L * b->K;
+                ml.K = b->K;
+                ml.parity = L & 1;
+                ml.shape = b->mshape;
+                ml.general = b->general;
+                le = launch_sweep2d_tb_mrhs(ml, b->f64, s);
+            }
         }
         // Table 1 with 4 not dividing n_P: Im U from the two samples (2x2 solve)
         for (int q : act) {
@@ -347,7 +404,9 @@ extern "C" int tdp_batch_precond(tdp_batch *b, const int *periods_T, double rho,
 }
 
 // Autotuner of the batched sweep: times one batched application (periods_T
-// per op) for every tile shape x depth, keeps the fastest.
+// per op) for every depth x per-field tile shape (with the current
+// shared-medium tile), then for every shared-medium tile (and none) with
+// that depth's best per-field tile; keeps the fastest.
 extern "C" int tdp_batch_autotune(tdp_batch *b, const int *periods_T, double rho, double *table,
                                   int cap)
 {
@@ -357,43 +416,63 @@ extern "C" int tdp_batch_autotune(tdp_batch *b, const int *periods_T, double rho
     StreamJoin join(b->ops[0]->user_stream, b->s, b->ops[0]->ev);
     std::vector<char> active(b->f.size(), 1);
     for (auto &fl : b->f) TDP_CHECK_HIP(launch_fill_zero(fl.pin, 16 * fl.N, b->s));
-    const int K0 = b->K, S0 = b->shape;
+    const int K0 = b->K, S0 = b->shape, M0 = b->mshape;
     double best = INFINITY;
-    int bk = K0, bs = S0, n = 0;
+    int bk = K0, bs = S0, bm = M0, n = 0;
     hipEvent_t e0, e1;
     TDP_CHECK_HIP(hipEventCreate(&e0));
     TDP_CHECK_HIP(hipEventCreate(&e1));
     int rc = TDP_OK;
-    for (int shape = 0; shape < 9 && rc == TDP_OK; ++shape) {
-        if ((shape == 2 || shape == 8) && b->f64) continue;
-        const int rows = tb2d_tile_rows(shape, b->f64);
-        for (int K : {4, 6, 8}) {
-            if (4 * K > rows) continue;
-            b->K = K;
-            b->shape = shape;
-            rc = batch_precond(b, periods_T, rho, active);   // capture + warm
-            if (rc != TDP_OK) break;
-            float ms = 0.f;
-            if (hipEventRecord(e0, b->s) != hipSuccess) { rc = TDP_EHIP; break; }
-            for (int r = 0; r < 2 && rc == TDP_OK; ++r) rc = batch_precond(b, periods_T, rho, active);
-            if (rc != TDP_OK) break;
-            if (hipEventRecord(e1, b->s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                rc = TDP_EHIP;
-                break;
-            }
-            if (table && n < cap) {
-                table[3 * n] = K;
-                table[3 * n + 1] = shape;
-                table[3 * n + 2] = ms / 2;
-            }
-            ++n;
-            if (ms < best) {
-                best = ms;
-                bk = K;
-                bs = shape;
+    // one candidate: capture + warm, then two timed applications
+    auto trial = [&](int K, int shape, int mshape, double *out_ms) -> int {
+        b->K = K;
+        b->shape = shape;
+        b->mshape = mshape;
+        int r = batch_precond(b, periods_T, rho, active);
+        if (r != TDP_OK) return r;
+        float ms = 0.f;
+        if (hipEventRecord(e0, b->s) != hipSuccess) return TDP_EHIP;
+        for (int i = 0; i < 2 && r == TDP_OK; ++i) r = batch_precond(b, periods_T, rho, active);
+        if (r != TDP_OK) return r;
+        if (hipEventRecord(e1, b->s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return TDP_EHIP;
+        *out_ms = ms / 2;
+        if (table && n < cap) {
+            table[4 * n] = K;
+            table[4 * n + 1] = shape;
+            table[4 * n + 2] = mshape;
+            table[4 * n + 3] = ms / 2;
+        }
+        ++n;
+        if (*out_ms < best) {
+            best = *out_ms;
+            bk = K;
+            bs = shape;
+            bm = mshape;
+        }
+        return TDP_OK;
+    };
+    for (int K : {4, 6, 8}) {
+        const int mcur = (M0 >= 0 && 4 * K <= mrhs_rows(M0, b->f64)) ? M0 : -1;
+        double kbest = INFINITY;
+        int kshape = -1;
+        for (int shape = 0; shape < 9 && rc == TDP_OK; ++shape) {
+            if ((shape == 2 || shape == 8) && b->f64) continue;
+            if (4 * K > tb2d_tile_rows(shape, b->f64)) continue;
+            double ms = INFINITY;
+            rc = trial(K, shape, mcur, &ms);
+            if (rc == TDP_OK && ms < kbest) {
+                kbest = ms;
+                kshape = shape;
             }
         }
+        for (int ms_ = -1; ms_ < 3 && rc == TDP_OK && kshape >= 0; ++ms_) {
+            if (ms_ == mcur || (ms_ >= 0 && 4 * K > mrhs_rows(ms_, b->f64))) continue;
+            double ms = INFINITY;
+            rc = trial(K, kshape, ms_, &ms);
+        }
+        if (rc != TDP_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -410,10 +489,12 @@ extern "C" int tdp_batch_autotune(tdp_batch *b, const int *periods_T, double rho
     if (rc != TDP_OK) {
         b->K = K0;
         b->shape = S0;
+        b->mshape = M0;
         return rc;
     }
     b->K = bk;
     b->shape = bs;
+    b->mshape = bm;
     return n;
 }
 

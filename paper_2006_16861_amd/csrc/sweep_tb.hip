@@ -24,19 +24,9 @@
 #include <hip/hip_runtime.h>
 
 #include "tdp_internal.h"
+#include "lanes.h"
 
 namespace tdp {
-
-template <typename T>
-struct V2t;
-template <>
-struct V2t<double> {
-    using type = double2;
-};
-template <>
-struct V2t<float> {
-    using type = float2;
-};
 
 // assembled 9-point stencil from LDS (same formula as eval_stencil in
 // kernels.hip, specialised to 2-D): uc(r, e) is the field at tile row r,
@@ -166,41 +156,6 @@ __device__ __forceinline__ void tb_tile(T *__restrict__ ul, T *__restrict__ cl,
     }
 }
 
-// Cross-lane neighbours of a row held one node per lane (lane = tile column):
-// the value of the lane to the left (x-1) or right (x+1), 0 past the wave's
-// ends, which is the tile's zero pad.  DPP wave shifts by one lane (VALU
-// moves; no LDS traffic).
-__device__ __forceinline__ int dpp_from_left(int v)
-{
-    return __builtin_amdgcn_update_dpp(0, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
-}
-__device__ __forceinline__ int dpp_from_right(int v)
-{
-    return __builtin_amdgcn_update_dpp(0, v, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
-}
-__device__ __forceinline__ float lane_west(float v)
-{
-    return __int_as_float(dpp_from_left(__float_as_int(v)));
-}
-__device__ __forceinline__ float lane_east(float v)
-{
-    return __int_as_float(dpp_from_right(__float_as_int(v)));
-}
-__device__ __forceinline__ double lane_west(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const unsigned lo = (unsigned)dpp_from_left((int)b);
-    const unsigned hi = (unsigned)dpp_from_left((int)(b >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-__device__ __forceinline__ double lane_east(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const unsigned lo = (unsigned)dpp_from_right((int)b);
-    const unsigned hi = (unsigned)dpp_from_right((int)(b >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 // Second form of the tile update: the cell-mass sums do not change in time,
 // so each lane folds them once per launch into per-node stencil coefficients
 // held in registers (centre, W, E, S, N; the corners too when they are not
@@ -217,11 +172,36 @@ __device__ __forceinline__ double lane_east(double v)
 // wave whose rows all lie outside that window skips the step (its stale rows
 // are never read again).  The exact-region, Dirichlet and output rules are
 // those of tb_tile.
-template <typename T, int SC, int MC, int R, int NCO, int US>
+// Per-node coefficients of the step from the four cells around a node (SW,
+// SE, NW, NE) and its damping factor dd: centre, W, E, S, N, then the corner
+// weights (four with corner mass terms, one shared weight without).
+template <typename T, int SC, int MC, int NCO>
+__device__ __forceinline__ void fold_node(const Stencil<T> &st, T dd, T mSW, T mSE, T mNW, T mNE,
+                                          T (&c)[NCO])
+{
+    c[0] = dd * (st.c0 + st.m[0] * ((mSW + mSE) + (mNW + mNE)));
+    c[1] = dd * (st.s[1] + st.m[1] * (mSW + mNW));   // W
+    c[2] = dd * (st.s[1] + st.m[1] * (mSE + mNE));   // E
+    c[3] = dd * (st.s[1] + st.m[1] * (mSW + mSE));   // S
+    c[4] = dd * (st.s[1] + st.m[1] * (mNW + mNE));   // N
+    if (MC > 2) {
+        c[5] = dd * (st.s[2] + st.m[2] * mSW);
+        c[6] = dd * (st.s[2] + st.m[2] * mSE);
+        c[7] = dd * (st.s[2] + st.m[2] * mNW);
+        c[8] = dd * (st.s[2] + st.m[2] * mNE);
+    } else if (SC > 2) {
+        c[5] = dd * st.s[2];   // the four corners share one weight
+    }
+}
+
+// cur[rs - 1 .. rs + 1] and cur[rn - 1 .. rn + 1] hold the halo rows south
+// and north of the wave's rows at x-1, x, x+1; the wave's first and last new
+// rows go to nxt[wf] and nxt[wl].
+template <typename T, int SC, int MC, int R, int NCO>
 __device__ __forceinline__ void tb2_step(const T *__restrict__ cur, T *__restrict__ nxt, int rs,
-                                         int rn, const T (&co)[R][NCO], const T (&fr)[R],
-                                         const T (&fi)[R], const T (&e)[R], const T (&a)[R],
-                                         T (&b)[R], T fas, T fbs)
+                                         int rn, int wf, int wl, const T (&co)[R][NCO],
+                                         const T (&fr)[R], const T (&fi)[R], const T (&e)[R],
+                                         const T (&a)[R], T (&b)[R], T fas, T fbs)
 {
     constexpr bool CORNER = MC > 2 || SC > 2;
     // rows r0-1 .. r0+R at x-1, x, x+1: the two halo rows from LDS, the own
@@ -260,8 +240,8 @@ __device__ __forceinline__ void tb2_step(const T *__restrict__ cur, T *__restric
         b[i] = acc + e[i] * b[i];
     }
     // the wave's first and last rows for its neighbours' next step
-    nxt[rs + US] = b[0];
-    nxt[rn - US] = b[R - 1];
+    nxt[wf] = b[0];
+    nxt[wl] = b[R - 1];
 }
 
 template <typename T, int SC, int MC, int R, int W>
@@ -319,24 +299,10 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
         }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const T mSW = ca[i], mSE = cb[i], mNW = ca[i + 1], mNE = cb[i + 1];
-            const T dd = d[i];
-            co[i][0] = dd * (st.c0 + st.m[0] * ((mSW + mSE) + (mNW + mNE)));
-            co[i][1] = dd * (st.s[1] + st.m[1] * (mSW + mNW));   // W
-            co[i][2] = dd * (st.s[1] + st.m[1] * (mSE + mNE));   // E
-            co[i][3] = dd * (st.s[1] + st.m[1] * (mSW + mSE));   // S
-            co[i][4] = dd * (st.s[1] + st.m[1] * (mNW + mNE));   // N
-            if (MC > 2) {
-                co[i][5] = dd * (st.s[2] + st.m[2] * mSW);
-                co[i][6] = dd * (st.s[2] + st.m[2] * mSE);
-                co[i][7] = dd * (st.s[2] + st.m[2] * mNW);
-                co[i][8] = dd * (st.s[2] + st.m[2] * mNE);
-            } else if (SC > 2) {
-                co[i][5] = dd * st.s[2];   // the four corners share one weight
-            }
-            fr[i] *= dd;
-            fi[i] *= dd;
-            e[i] = T(1) - T(2) * dd;
+            fold_node<T, SC, MC, NCO>(st, d[i], ca[i], cb[i], ca[i + 1], cb[i + 1], co[i]);
+            fr[i] *= d[i];
+            fi[i] *= d[i];
+            e[i] = T(1) - T(2) * d[i];
         }
     }
     // LDS copy c holds, at row r+1, tile row r of level c (mod 2) for the
@@ -373,15 +339,15 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
     auto active = [&](int s) { return r0 + R > s + 1 && r0 < EY - 1 - s; };
     for (int s = 0; s < k; s += 2) {
         if (active(s)) {
-            tb2_step<T, SC, MC, R, NCO, US>(ul, ul + UB, rs, rn, co, fr, fi, e, u0, u1,
-                                        (T)fa[s * fstride], (T)fb[s * fstride]);
+            tb2_step<T, SC, MC, R, NCO>(ul, ul + UB, rs, rn, rs + US, rn - US, co, fr, fi, e, u0,
+                                        u1, (T)fa[s * fstride], (T)fb[s * fstride]);
             snapshot(s, u1);
         }
         __syncthreads();
         if (s + 1 == k) break;
         if (active(s + 1)) {
-            tb2_step<T, SC, MC, R, NCO, US>(ul + UB, ul, rs, rn, co, fr, fi, e, u1, u0,
-                                        (T)fa[(s + 1) * fstride], (T)fb[(s + 1) * fstride]);
+            tb2_step<T, SC, MC, R, NCO>(ul + UB, ul, rs, rn, rs + US, rn - US, co, fr, fi, e, u1,
+                                        u0, (T)fa[(s + 1) * fstride], (T)fb[(s + 1) * fstride]);
             snapshot(s + 1, u0);
         }
         __syncthreads();
@@ -486,6 +452,194 @@ void k_sweep2d_tb_batch(
                                  (const typename V2t<T>::type *)f.F, f.ny, f.nx, f.st, k, K,
                                  ty * OY - K, tx * OX - K, f.tab + 2 * j0, f.tab + 2 * j0 + 1, 2,
                                  out_step, out);
+}
+
+// Shared-medium form of the batched tile: one workgroup advances up to NR
+// right-hand sides of one medium over the same extended tile.  The medium's
+// per-node coefficients (cell slowness and damping factor) are loaded and
+// folded once for all of them; each right-hand side keeps its own u_j,
+// u_{j-1} and d-scaled F in registers, and the NR updates of a node are
+// independent FMA chains with the same coefficients.  Each wave passes only
+// its first and last rows through LDS, packed per right-hand side as 2W + 2
+// rows per copy (wave w writes slots 2w + 1 and 2w + 2 and reads slots 2w and
+// 2w + 3; slots 0 and 2W + 1 and the end columns are the zero pad).
+template <typename T, int SC, int MC, int R, int W, int NR>
+__device__ __forceinline__ void tb_tile_mrhs(T *__restrict__ xl, const BFieldT<T> *__restrict__ fields,
+                                             const int *__restrict__ slab, int k, int halo,
+                                             int gy0, int gx0, int j0, int parity)
+{
+    constexpr int EX = 64, EY = R * W;
+    constexpr int US = EX + 2;
+    constexpr int CB = (2 * W + 2) * US;      // one copy of one right-hand side
+    constexpr int NCO = MC > 2 ? 9 : (SC > 2 ? 6 : 5);
+    const BFieldT<T> &f0 = fields[slab[0]];
+    const int ny = f0.ny, nx = f0.nx;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r0 = wv * R;
+    const int gx = gx0 + lane;
+    const bool xin = (unsigned)gx < (unsigned)nx;
+    int nr = 0;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) nr += slab[q] >= 0 ? 1 : 0;
+
+    T co[R][NCO], e[R];
+    T fr[NR][R], fi[NR][R];
+    T u0[NR][R], u1[NR][R];
+    {
+        T ca[R + 1], cb[R + 1], d[R];
+#pragma unroll
+        for (int i = 0; i <= R; ++i) {
+            const int sy = gy0 + r0 + i;
+            const bool rok = (unsigned)sy <= (unsigned)ny;
+            const T *mrow = f0.m + (int64_t)sy * (nx + 1);
+            ca[i] = (rok && (unsigned)gx <= (unsigned)nx) ? mrow[gx] : T(0);
+            cb[i] = (rok && (unsigned)(gx + 1) <= (unsigned)nx) ? mrow[gx + 1] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int gy = gy0 + r0 + i;
+            d[i] = (xin && (unsigned)gy < (unsigned)ny) ? (f0.dn + (int64_t)gy * nx)[gx] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const BFieldT<T> &f = fields[slab[q >= nr ? 0 : q]];
+            const T *u_in = parity ? f.b0 : f.a0, *up_in = parity ? f.b1 : f.a1;
+            const auto *F = (const typename V2t<T>::type *)f.F;
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int gy = gy0 + r0 + i;
+                const bool in = q < nr && xin && (unsigned)gy < (unsigned)ny;
+                const int64_t row = (int64_t)gy * nx;
+                u0[q][i] = u1[q][i] = fr[q][i] = fi[q][i] = T(0);
+                if (in) {
+                    u0[q][i] = (u_in + row)[gx];
+                    u1[q][i] = (up_in + row)[gx];
+                    const auto fv = (F + row)[gx];
+                    fr[q][i] = fv.x;
+                    fi[q][i] = fv.y;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            fold_node<T, SC, MC, NCO>(f0.st, d[i], ca[i], cb[i], ca[i + 1], cb[i + 1], co[i]);
+            e[i] = T(1) - T(2) * d[i];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                fr[q][i] *= d[i];
+                fi[q][i] *= d[i];
+            }
+        }
+    }
+    for (int t = threadIdx.x; t < NR * 2 * CB; t += 64 * W) xl[t] = T(0);
+    __syncthreads();
+    const int rs = 2 * wv * US + lane + 1, rn = (2 * wv + 3) * US + lane + 1;
+    const int wf = (2 * wv + 1) * US + lane + 1, wl = (2 * wv + 2) * US + lane + 1;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        xl[2 * q * CB + wf] = u0[q][0];
+        xl[2 * q * CB + wl] = u0[q][R - 1];
+    }
+    __syncthreads();
+
+    const bool xout = lane >= halo && lane < EX - halo && xin;
+    const int out_snap = (f0.jsnap > j0 && f0.jsnap <= j0 + k) ? f0.jsnap - j0 : 0;
+    const int out_fin = (f0.Ns > j0 && f0.Ns <= j0 + k) ? f0.Ns - j0 : 0;
+    auto snapshot = [&](int s, int q, const T(&v)[R]) {
+        if (q < nr && (s + 1 == out_snap || s + 1 == out_fin)) {
+            double *o = fields[slab[q]].U + (s + 1 == out_snap ? 1 : 0);
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int r = r0 + i;
+                const int gy = gy0 + r;
+                if (r >= halo && r < EY - halo && (unsigned)gy < (unsigned)ny && xout)
+                    (o + 2 * (int64_t)gy * nx)[2 * gx] = (double)v[i];
+            }
+        }
+    };
+    auto active = [&](int s) { return r0 + R > s + 1 && r0 < EY - 1 - s; };
+    const double *tab = f0.tab + 2 * j0;
+    for (int s = 0; s < k; s += 2) {
+        if (active(s)) {
+            const T fas = (T)tab[2 * s], fbs = (T)tab[2 * s + 1];
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                if (q < nr) {
+                    tb2_step<T, SC, MC, R, NCO>(xl + 2 * q * CB, xl + (2 * q + 1) * CB, rs, rn, wf,
+                                                wl, co, fr[q], fi[q], e, u0[q], u1[q], fas, fbs);
+                    snapshot(s, q, u1[q]);
+                }
+        }
+        __syncthreads();
+        if (s + 1 == k) break;
+        if (active(s + 1)) {
+            const T fas = (T)tab[2 * s + 2], fbs = (T)tab[2 * s + 3];
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                if (q < nr) {
+                    tb2_step<T, SC, MC, R, NCO>(xl + (2 * q + 1) * CB, xl + 2 * q * CB, rs, rn, wf,
+                                                wl, co, fr[q], fi[q], e, u1[q], u0[q], fas, fbs);
+                    snapshot(s + 1, q, u0[q]);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        if (q >= nr) continue;
+        const BFieldT<T> &f = fields[slab[q]];
+        T *u_out = parity ? f.a0 : f.b0, *up_out = parity ? f.a1 : f.b1;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = r0 + i;
+            const int gy = gy0 + r;
+            if (r >= halo && r < EY - halo && (unsigned)gy < (unsigned)ny && xout) {
+                const int64_t row = (int64_t)gy * nx;
+                (u_out + row)[gx] = (k & 1) ? u1[q][i] : u0[q][i];
+                (up_out + row)[gx] = (k & 1) ? u0[q][i] : u1[q][i];
+            }
+        }
+    }
+}
+
+// One launch advances every slab of the work list by up to K steps:
+// workgroup -> (slab, tile) through the per-launch tile prefix sums; a slab
+// lists up to NR fields of one medium (-1 past its end).
+// Register budget: 1024-thread workgroups need four waves per SIMD (128
+// VGPRs); 512-thread ones ask for the same when their per-node state is
+// small (two workgroups per CU), else for two waves per SIMD (256 VGPRs).
+template <typename T, int R, int W, int NR>
+constexpr int mrhs_waves_per_eu()
+{
+    return (W >= 16 || R * (7 + 4 * NR) * (int)sizeof(T) / 4 <= 100) ? 4 : 2;
+}
+
+template <typename T, int SC, int MC, int R, int W, int NR>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(mrhs_waves_per_eu<T, R, W, NR>())))
+void k_sweep2d_tb_mrhs(const BFieldT<T> *__restrict__ fields, const int *__restrict__ slabs,
+                       const int *__restrict__ prefix, int nslab, int j0, int K, int parity,
+                       int ntiles, int per_xcd)
+{
+    constexpr int EX = 64, EY = R * W;
+    __shared__ T xl[NR * 2 * (2 * W + 2) * (EX + 2)];
+    const int id = blockIdx.x;
+    const int tile = (id % 8) * per_xcd + id / 8;
+    if (tile >= ntiles) return;
+    int lo = 0, hi = nslab;            // prefix[lo] <= tile < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= tile) lo = mid;
+        else hi = mid;
+    }
+    const int *slab = slabs + NR * lo;
+    const BFieldT<T> &f = fields[slab[0]];
+    const int t = tile - prefix[lo];
+    const int OX = EX - 2 * K, OY = EY - 2 * K;
+    const int tiles_x = (f.nx + OX - 1) / OX;
+    const int ty = t / tiles_x, tx = t % tiles_x;
+    const int k = min(K, f.Ns - j0);
+    tb_tile_mrhs<T, SC, MC, R, W, NR>(xl, fields, slab, k, K, ty * OY - K, tx * OX - K, j0, parity);
 }
 
 // Frequency-adapted backward-differences damped leapfrog I_abd (Sec. 6) with
@@ -815,6 +969,55 @@ hipError_t launch_sweep2d_tb_batch(const TBBatchLaunch &L, bool f64, hipStream_t
     case 8: return launch_tb_batch_t<float, 8, 16>(L, s);
     default: return launch_tb_batch_t<float, 8, 8>(L, s);
     }
+}
+
+template <typename T, int R, int W, int NR>
+static hipError_t launch_tb_mrhs_t(const TBMrhsLaunch &L, hipStream_t s)
+{
+    const int per_xcd = (L.ntiles + 7) / 8;
+    dim3 grd(8 * per_xcd), blk(64 * W);
+    const BFieldT<T> *f = (const BFieldT<T> *)L.fields;
+    if (L.general)
+        hipLaunchKernelGGL((k_sweep2d_tb_mrhs<T, 3, 3, R, W, NR>), grd, blk, 0, s, f, L.slabs,
+                           L.prefix, L.nslab, L.j0, L.K, L.parity, L.ntiles, per_xcd);
+    else
+        hipLaunchKernelGGL((k_sweep2d_tb_mrhs<T, 3, 2, R, W, NR>), grd, blk, 0, s, f, L.slabs,
+                           L.prefix, L.nslab, L.j0, L.K, L.parity, L.ntiles, per_xcd);
+    return hipGetLastError();
+}
+
+// Shared-medium tiles (rows per lane R x waves W, right-hand sides per
+// workgroup NR; 64 columns):
+//   FP32  0: 4 x 8, NR 4 (32 x 64)    1: 4 x 16, NR 4 (64 x 64)    2: 2 x 16, NR 6 (32 x 64)
+//   FP64  0: 2 x 16, NR 3 (32 x 64)   1: 4 x 8, NR 2 (32 x 64)     2: 2 x 16, NR 2 (32 x 64)
+hipError_t launch_sweep2d_tb_mrhs(const TBMrhsLaunch &L, bool f64, hipStream_t s)
+{
+    if (f64) {
+        switch (L.shape) {
+        case 0: return launch_tb_mrhs_t<double, 2, 16, 3>(L, s);
+        case 1: return launch_tb_mrhs_t<double, 4, 8, 2>(L, s);
+        case 2: return launch_tb_mrhs_t<double, 2, 16, 2>(L, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (L.shape) {
+    case 0: return launch_tb_mrhs_t<float, 4, 8, 4>(L, s);
+    case 1: return launch_tb_mrhs_t<float, 4, 16, 4>(L, s);
+    case 2: return launch_tb_mrhs_t<float, 2, 16, 6>(L, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int mrhs_nr(int shape, bool f64)
+{
+    static const int nr32[3] = {4, 4, 6}, nr64[3] = {3, 2, 2};
+    return (shape < 0 || shape > 2) ? 0 : (f64 ? nr64[shape] : nr32[shape]);
+}
+
+int mrhs_rows(int shape, bool f64)
+{
+    static const int r32[3] = {32, 64, 32}, r64[3] = {32, 32, 32};
+    return (shape < 0 || shape > 2) ? 0 : (f64 ? r64[shape] : r32[shape]);
 }
 
 int tb2d_tiles(int shape, int K, int ny, int nx)

@@ -149,6 +149,18 @@ struct TBBatchLaunch {
     bool general;               // class pattern (3,3) instead of (3,2)
 };
 hipError_t launch_sweep2d_tb_batch(const TBBatchLaunch &L, bool f64, hipStream_t s);
+// Shared-medium batched tile: workgroup -> (slab, tile); a slab lists up to
+// mrhs_nr(shape) fields of one medium (-1 past its end), nslab x NR ints.
+struct TBMrhsLaunch {
+    const void *fields;         // device BFieldT<T>[]
+    const int *slabs;           // device: nslab x NR field indices
+    const int *prefix;          // device: tile prefix sums, nslab + 1 entries
+    int nslab, j0, K, parity, ntiles, shape;
+    bool general;
+};
+hipError_t launch_sweep2d_tb_mrhs(const TBMrhsLaunch &L, bool f64, hipStream_t s);
+int mrhs_nr(int shape, bool f64);     // right-hand sides per workgroup (0: no such shape)
+int mrhs_rows(int shape, bool f64);   // extended tile rows
 int tb2d_tiles(int shape, int K, int ny, int nx);
 
 hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hipStream_t s);

@@ -109,7 +109,7 @@ def load(path: str = LIB_PATH):
     L.tdp_op_autotune.argtypes = [P, I, D, I, ctypes.POINTER(Tuning), P, I]
     L.tdp_batch_create.argtypes = [P, I, P, ctypes.POINTER(P)]
     L.tdp_batch_destroy.argtypes = [P]
-    L.tdp_batch_set_tuning.argtypes = [P, I, I]
+    L.tdp_batch_set_tuning.argtypes = [P, I, I, I]
     L.tdp_batch_precond.argtypes = [P, P, D, P, P]
     L.tdp_batch_solve.argtypes = [P, ctypes.POINTER(GmresCfg), P, P, P, P]
     L.tdp_batch_autotune.argtypes = [P, P, D, P, I]
@@ -339,19 +339,21 @@ class Batch:
 
     __del__ = close
 
-    def set_tuning(self, depth, tile):
-        _check(load().tdp_batch_set_tuning(self._h, int(depth), int(tile)), "tdp_batch_set_tuning")
+    def set_tuning(self, depth, tile, medium_tile=0):
+        """Steps per launch, single-field tile and shared-medium tile (-1: none)."""
+        _check(load().tdp_batch_set_tuning(self._h, int(depth), int(tile), int(medium_tile)),
+               "tdp_batch_set_tuning")
 
     def autotune(self, T, rho=0.25):
         """Time the batched sweep variants, keep the fastest; returns rows
-        (depth, tile, ms per application)."""
+        (depth, tile, medium_tile, ms per application)."""
         cap = 128
-        tab = (ctypes.c_double * (3 * cap))()
+        tab = (ctypes.c_double * (4 * cap))()
         Tv = (ctypes.c_int * len(self.ops))(*[int(t) for t in T])
         n = _check(load().tdp_batch_autotune(self._h, ctypes.cast(Tv, ctypes.c_void_p), float(rho),
                                              ctypes.cast(tab, ctypes.c_void_p), cap),
                    "tdp_batch_autotune")
-        return [tuple(tab[3 * i: 3 * i + 3]) for i in range(min(n, cap))]
+        return [tuple(tab[4 * i: 4 * i + 4]) for i in range(min(n, cap))]
 
     def _ptrs(self, tensors, what):
         import torch

@@ -136,7 +136,8 @@ def test_batch_autotune_keeps_results_exact():
     note("batch autotune")
     b = tdp.Batch(ops, nrhs)
     table = b.autotune([2, 2, 2])
-    assert len(table) >= 10 and min(r[2] for r in table) > 0
+    assert len(table) >= 10 and min(r[3] for r in table) > 0
+    assert {int(r[2]) for r in table} >= {-1, 0, 1, 2}      # shared-medium tiles and none
     T = [3, 2, 4]
     Us = b.precond([dev(F) for F in Fs], T)
     q = 0
@@ -211,8 +212,8 @@ def test_batch_f32_tall_tile():
     note("batch f32 tile 8")
     b = tdp.Batch(ops, nrhs)
     T = [3, 2, 4]
-    for depth in (8, 12):
-        b.set_tuning(depth, 8)
+    for depth, mt in ((8, 0), (12, 1)):
+        b.set_tuning(depth, 8, mt)
         Us = b.precond([dev(F) for F in Fs], T)
         q = 0
         for i, (p, r) in enumerate(zip(probs, nrhs)):
@@ -227,3 +228,123 @@ def test_batch_f32_tall_tile():
     b64 = tdp.Batch(ops64, nrhs64)
     with pytest.raises(tdp.TdpError):
         b64.set_tuning(8, 8)
+    with pytest.raises(tdp.TdpError):          # 4 x 12 rows exceed the 32-row shared tile
+        b64.set_tuning(12, 4, 0)
+    with pytest.raises(tdp.TdpError):
+        b64.set_tuning(8, 4, 3)
+
+
+def medium_batch(prec, nshared=7):
+    """One medium with `nshared` right-hand sides (slabs of every shared tile
+    end ragged) next to a second medium with one."""
+    from paper_2006_16861_amd import tdp
+    probs = [inputs.random_medium((75, 140), seed=11, width=5),
+             inputs.random_medium((50, 61), seed=12, width=3)]
+    nrhs = [nshared, 1]
+    ops = [tdp.operator_from_problem(p, prec=prec) for p in probs]
+    rng = np.random.default_rng(13)
+    Fs = [rng.standard_normal(probs[0].n) + 1j * rng.standard_normal(probs[0].n)
+          for _ in range(nshared)] + [probs[1].F]
+    return probs, nrhs, ops, Fs
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("mtile", [0, 1, 2])
+def test_shared_medium_tile_matches_oracle_and_per_field_tiles(prec, mtile):
+    """Shared-medium tile: every right-hand side of the medium matches the
+    oracle (FP64 fields: <= 1e-10; FP32 fields: <= 1e-4 against the FP64
+    oracle) and the per-field tile with the same arithmetic (tile 5), at two
+    depths, including the slab that ends short."""
+    from paper_2006_16861_amd import tdp
+    probs, nrhs, ops, Fs = medium_batch(prec)
+    b = tdp.Batch(ops, nrhs)
+    T = [3, 2]
+    orc = [oracle.Op.from_problem(p) for p in probs]
+    fo = [0] * nrhs[0] + [1]
+    for depth in (8, 5):
+        note(f"shared-medium tile {mtile} prec={prec} depth={depth}")
+        b.set_tuning(depth, 5, -1)
+        ref = [U.cpu().numpy() for U in b.precond([dev(F) for F in Fs], T)]
+        b.set_tuning(depth, 5, mtile)
+        Us = b.precond([dev(F) for F in Fs], T)
+        for q, F in enumerate(Fs):
+            got = Us[q].cpu().numpy()
+            assert np.isfinite(got).all()
+            assert rel(got, ref[q]) <= (1e-13 if prec == 0 else 1e-6), (q, depth)
+            assert rel(got, orc[fo[q]].precond(F, T[fo[q]])) <= (1e-10 if prec == 0 else 1e-4), (q, depth)
+
+
+def test_shared_medium_gmres_lockstep_matches_oracle():
+    """GMRES in lockstep over the shared-medium tile: fixed iterations agree
+    with the oracle element-wise, and tolerance mode takes each field's own
+    decisions (same iterations and restarts as the oracle).  The right-hand
+    sides converge after different numbers of iterations, so the slabs of
+    live fields change between applications."""
+    from paper_2006_16861_amd import tdp
+    probs, nrhs, ops, Fs = medium_batch(0, nshared=5)
+    # one zero right-hand side (done before the first application) and one
+    # smooth one next to the random ones
+    ny, nx = probs[0].n
+    iy, ix = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    Fs[2] = np.sin(np.pi * (iy + 1) / (ny + 1)) * np.sin(np.pi * (ix + 1) / (nx + 1)) + 0j
+    Fs[3] = np.zeros(probs[0].n, dtype=np.complex128)
+    b = tdp.Batch(ops, nrhs)
+    b.set_tuning(8, 5, 0)
+    T = [p.periods for p in probs]
+    fo = [0] * nrhs[0] + [1]
+    orc = [oracle.Op.from_problem(p) for p in probs]
+    note("shared-medium gmres fixed")
+    Us, infos, rc = b.solve([dev(F) for F in Fs], T, restart=4, fixed_iters=6)
+    for q, F in enumerate(Fs):
+        Uo, io = orc[fo[q]].gmres(F, T[fo[q]], restart=4, fixed_iters=6)
+        if q == 3:
+            assert not Us[q].cpu().numpy().any()
+            continue
+        assert infos[q].iters == 6 and rel(Us[q].cpu().numpy(), Uo) <= 1e-10, q
+    note("shared-medium gmres tol 1e-8")
+    Us, infos, rc = b.solve([dev(F) for F in Fs], T, tol=1e-8)
+    assert rc == 0
+    its = []
+    for q, F in enumerate(Fs):
+        Uo, io = orc[fo[q]].gmres(F, T[fo[q]], tol=1e-8)
+        U = Us[q].cpu().numpy()
+        its.append(infos[q].iters)
+        if q == 3:
+            assert not U.any()
+            continue
+        assert infos[q].iters == io["iters"] and infos[q].restarts == io["restarts"], q
+        assert rel(orc[fo[q]].apply_H(U), F) <= 1e-8 * (1 + 1e-9)
+        assert rel(U, Uo) <= 1e-10
+    assert its[3] == 0 and len(set(its[:nrhs[0]])) > 1   # slabs of the live fields only
+
+
+def test_batch_full_size_application_elementwise():
+    """One batched application of the benchmarked configuration (64 right-hand
+    sides on the 512^2 medium through the shared-medium tile, 32 uneven
+    problems, FP32 fields) against the FP64 oracle element-wise on two of the
+    64 fields and on the largest uneven field, and against the same fields
+    run alone through the single-field FP32 path."""
+    from paper_2006_16861_amd import tdp
+    note("batch full-size application, f32")
+    base = inputs.smooth2d(512, seed=4, src_seed=5)
+    srcs = inputs.random_sources(base.n, 64, seed=5, margin=32)
+    uneven = inputs.uneven_problems()
+    probs = [base] + uneven
+    nrhs = [64] + [1] * len(uneven)
+    ops = [tdp.operator_from_problem(p, prec=1) for p in probs]
+    b = tdp.Batch(ops, nrhs)
+    T = [p.periods for p in probs]
+    Fs = [dev(srcs[k]) for k in range(64)] + [dev(p.F) for p in uneven]
+    Us = b.precond(Fs, T)
+    big = max(range(len(uneven)), key=lambda i: uneven[i].N)
+    for q in (5, 63, 64 + big):
+        p = base if q < 64 else uneven[q - 64]
+        F = srcs[q] if q < 64 else p.F
+        i = 0 if q < 64 else q - 63
+        got = Us[q].cpu().numpy()
+        single = ops[i].precond(Fs[q], T[i]).cpu().numpy()
+        ref = oracle.Op.from_problem(p).precond(F, T[i])
+        e_single, e_orc = rel(got, single), rel(got, ref)
+        note(f"  field {q} n={p.n}: vs single FP32 {e_single:.2e}, vs FP64 oracle {e_orc:.2e}")
+        assert e_single <= 1e-6
+        assert e_orc <= 1e-4
