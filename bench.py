@@ -25,11 +25,59 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
 WORDS_PER_NODE_STEP = 7          # u_j, u_{j-1}, u_{j+1}, m, damping, Re F, Im F
+# a launch of k steps must read u_j, u_{j-1}, m, the damping factor and F
+# (2 words) and write u_{j+k}, u_{j+k-1}: 8 words per node, whatever k
+WORDS_PER_NODE_LAUNCH = 8
+# published MI355X vector peaks (TFLOP/s); the FP32 figure needs packed FP32
+# instructions, which this build does not emit (non-packed FP32 issues at the
+# FP64 rate)
+ALU_PEAK = {8: 78.6, 4: 157.3}
+ALU_PEAK_UNPACKED_F32 = 78.6
 
 
-# FP64/FP32 operations of one 9-point node update (stencil with the cell-mass
-# terms of the compact table, forcing, damping; an FMA counts 2)
-FLOPS_PER_NODE_STEP = 39
+def flops_per_node_step(ndim, stencil_points):
+    """Floating-point operations of one node update: one FMA (2 flops) per
+    stencil point, two for the forcing (Re F, Im F) and one for the u_{j-1}
+    term."""
+    return 2 * stencil_points + 6
+
+
+def roofline_block(kernel, launch_us, alg_bytes, alg_flops, word, traffic=None,
+                   effective_bytes=None, note=None):
+    """Roofline of one launch of a kernel: the algorithmic bytes it must move
+    (its inputs read once, its outputs written once) and its useful flops,
+    each over the launch time, against the HBM peak and the vector ALU peak.
+    frac is the larger of the two fractions (<= 1 by construction); bound names
+    that roof, or "latency" when neither reaches half of its peak.
+    effective_bytes, if given, is the per-step 7-word model over the launch's
+    steps (no reuse across steps), reported separately: temporal blocking
+    takes it above the HBM peak."""
+    t = launch_us * 1e-6
+    gbps = alg_bytes / t / 1e9
+    tflops = alg_flops / t / 1e12
+    f_hbm = gbps / HBM_PEAK_GBS
+    f_alu = tflops / ALU_PEAK[word]
+    roof = "hbm" if f_hbm >= f_alu else "alu"
+    frac = max(f_hbm, f_alu)
+    out = {"bound": roof if frac >= 0.5 else "latency", "roof": roof,
+           "achieved": gbps if roof == "hbm" else tflops,
+           "peak": HBM_PEAK_GBS if roof == "hbm" else ALU_PEAK[word],
+           "unit": "GB/s" if roof == "hbm" else "TFLOP/s", "frac": frac,
+           "traffic": traffic, "kernel": kernel, "avg_launch_us": launch_us,
+           "algorithmic_bytes_per_launch": alg_bytes, "hbm_frac": f_hbm,
+           "alu": {"flops_per_launch": alg_flops, "achieved_TFLOPs": tflops,
+                   "peak_TFLOPs": ALU_PEAK[word], "frac": f_alu}}
+    if word == 4:
+        out["alu"]["peak_TFLOPs_unpacked"] = ALU_PEAK_UNPACKED_F32
+    if traffic:
+        out["traffic_GBps"] = traffic / t / 1e9
+        out["traffic_frac"] = traffic / t / 1e9 / HBM_PEAK_GBS
+    if effective_bytes:
+        out["effective_GBps_7word"] = effective_bytes / t / 1e9
+        out["effective_frac_7word"] = effective_bytes / t / 1e9 / HBM_PEAK_GBS
+    if note:
+        out["note"] = note
+    return out
 
 
 def measured_traffic(workload, prec, variant, tun, damping="node"):
@@ -117,7 +165,7 @@ def cpu_one_thread(workload, rho):
     return json.loads(r.stdout.strip().splitlines()[-1])["ms_per_step"]
 
 
-def cpu_baseline(p, T, rho, napply, target_s=12.0, workload=None):
+def cpu_baseline(p, T, rho, napply, target_s=12.0, workload=None, handoff=None):
     """The oracle (plain C, OpenMP) on the host cores: time one H-apply and a
     bounded number of recurrence steps, scale to napply preconditioner
     applications (+ H-applies) per solve.  Also one period of steps on a
@@ -150,7 +198,73 @@ def cpu_baseline(p, T, rho, napply, target_s=12.0, workload=None):
             out["one_thread_ms_per_step"] = one
             # the H-applies (< 1% of a solve) left out
             out["one_thread_solves_per_s_steps_only"] = 1.0 / (napply * one * 1e-3 * T * op.nP)
+    if handoff:
+        out["legs"] = cpu_baseline_legs(oracle, handoff, rho)
     return out
+
+
+def cpu_baseline_legs(oracle, handoff, rho):
+    """Part of the CPU baseline leg (called from cpu_baseline, which passes
+    the oracle module): the oracle on the configurations beyond the headline: one recurrence
+    period and one H-apply on the full grid, extrapolated to the GPU run's
+    preconditioner applications (labelled "extrapolated"); for the precision
+    form also the oracle's check of the GPU results: its one-period S_T F
+    against both GPU paths', and the true residual of both GPU solutions under
+    the oracle's H."""
+    legs = {}
+
+    def period(p, nP, T):
+        op = oracle.Op.from_problem(p, nP=nP) if nP else oracle.Op.from_problem(p)
+        t = time.perf_counter()
+        pf = op.precond(p.F, 1, rho)
+        t_period = time.perf_counter() - t
+        t = time.perf_counter()
+        op.apply_H(p.F)
+        t_h = time.perf_counter() - t
+        return op, pf, t_period / op.nP, t_h
+
+    if "precision" in handoff:
+        h = handoff["precision"]
+        p = h["problem"]
+        op, pf, t_step, t_h = period(p, h["n_P"], p.periods)
+        t_solve = h["napply"] * (t_step * p.periods * h["n_P"] + t_h)
+        nrm = float(np.linalg.norm(p.F))
+        chk = {"pf1_rel_error_vs_oracle": {k: float(np.linalg.norm(v - pf) / np.linalg.norm(pf))
+                                           for k, v in h["PF1"].items()},
+               "true_relres_under_oracle_H": {k: float(np.linalg.norm(op.apply_H(v) - p.F) / nrm)
+                                              for k, v in h["U"].items()}}
+        legs["precision"] = {"workload": "layered3d-256", "kind": "oracle", "extrapolated": True,
+                             "ms_per_step": t_step * 1e3, "H_ms": t_h * 1e3,
+                             "solves_per_s": 1.0 / t_solve,
+                             "sample": f"{h['n_P']} recurrence steps + 1 H-apply on the full "
+                                       f"grid, scaled to {h['napply']} applications of "
+                                       f"{p.periods * h['n_P']} steps",
+                             "oracle_check": chk}
+        log(f"cpu leg precision: {t_step * 1e3:.0f} ms/step; check {chk}")
+    if "batched" in handoff:
+        h = handoff["batched"]
+        p = h["problem"]
+        op, _, t_step, t_h = period(p, 0, p.periods)
+        # per field: its applications x (T n_P steps + one H-apply), at the
+        # sampled per-node rate for the other grid sizes
+        t_node_step, t_node_h = t_step / p.N, t_h / p.N
+        t_all = sum(na * N * (T * nP * t_node_step + t_node_h)
+                    for na, N, T, nP in h["fields"])
+        legs["batched"] = {"workload": "64 rhs on smooth2d-512 + 32 uneven", "kind": "oracle",
+                           "extrapolated": True, "ms_per_step_512": t_step * 1e3,
+                           "solves_per_s": len(h["fields"]) / t_all,
+                           "sample": "one period + 1 H-apply on the 512^2 grid, scaled per node "
+                                     "to every field's applications"}
+    if "adjoint" in handoff:
+        h = handoff["adjoint"]
+        p = h["problem"]
+        op, _, t_step, t_h = period(p, h["n_P"], p.periods)
+        t_grad = h["napply_per_gradient"] * (t_step * p.periods * h["n_P"] + t_h)
+        legs["adjoint"] = {"workload": "smooth3d-128", "kind": "oracle", "extrapolated": True,
+                           "ms_per_step": t_step * 1e3, "gradients_per_s": 1.0 / t_grad,
+                           "sample": f"{h['n_P']} recurrence steps + 1 H-apply, scaled to "
+                                     f"{h['napply_per_gradient']} applications per gradient"}
+    return legs
 
 
 def stream_probe(nbytes=2 << 30, reps=5):
@@ -194,13 +308,15 @@ def form_precision(rho):
     the smallest integer above the CFL bound 9.58, with Im U from the 2x2
     solve of Sec. 2.3, against 12 for a multiple of 4): FP32
     recurrence fields inside FP64 GMRES (whose restarts recompute the true
-    residual in FP64: the outer refinement), against the FP64 path."""
+    residual in FP64: the outer refinement), against the FP64 path.  Returns
+    the result and what the CPU baseline leg checks against the oracle: both
+    solutions and both paths' one-period preconditioner application."""
     import torch
     from paper_2006_16861_amd import inputs, tdp
     p = inputs.layered3d(256)
     F = torch.as_tensor(p.F, device="cuda")
     res = {"workload": "layered3d-256", "n": list(p.n), "periods_T": p.periods}
-    U = {}
+    U, PF1 = {}, {}
     for name, prec in (("f64", tdp.F64), ("f32", tdp.F32)):
         op = tdp.operator_from_problem(p, prec=prec, steps_per_period=-1)
         best, table = op.autotune(T=4, rho=rho)
@@ -209,24 +325,49 @@ def form_precision(rho):
         _, step_ms = sweep_timing(op, F, p.periods, rho, 1, torch.cuda.current_stream())
         us_step = step_ms * 1e3
         r = float(torch.linalg.norm(F - op.apply_H(Uq)) / torch.linalg.norm(F))
-        U[name] = Uq
+        U[name] = Uq.cpu().numpy()
+        PF1[name] = op.precond(F, 1, rho).cpu().numpy()
         word = 8 if prec == tdp.F64 else 4
+        tun = op.get_tuning()
+        kname = (f"k_sweep3d_stream<{'double' if word == 8 else 'float'}> shape={tun['tile']} "
+                 f"z-chunk={tun['tb_depth']}" if tun["kernel"] == 3 else f"kernel {tun['kernel']}")
+        spl = {4: 2}.get(tun["kernel"], 1)
+        words_launch = WORDS_PER_NODE_LAUNCH if spl > 1 else WORDS_PER_NODE_STEP
+        key = f"layered3d-256|{name}|v0|k{tun['kernel']}|d{tun['tb_depth']}|t{tun['tile']}"
+        traffic = _traffic(key) if op.nP == 10 else None
         res[name] = {"solves_per_s": 1.0 / dt, "seconds": dt, "iters": info.iters, "n_P": op.nP,
                      "precond_applications": info.steps // (p.periods * op.nP),
+                     "switched": int(info.switched),
                      "true_relres_fp64": r, "tuning": best, "sweep_us_per_step": us_step,
-                     "sweep_algorithmic_GBps": 7 * word * p.N / (us_step * 1e-6) / 1e9}
+                     "roofline": roofline_block(kname, us_step * spl,
+                                                p.N * word * words_launch,
+                                                flops_per_node_step(3, 19) * p.N * spl, word,
+                                                traffic=traffic if spl == 1 else None)}
         log(f"form precision {name}: {dt:.3f} s, iters {info.iters}, relres {r:.2e}")
         del op
     res["f32_rel_error_vs_f64_gpu_solution"] = float(
-        torch.linalg.norm(U["f32"] - U["f64"]) / torch.linalg.norm(U["f64"]))
+        np.linalg.norm(U["f32"] - U["f64"]) / np.linalg.norm(U["f64"]))
     res["speedup_f32_vs_f64"] = res["f32"]["solves_per_s"] / res["f64"]["solves_per_s"]
-    return res
+    handoff = {"problem": p, "U": U, "PF1": PF1, "rho": rho, "n_P": res["f64"]["n_P"],
+               "napply": res["f64"]["precond_applications"]}
+    return res, handoff
+
+
+def _traffic(key):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(key)
+    return None if rec is None else rec["bytes_per_launch"]
 
 
 def form_batched(rho):
     """Batched form: 64 right-hand sides (seeded unit sources) on one 512^2
     smooth medium plus 32 independent problems of sizes 128..768 per side,
-    FP32 fields / FP64 GMRES, all in one batched launch sequence."""
+    FP32 fields / FP64 GMRES, all in one batched launch sequence.  Also the 64
+    right-hand sides alone, on the shared-medium tile and on per-field tiles,
+    against the plain single-solve FP32 and FP64 paths on a sample of the
+    same fields."""
     import torch
     from paper_2006_16861_amd import inputs, tdp
     base = inputs.smooth2d(512, seed=4, src_seed=5)
@@ -236,41 +377,103 @@ def form_batched(rho):
     nrhs = [64] + [1] * len(uneven)
     T = [p.periods for p in probs]
     ops = [tdp.operator_from_problem(p, prec=tdp.F32) for p in probs]
-    b = tdp.Batch(ops, nrhs)
     Fs = [torch.as_tensor(srcs[k], device="cuda") for k in range(64)] + \
          [torch.as_tensor(p.F, device="cuda") for p in uneven]
+    field_N = [base.N] * 64 + [p.N for p in uneven]
+
+    def timed_solve(b, fs, field_n, Tb):
+        b.solve(fs, Tb, rho=rho, tol=1e-6)                               # warm (graphs)
+        (out, dt) = _timed(lambda: b.solve(fs, Tb, rho=rho, tol=1e-6))
+        Us, infos, rc = out
+        steps = sum(i.steps * n for i, n in zip(infos, field_n))
+        return {"solves_per_s": len(fs) / dt, "seconds": dt, "status": rc,
+                "worst_relres": max(i.relres for i in infos),
+                "node_steps_per_s": steps / dt, "fields": len(fs),
+                "iters_max": max(i.iters for i in infos)}, infos
+
+    b = tdp.Batch(ops, nrhs)
     t = time.perf_counter()
     table = b.autotune([max(1, t_ // 8) for t_ in T], rho=rho)
-    best = min(table, key=lambda r: r[2])
+    best = min(table, key=lambda r: r[3])
     log(f"form batched: autotune {len(table)} variants in {time.perf_counter() - t:.2f} s, "
-        f"best depth {int(best[0])} tile {int(best[1])}")
-    b.solve(Fs, T, rho=rho, tol=1e-6)                                   # warm (graphs)
-    (out, dt) = _timed(lambda: b.solve(Fs, T, rho=rho, tol=1e-6))
-    Us, infos, rc = out
-    worst = max(i.relres for i in infos)
-    nodes = sum(p.N * r for p, r in zip(probs, nrhs))
-    steps = sum(i.steps * probs_n for i, probs_n in
-                zip(infos, [base.N] * 64 + [p.N for p in uneven]))
+        f"best depth {int(best[0])} tile {int(best[1])} shared tile {int(best[2])}")
+    b.set_tuning(int(best[0]), int(best[1]), int(best[2]))
     res = {"workload": "64 rhs on smooth2d-512 + 32 uneven 128..768", "fields": len(Fs),
-           "tuning": {"depth": int(best[0]), "tile": int(best[1])},
-           "solves_per_s": len(Fs) / dt, "seconds": dt, "status": rc, "worst_relres": worst,
-           "node_steps_per_s": steps / dt, "total_nodes": nodes}
-    # the plain FP64 single-solve path on a sample of the same fields
-    sample = [0, 1, 64, 65]
-    t_single = 0.0
-    for q in sample:
-        p = base if q < 64 else uneven[q - 64]
-        op = tdp.operator_from_problem(p, prec=tdp.F64)
-        op.solve(Fs[q], T=p.periods, rho=rho, tol=1e-6)
-        (_, dt1) = _timed(lambda: op.solve(Fs[q], T=p.periods, rho=rho, tol=1e-6))
-        t_single += dt1 * (64 if q < 64 else len(uneven)) / 2
-        del op
-    res["plain_f64_single_solves_per_s_extrapolated"] = len(Fs) / t_single
-    res["plain_f64_sample"] = "2 of the 64 sources and 2 of the 32 uneven problems, scaled"
-    res["speedup_vs_plain_f64"] = res["solves_per_s"] / res["plain_f64_single_solves_per_s_extrapolated"]
-    log(f"form batched: {len(Fs)} solves in {dt:.3f} s, worst relres {worst:.2e}")
+           "tuning": {"depth": int(best[0]), "tile": int(best[1]), "medium_tile": int(best[2])},
+           "total_nodes": sum(field_N)}
+    r_all, infos_all = timed_solve(b, Fs, field_N, T)
+    res.update(r_all)
+    fo = [0] * 64 + list(range(1, len(probs)))
+    handoff = {"problem": base, "fields": [(i.steps // (T[fo[q]] * ops[fo[q]].nP), field_N[q],
+                                            T[fo[q]], ops[fo[q]].nP)
+                                           for q, i in enumerate(infos_all)]}
+    log(f"form batched: {len(Fs)} solves in {res['seconds']:.3f} s, worst relres {res['worst_relres']:.2e}")
     b.close()
-    return res
+
+    # the 64 right-hand sides of one medium alone: shared-medium tile against
+    # per-field tiles, and the kernel launch time of one batched application
+    b64 = tdp.Batch([ops[0]], [64])
+    tab64 = b64.autotune([max(1, T[0] // 8)], rho=rho)
+    # best of each kind (every field on its own tile: medium_tile -1)
+    shared = min((r for r in tab64 if r[2] >= 0), key=lambda r: r[3])
+    single = min((r for r in tab64 if r[2] < 0), key=lambda r: r[3])
+    sub = {}
+    for name, r in (("shared_medium_tile", shared), ("per_field_tiles", single)):
+        b64.set_tuning(int(r[0]), int(r[1]), int(r[2]))
+        sub[name] = timed_solve(b64, Fs[:64], field_N[:64], T[:1])[0]
+        sub[name]["tuning"] = {"depth": int(r[0]), "tile": int(r[1]), "medium_tile": int(r[2])}
+    b64.set_tuning(int(shared[0]), int(shared[1]), int(shared[2]))
+    U64 = b64.precond(Fs[:64], T[:1], rho)                             # warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        b64.precond(Fs[:64], T[:1], rho)
+    e1.record()
+    torch.cuda.synchronize()
+    app_ms = e0.elapsed_time(e1) / 3
+    K = int(shared[0])
+    launches = -(-T[0] * ops[0].nP // K)
+    nr = {0: 4, 1: 2, 2: 2}[int(shared[2])]
+    slabs = -(-64 // nr)
+    # per launch: each right-hand side reads u_j, u_{j-1} and F and writes two
+    # fields (6 words per node); the medium (m, damping) is read once per slab
+    alg_bytes = 4 * base.N * (6 * 64 + 2 * slabs)
+    launch_us = app_ms * 1e3 / launches
+    sub["shared_medium_tile"]["roofline"] = roofline_block(
+        f"k_sweep2d_tb_mrhs<float> medium tile {int(shared[2])} ({nr} right-hand sides per "
+        f"workgroup) depth={K}", launch_us, alg_bytes,
+        flops_per_node_step(2, 9) * base.N * 64 * K, 4,
+        traffic=_traffic(f"batch64-smooth2d-512|f32|d{K}|m{int(shared[2])}"),
+        effective_bytes=4 * base.N * 64 * (5 + 2.0 / 64) * K,
+        note="launch time = one batched application (HIP events) / its launches; "
+             "effective bytes: (5 + 2/64) words per right-hand side per node-step")
+    sub["shared_medium_tile"]["application_ms"] = app_ms
+    sub["speedup_shared_vs_per_field_tiles"] = (sub["shared_medium_tile"]["node_steps_per_s"] /
+                                                sub["per_field_tiles"]["node_steps_per_s"])
+    res["rhs64_on_one_medium"] = sub
+    b64.close()
+    log(f"form batched 64 rhs: shared tile {sub['shared_medium_tile']['node_steps_per_s']:.3g} "
+        f"node-steps/s, per-field tiles {sub['per_field_tiles']['node_steps_per_s']:.3g}")
+
+    # the plain single-solve paths on a sample of the same fields
+    sample = [0, 1, 64, 65]
+    for name, prec in (("f32", tdp.F32), ("f64", tdp.F64)):
+        t_single, steps_single = 0.0, 0.0
+        for q in sample:
+            p = base if q < 64 else uneven[q - 64]
+            op = tdp.operator_from_problem(p, prec=prec)
+            op.solve(Fs[q], T=p.periods, rho=rho, tol=1e-6)
+            ((_, info), dt1) = _timed(lambda: op.solve(Fs[q], T=p.periods, rho=rho, tol=1e-6))
+            w = (64 if q < 64 else len(uneven)) / 2
+            t_single += dt1 * w
+            steps_single += info.steps * p.N * w
+            del op
+        res[f"plain_{name}_single_solves_per_s_extrapolated"] = len(Fs) / t_single
+        res[f"plain_{name}_single_node_steps_per_s"] = steps_single / t_single
+        res[f"speedup_vs_plain_{name}"] = res["solves_per_s"] / (len(Fs) / t_single)
+    res["plain_sample"] = "2 of the 64 sources and 2 of the 32 uneven problems, each solved " \
+                          "alone, scaled to all 96 fields"
+    return res, handoff
 
 
 def form_cell_damping(rho):
@@ -335,8 +538,18 @@ def form_adjoint(rho):
     grad_eval()
     g, dt = _timed(grad_eval)
     log(f"form adjoint: gradient in {dt:.3f} s")
-    return {"workload": "smooth3d-128, 4 sources, 256 receivers", "gradients_per_s": 1.0 / dt,
-            "solves_per_s": 8.0 / dt, "seconds": dt, "grad_norm": float(torch.linalg.norm(g))}
+    # preconditioner applications of the forward solves (the adjoint solves
+    # use the same operator and right-hand sides of the same kind)
+    op = tdp.Operator(torch.rsqrt(torch.as_tensor(m0, device="cuda")).contiguous(), R, p.omega,
+                      p.h, steps_per_period=-1)
+    napply = []
+    for s_ in range(F.shape[0]):
+        _, info = op.solve(F[s_].contiguous(), T=p.periods, tol=1e-6)
+        napply.append(info.steps // (p.periods * op.nP))
+    res = {"workload": "smooth3d-128, 4 sources, 256 receivers", "gradients_per_s": 1.0 / dt,
+           "solves_per_s": 8.0 / dt, "seconds": dt, "grad_norm": float(torch.linalg.norm(g)),
+           "forward_precond_applications": napply}
+    return res, {"problem": p, "n_P": op.nP, "napply_per_gradient": 2 * sum(napply)}
 
 
 XGMI_LINK_GBS = 153.0           # one MI355X xGMI link, one direction, published
@@ -517,6 +730,9 @@ def main():
                     help="print the autotuner's per-variant step times and exit")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision / batched / adjoint form measurements")
+    ap.add_argument("--forms", default="",
+                    help="comma list of forms to measure (precision, batched, adjoint, "
+                         "cell_damping); default all")
     ap.add_argument("--profile-sweeps", type=int, default=0,
                     help="profiling mode: one 256 MiB device copy (counter calibration), then "
                          "this many preconditioner applications, then exit")
@@ -614,8 +830,9 @@ def main():
         log(f"timed {args.steps} solves in {wall:.3f} s; last true relres {relres:.3e}")
         apply_ms, step_ms = sweep_timing(op, F, T, args.rho, args.sweep_reps, stream,
                                          args.variant)
+    word = 8 if prec == tdp.F64 else 4
     words = WORDS_PER_NODE_STEP if args.variant == 0 else 10
-    bytes_per = words * (8 if prec == tdp.F64 else 4)
+    bytes_per = words * word
     tun = op.get_tuning()
     blocked = tun["kernel"] == 2
     steps_per_launch = tun["tb_depth"] if blocked else (2 if tun["kernel"] == 4 else 1)
@@ -629,9 +846,9 @@ def main():
     # (with its staging copies) is reported beside it
     launch_us = float(np.median([i.ms_precond for i in infos])) * 1e3 / (napply * launches)
     standalone_launch_us = apply_ms * 1e3 / launches
-    # algorithmic bytes of one launch: 7 words per node-step (u_j, u_{j-1}, u_{j+1},
-    # m, damping, Re F, Im F) x N nodes x the steps the launch advances
-    achieved = p.N * bytes_per * (Ns / launches) / (launch_us * 1e-6) / 1e9
+    # the per-step 7-word model over the steps of one launch (no reuse across
+    # steps; above the HBM peak under temporal blocking)
+    effective = p.N * bytes_per * (Ns / launches) / (launch_us * 1e-6) / 1e9
     tname = "double" if prec == tdp.F64 else "float"
     if args.damping == "cell" and tun["kernel"] == 2:
         kname = (f"k_sweep2d_abd_tb<{tname}> depth={steps_per_launch} tile={tun['tile']} "
@@ -652,7 +869,24 @@ def main():
                if args.scheme == "compact" and args.steps_per_period == 0 else None)
     ceiling = stream_probe()
     log(f"stream probe: copy {ceiling['copy']:.0f} GB/s, triad {ceiling['triad']:.0f} GB/s")
-    log(f"precond apply {apply_ms:.3f} ms, {step_ms * 1e3:.2f} us/step, {achieved:.1f} GB/s algorithmic")
+    # bytes one launch must move: a blocked or two-step launch reads u_j,
+    # u_{j-1}, m, the damping factor and F once and writes two fields (8 words
+    # per node); a one-step launch moves the 7 words of one step; Def. 4 on the
+    # complex field in one pass moves 10
+    spl = Ns / launches
+    cell = args.damping == "cell"
+    if tun["kernel"] in (2, 4) or cell and tun["kernel"] == 2:
+        words_launch = WORDS_PER_NODE_LAUNCH
+    else:
+        words_launch = 10 if (args.variant == 1 and tun["kernel"] == 1) else WORDS_PER_NODE_STEP
+    points = {("compact", 2): 9, ("fd2", 2): 5, ("compact", 3): 19, ("fd2", 3): 7}[(args.scheme, len(p.n))]
+    if cell:
+        points += 5 if len(p.n) == 2 else 7           # the damping stencil of I_abd
+    flops = flops_per_node_step(len(p.n), points) * (2 if args.variant == 1 and tun["kernel"] == 1 else 1)
+    roof = roofline_block(kname, launch_us, p.N * word * words_launch, flops * p.N * spl, word,
+                          traffic=traffic, effective_bytes=p.N * bytes_per * spl)
+    log(f"precond apply {apply_ms:.3f} ms, {step_ms * 1e3:.2f} us/step; launch {launch_us:.2f} us: "
+        f"bound {roof['bound']} ({roof['roof']} {roof['frac']:.3f}), effective {effective:.0f} GB/s")
     out = {
         "metric": "Helmholtz solves/s at 1e-6 residual; recurrence-step GB/s vs HBM peak",
         "value": args.steps / wall,
@@ -671,6 +905,7 @@ def main():
                    "ppw": p.ppw, "damping_width": p.width, "periods_T": T, "n_P": op.nP,
                    "N_s": Ns, "rho": args.rho, "variant": args.variant, "restart": args.restart, "tol": args.tol,
                    "gmres_iters": infos[-1].iters, "gmres_restarts": infos[-1].restarts,
+                   "switched": [int(i.switched) for i in infos],
                    "precond_applications": int(napply),
                    "true_relres": relres, "setup_ms": setup_ms,
                    "solve_ms": [round(i.ms_total, 3) for i in infos],
@@ -679,38 +914,40 @@ def main():
                    "arnoldi_ms": [round(i.ms_arnoldi, 3) for i in infos],
                    "solve_ms_median": float(np.median([i.ms_total for i in infos])),
                    "kernel": op.get_tuning(), "parallelism": "single-gpu"},
-        "recurrence_GBps": achieved,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": kname, "bytes_per_node_step": bytes_per,
-                     "nodes_per_launch": p.N, "steps_per_launch": Ns / launches,
-                     "avg_launch_us": launch_us,
-                     "avg_launch_us_source": "HIP events around the preconditioner "
-                                             "applications of the timed solves",
-                     "standalone_launch_us": standalone_launch_us,
-                     # HBM bytes actually moved per launch (the counters) over the
-                     # same launch time; with temporal blocking the algorithmic
-                     # rate exceeds the HBM peak and the step loop, not HBM,
-                     # sets the launch time
-                     "traffic_GBps": (traffic / (launch_us * 1e-6) / 1e9) if traffic else None,
-                     "traffic_frac": (traffic / (launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS)
-                     if traffic else None,
-                     "measured_ceiling_GBps": ceiling,
-                     "alu": {"flops_per_node_step": FLOPS_PER_NODE_STEP,
-                             "achieved_TFLOPs": FLOPS_PER_NODE_STEP * p.N * Ns / (apply_ms * 1e-3) / 1e12,
-                             "peak_TFLOPs": 78.6 if prec == tdp.F64 else 157.3}},
+        "recurrence_GBps_7word": effective,
+        "roofline": dict(roof, **{
+            "words_per_node_launch": words_launch, "word_bytes": word,
+            "bytes_per_node_step_7word": bytes_per, "nodes_per_launch": p.N,
+            "steps_per_launch": spl, "flops_per_node_step": flops,
+            "avg_launch_us_source": "HIP events around the preconditioner applications of "
+                                    "the timed solves",
+            "standalone_launch_us": standalone_launch_us,
+            "measured_ceiling_GBps": ceiling}),
     }
+    handoff = {}
     if not args.no_forms and args.workload == "smooth2d-1024":
-        import numpy as np  # noqa: F811
         forms = {}
+        chosen = set(args.forms.split(",")) if args.forms else None
         for name, fn in (("precision", form_precision), ("batched", form_batched),
                          ("adjoint", form_adjoint), ("cell_damping", form_cell_damping)):
+            if chosen is not None and name not in chosen:
+                continue
             log(f"form {name} ...")
-            forms[name] = fn(args.rho)
+            r = fn(args.rho)
+            if isinstance(r, tuple):
+                forms[name], handoff[name] = r
+            else:
+                forms[name] = r
+            torch.cuda.empty_cache()
         out["forms"] = forms
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(p, T, args.rho, int(napply), workload=args.workload)
+        out["cpu_baseline"] = cpu_baseline(p, T, args.rho, int(napply), workload=args.workload,
+                                           handoff=handoff)
+        # the oracle's checks of the forms' GPU results go back beside them
+        for name, leg in out["cpu_baseline"].get("legs", {}).items():
+            if "oracle_check" in leg and name in out.get("forms", {}):
+                out["forms"][name]["oracle_check"] = leg["oracle_check"]
         log(f"cpu baseline {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 

@@ -332,16 +332,16 @@ int tdp_batch_destroy(tdp_batch *b);
  * and shared-medium tile of the batched blocked sweep.  medium_tile: -1 runs
  * every field on its own tile; 0..2 select rows per lane x waves and
  * right-hand sides per workgroup:
- *   FP32 fields  0: 4 x 8, 4 (32 x 64 tile)   1: 4 x 16, 4 (64 x 64)   2: 2 x 16, 6 (32 x 64)
+ *   FP32 fields  0: 4 x 8, 4 (32 x 64 tile)   1: 6 x 8, 2 (48 x 64)    2: 8 x 8, 2 (64 x 64)
  *   FP64 fields  0: 2 x 16, 3 (32 x 64)       1: 4 x 8, 2 (32 x 64)    2: 2 x 16, 2 (32 x 64)
  * Default: depth 8, tile 8 (FP32) or 4 (FP64), medium tile 0.  4 x depth
  * must not exceed either tile's rows (else TDP_EINVAL). */
 int tdp_batch_set_tuning(tdp_batch *b, int depth, int tile, int medium_tile);
 
 /* Autotuner of the batched sweep: times one batched application for every
- * depth (4, 6, 8) x single-field tile shape, then every shared-medium tile
- * (and none) with that depth's best single-field tile, and keeps the
- * fastest.  table (host, may be NULL) receives up to cap rows {depth, tile,
+ * depth (4, 6, 8) x single-field tile shape with every field on its own tile
+ * (medium_tile -1), then every shared-medium tile with that depth's best
+ * single-field tile, and keeps the fastest.  table (host, may be NULL) receives up to cap rows {depth, tile,
  * medium_tile, milliseconds per application}.  Returns the number of
  * candidates timed or a negative error. */
 int tdp_batch_autotune(tdp_batch *b, const int *periods_T, double rho, double *table, int cap);

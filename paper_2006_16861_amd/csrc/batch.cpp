@@ -404,9 +404,9 @@ extern "C" int tdp_batch_precond(tdp_batch *b, const int *periods_T, double rho,
 }
 
 // Autotuner of the batched sweep: times one batched application (periods_T
-// per op) for every depth x per-field tile shape (with the current
-// shared-medium tile), then for every shared-medium tile (and none) with
-// that depth's best per-field tile; keeps the fastest.
+// per op) for every depth x per-field tile shape with every field on its own
+// tile, then for every shared-medium tile with that depth's best per-field
+// tile; keeps the fastest.
 extern "C" int tdp_batch_autotune(tdp_batch *b, const int *periods_T, double rho, double *table,
                                   int cap)
 {
@@ -453,24 +453,26 @@ extern "C" int tdp_batch_autotune(tdp_batch *b, const int *periods_T, double rho
         }
         return TDP_OK;
     };
+    // stage 1: every depth x single-field tile with each field on its own
+    // tile; stage 2: every shared-medium tile with that depth's best
+    // single-field tile (which then runs the fields that have no partner)
     for (int K : {4, 6, 8}) {
-        const int mcur = (M0 >= 0 && 4 * K <= mrhs_rows(M0, b->f64)) ? M0 : -1;
         double kbest = INFINITY;
         int kshape = -1;
         for (int shape = 0; shape < 9 && rc == TDP_OK; ++shape) {
             if ((shape == 2 || shape == 8) && b->f64) continue;
             if (4 * K > tb2d_tile_rows(shape, b->f64)) continue;
             double ms = INFINITY;
-            rc = trial(K, shape, mcur, &ms);
+            rc = trial(K, shape, -1, &ms);
             if (rc == TDP_OK && ms < kbest) {
                 kbest = ms;
                 kshape = shape;
             }
         }
-        for (int ms_ = -1; ms_ < 3 && rc == TDP_OK && kshape >= 0; ++ms_) {
-            if (ms_ == mcur || (ms_ >= 0 && 4 * K > mrhs_rows(ms_, b->f64))) continue;
+        for (int mt = 0; mt < 3 && rc == TDP_OK && kshape >= 0; ++mt) {
+            if (4 * K > mrhs_rows(mt, b->f64)) continue;
             double ms = INFINITY;
-            rc = trial(K, kshape, ms_, &ms);
+            rc = trial(K, kshape, mt, &ms);
         }
         if (rc != TDP_OK) break;
     }

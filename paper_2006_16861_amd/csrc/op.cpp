@@ -398,10 +398,9 @@ extern "C" int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t)
         if (t->tile < 0 || t->tile > 2) TDP_FAIL(TDP_EINVAL, "tile must be 0, 1 or 2 for kernels 3 and 4");
     } else {
         if (t->tb_depth < 0 || t->tb_depth > TDP_TB_KMAX) TDP_FAIL(TDP_EINVAL, "tb_depth must be in [0, 16]");
-        if (t->tile < 0 || t->tile > 8) TDP_FAIL(TDP_EINVAL, "tile must be in [0, 8]");
-        if ((t->kernel == 0 || t->kernel == 2) && (t->tile == 2 || t->tile == 8) &&
-            op->prec == TDP_F64)
-            TDP_FAIL(TDP_EINVAL, "tiles 2 and 8 are FP32 only");
+        if (t->tile < 0 || t->tile > 13) TDP_FAIL(TDP_EINVAL, "tile must be in [0, 13]");
+        if ((t->kernel == 0 || t->kernel == 2) && tb2d_f32_only(t->tile) && op->prec == TDP_F64)
+            TDP_FAIL(TDP_EINVAL, "tiles 2, 8, 12 and 13 are FP32 only");
     }
     op->tune = *t;
     return TDP_OK;
@@ -546,7 +545,7 @@ static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth, i
     if (kern == 2) {
         if (k == 0) k = 4;
         const int rows = tb2d_tile_rows(t, op->prec == TDP_F64);
-        if (4 * k > rows || 4 * k > 64) k = rows / 8;   // keep at least half the tile exact
+        if (4 * k > rows || 4 * k > tb2d_tile_cols(t)) k = rows / 8;   // keep at least half the tile exact
     } else if (kern == 3 || kern == 4) {
         if (t > 2) t = 1;
         if (k == 0) {
@@ -974,13 +973,12 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
     std::vector<tdp_tuning> cand;
     cand.push_back({1, 0, 1, 0});
     if (op->ndim == 2 && op->dform == TDP_DAMP_NODE) {
-        const int tiles[] = {0, 1, 2, 3, 4, 5, 6, 7, 8};
         const int depths[] = {2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16};
-        for (int tile : tiles) {
-            if ((tile == 2 || tile == 8) && op->prec == TDP_F64) continue;
+        for (int tile = 0; tile <= 13; ++tile) {
+            if (tb2d_f32_only(tile) && op->prec == TDP_F64) continue;
             const int rows = tb2d_tile_rows(tile, op->prec == TDP_F64);
             for (int k : depths)
-                if (4 * k <= rows && 4 * k <= 64) cand.push_back({2, k, 1, tile});
+                if (4 * k <= rows && 4 * k <= tb2d_tile_cols(tile)) cand.push_back({2, k, 1, tile});
         }
     }
     if (op->ndim == 2 && op->dform == TDP_DAMP_CELL && op->mc <= 2) {

@@ -337,20 +337,33 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
     };
     // rows whose new value is still read by a later step or written out
     auto active = [&](int s) { return r0 + R > s + 1 && r0 < EY - 1 - s; };
-    for (int s = 0; s < k; s += 2) {
+    // two steps (the register arrays swap roles); false once k is reached
+    auto step_pair = [&](int s) -> bool {
         if (active(s)) {
             tb2_step<T, SC, MC, R, NCO>(ul, ul + UB, rs, rn, rs + US, rn - US, co, fr, fi, e, u0,
                                         u1, (T)fa[s * fstride], (T)fb[s * fstride]);
             snapshot(s, u1);
         }
         __syncthreads();
-        if (s + 1 == k) break;
+        if (s + 1 == k) return false;
         if (active(s + 1)) {
             tb2_step<T, SC, MC, R, NCO>(ul + UB, ul, rs, rn, rs + US, rn - US, co, fr, fi, e, u1,
                                         u0, (T)fa[(s + 1) * fstride], (T)fb[(s + 1) * fstride]);
             snapshot(s + 1, u0);
         }
         __syncthreads();
+        return s + 2 < k;
+    };
+    if constexpr (MC > 2) {
+        for (int s = 0; step_pair(s); s += 2) {
+        }
+    } else {
+        // unrolled up to the deepest depth: the scalar bookkeeping and the
+        // forcing scalars leave the step loop (5% of a depth-8 launch); the
+        // tables with corner mass terms would spill registers unrolled
+#pragma unroll
+        for (int s = 0; s < TDP_TB_KMAX; s += 2)
+            if (!step_pair(s)) break;
     }
     // every output row lies in a wave that ran every step: level k is in u1
     // for odd k, in u0 for even k
@@ -364,6 +377,229 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
             (up_out + row)[gx] = (k & 1) ? u0[i] : u1[i];
         }
     }
+}
+
+// Third form: each lane holds two adjacent columns (x = 2 lane, 2 lane + 1),
+// so a wave spans 128 columns.  Against one column per lane this halves the
+// share of columns lost to the halo at a given depth and the DPP moves per
+// node (the inner x-neighbours of the pair are the lane's own values; only
+// the outer ones cross lanes).  Coefficients, the exact region, the skipped
+// waves and the outputs follow tb_tile2.  Each wave passes its first and
+// last rows through LDS in packed slots (2W + 2 rows per copy; wave w writes
+// slots 2w + 1 and 2w + 2 and reads slots 2w and 2w + 3, slots 0 and 2W + 1
+// stay zero); a slot holds columns -2 .. EX + 1 so that the lane's pair is
+// one 16-byte access.
+template <typename T, int SC, int MC, int R, int NCO>
+__device__ __forceinline__ void tb3_step(const T *__restrict__ cur, T *__restrict__ nxt, int rs,
+                                         int rn, int wf, int wl, const T (&co)[R][2][NCO],
+                                         const T (&fr)[R][2], const T (&fi)[R][2],
+                                         const T (&e)[R][2], const T (&a)[R][2],
+                                         T (&b)[R][2], T fas, T fbs)
+{
+    constexpr bool CORNER = MC > 2 || SC > 2;
+    // rows r0-1 .. r0+R at columns 2l-1, 2l, 2l+1, 2l+2 (LDS offsets base +
+    // 1 .. base + 4 of a slot whose column x sits at x + 2)
+    T v[R + 2][4];
+    v[0][0] = cur[rs + 1];
+    v[0][1] = cur[rs + 2];
+    v[0][2] = cur[rs + 3];
+    v[0][3] = cur[rs + 4];
+    v[R + 1][0] = cur[rn + 1];
+    v[R + 1][1] = cur[rn + 2];
+    v[R + 1][2] = cur[rn + 3];
+    v[R + 1][3] = cur[rn + 4];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        v[i + 1][0] = lane_west(a[i][1]);
+        v[i + 1][1] = a[i][0];
+        v[i + 1][2] = a[i][1];
+        v[i + 1][3] = lane_east(a[i][0]);
+    }
+    T ps[R + 2][2];     // x-1 + x+1 of each row, shared by the corner terms above and below
+    if (!(MC > 2) && CORNER) {
+#pragma unroll
+        for (int j = 0; j < R + 2; ++j) {
+            ps[j][0] = v[j][0] + v[j][2];
+            ps[j][1] = v[j][1] + v[j][3];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            T acc = co[i][c][0] * v[i + 1][c + 1];
+            acc += co[i][c][1] * v[i + 1][c];
+            acc += co[i][c][2] * v[i + 1][c + 2];
+            acc += co[i][c][3] * v[i][c + 1];
+            acc += co[i][c][4] * v[i + 2][c + 1];
+            if (MC > 2) {
+                acc += co[i][c][5] * v[i][c];
+                acc += co[i][c][6] * v[i][c + 2];
+                acc += co[i][c][7] * v[i + 2][c];
+                acc += co[i][c][8] * v[i + 2][c + 2];
+            } else if (CORNER) {
+                acc += co[i][c][5] * (ps[i][c] + ps[i + 2][c]);
+            }
+            acc += fas * fr[i][c];
+            acc += fbs * fi[i][c];
+            b[i][c] = acc + e[i][c] * b[i][c];
+        }
+    }
+    nxt[wf] = b[0][0];
+    nxt[wf + 1] = b[0][1];
+    nxt[wl] = b[R - 1][0];
+    nxt[wl + 1] = b[R - 1][1];
+}
+
+template <typename T, int SC, int MC, int R, int W>
+__device__ __forceinline__ void tb_tile3(T *__restrict__ xl, const T *__restrict__ u_in,
+                                         const T *__restrict__ up_in, T *__restrict__ u_out,
+                                         T *__restrict__ up_out, const T *__restrict__ m,
+                                         const T *__restrict__ dn,
+                                         const typename V2t<T>::type *__restrict__ F, int ny,
+                                         int nx, const Stencil<T> &st, int k, int halo, int gy0,
+                                         int gx0, const double *fa, const double *fb,
+                                         const int *out_step, double *const *out)
+{
+    constexpr int EX = 128, EY = R * W;
+    constexpr int US = EX + 4;
+    constexpr int CB = (2 * W + 2) * US;
+    constexpr int NCO = MC > 2 ? 9 : (SC > 2 ? 6 : 5);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r0 = wv * R;
+    const int gxl = gx0 + 2 * lane;      // the lane's first column
+
+    T co[R][2][NCO], fr[R][2], fi[R][2], e[R][2];
+    T u0[R][2], u1[R][2];
+    {
+        // cells at storage columns gxl, gxl + 1, gxl + 2 of rows gy0+r0 .. gy0+r0+R
+        T cm[R + 1][3], d[R][2];
+#pragma unroll
+        for (int i = 0; i <= R; ++i) {
+            const int sy = gy0 + r0 + i;
+            const bool rok = (unsigned)sy <= (unsigned)ny;
+            const T *mrow = m + (int64_t)sy * (nx + 1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                cm[i][c] = (rok && (unsigned)(gxl + c) <= (unsigned)nx) ? mrow[gxl + c] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int gy = gy0 + r0 + i;
+            const int64_t row = (int64_t)gy * nx;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const bool in = (unsigned)gy < (unsigned)ny && (unsigned)(gxl + c) < (unsigned)nx;
+                u0[i][c] = u1[i][c] = d[i][c] = fr[i][c] = fi[i][c] = T(0);
+                if (in) {
+                    u0[i][c] = (u_in + row)[gxl + c];
+                    u1[i][c] = (up_in + row)[gxl + c];
+                    d[i][c] = (dn + row)[gxl + c];
+                    const auto f = (F + row)[gxl + c];
+                    fr[i][c] = f.x;
+                    fi[i][c] = f.y;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                fold_node<T, SC, MC, NCO>(st, d[i][c], cm[i][c], cm[i][c + 1], cm[i + 1][c],
+                                          cm[i + 1][c + 1], co[i][c]);
+                fr[i][c] *= d[i][c];
+                fi[i][c] *= d[i][c];
+                e[i][c] = T(1) - T(2) * d[i][c];
+            }
+    }
+    for (int t = threadIdx.x; t < 2 * CB; t += 64 * W) xl[t] = T(0);
+    __syncthreads();
+    const int rs = 2 * wv * US + 2 * lane, rn = (2 * wv + 3) * US + 2 * lane;
+    const int wf = (2 * wv + 1) * US + 2 * lane + 2, wl = (2 * wv + 2) * US + 2 * lane + 2;
+    xl[wf] = u0[0][0];
+    xl[wf + 1] = u0[0][1];
+    xl[wl] = u0[R - 1][0];
+    xl[wl + 1] = u0[R - 1][1];
+    __syncthreads();
+
+    auto xok = [&](int c) {
+        const int x = 2 * lane + c;
+        return x >= halo && x < EX - halo && (unsigned)(gxl + c) < (unsigned)nx;
+    };
+    auto snapshot = [&](int s, const T(&v)[R][2]) {
+        if (s + 1 == out_step[0] || s + 1 == out_step[1]) {
+            double *o = (s + 1 == out_step[0]) ? out[0] : out[1];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int r = r0 + i;
+                const int gy = gy0 + r;
+                if (r < halo || r >= EY - halo || (unsigned)gy >= (unsigned)ny) continue;
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    if (xok(c)) (o + 2 * (int64_t)gy * nx)[2 * (gxl + c)] = (double)v[i][c];
+            }
+        }
+    };
+    auto active = [&](int s) { return r0 + R > s + 1 && r0 < EY - 1 - s; };
+    T *c0 = xl, *c1 = xl + CB;
+    for (int s = 0; s < k; s += 2) {
+        if (active(s)) {
+            tb3_step<T, SC, MC, R, NCO>(c0, c1, rs, rn, wf, wl, co, fr, fi, e, u0, u1,
+                                        (T)fa[s], (T)fb[s]);
+            snapshot(s, u1);
+        }
+        __syncthreads();
+        if (s + 1 == k) break;
+        if (active(s + 1)) {
+            tb3_step<T, SC, MC, R, NCO>(c1, c0, rs, rn, wf, wl, co, fr, fi, e, u1, u0,
+                                        (T)fa[s + 1], (T)fb[s + 1]);
+            snapshot(s + 1, u0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int r = r0 + i;
+        const int gy = gy0 + r;
+        if (r < halo || r >= EY - halo || (unsigned)gy >= (unsigned)ny) continue;
+        const int64_t row = (int64_t)gy * nx;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            if (xok(c)) {
+                (u_out + row)[gxl + c] = (k & 1) ? u1[i][c] : u0[i][c];
+                (up_out + row)[gxl + c] = (k & 1) ? u0[i][c] : u1[i][c];
+            }
+    }
+}
+
+// 1024-thread workgroups need the 128-VGPR budget of four waves per SIMD;
+// 512-thread ones ask for it too when their per-node state (about 11 words
+// per node, 2R nodes per lane) leaves room, so that two workgroups share a CU.
+template <typename T, int R, int W>
+constexpr int tb3_waves_per_eu()
+{
+    return (W >= 16 || 2 * R * 11 * (int)sizeof(T) / 4 <= 100) ? 4 : 2;
+}
+
+template <typename T, int SC, int MC, int R, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(tb3_waves_per_eu<T, R, W>())))
+void k_sweep2d_tb3(
+    const T *__restrict__ u_in, const T *__restrict__ up_in, T *__restrict__ u_out,
+    T *__restrict__ up_out, const T *__restrict__ m, const T *__restrict__ dn,
+    const typename V2t<T>::type *__restrict__ F, int ny, int nx, Stencil<T> st, TBCoef cf,
+    int tiles_x, int ntiles, int per_xcd)
+{
+    constexpr int EX = 128, EY = R * W;
+    __shared__ T xl[2 * (2 * W + 2) * (EX + 4)];
+    const int id = blockIdx.x;
+    const int tile = (id % 8) * per_xcd + id / 8;
+    if (tile >= ntiles) return;
+    const int k = cf.k;
+    const int OX = EX - 2 * k, OY = EY - 2 * k;
+    const int ty = tile / tiles_x, tx = tile % tiles_x;
+    tb_tile3<T, SC, MC, R, W>(xl, u_in, up_in, u_out, up_out, m, dn, F, ny, nx, st, k, k,
+                              ty * OY - k, tx * OX - k, cf.fa, cf.fb, cf.out_step, cf.out);
 }
 
 // Tiles of 32 rows are sized for two workgroups per CU: ask for the
@@ -560,7 +796,7 @@ __device__ __forceinline__ void tb_tile_mrhs(T *__restrict__ xl, const BFieldT<T
     };
     auto active = [&](int s) { return r0 + R > s + 1 && r0 < EY - 1 - s; };
     const double *tab = f0.tab + 2 * j0;
-    for (int s = 0; s < k; s += 2) {
+    auto step_pair = [&](int s) -> bool {
         if (active(s)) {
             const T fas = (T)tab[2 * s], fbs = (T)tab[2 * s + 1];
 #pragma unroll
@@ -572,7 +808,7 @@ __device__ __forceinline__ void tb_tile_mrhs(T *__restrict__ xl, const BFieldT<T
                 }
         }
         __syncthreads();
-        if (s + 1 == k) break;
+        if (s + 1 == k) return false;
         if (active(s + 1)) {
             const T fas = (T)tab[2 * s + 2], fbs = (T)tab[2 * s + 3];
 #pragma unroll
@@ -584,6 +820,15 @@ __device__ __forceinline__ void tb_tile_mrhs(T *__restrict__ xl, const BFieldT<T
                 }
         }
         __syncthreads();
+        return s + 2 < k;
+    };
+    if constexpr (MC > 2) {
+        for (int s = 0; step_pair(s); s += 2) {
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < TDP_TB_KMAX; s += 2)
+            if (!step_pair(s)) break;
     }
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
@@ -907,6 +1152,30 @@ static hipError_t launch_tb2_t(const TBArgs &a, const Stencil<T> &st, hipStream_
 }
 
 template <typename T, int R, int W>
+static hipError_t launch_tb3_t(const TBArgs &a, const Stencil<T> &st, hipStream_t s)
+{
+    constexpr int EX = 128, EY = R * W;
+    const int k = a.cf.k;
+    const int OX = EX - 2 * k, OY = EY - 2 * k;
+    if (k < 1 || k > TDP_TB_KMAX || OY < 1) return hipErrorInvalidValue;
+    const int tiles_x = (a.nx + OX - 1) / OX, tiles_y = (a.ny + OY - 1) / OY;
+    const int ntiles = tiles_x * tiles_y;
+    const int per_xcd = (ntiles + 7) / 8;
+    dim3 grd(8 * per_xcd), blk(64 * W);
+    const T *u = (const T *)a.u_in, *up = (const T *)a.up_in;
+    T *uo = (T *)a.u_out, *upo = (T *)a.up_out;
+    const T *m = (const T *)a.m, *dn = (const T *)a.dn;
+    const auto *F = (const typename V2t<T>::type *)a.F;
+    if (a.sc <= 3 && a.mc <= 2)
+        hipLaunchKernelGGL((k_sweep2d_tb3<T, 3, 2, R, W>), grd, blk, 0, s, u, up, uo, upo, m, dn,
+                           F, a.ny, a.nx, st, a.cf, tiles_x, ntiles, per_xcd);
+    else
+        hipLaunchKernelGGL((k_sweep2d_tb3<T, 3, 3, R, W>), grd, blk, 0, s, u, up, uo, upo, m, dn,
+                           F, a.ny, a.nx, st, a.cf, tiles_x, ntiles, per_xcd);
+    return hipGetLastError();
+}
+
+template <typename T, int R, int W>
 static hipError_t launch_tb_t(const TBArgs &a, const Stencil<T> &st, hipStream_t s)
 {
     constexpr int EX = 64, EY = R * W;
@@ -988,7 +1257,7 @@ static hipError_t launch_tb_mrhs_t(const TBMrhsLaunch &L, hipStream_t s)
 
 // Shared-medium tiles (rows per lane R x waves W, right-hand sides per
 // workgroup NR; 64 columns):
-//   FP32  0: 4 x 8, NR 4 (32 x 64)    1: 4 x 16, NR 4 (64 x 64)    2: 2 x 16, NR 6 (32 x 64)
+//   FP32  0: 4 x 8, NR 4 (32 x 64)    1: 6 x 8, NR 2 (48 x 64)     2: 8 x 8, NR 2 (64 x 64)
 //   FP64  0: 2 x 16, NR 3 (32 x 64)   1: 4 x 8, NR 2 (32 x 64)     2: 2 x 16, NR 2 (32 x 64)
 hipError_t launch_sweep2d_tb_mrhs(const TBMrhsLaunch &L, bool f64, hipStream_t s)
 {
@@ -1002,21 +1271,21 @@ hipError_t launch_sweep2d_tb_mrhs(const TBMrhsLaunch &L, bool f64, hipStream_t s
     }
     switch (L.shape) {
     case 0: return launch_tb_mrhs_t<float, 4, 8, 4>(L, s);
-    case 1: return launch_tb_mrhs_t<float, 4, 16, 4>(L, s);
-    case 2: return launch_tb_mrhs_t<float, 2, 16, 6>(L, s);
+    case 1: return launch_tb_mrhs_t<float, 6, 8, 2>(L, s);
+    case 2: return launch_tb_mrhs_t<float, 8, 8, 2>(L, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 int mrhs_nr(int shape, bool f64)
 {
-    static const int nr32[3] = {4, 4, 6}, nr64[3] = {3, 2, 2};
+    static const int nr32[3] = {4, 2, 2}, nr64[3] = {3, 2, 2};
     return (shape < 0 || shape > 2) ? 0 : (f64 ? nr64[shape] : nr32[shape]);
 }
 
 int mrhs_rows(int shape, bool f64)
 {
-    static const int r32[3] = {32, 64, 32}, r64[3] = {32, 32, 32};
+    static const int r32[3] = {32, 48, 64}, r64[3] = {32, 32, 32};
     return (shape < 0 || shape > 2) ? 0 : (f64 ? r64[shape] : r32[shape]);
 }
 
@@ -1035,15 +1304,22 @@ int tb2d_tiles(int shape, int K, int ny, int nx)
 //   2: 8 x 16 -> 128 x 64 (FP32 only)     6: 8 x 8  -> 64 x 64, 512 threads
 //   3: 4 x 8  -> 32 x 64, 512 threads     7: 2 x 16 -> 32 x 64, 1024 threads
 //   8: 8 x 16 -> 128 x 64 with per-node coefficients (FP32 only)
+// Shapes 9..13 use tb_tile3 (two columns per lane, 128 columns):
+//   9: 2 x 16 -> 32 x 128, 1024 threads   10: 4 x 8 -> 32 x 128, 512 threads
+//  11: 2 x 8  -> 16 x 128, 512 threads    12: 4 x 16 -> 64 x 128 (FP32 only)
+//  13: 8 x 8  -> 64 x 128 (FP32 only)
 int tb2d_tile_rows(int shape, bool f64)
 {
     (void)f64;
     switch (shape) {
     case 2: case 8: return 128;
-    case 3: case 5: case 7: return 32;
+    case 3: case 5: case 7: case 9: case 10: return 32;
+    case 11: return 16;
     default: return 64;
     }
 }
+
+int tb2d_tile_cols(int shape) { return shape >= 9 ? 128 : 64; }
 
 bool abd_tile_ok(int shape, bool f64)
 {
@@ -1059,7 +1335,10 @@ hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hip
     case 5: return launch_tb2_t<double, 4, 8>(a, st, s);
     case 6: return launch_tb2_t<double, 8, 8>(a, st, s);
     case 7: return launch_tb2_t<double, 2, 16>(a, st, s);
-    case 2: case 8: return hipErrorInvalidValue;     // FP32-only shapes
+    case 9: return launch_tb3_t<double, 2, 16>(a, st, s);
+    case 10: return launch_tb3_t<double, 4, 8>(a, st, s);
+    case 11: return launch_tb3_t<double, 2, 8>(a, st, s);
+    case 2: case 8: case 12: case 13: return hipErrorInvalidValue;     // FP32-only shapes
     default: return launch_tb_t<double, 8, 8>(a, st, s);
     }
 }
@@ -1102,6 +1381,11 @@ hipError_t launch_sweep2d_tb_f32(const TBArgs &a, const Stencil<float> &st, hipS
     case 6: return launch_tb2_t<float, 8, 8>(a, st, s);
     case 7: return launch_tb2_t<float, 2, 16>(a, st, s);
     case 8: return launch_tb2_t<float, 8, 16>(a, st, s);
+    case 9: return launch_tb3_t<float, 2, 16>(a, st, s);
+    case 10: return launch_tb3_t<float, 4, 8>(a, st, s);
+    case 11: return launch_tb3_t<float, 2, 8>(a, st, s);
+    case 12: return launch_tb3_t<float, 4, 16>(a, st, s);
+    case 13: return launch_tb3_t<float, 8, 8>(a, st, s);
     default: return launch_tb_t<float, 8, 8>(a, st, s);
     }
 }

@@ -172,6 +172,8 @@ hipError_t launch_sweep2d_abd_tb_f64(const TBArgs &a, const Stencil<double> &sa,
 hipError_t launch_sweep2d_abd_tb_f32(const TBArgs &a, const Stencil<float> &sa,
                                      const Stencil<float> &sb, hipStream_t s);
 int tb2d_tile_rows(int shape, bool f64);
+int tb2d_tile_cols(int shape);            // 64, or 128 for the two-column shapes 9..13
+inline bool tb2d_f32_only(int shape) { return shape == 2 || shape == 8 || shape == 12 || shape == 13; }
 bool abd_tile_ok(int shape, bool f64);    // tile shapes of the blocked I_abd kernel
 
 // 3-D sweep streamed along axis 0 (sweep3d.hip), one step per launch.

@@ -35,8 +35,19 @@ def test_bench_json_line():
     rf = out["roofline"]
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in rf, k
-    assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
+    # frac is a fraction of a real roof: the larger of the HBM fraction of the
+    # bytes a launch must move and the ALU fraction of its flops; bound names
+    # that roof, or "latency" below half of it
+    assert rf["bound"] in ("hbm", "alu", "latency") and rf["roof"] in ("hbm", "alu")
+    assert (rf["unit"], rf["peak"]) == (("GB/s", 8000.0) if rf["roof"] == "hbm" else ("TFLOP/s", 78.6))
     assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) <= 1e-12
+    assert 0 < rf["frac"] <= 1 and (rf["bound"] == "latency") == (rf["frac"] < 0.5)
+    assert rf["frac"] == max(rf["hbm_frac"], rf["alu"]["frac"])
+    launch_s = rf["avg_launch_us"] * 1e-6
+    assert abs(rf["hbm_frac"] - rf["algorithmic_bytes_per_launch"] / launch_s / 8e12) <= 1e-9
+    # the per-step 7-word model is kept apart from the roofline fraction
+    assert rf["effective_GBps_7word"] > 0
+    assert out["config"]["switched"] == [0]
 
 
 def test_traffic_table_is_consistent():
