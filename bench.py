@@ -80,7 +80,7 @@ def roofline_block(kernel, launch_us, alg_bytes, alg_flops, word, traffic=None,
     return out
 
 
-def measured_traffic(workload, prec, variant, tun, damping="node"):
+def measured_traffic(workload, prec, variant, tun, damping="node", scheme="compact"):
     """HBM bytes per launch of the dominant kernel, from the rocprofv3
     FETCH_SIZE / WRITE_SIZE runs recorded in profiles/traffic.json (scaled by
     the copy-kernel calibration); None when that kernel configuration was not
@@ -91,6 +91,8 @@ def measured_traffic(workload, prec, variant, tun, damping="node"):
     key = f"{workload}|{prec}|v{variant}|k{tun['kernel']}|d{tun['tb_depth']}|t{tun['tile']}"
     if damping != "node":
         key += f"|{damping}"
+    if scheme != "compact":
+        key += f"|{scheme}"
     rec = json.load(open(path)).get(key)
     return None if rec is None else rec["bytes_per_launch"]
 
@@ -334,7 +336,7 @@ def form_precision(rho):
         spl = {4: 2}.get(tun["kernel"], 1)
         words_launch = WORDS_PER_NODE_LAUNCH if spl > 1 else WORDS_PER_NODE_STEP
         key = f"layered3d-256|{name}|v0|k{tun['kernel']}|d{tun['tb_depth']}|t{tun['tile']}"
-        traffic = _traffic(key) if op.nP == 10 else None
+        traffic = _traffic(key)
         res[name] = {"solves_per_s": 1.0 / dt, "seconds": dt, "iters": info.iters, "n_P": op.nP,
                      "precond_applications": info.steps // (p.periods * op.nP),
                      "switched": int(info.switched),
@@ -443,7 +445,7 @@ def form_batched(rho):
         f"k_sweep2d_tb_mrhs<float> medium tile {int(shared[2])} ({nr} right-hand sides per "
         f"workgroup) depth={K}", launch_us, alg_bytes,
         flops_per_node_step(2, 9) * base.N * 64 * K, 4,
-        traffic=_traffic(f"batch64-smooth2d-512|f32|d{K}|m{int(shared[2])}"),
+        traffic=_traffic(f"batch64-smooth2d-512|f32|v0|kmrhs|d{K}|t{int(shared[2])}"),
         effective_bytes=4 * base.N * 64 * (5 + 2.0 / 64) * K,
         note="launch time = one batched application (HIP events) / its launches; "
              "effective bytes: (5 + 2/64) words per right-hand side per node-step")
@@ -713,9 +715,10 @@ def main():
     ap.add_argument("--steps-per-period", type=int, default=0,
                     help="n_P: 0 the smallest multiple of 4 above the CFL bound (Table 1), "
                          "-1 the smallest integer >= 3 above it (Im U by the 2x2 solve)")
-    ap.add_argument("--scheme", choices=["compact", "fd2"], default="compact",
+    ap.add_argument("--scheme", choices=["compact", "fd2", "q1"], default="compact",
                     help="fd2: the second-order 5-/7-point scheme of Sec. 3.1 instead of the "
-                         "compact fourth-order one")
+                         "compact fourth-order one; q1: bilinear / trilinear elements (all 27 "
+                         "points in 3-D)")
     ap.add_argument("--damping", choices=["node", "cell"], default="node",
                     help="cell: the non-diagonal damping of Sec. 6 (I_abd; needs --variant 1)")
     ap.add_argument("--variant", type=int, default=0,
@@ -865,8 +868,9 @@ def main():
     else:
         kname = f"k_sweep<{tname}> (one step per launch)"
     # the counters were taken with the compact scheme
-    traffic = (measured_traffic(args.workload, args.prec, args.variant, tun, args.damping)
-               if args.scheme == "compact" and args.steps_per_period == 0 else None)
+    # per-launch counters do not depend on n_P; they do on the stencil tables
+    traffic = measured_traffic(args.workload, args.prec, args.variant, tun, args.damping,
+                               args.scheme)
     ceiling = stream_probe()
     log(f"stream probe: copy {ceiling['copy']:.0f} GB/s, triad {ceiling['triad']:.0f} GB/s")
     # bytes one launch must move: a blocked or two-step launch reads u_j,
@@ -879,7 +883,8 @@ def main():
         words_launch = WORDS_PER_NODE_LAUNCH
     else:
         words_launch = 10 if (args.variant == 1 and tun["kernel"] == 1) else WORDS_PER_NODE_STEP
-    points = {("compact", 2): 9, ("fd2", 2): 5, ("compact", 3): 19, ("fd2", 3): 7}[(args.scheme, len(p.n))]
+    points = {("compact", 2): 9, ("fd2", 2): 5, ("q1", 2): 9, ("compact", 3): 19, ("fd2", 3): 7,
+              ("q1", 3): 27}[(args.scheme, len(p.n))]
     if cell:
         points += 5 if len(p.n) == 2 else 7           # the damping stencil of I_abd
     flops = flops_per_node_step(len(p.n), points) * (2 if args.variant == 1 and tun["kernel"] == 1 else 1)

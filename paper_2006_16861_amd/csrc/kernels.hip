@@ -136,6 +136,60 @@ __global__ __launch_bounds__(256) void k_sweep(const T *__restrict__ u, T *__res
     if (out) out[2 * i] = (double)r;
 }
 
+// 2-D form of the same step for grids beyond the MALL: a thread updates RY
+// consecutive rows of one column (a workgroup 64 columns x WV * RY rows), so
+// each u row and cell row it loads serves up to three of its updates and the
+// rows shared with the workgroups above and below are RY * WV apart instead
+// of 4 (less halo re-read from HBM).
+template <int SC, int MC, typename T, bool NT, int RY>
+__global__ __launch_bounds__(256) void k_sweep2d_col(const T *__restrict__ u, T *__restrict__ up,
+                                                     const T *__restrict__ m,
+                                                     const T *__restrict__ dn,
+                                                     const typename V2<T>::type *__restrict__ F,
+                                                     int ny, int nx, Stencil<T> st, T fa, T fb,
+                                                     double *__restrict__ out)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * RY;
+    if (x >= nx || y0 >= ny) return;
+    // u at rows y0-1 .. y0+RY, columns x-1, x, x+1; cells at rows y0 .. y0+RY,
+    // columns x, x+1 (0 outside the box)
+    T uv[RY + 2][3], cv[RY + 1][2];
+#pragma unroll
+    for (int r = 0; r < RY + 2; ++r) {
+        const int y = y0 - 1 + r;
+        const bool yin = (unsigned)y < (unsigned)ny;
+        const T *row = u + (int64_t)y * nx;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int xx = x - 1 + c;
+            uv[r][c] = (yin && (unsigned)xx < (unsigned)nx) ? row[xx] : T(0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RY + 1; ++r) {
+        const int y = y0 + r;
+        const T *row = m + (int64_t)y * (nx + 1);
+        const bool yin = y <= ny;
+        cv[r][0] = yin ? row[x] : T(0);
+        cv[r][1] = yin ? row[x + 1] : T(0);
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int y = y0 + r;
+        if (y >= ny) break;
+        const int64_t i = (int64_t)y * nx + x;
+        const T w[4] = {cv[r][0], cv[r][1], cv[r + 1][0], cv[r + 1][1]};
+        auto U = [&](int, int oy, int ox) -> T { return uv[r + 1 + oy][1 + ox]; };
+        const T acc = eval_stencil<2, SC, MC>(U, w, st);
+        const T fx = ldnt<NT>(&F[i].x), fy = ldnt<NT>(&F[i].y);
+        const T d = ldnt<NT>(dn + i);
+        const T res = d * (acc + fa * fx + fb * fy) - (T(2) * d - T(1)) * ldnt<NT>(up + i);
+        stnt<NT>(res, up + i);
+        if (out) out[2 * i] = (double)res;
+    }
+}
+
 template <typename T>
 static hipError_t launch_sweep_t(const SweepArgs &a, const Stencil<T> &st, T fa, T fb,
                                  hipStream_t s)
@@ -158,7 +212,17 @@ static hipError_t launch_sweep_t(const SweepArgs &a, const Stencil<T> &st, T fa,
         else                                                                                        \
             hipLaunchKernelGGL((k_sweep<D, SC, MC, T, false>), grd, blk, 0, s, u, up, m, dn, F, nz, ny, nx, st, fa, fb, a.out); \
     } while (0)
-    if (a.ndim == 2) {
+    if (a.ndim == 2 && nt) {
+        // beyond the MALL: RY rows per thread (fewer halo re-reads from HBM)
+        constexpr int RY = 4;
+        dim3 cgrd((nx + 63) / 64, (ny + 4 * RY - 1) / (4 * RY), 1);
+        if (a.sc <= 3 && a.mc <= 2)
+            hipLaunchKernelGGL((k_sweep2d_col<3, 2, T, true, RY>), cgrd, dim3(256), 0, s, u, up, m,
+                               dn, F, ny, nx, st, fa, fb, a.out);
+        else
+            hipLaunchKernelGGL((k_sweep2d_col<3, 3, T, true, RY>), cgrd, dim3(256), 0, s, u, up, m,
+                               dn, F, ny, nx, st, fa, fb, a.out);
+    } else if (a.ndim == 2) {
         if (a.sc <= 3 && a.mc <= 2) TDP_SWEEP(2, 3, 2);
         else TDP_SWEEP(2, 3, 3);
     } else {

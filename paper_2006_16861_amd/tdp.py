@@ -33,10 +33,15 @@ SYMBOLS = ("tdp_op_create", "tdp_op_destroy", "tdp_op_query", "tdp_apply_H",
 #          node and -1 on each axis neighbour, with a lumped (diagonal) mass; a node
 #          lies in 2^d cells and an axis pair in 2^(d-1), so S = (2d/2^d, -1/2^(d-1), 0..)
 #          and M = (1/2^d, 0..).
+#   "q1":  bilinear / trilinear finite elements (consistent mass): every class of the
+#          9- / 27-point stencil is nonzero in the mass table, so the full 27-point
+#          stencil runs in 3-D.
 SCHEMES = {
     "compact": {2: (None, None), 3: (None, None)},
     "fd2": {2: ((1.0, -0.5, 0.0), (0.25, 0.0, 0.0)),
             3: ((0.75, -0.25, 0.0, 0.0), (0.125, 0.0, 0.0, 0.0))},
+    "q1": {2: ((2 / 3, -1 / 6, -1 / 3), (1 / 9, 1 / 18, 1 / 36)),
+           3: ((1 / 3, 0.0, -1 / 12, -1 / 12), (1 / 27, 1 / 54, 1 / 108, 1 / 216))},
 }
 
 

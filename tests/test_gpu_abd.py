@@ -201,3 +201,25 @@ def test_abd_blocked_degenerate_damping():
             note(f"abd blocked degenerate damping {name} tile={tile}")
             g.set_tuning(kernel=2, tb_depth=8, tile=tile)
             assert rel(host(g.precond(dev(p.F), 2, 0.25, variant=1)), Uo) <= TOL64
+
+
+def test_abd_blocked_full_size_one_period():
+    """The benchmarked cell-damping workload (smooth2d-1024 with the cell
+    damping of Sec. 6): one period of S_T^abd on the blocked I_abd kernel
+    (tile 7 and tile 5 at depth 8, and the one-step complex kernel) against
+    the oracle element-wise; FP32 fields against it at the FP32 bar."""
+    from paper_2006_16861_amd import tdp
+    p = inputs.smooth2d(1024)
+    note("abd full size 1024^2, one period")
+    g = tdp.Operator(dev(p.c), dev(p.R), p.omega, p.h, damping="cell")
+    o = oracle.Op(p.n, p.h, p.omega, p.c, p.R, damping="cell")
+    assert g.nP == o.nP
+    Uo = o.precond(p.F, 1, 0.25, variant=1)
+    F = dev(p.F)
+    for kern, depth, tile in ((0, 0, 0), (2, 8, 7), (2, 8, 5), (1, 0, 0)):
+        g.set_tuning(kernel=kern, tb_depth=depth, tile=tile)
+        err = rel(host(g.precond(F, 1, 0.25, variant=1)), Uo)
+        note(f"  kernel {kern} depth {depth} tile {tile}: {err:.2e}")
+        assert err <= TOL64, (kern, depth, tile)
+    g32 = tdp.Operator(dev(p.c), dev(p.R), p.omega, p.h, damping="cell", prec=tdp.F32)
+    assert rel(host(g32.precond(F, 1, 0.25, variant=1)), Uo) <= 1e-4

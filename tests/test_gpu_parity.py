@@ -758,3 +758,19 @@ def test_gmres_phase_time_and_cycle_log():
     cycles = [l for l in r.stderr.splitlines() if l.startswith("tdp gmres: cycle")]
     assert len(cycles) == int(r.stdout.strip().splitlines()[-1]) and len(cycles) >= 2
     assert any(l.startswith("tdp gmres: done after") for l in r.stderr.splitlines())
+
+
+def test_onestep_2d_beyond_the_mall():
+    """The one-step 2-D sweep on a grid whose step working set exceeds the
+    MALL (non-temporal streams, RY rows per thread), with ragged edges on both
+    axes: one period against the oracle element-wise, FP64 and FP32."""
+    from paper_2006_16861_amd import tdp
+    p = inputs.random_medium((3001, 2999), seed=41, width=8)
+    note("one-step 2-D 3001 x 2999 (beyond the MALL)")
+    g, o = make_ops(p)
+    g.set_tuning(kernel=1)
+    Uo = o.precond(p.F, 1, 0.25)
+    assert rel(host(g.precond(dev(p.F), 1, 0.25)), Uo) <= TOL64
+    g32 = tdp.operator_from_problem(p, prec=tdp.F32)
+    g32.set_tuning(kernel=1)
+    assert rel(host(g32.precond(dev(p.F), 1, 0.25)), Uo) <= 1e-4
