@@ -109,3 +109,46 @@ def test_create_rejects_bad_modes_and_tables():
                 setattr(d, name, ctypes.cast(arr, ctypes.c_void_p))
         assert L.tdp_op_create(ctypes.byref(d), ctypes.byref(h)) == tdp.EINVAL, msg
         assert msg in tdp.last_error(), (msg, tdp.last_error())
+
+
+def _element_tables(d, order=3):
+    """Stiffness and mass tables of the d-linear element on the unit cell by
+    Gauss quadrature: entry k is the element-matrix value for two corners that
+    differ in k axes (scaled by the cell volume, h = 1)."""
+    import itertools
+    import numpy as np
+    x, w = np.polynomial.legendre.leggauss(order)
+    x, w = (x + 1) / 2, w / 2
+    corners = list(itertools.product((0, 1), repeat=d))
+
+    def phi(c, p):
+        return np.prod([p[a] if c[a] else 1 - p[a] for a in range(d)])
+
+    def dphi(c, p, a):
+        return np.prod([(1 if c[b] else -1) if b == a else (p[b] if c[b] else 1 - p[b])
+                        for b in range(d)])
+
+    S = np.zeros(d + 1)
+    M = np.zeros(d + 1)
+    b0 = corners[0]
+    for g in corners:
+        k = sum(1 for a in range(d) if g[a] != b0[a])
+        s_ = m_ = 0.0
+        for idx in itertools.product(range(order), repeat=d):
+            p = [x[i] for i in idx]
+            wt = np.prod([w[i] for i in idx])
+            s_ += wt * sum(dphi(b0, p, a) * dphi(g, p, a) for a in range(d))
+            m_ += wt * phi(b0, p) * phi(g, p)
+        S[k], M[k] = s_, m_
+    return S, M
+
+
+def test_q1_scheme_is_the_linear_element():
+    """The binding's "q1" preset equals the bilinear / trilinear element
+    stiffness and mass matrices, computed here from the shape functions."""
+    import numpy as np
+    from paper_2006_16861_amd import tdp
+    for d in (2, 3):
+        S, M = _element_tables(d)
+        s_pre, m_pre = tdp.SCHEMES["q1"][d]
+        assert np.allclose(S, s_pre, atol=1e-14) and np.allclose(M, m_pre, atol=1e-14), d
