@@ -398,7 +398,7 @@ extern "C" int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t)
         if (t->tile < 0 || t->tile > 2) TDP_FAIL(TDP_EINVAL, "tile must be 0, 1 or 2 for kernels 3 and 4");
     } else {
         if (t->tb_depth < 0 || t->tb_depth > TDP_TB_KMAX) TDP_FAIL(TDP_EINVAL, "tb_depth must be in [0, 16]");
-        if (t->tile < 0 || t->tile > 13) TDP_FAIL(TDP_EINVAL, "tile must be in [0, 13]");
+        if (t->tile < 0 || t->tile > 15) TDP_FAIL(TDP_EINVAL, "tile must be in [0, 15]");
         if ((t->kernel == 0 || t->kernel == 2) && tb2d_f32_only(t->tile) && op->prec == TDP_F64)
             TDP_FAIL(TDP_EINVAL, "tiles 2, 8, 12 and 13 are FP32 only");
     }
@@ -541,6 +541,9 @@ static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth, i
         !(kern == 2 && op->ndim == 2 && op->mc <= 2 && abd_tile_ok(t, f64)))
         kern = 1;
     if (kern == 2 && op->ndim != 2) kern = 1;
+    // the weights-without-d tiles hold one corner weight: tables with corner
+    // mass terms take the 32 x 64 tile instead
+    if (kern == 2 && (t == 14 || t == 15) && op->mc > 2) t = 5;
     if ((kern == 3 || kern == 4) && op->ndim != 3) kern = 1;
     if (kern == 2) {
         if (k == 0) k = 4;
@@ -974,8 +977,9 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
     cand.push_back({1, 0, 1, 0});
     if (op->ndim == 2 && op->dform == TDP_DAMP_NODE) {
         const int depths[] = {2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16};
-        for (int tile = 0; tile <= 13; ++tile) {
+        for (int tile = 0; tile <= 15; ++tile) {
             if (tb2d_f32_only(tile) && op->prec == TDP_F64) continue;
+            if ((tile == 14 || tile == 15) && op->mc > 2) continue;
             const int rows = tb2d_tile_rows(tile, op->prec == TDP_F64);
             for (int k : depths)
                 if (4 * k <= rows && 4 * k <= tb2d_tile_cols(tile)) cand.push_back({2, k, 1, tile});

@@ -379,6 +379,202 @@ __device__ __forceinline__ void tb_tile2(T *__restrict__ ul, const T *__restrict
     }
 }
 
+// Fourth form, for taller tiles (tables without corner mass terms): the
+// stencil weights are kept without the damping factor d, and d is applied
+// once per update,
+//   u_{j+1} = d (sum_q w_q u_j(q) + fa Re F + fb Im F - 2 u_{j-1}) + u_{j-1},
+// which needs no 1 - 2d factor and lets neighbouring nodes share weights: the
+// weight of the edge between rows i and i+1 of a column is stored once
+// (R + 1 per lane), the corner weight is one uniform constant, and F lives
+// in LDS (read once per node-update).  The step walks a rolling window of
+// three rows and the edge rows use packed slots (as in tb_tile_mrhs).
+// Per-node register state drops from 11 to about 7 words, so 5 or 6 rows per
+// lane fit the budget of two workgroups per CU in FP64: more work per
+// barrier, a smaller share of halo rows and fewer workgroups per launch.
+template <typename T, int SC, int R>
+__device__ __forceinline__ void tb4_step(const T *__restrict__ cur, T *__restrict__ nxt, int rs,
+                                         int rn, int wf, int wl,
+                                         const typename V2t<T>::type *__restrict__ fl,
+                                         const T (&wc)[R], const T (&ww)[R], const T (&we)[R],
+                                         const T (&wy)[R + 1], const T (&d)[R], T s2,
+                                         const T (&a)[R], T (&b)[R], T fas, T fbs)
+{
+    // rows i-1 (p), i (c), i+1 (x) at x-1, x, x+1
+    T pc = cur[rs];
+    T pp = cur[rs - 1] + cur[rs + 1];
+    T cw = lane_west(a[0]), cc = a[0], ce = lane_east(a[0]);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        T xw, xc, xe;
+        if (i + 1 < R) {
+            xc = a[i + 1];
+            xw = lane_west(xc);
+            xe = lane_east(xc);
+        } else {
+            xw = cur[rn - 1];
+            xc = cur[rn];
+            xe = cur[rn + 1];
+        }
+        const T xp = xw + xe;
+        const auto f = fl[i * 64];
+        T acc = wc[i] * cc;
+        acc += ww[i] * cw;
+        acc += we[i] * ce;
+        acc += wy[i] * pc;
+        acc += wy[i + 1] * xc;
+        if (SC > 2) acc += s2 * (pp + xp);
+        acc += fas * f.x;
+        acc += fbs * f.y;
+        acc += T(-2) * b[i];
+        b[i] = d[i] * acc + b[i];
+        pc = cc;
+        pp = cw + ce;
+        cw = xw;
+        cc = xc;
+        ce = xe;
+    }
+    nxt[wf] = b[0];
+    nxt[wl] = b[R - 1];
+}
+
+template <typename T, int SC, int R, int W>
+__device__ __forceinline__ void tb_tile4(T *__restrict__ xl, const T *__restrict__ u_in,
+                                         const T *__restrict__ up_in, T *__restrict__ u_out,
+                                         T *__restrict__ up_out, const T *__restrict__ m,
+                                         const T *__restrict__ dn,
+                                         const typename V2t<T>::type *__restrict__ F, int ny,
+                                         int nx, const Stencil<T> &st, int k, int halo, int gy0,
+                                         int gx0, const double *fa, const double *fb,
+                                         const int *out_step, double *const *out)
+{
+    using V2 = typename V2t<T>::type;
+    constexpr int EX = 64, EY = R * W;
+    constexpr int US = EX + 2;
+    constexpr int CB = (2 * W + 2) * US;
+    V2 *fl_all = (V2 *)(xl + 2 * CB);      // F of the tile, [EY][64]
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r0 = wv * R;
+    const int gx = gx0 + lane;
+    const bool xin = (unsigned)gx < (unsigned)nx;
+
+    // weights from the four cells around each node (stiffness + cell mass);
+    // zero with d at nodes outside the domain, which then stay 0
+    T wc[R], ww[R], we[R], wy[R + 1], d[R];
+    T u0[R], u1[R];
+    {
+        T ca[R + 1], cb[R + 1];
+#pragma unroll
+        for (int i = 0; i <= R; ++i) {
+            const int sy = gy0 + r0 + i;
+            const bool rok = (unsigned)sy <= (unsigned)ny;
+            const T *mrow = m + (int64_t)sy * (nx + 1);
+            ca[i] = (rok && (unsigned)gx <= (unsigned)nx) ? mrow[gx] : T(0);
+            cb[i] = (rok && (unsigned)(gx + 1) <= (unsigned)nx) ? mrow[gx + 1] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int gy = gy0 + r0 + i;
+            const bool in = xin && (unsigned)gy < (unsigned)ny;
+            const int64_t row = (int64_t)gy * nx;
+            u0[i] = u1[i] = d[i] = T(0);
+            V2 f;
+            f.x = f.y = T(0);
+            if (in) {
+                u0[i] = (u_in + row)[gx];
+                u1[i] = (up_in + row)[gx];
+                d[i] = (dn + row)[gx];
+                f = (F + row)[gx];
+            }
+            fl_all[(r0 + i) * 64 + lane] = f;
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const T mSW = ca[i], mSE = cb[i], mNW = ca[i + 1], mNE = cb[i + 1];
+            wc[i] = st.c0 + st.m[0] * ((mSW + mSE) + (mNW + mNE));
+            ww[i] = st.s[1] + st.m[1] * (mSW + mNW);
+            we[i] = st.s[1] + st.m[1] * (mSE + mNE);
+        }
+#pragma unroll
+        for (int i = 0; i <= R; ++i) wy[i] = st.s[1] + st.m[1] * (ca[i] + cb[i]);
+    }
+    const T s2 = st.s[2];
+    for (int t = threadIdx.x; t < 2 * CB; t += 64 * W) xl[t] = T(0);
+    __syncthreads();
+    const int rs = 2 * wv * US + lane + 1, rn = (2 * wv + 3) * US + lane + 1;
+    const int wf = (2 * wv + 1) * US + lane + 1, wl = (2 * wv + 2) * US + lane + 1;
+    xl[wf] = u0[0];
+    xl[wl] = u0[R - 1];
+    __syncthreads();
+
+    const V2 *fl = fl_all + r0 * 64 + lane;
+    const bool xout = lane >= halo && lane < EX - halo && xin;
+    auto snapshot = [&](int s, const T(&v)[R]) {
+        if (s + 1 == out_step[0] || s + 1 == out_step[1]) {
+            double *o = (s + 1 == out_step[0]) ? out[0] : out[1];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int r = r0 + i;
+                const int gy = gy0 + r;
+                if (r >= halo && r < EY - halo && (unsigned)gy < (unsigned)ny && xout)
+                    (o + 2 * (int64_t)gy * nx)[2 * gx] = (double)v[i];
+            }
+        }
+    };
+    auto active = [&](int s) { return r0 + R > s + 1 && r0 < EY - 1 - s; };
+    T *c0 = xl, *c1 = xl + CB;
+    auto step_pair = [&](int s) -> bool {
+        if (active(s)) {
+            tb4_step<T, SC, R>(c0, c1, rs, rn, wf, wl, fl, wc, ww, we, wy, d, s2, u0, u1,
+                               (T)fa[s], (T)fb[s]);
+            snapshot(s, u1);
+        }
+        __syncthreads();
+        if (s + 1 == k) return false;
+        if (active(s + 1)) {
+            tb4_step<T, SC, R>(c1, c0, rs, rn, wf, wl, fl, wc, ww, we, wy, d, s2, u1, u0,
+                               (T)fa[s + 1], (T)fb[s + 1]);
+            snapshot(s + 1, u0);
+        }
+        __syncthreads();
+        return s + 2 < k;
+    };
+#pragma unroll
+    for (int s = 0; s < TDP_TB_KMAX; s += 2)
+        if (!step_pair(s)) break;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int r = r0 + i;
+        const int gy = gy0 + r;
+        if (r >= halo && r < EY - halo && (unsigned)gy < (unsigned)ny && xout) {
+            const int64_t row = (int64_t)gy * nx;
+            (u_out + row)[gx] = (k & 1) ? u1[i] : u0[i];
+            (up_out + row)[gx] = (k & 1) ? u0[i] : u1[i];
+        }
+    }
+}
+
+template <typename T, int SC, int R, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4)))
+void k_sweep2d_tb4(
+    const T *__restrict__ u_in, const T *__restrict__ up_in, T *__restrict__ u_out,
+    T *__restrict__ up_out, const T *__restrict__ m, const T *__restrict__ dn,
+    const typename V2t<T>::type *__restrict__ F, int ny, int nx, Stencil<T> st, TBCoef cf,
+    int tiles_x, int ntiles, int per_xcd)
+{
+    constexpr int EX = 64, EY = R * W;
+    // two packed copies of the edge rows, then F of the tile (2 words per node)
+    __shared__ T xl[2 * (2 * W + 2) * (EX + 2) + 2 * EY * EX];
+    const int id = blockIdx.x;
+    const int tile = (id % 8) * per_xcd + id / 8;
+    if (tile >= ntiles) return;
+    const int k = cf.k;
+    const int OX = EX - 2 * k, OY = EY - 2 * k;
+    const int ty = tile / tiles_x, tx = tile % tiles_x;
+    tb_tile4<T, SC, R, W>(xl, u_in, up_in, u_out, up_out, m, dn, F, ny, nx, st, k, k,
+                          ty * OY - k, tx * OX - k, cf.fa, cf.fb, cf.out_step, cf.out);
+}
+
 // Third form: each lane holds two adjacent columns (x = 2 lane, 2 lane + 1),
 // so a wave spans 128 columns.  Against one column per lane this halves the
 // share of columns lost to the halo at a given depth and the DPP moves per
@@ -1152,6 +1348,31 @@ static hipError_t launch_tb2_t(const TBArgs &a, const Stencil<T> &st, hipStream_
 }
 
 template <typename T, int R, int W>
+static hipError_t launch_tb4_t(const TBArgs &a, const Stencil<T> &st, hipStream_t s)
+{
+    constexpr int EX = 64, EY = R * W;
+    const int k = a.cf.k;
+    const int OX = EX - 2 * k, OY = EY - 2 * k;
+    if (k < 1 || k > TDP_TB_KMAX || OX < 1 || OY < 1) return hipErrorInvalidValue;
+    const int tiles_x = (a.nx + OX - 1) / OX, tiles_y = (a.ny + OY - 1) / OY;
+    const int ntiles = tiles_x * tiles_y;
+    const int per_xcd = (ntiles + 7) / 8;
+    dim3 grd(8 * per_xcd), blk(64 * W);
+    const T *u = (const T *)a.u_in, *up = (const T *)a.up_in;
+    T *uo = (T *)a.u_out, *upo = (T *)a.up_out;
+    const T *m = (const T *)a.m, *dn = (const T *)a.dn;
+    const auto *F = (const typename V2t<T>::type *)a.F;
+    if (a.mc > 2) return hipErrorInvalidValue;     // corner mass terms: per-cell corner weights
+    if (a.sc > 2)
+        hipLaunchKernelGGL((k_sweep2d_tb4<T, 3, R, W>), grd, blk, 0, s, u, up, uo, upo, m, dn, F,
+                           a.ny, a.nx, st, a.cf, tiles_x, ntiles, per_xcd);
+    else
+        hipLaunchKernelGGL((k_sweep2d_tb4<T, 2, R, W>), grd, blk, 0, s, u, up, uo, upo, m, dn, F,
+                           a.ny, a.nx, st, a.cf, tiles_x, ntiles, per_xcd);
+    return hipGetLastError();
+}
+
+template <typename T, int R, int W>
 static hipError_t launch_tb3_t(const TBArgs &a, const Stencil<T> &st, hipStream_t s)
 {
     constexpr int EX = 128, EY = R * W;
@@ -1308,6 +1529,9 @@ int tb2d_tiles(int shape, int K, int ny, int nx)
 //   9: 2 x 16 -> 32 x 128, 1024 threads   10: 4 x 8 -> 32 x 128, 512 threads
 //  11: 2 x 8  -> 16 x 128, 512 threads    12: 4 x 16 -> 64 x 128 (FP32 only)
 //  13: 8 x 8  -> 64 x 128 (FP32 only)
+// Shapes 14..15 use tb_tile4 (weights without d, F in LDS, rolling row
+// window; tables without corner mass terms):
+//  14: 5 x 8  -> 40 x 64, 512 threads    15: 6 x 8 -> 48 x 64, 512 threads
 int tb2d_tile_rows(int shape, bool f64)
 {
     (void)f64;
@@ -1315,11 +1539,13 @@ int tb2d_tile_rows(int shape, bool f64)
     case 2: case 8: return 128;
     case 3: case 5: case 7: case 9: case 10: return 32;
     case 11: return 16;
+    case 14: return 40;
+    case 15: return 48;
     default: return 64;
     }
 }
 
-int tb2d_tile_cols(int shape) { return shape >= 9 ? 128 : 64; }
+int tb2d_tile_cols(int shape) { return shape >= 9 && shape <= 13 ? 128 : 64; }
 
 bool abd_tile_ok(int shape, bool f64)
 {
@@ -1338,6 +1564,8 @@ hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hip
     case 9: return launch_tb3_t<double, 2, 16>(a, st, s);
     case 10: return launch_tb3_t<double, 4, 8>(a, st, s);
     case 11: return launch_tb3_t<double, 2, 8>(a, st, s);
+    case 14: return launch_tb4_t<double, 5, 8>(a, st, s);
+    case 15: return launch_tb4_t<double, 6, 8>(a, st, s);
     case 2: case 8: case 12: case 13: return hipErrorInvalidValue;     // FP32-only shapes
     default: return launch_tb_t<double, 8, 8>(a, st, s);
     }
@@ -1386,6 +1614,8 @@ hipError_t launch_sweep2d_tb_f32(const TBArgs &a, const Stencil<float> &st, hipS
     case 11: return launch_tb3_t<float, 2, 8>(a, st, s);
     case 12: return launch_tb3_t<float, 4, 16>(a, st, s);
     case 13: return launch_tb3_t<float, 8, 8>(a, st, s);
+    case 14: return launch_tb4_t<float, 5, 8>(a, st, s);
+    case 15: return launch_tb4_t<float, 6, 8>(a, st, s);
     default: return launch_tb_t<float, 8, 8>(a, st, s);
     }
 }

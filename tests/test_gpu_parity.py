@@ -214,7 +214,8 @@ def test_precond_complex_variant(name, mk):
     g, o = make_ops(p)
     T = min(p.periods, 4)
     Uo = o.precond(p.F, T, 0.25, variant=1)
-    kernels = [(1, 0, 0), (0, 0, 0)] + ([(2, 8, 5), (2, 4, 1), (2, 3, 7), (2, 8, 9)] if len(p.n) == 2 else
+    kernels = [(1, 0, 0), (0, 0, 0)] + ([(2, 8, 5), (2, 4, 1), (2, 3, 7), (2, 8, 9), (2, 8, 14)]
+                                        if len(p.n) == 2 else
                                         [(3, 8, 0), (3, 16, 2), (4, 7, 1)])
     for kern, depth, tile in kernels:
         for graph in (0, 1):
@@ -355,10 +356,10 @@ TB_CASES = [
 
 
 # deepest depth each tile is run at here (4 x depth <= its rows)
-TILE_MAX_DEPTH = {3: 4, 5: 4, 7: 4, 9: 8, 10: 8, 11: 4}
+TILE_MAX_DEPTH = {3: 4, 5: 4, 7: 4, 9: 8, 10: 8, 11: 4, 14: 10, 15: 12}
 
 
-@pytest.mark.parametrize("tile", [0, 1, 3, 4, 5, 6, 7, 9, 10, 11])
+@pytest.mark.parametrize("tile", [0, 1, 3, 4, 5, 6, 7, 9, 10, 11, 14, 15])
 @pytest.mark.parametrize("depth", [1, 3, 4, 5, 8, 12, 16])
 @pytest.mark.parametrize("name,mk", TB_CASES)
 def test_precond_blocked_f64(name, mk, depth, tile):
@@ -376,7 +377,7 @@ def test_precond_blocked_f64(name, mk, depth, tile):
     assert rel(U, U1) <= 1e-13
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15])
 def test_precond_blocked_f32(tile):
     p = inputs.random_medium((150, 200), seed=18, width=6)
     note(f"precond blocked f32 150x200 tile={tile}")
@@ -459,7 +460,7 @@ def test_general_cell_tables(ndim):
     x = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
     assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
     kernels = [(1, 0, 0), (2, 4, 0), (2, 3, 3), (2, 4, 4), (2, 3, 7), (2, 5, 9), (2, 3, 10),
-               (2, 4, 11)] if ndim == 2 else \
+               (2, 4, 11), (2, 6, 14)] if ndim == 2 else \
         [(1, 0, 0), (3, 16, 1), (4, 16, 1), (4, 9, 0)]
     Uo = o.precond(p.F, 2, 0.25)
     for kern, depth, tile in kernels:
@@ -492,7 +493,8 @@ def test_fd2_scheme_every_kernel(n):
     rng = np.random.default_rng(5)
     x = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
     assert rel(host(g.apply_H(dev(x))), o.apply_H(x)) <= 1e-13
-    kernels = [(1, 0, 0), (2, 8, 4), (2, 6, 5), (2, 3, 1), (2, 4, 3), (2, 8, 9), (2, 7, 10)] \
+    kernels = [(1, 0, 0), (2, 8, 4), (2, 6, 5), (2, 3, 1), (2, 4, 3), (2, 8, 9), (2, 7, 10),
+               (2, 8, 14), (2, 9, 15)] \
         if ndim == 2 else \
         [(1, 0, 0), (3, 16, 1), (3, 32, 2), (3, 7, 0), (4, 16, 1), (4, 32, 2), (4, 7, 0)]
     Uo = o.precond(p.F, 2, 0.25)
@@ -592,7 +594,8 @@ def test_general_steps_per_period_every_kernel(n):
     assert g.nP % 4 != 0
     with pytest.raises(oracle.OracleError):
         oracle.Op.from_problem(p, nP=g.nP - 1)
-    kernels = [(1, 0, 0), (2, 8, 4), (2, 6, 5), (2, 3, 1), (2, 8, 9), (2, 5, 11)] if len(n) == 2 else \
+    kernels = [(1, 0, 0), (2, 8, 4), (2, 6, 5), (2, 3, 1), (2, 8, 9), (2, 5, 11), (2, 8, 14),
+               (2, 10, 15)] if len(n) == 2 else \
         [(1, 0, 0), (3, 16, 1), (3, 7, 0), (4, 16, 1), (4, 7, 2)]
     for nP in (g.nP, g.nP + 1, g.nP + 3):
         if nP % 4 == 0:
@@ -645,7 +648,7 @@ def test_gmres_complex_variant_one_iteration_on_eigenvector(n, mode):
 
 
 @pytest.mark.parametrize("n,kernels", [
-    ((262139, 2), [(1, 0, 0), (2, 8, 5), (2, 4, 4), (2, 8, 9)]),
+    ((262139, 2), [(1, 0, 0), (2, 8, 5), (2, 4, 4), (2, 8, 9), (2, 8, 14)]),
     ((65534, 2, 3), [(1, 0, 0), (3, 32, 1), (4, 16, 0)]),
 ])
 def test_maximum_axis_lengths(n, kernels):
