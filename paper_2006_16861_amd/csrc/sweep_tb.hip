@@ -82,32 +82,44 @@ __device__ __forceinline__ void tb_tile(T *__restrict__ ul, T *__restrict__ cl,
         ul[t * US] = T(0);
         ul[t * US + EX + 1] = T(0);
     }
-    // cells: storage rows gy0 .. gy0+EY, columns gx0 .. gx0+EX
-    for (int t = threadIdx.x; t < (EY + 1) * (EX + 1); t += 64 * W) {
+    // cells (storage rows gy0 .. gy0+EY, columns gx0 .. gx0+EX) and node data
+    // are all loaded into registers before any of it goes to LDS, so the tile
+    // load is one memory round trip
+    constexpr int NCL = (EY + 1) * (EX + 1);
+    constexpr int CPT = (NCL + 64 * W - 1) / (64 * W);
+    T cv[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int t = threadIdx.x + q * 64 * W;
         const int cy = t / (EX + 1), cx = t % (EX + 1);
         const int sy = gy0 + cy, sx = gx0 + cx;
-        const bool ok = (unsigned)sy <= (unsigned)ny && (unsigned)sx <= (unsigned)nx;
-        cl[cy * CS + cx] = ok ? m[(int64_t)sy * (nx + 1) + sx] : T(0);
+        const bool ok = t < NCL && (unsigned)sy <= (unsigned)ny && (unsigned)sx <= (unsigned)nx;
+        cv[q] = ok ? m[(int64_t)sy * (nx + 1) + sx] : T(0);
     }
-    T uprev[R], d[R], fr[R], fi[R];
+    T uprev[R], d[R], fr[R], fi[R], uc[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const int r = wv * R + i;
         const int gy = gy0 + r;
         const bool in = xin && (unsigned)gy < (unsigned)ny;
         const int64_t g = (int64_t)gy * nx + gx;
-        T uc = T(0);
-        uprev[i] = d[i] = fr[i] = fi[i] = T(0);
+        uc[i] = uprev[i] = d[i] = fr[i] = fi[i] = T(0);
         if (in) {
-            uc = u_in[g];
+            uc[i] = u_in[g];
             uprev[i] = up_in[g];
             d[i] = dn[g];
             const auto f = F[g];
             fr[i] = f.x;
             fi[i] = f.y;
         }
-        ul[(r + 1) * US + lane + 1] = uc;
     }
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int t = threadIdx.x + q * 64 * W;
+        if (t < NCL) cl[(t / (EX + 1)) * CS + t % (EX + 1)] = cv[q];
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) ul[(wv * R + i + 1) * US + lane + 1] = uc[i];
     __syncthreads();
 
     T unew[R];
@@ -472,22 +484,25 @@ __device__ __forceinline__ void tb_tile4(T *__restrict__ xl, const T *__restrict
             ca[i] = (rok && (unsigned)gx <= (unsigned)nx) ? mrow[gx] : T(0);
             cb[i] = (rok && (unsigned)(gx + 1) <= (unsigned)nx) ? mrow[gx + 1] : T(0);
         }
+        // every row's loads are issued before F goes to LDS: storing a row as
+        // soon as it is loaded would cost one memory round trip per row
+        V2 f[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const int gy = gy0 + r0 + i;
             const bool in = xin && (unsigned)gy < (unsigned)ny;
             const int64_t row = (int64_t)gy * nx;
             u0[i] = u1[i] = d[i] = T(0);
-            V2 f;
-            f.x = f.y = T(0);
+            f[i].x = f[i].y = T(0);
             if (in) {
                 u0[i] = (u_in + row)[gx];
                 u1[i] = (up_in + row)[gx];
                 d[i] = (dn + row)[gx];
-                f = (F + row)[gx];
+                f[i] = (F + row)[gx];
             }
-            fl_all[(r0 + i) * 64 + lane] = f;
         }
+#pragma unroll
+        for (int i = 0; i < R; ++i) fl_all[(r0 + i) * 64 + lane] = f[i];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const T mSW = ca[i], mSE = cb[i], mNW = ca[i + 1], mNE = cb[i + 1];
