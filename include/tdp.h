@@ -122,13 +122,17 @@ typedef struct {
  * (computational frequency), dt = 2 pi / (omega_c n_P),
  * alpha = (omega_c dt)^2 / (4 sin^2(omega_c dt / 2)),
  * beta = omega_c dt / sin(omega_c dt), lam_bar = upper bound on lambda_max(A),
- * lam_im = upper bound on lambda_max(Im H) with the cell damping (else 0). */
+ * lam_im = upper bound on lambda_max(Im H) with the cell damping (else 0).
+ * res_aborts: resident-tile launches (tuning kernel 5) that ended early
+ * because not every tile was resident; each such application was redone
+ * with the blocked sweep, and the op's tuning went back to auto. */
 typedef struct {
     double omega_c, dt, alpha, beta, lam_bar;
     int n_P;
     int ndim;
     int64_t N;
     double lam_im;
+    int res_aborts;
 } tdp_op_info;
 
 /* GMRES configuration (Sec. 2.4: left preconditioning P H U = P F with
@@ -269,8 +273,17 @@ int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
  *               cell damping, tiles 5 and 7 in FP64 and 4..7 in FP32, mass
  *               tables without corner entries), 3 streamed along axis 0 (3-D, Table 1
  *               variant), 4 streamed along axis 0 with two steps per launch
- *               (3-D, Table 1 variant); inapplicable choices fall back to 1
+ *               (3-D, Table 1 variant), 5 resident tiles (2-D, FP64, node
+ *               damping, tables without corner mass entries: each 88x64
+ *               tile stays on one compute unit for up to 1024 steps per
+ *               launch and swaps k-wide halo bands with its neighbours
+ *               through global memory every k steps; the tiles must fit the
+ *               compute units and all be resident at once, so a concurrent
+ *               kernel that holds compute units makes the application fail
+ *               with TDP_EHIP; elsewhere kernel 5 falls back to the auto
+ *               choice); inapplicable choices fall back to 1
  *  tb_depth     kernel 2: steps per launch, 1..16 (0 auto);
+ *               kernel 5: steps between halo exchanges, 2, 4, 6 or 8 (0: 4);
  *               kernels 3, 4: planes per chunk (0 auto: 32, halved down
  *               to 8 until the launch has about 8192 waves)
  *  use_graph    1 capture the step loop in a hipGraph and replay it (loops
@@ -293,9 +306,18 @@ typedef struct {
 
 int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t);
 
+/* Test hook of the resident sweep's recovery path (tuning kernel 5): with
+ * on = 1, each resident launch of this op waits for a flag value that no
+ * tile writes, gives up after 16 polls and ends early, as it does when its
+ * tiles are not all resident; the application is then redone with the
+ * blocked sweep and counted in tdp_op_info.res_aborts.  on = 0 restores the
+ * normal waits.  Returns TDP_OK or TDP_EINVAL. */
+int tdp_op_force_resident_abort(tdp_op *op, int on);
+
 /* Autotuner: times each sweep variant applicable to this op (one step per
  * launch; blocked tile shapes x depths 2-10, 12, 16 (4 x depth
- * at most the tile's rows) for the 2-D Table 1 loop; the blocked I_abd tiles
+ * at most the tile's rows) and the resident tiles at exchange depths 2, 4, 6,
+ * 8 for the 2-D Table 1 loop; the blocked I_abd tiles
  * x depths 2, 3, 4, 6, 8 with the 2-D cell damping; streamed column shapes x
  * chunk lengths 4, 8, 16, 32, 64 in 3-D, with one and two steps per launch) over
  * periods_T periods with HIP events on the op's stream, and makes

@@ -119,6 +119,10 @@ static int free_op(tdp_op *op)
                     op->u3, op->u4, op->rc, op->Fst, op->scratch, op->V, op->wv, op->tv, op->rv,
                     op->xv, op->red, op->dcoef};
     for (void *b : bufs) (void)hipFree(b);
+    (void)hipFree(op->res_shadow);
+    (void)hipFree(op->res_flags);
+    for (auto &kv : op->dtables) (void)hipFree(kv.second);
+    if (op->res_host) (void)hipHostFree(op->res_host);
     if (op->hres) (void)hipHostFree(op->hres);
     if (op->own_stream && op->stream) (void)hipStreamDestroy(op->stream);
     delete op;
@@ -194,6 +198,7 @@ static int create_impl(const tdp_op_desc *d, tdp_op *op)
 
     TDP_CHECK_HIP(hipGetDevice(&op->device));
     TDP_CHECK(noalloc_setup_device(op->device));
+    TDP_CHECK_HIP(hipDeviceGetAttribute(&op->ncu, hipDeviceAttributeMultiprocessorCount, op->device));
     op->user_stream = (hipStream_t)d->stream;
     if (op->user_stream) {
         op->stream = op->user_stream;
@@ -385,6 +390,7 @@ extern "C" int tdp_op_query(const tdp_op *op, tdp_op_info *o)
     o->ndim = op->ndim;
     o->N = op->N;
     o->lam_im = op->lam_im;
+    o->res_aborts = op->res_aborts;
     return TDP_OK;
 }
 
@@ -392,7 +398,7 @@ extern "C" int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t)
 {
     clear_error();
     if (!op || !t) TDP_FAIL(TDP_EINVAL, "NULL argument");
-    if (t->kernel < 0 || t->kernel > 4) TDP_FAIL(TDP_EINVAL, "kernel must be in [0, 4]");
+    if (t->kernel < 0 || t->kernel > 5) TDP_FAIL(TDP_EINVAL, "kernel must be in [0, 5]");
     if (t->kernel == 3 || t->kernel == 4) {
         if (t->tb_depth < 0 || t->tb_depth > (1 << 20)) TDP_FAIL(TDP_EINVAL, "bad chunk length");
         if (t->tile < 0 || t->tile > 2) TDP_FAIL(TDP_EINVAL, "tile must be 0, 1 or 2 for kernels 3 and 4");
@@ -403,6 +409,17 @@ extern "C" int tdp_op_set_tuning(tdp_op *op, const tdp_tuning *t)
             TDP_FAIL(TDP_EINVAL, "tiles 2, 8, 12 and 13 are FP32 only");
     }
     op->tune = *t;
+    return TDP_OK;
+}
+
+extern "C" int tdp_op_force_resident_abort(tdp_op *op, int on)
+{
+    clear_error();
+    if (!op) TDP_FAIL(TDP_EINVAL, "NULL argument");
+    if (on != 0 && on != 1) TDP_FAIL(TDP_EINVAL, "on must be 0 or 1");
+    op->res_force_abort = on != 0;
+    for (auto &kv : op->graphs) (void)hipGraphExecDestroy(kv.second);   // graphs hold the old waits
+    op->graphs.clear();
     return TDP_OK;
 }
 
@@ -524,11 +541,34 @@ static int ensure_complex_fields(tdp_op *op)
 // (depth = planes per chunk).  kernel 0 chooses all three: the blocked 2-D
 // sweep on the 32 x 64 tile (FP64) or the 128 x 64 tile (FP32) at depth 8,
 // the streamed 3-D sweep on 8 x 64 columns, with the chunk below.
-static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth, int *tile)
+// Kernel 5, the resident-tile 2-D sweep (exchange depth = depth), applies to
+// FP64 Table 1 fields with node damping and tables without corner mass
+// terms, on grids whose tiles fit the compute units (one workgroup each);
+// elsewhere, and for the allocation-free entry point (resident = false), the
+// plan falls back to the blocked sweep.
+static bool res_applies(const tdp_op *op, int k)
+{
+    return op->ndim == 2 && op->dform == TDP_DAMP_NODE && op->mc <= 2 && op->prec == TDP_F64 &&
+           res_tiles(op->n[0], op->n[1], k, true, nullptr, nullptr) > 0 &&
+           res_tiles(op->n[0], op->n[1], k, true, nullptr, nullptr) <= op->ncu;
+}
+
+static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth, int *tile,
+                       bool resident = true)
 {
     int kern = op->tune.kernel, k = op->tune.tb_depth, t = op->tune.tile;
     (void)variant;    // Definition 4 runs the same kernels as two real passes
     const bool f64 = op->prec == TDP_F64;
+    if (kern == 5) {
+        if (k == 0) k = 4;
+        if (resident && res_applies(op, k)) {
+            *kernel = 5;
+            *depth = k;
+            *tile = 0;
+            return;
+        }
+        kern = k = t = 0;
+    }
     if (kern == 0) {
         kern = op->ndim == 2 ? 2 : 3;
         k = kern == 2 ? 8 : 0;
@@ -636,6 +676,102 @@ static int issue_steps_tb(tdp_op *op, const LoopBufs &lb, int T, double rho, int
         std::swap(prev, nprev);
     }
     return TDP_OK;
+}
+
+// Resident-tile loop (kernel 5): launches of up to TDP_RES_MAXSTEPS steps,
+// each preceded by a fill of the tile flags and the abort word, ping-ponging
+// between the field pairs (u0, u1) and (v0, v1).
+static int issue_steps_res(tdp_op *op, const LoopBufs &lb, int T, double rho, int k,
+                           const void *Fin, int tabv, double *out_final, double *out_snap)
+{
+    hipStream_t s = op->stream;
+    const int64_t Ns = (int64_t)T * op->nP, jsnap = out_snap ? Ns - snap_lag(op->nP) : -1;
+    auto it = op->dtables.find(std::make_tuple(T, rho, tabv));
+    if (it == op->dtables.end()) TDP_FAIL(TDP_EINVAL, "resident sweep: forcing table not staged");
+    ResArgs a;
+    a.ny = op->n[0];
+    a.nx = op->n[1];
+    a.sc = op->sc;
+    a.k = k;
+    const int nt = res_tiles(a.ny, a.nx, k, true, &a.tiles_x, &a.tiles_y);
+    if (nt <= 0 || nt > op->res_ntiles) TDP_FAIL(TDP_EINVAL, "resident sweep: tile grid not set up");
+    a.m = op->m;
+    a.dn = op->dn;
+    a.F = Fin;
+    a.shadow = op->res_shadow;
+    a.flags = op->res_flags;
+    a.poll_limit = op->res_force_abort ? 16 : (1 << 20);
+    a.wait_bias = op->res_force_abort ? (1 << 30) : 0;
+    const size_t fb = sizeof(double) * op->N;
+    const size_t flag_bytes = sizeof(int) * ((size_t)nt * TDP_RES_FLAG_STRIDE + TDP_RES_FLAG_STRIDE);
+    void *cur = lb.u0, *prev = lb.u1, *ncur = lb.v0, *nprev = lb.v1;
+    TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
+    TDP_CHECK_HIP(launch_fill_zero(prev, fb, s));
+    for (int64_t j0 = 0; j0 < Ns; j0 += TDP_RES_MAXSTEPS) {
+        const int n = (int)std::min<int64_t>(TDP_RES_MAXSTEPS, Ns - j0);
+        a.nsteps = n;
+        a.u_in = cur;
+        a.up_in = prev;
+        a.u_out = ncur;
+        a.up_out = nprev;
+        a.tab = it->second + 2 * j0;
+        a.out_step[0] = (jsnap > j0 && jsnap <= j0 + n) ? (int)(jsnap - j0) : 0;
+        a.out[0] = out_snap;
+        a.out_step[1] = (Ns > j0 && Ns <= j0 + n) ? (int)(Ns - j0) : 0;
+        a.out[1] = out_final;
+        TDP_CHECK_HIP(launch_fill_zero(op->res_flags, flag_bytes, s));
+        TDP_CHECK_HIP(launch_sweep2d_res_f64(a, op->st_step, s));
+        std::swap(cur, ncur);
+        std::swap(prev, nprev);
+    }
+    return TDP_OK;
+}
+
+// Buffers of the resident sweep, allocated before any capture: exchange
+// buffer (two parities of every tile's two-level band), tile flags with the abort word, its pinned mirror, and device
+// copies of the forcing tables the loop reads.
+static int ensure_res(tdp_op *op, int T, double rho, int variant)
+{
+    if (!op->res_shadow) {
+        const size_t n = 2 * (size_t)op->ncu * res_band_values(true);
+        if (hipMalloc(&op->res_shadow, sizeof(double) * n) != hipSuccess)
+            TDP_FAIL(TDP_ENOMEM, "device allocation of the exchange buffer failed");
+    }
+    if (!op->res_flags) {
+        const size_t n = (size_t)op->ncu * TDP_RES_FLAG_STRIDE + TDP_RES_FLAG_STRIDE;
+        if (hipMalloc(&op->res_flags, sizeof(int) * n) != hipSuccess ||
+            hipHostMalloc(&op->res_host, sizeof(int)) != hipSuccess)
+            TDP_FAIL(TDP_ENOMEM, "allocation of the tile flags failed");
+        op->res_ntiles = op->ncu;
+    }
+    const int tabvs[2] = {0, 2};
+    for (int q = 0; q < (variant ? 2 : 1); ++q) {
+        const auto key = std::make_tuple(T, rho, tabvs[q]);
+        if (op->dtables.count(key)) continue;
+        const std::vector<double> &h = forcing_table(op, T, rho, tabvs[q]);
+        double *d = nullptr;
+        if (hipMalloc(&d, sizeof(double) * h.size()) != hipSuccess)
+            TDP_FAIL(TDP_ENOMEM, "device allocation of a forcing table failed");
+        if (hipMemcpy(d, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(d);
+            TDP_FAIL(TDP_EHIP, "copy of a forcing table failed");
+        }
+        op->dtables.emplace(key, d);
+    }
+    return TDP_OK;
+}
+
+// After a resident loop: the abort word is raised when a tile waited in vain
+// for a neighbour, which happens when not every tile was resident at once
+// (other work holding compute units).  Returns 1 then, else TDP_OK or a HIP
+// error.
+static int res_check(tdp_op *op, int ntiles)
+{
+    hipStream_t s = op->stream;
+    TDP_CHECK_HIP(hipMemcpyAsync(op->res_host, op->res_flags + (size_t)ntiles * TDP_RES_FLAG_STRIDE,
+                                 sizeof(int), hipMemcpyDeviceToHost, s));
+    TDP_CHECK_HIP(hipStreamSynchronize(s));
+    return *op->res_host ? 1 : TDP_OK;
 }
 
 // Streamed 3-D loop with two steps per launch, ping-ponging between the field
@@ -758,9 +894,10 @@ static int issue_steps_loop(tdp_op *op, const LoopBufs &lb, int T, double rho, i
                             const void *Fin, void *U)
 {
     int kern, depth, tile;
-    sweep_plan(op, variant, &kern, &depth, &tile);
+    sweep_plan(op, variant, &kern, &depth, &tile, !lb.table_free);
     double *Ud = (double *)U;
     auto real_pass = [&](int tabv, double *fin, double *snap) -> int {
+        if (kern == 5) return issue_steps_res(op, lb, T, rho, depth, Fin, tabv, fin, snap);
         if (kern == 2) return issue_steps_tb(op, lb, T, rho, depth, tile, Fin, tabv, fin, snap);
         if (kern == 4) return issue_steps_3d2(op, lb, T, rho, depth, tile, Fin, tabv, fin, snap);
         return issue_steps_real1(op, lb, T, rho, kern, depth, tile, Fin, tabv, fin, snap);
@@ -828,6 +965,9 @@ static int issue_steps(tdp_op *op, const LoopBufs &lb, int T, double rho, int va
     return TDP_OK;
 }
 
+static int res_finish(tdp_op *op, int ntiles, int T, double rho, int variant, const void *F,
+                      void *U, bool direct);
+
 // direct: F and U are buffers owned by the op (GMRES work vectors), so the
 // loop may be captured on them; otherwise a captured loop works on the
 // staging buffers, with copies of F in and U out around the replay.
@@ -845,11 +985,19 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
         TDP_FAIL(TDP_EINVAL, "N_s = periods_T n_P = %lld exceeds 2^24", (long long)Ns);
     if (variant) TDP_CHECK(ensure_complex_fields(op));
     int64_t launches;
+    int res_nt = 0;      // tiles of the resident sweep, when it runs
     {   // allocate before any stream capture: no allocation may happen inside it
         int kern, depth, tile;
         sweep_plan(op, variant, &kern, &depth, &tile);
-        if (kern == 2 || kern == 4) TDP_CHECK(ensure_tb_fields(op));
-        launches = kern == 2 ? (Ns + depth - 1) / depth : (kern == 4 ? (Ns + 1) / 2 : Ns);
+        if (kern == 2 || kern == 4 || kern == 5) TDP_CHECK(ensure_tb_fields(op));
+        if (kern == 5) {
+            TDP_CHECK(ensure_res(op, T, rho, variant));
+            res_nt = res_tiles(op->n[0], op->n[1], depth, true, nullptr, nullptr);
+        }
+        launches = kern == 2 ? (Ns + depth - 1) / depth
+                 : kern == 4 ? (Ns + 1) / 2
+                 : kern == 5 ? 2 * ((Ns + TDP_RES_MAXSTEPS - 1) / TDP_RES_MAXSTEPS)
+                             : Ns;
         if (variant == 1 && kern != 1) launches *= 2;     // two real passes
     }
     const LoopBufs lb{op->u0, op->u1, op->v0, op->v1, false};
@@ -862,7 +1010,8 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
             TDP_CHECK_HIP(launch_cvt_c128_to_c64(F, op->Fst, op->N, s));
             Fin = op->Fst;
         }
-        return issue_steps(op, lb, T, rho, variant, Fin, U);
+        TDP_CHECK(issue_steps(op, lb, T, rho, variant, Fin, U));
+        return res_nt ? res_finish(op, res_nt, T, rho, variant, F, U, direct) : TDP_OK;
     }
     // captured loop: on F and U themselves (direct), else reading op->Fstage
     // (F64) / op->Fst (F32) and writing op->Ustage
@@ -907,7 +1056,7 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
     }
     if (direct) {
         TDP_CHECK_HIP(hipGraphLaunch(it->second, s));
-        return TDP_OK;
+        return res_nt ? res_finish(op, res_nt, T, rho, variant, F, U, direct) : TDP_OK;
     }
     if (op->prec == TDP_F64)
         TDP_CHECK_HIP(hipMemcpyAsync(op->Fstage, F, 16 * op->N, hipMemcpyDeviceToDevice, s));
@@ -915,7 +1064,21 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
         TDP_CHECK_HIP(launch_cvt_c128_to_c64(F, op->Fst, op->N, s));
     TDP_CHECK_HIP(hipGraphLaunch(it->second, s));
     TDP_CHECK_HIP(hipMemcpyAsync(U, op->Ustage, 16 * op->N, hipMemcpyDeviceToDevice, s));
-    return TDP_OK;
+    return res_nt ? res_finish(op, res_nt, T, rho, variant, F, U, direct) : TDP_OK;
+}
+
+// A resident loop that ended early is redone with the blocked sweep, and the
+// op stops using the resident kernel (its tuning goes back to auto).
+static int res_finish(tdp_op *op, int ntiles, int T, double rho, int variant, const void *F,
+                      void *U, bool direct)
+{
+    const int rc = res_check(op, ntiles);
+    if (rc != 1) return rc;
+    ++op->res_aborts;
+    op->tune.kernel = 0;
+    op->tune.tb_depth = 0;
+    op->tune.tile = 0;
+    return precond_impl(op, T, rho, variant, F, U, direct);
 }
 
 int precond_noalloc_impl(tdp_op *op, int T, double rho, const void *F, void *U,
@@ -985,6 +1148,8 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
                 if (4 * k <= rows && 4 * k <= tb2d_tile_cols(tile)) cand.push_back({2, k, 1, tile});
         }
     }
+    for (int k : {2, 4, 6, 8})
+        if (res_applies(op, k)) cand.push_back({5, k, 1, 0});
     if (op->ndim == 2 && op->dform == TDP_DAMP_CELL && op->mc <= 2) {
         for (int tile = 4; tile <= 7; ++tile) {
             if (!abd_tile_ok(tile, op->prec == TDP_F64)) continue;

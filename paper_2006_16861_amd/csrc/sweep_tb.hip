@@ -184,28 +184,6 @@ __device__ __forceinline__ void tb_tile(T *__restrict__ ul, T *__restrict__ cl,
 // wave whose rows all lie outside that window skips the step (its stale rows
 // are never read again).  The exact-region, Dirichlet and output rules are
 // those of tb_tile.
-// Per-node coefficients of the step from the four cells around a node (SW,
-// SE, NW, NE) and its damping factor dd: centre, W, E, S, N, then the corner
-// weights (four with corner mass terms, one shared weight without).
-template <typename T, int SC, int MC, int NCO>
-__device__ __forceinline__ void fold_node(const Stencil<T> &st, T dd, T mSW, T mSE, T mNW, T mNE,
-                                          T (&c)[NCO])
-{
-    c[0] = dd * (st.c0 + st.m[0] * ((mSW + mSE) + (mNW + mNE)));
-    c[1] = dd * (st.s[1] + st.m[1] * (mSW + mNW));   // W
-    c[2] = dd * (st.s[1] + st.m[1] * (mSE + mNE));   // E
-    c[3] = dd * (st.s[1] + st.m[1] * (mSW + mSE));   // S
-    c[4] = dd * (st.s[1] + st.m[1] * (mNW + mNE));   // N
-    if (MC > 2) {
-        c[5] = dd * (st.s[2] + st.m[2] * mSW);
-        c[6] = dd * (st.s[2] + st.m[2] * mSE);
-        c[7] = dd * (st.s[2] + st.m[2] * mNW);
-        c[8] = dd * (st.s[2] + st.m[2] * mNE);
-    } else if (SC > 2) {
-        c[5] = dd * st.s[2];   // the four corners share one weight
-    }
-}
-
 // cur[rs - 1 .. rs + 1] and cur[rn - 1 .. rn + 1] hold the halo rows south
 // and north of the wave's rows at x-1, x, x+1; the wave's first and last new
 // rows go to nxt[wf] and nxt[wl].

@@ -176,6 +176,36 @@ int tb2d_tile_cols(int shape);            // 64, or 128 for the two-column shape
 inline bool tb2d_f32_only(int shape) { return shape == 2 || shape == 8 || shape == 12 || shape == 13; }
 bool abd_tile_ok(int shape, bool f64);    // tile shapes of the blocked I_abd kernel
 
+// Resident-tile 2-D sweep (sweep_res.hip): one workgroup per tile keeps its
+// tile in registers for a whole run of steps and swaps k-wide halo bands with
+// the neighbouring tiles through `shadow` every k steps.  Every tile must be
+// resident at once (tiles <= compute units); a wait that does not end sets
+// the abort word and the launch ends early with that status.
+#define TDP_RES_MAXSTEPS 1024   // steps of one launch (forcing scalars staged in LDS)
+#define TDP_RES_FLAG_STRIDE 32  // ints between tile flags (one 128-byte line each)
+struct ResArgs {
+    int ny, nx;
+    int sc;
+    int k;                      // steps between exchanges: 2, 4, 6 or 8
+    int nsteps;                 // steps of this launch, 1..TDP_RES_MAXSTEPS
+    int tiles_x, tiles_y;
+    const void *u_in, *up_in;   // u_j, u_{j-1}
+    void *u_out, *up_out;       // u_{j+nsteps}, u_{j+nsteps-1} (distinct from the inputs)
+    const void *m, *dn, *F;
+    const double *tab;          // (fa, fb) of the launch's steps
+    int out_step[2];            // 1-based step whose field goes to out[i] (0: none)
+    double *out[2];             // stride-2 outputs (complex128 real or imaginary part)
+    void *shadow;               // [2 parities][tiles][2 levels][band] exchange buffer
+    int *flags;                 // tiles x TDP_RES_FLAG_STRIDE ints, then the abort word
+    int poll_limit;             // flag polls before a wait gives up
+    int wait_bias;              // added to the awaited flag value (0; > 0 forces the abort path)
+};
+hipError_t launch_sweep2d_res_f64(const ResArgs &a, const Stencil<double> &st, hipStream_t s);
+int res_tile_rows(bool f64);    // extended tile rows (64 columns)
+int res_band_values(bool f64);  // exchange-buffer values per tile and parity (largest depth)
+// tiles of the resident grid at exchange depth k (0 if k is not supported)
+int res_tiles(int ny, int nx, int k, bool f64, int *tiles_x, int *tiles_y);
+
 // 3-D sweep streamed along axis 0 (sweep3d.hip), one step per launch.
 // shape 0/1/2: 8 x 64 (4 waves x 2 rows), 16 x 64 (4 waves x 4 rows), 16 x 64
 // (8 waves x 2 rows) node columns per workgroup; zc planes per chunk.
@@ -349,4 +379,15 @@ struct tdp_op {
     void *Fstage = nullptr;    // complex128 input of the captured loop (FP64)
     void *Ustage = nullptr;    // complex128 output of the captured loop
     double *gcell = nullptr;   // per-cell gradient scratch
+    // resident-tile sweep (kernel 5): compute units of the device, the
+    // exchange planes and tile flags, device copies of the forcing tables,
+    // a pinned mirror of the abort word
+    int ncu = 0;
+    void *res_shadow = nullptr;
+    int *res_flags = nullptr;
+    int res_ntiles = 0;                    // tiles the flag array holds
+    int res_aborts = 0;                    // resident launches redone with the blocked sweep
+    bool res_force_abort = false;          // test hook: every resident wait gives up
+    int *res_host = nullptr;
+    std::map<std::tuple<int, double, int>, double *> dtables;
 };

@@ -22,7 +22,8 @@ DAMPING = {"node": 0, "cell": 1}
 SYMBOLS = ("tdp_op_create", "tdp_op_destroy", "tdp_op_query", "tdp_apply_H",
            "tdp_precond_apply", "tdp_precond_apply_complex", "tdp_precond_apply_noalloc",
            "tdp_gmres_solve", "tdp_grad_m", "tdp_op_set_tuning", "tdp_op_autotune",
-           "tdp_op_get_tuning", "tdp_last_error", "tdp_batch_create", "tdp_batch_destroy",
+           "tdp_op_get_tuning", "tdp_op_force_resident_abort", "tdp_last_error",
+           "tdp_batch_create", "tdp_batch_destroy",
            "tdp_batch_set_tuning", "tdp_batch_precond", "tdp_batch_solve", "tdp_batch_autotune")
 
 
@@ -63,7 +64,7 @@ class OpInfo(ctypes.Structure):
     _fields_ = [("omega_c", ctypes.c_double), ("dt", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("lam_bar", ctypes.c_double), ("n_P", ctypes.c_int), ("ndim", ctypes.c_int),
-                ("N", ctypes.c_int64), ("lam_im", ctypes.c_double)]
+                ("N", ctypes.c_int64), ("lam_im", ctypes.c_double), ("res_aborts", ctypes.c_int)]
 
 
 class GmresCfg(ctypes.Structure):
@@ -118,6 +119,7 @@ def load(path: str = LIB_PATH):
     L.tdp_batch_precond.argtypes = [P, P, D, P, P]
     L.tdp_batch_solve.argtypes = [P, ctypes.POINTER(GmresCfg), P, P, P, P]
     L.tdp_batch_autotune.argtypes = [P, P, D, P, I]
+    L.tdp_op_force_resident_abort.argtypes = [P, I]
     L.tdp_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
         L[name].restype = L[name].restype if name == "tdp_last_error" else ctypes.c_int
@@ -307,6 +309,18 @@ class Operator:
         _check(load().tdp_op_get_tuning(self._h, ctypes.byref(t)), "tdp_op_get_tuning")
         return {"kernel": t.kernel, "tb_depth": t.tb_depth, "use_graph": t.use_graph,
                 "tile": t.tile}
+
+    @property
+    def resident_aborts(self):
+        """Resident-tile launches redone with the blocked sweep."""
+        info = OpInfo()
+        _check(load().tdp_op_query(self._h, ctypes.byref(info)), "tdp_op_query")
+        return info.res_aborts
+
+    def force_resident_abort(self, on=True):
+        """Test hook: every resident-tile launch gives up its first wait."""
+        _check(load().tdp_op_force_resident_abort(self._h, int(bool(on))),
+               "tdp_op_force_resident_abort")
 
 
 def operator_from_problem(p, device="cuda", **kw):

@@ -409,7 +409,7 @@ def test_autotune_picks_a_variant_and_stays_exact():
     note("autotune 200x180")
     g, o = make_ops(p)
     best, table = g.autotune(T=2)
-    assert len(table) >= 2 and best["kernel"] in (1, 2)
+    assert len(table) >= 2 and best["kernel"] in (1, 2, 5)
     assert min(r[3] for r in table) > 0
     U = host(g.precond(dev(p.F), 3, 0.25))
     assert rel(U, o.precond(p.F, 3, 0.25)) <= TOL64
