@@ -28,6 +28,7 @@ WORDS_PER_NODE_STEP = 7          # u_j, u_{j-1}, u_{j+1}, m, damping, Re F, Im F
 # a launch of k steps must read u_j, u_{j-1}, m, the damping factor and F
 # (2 words) and write u_{j+k}, u_{j+k-1}: 8 words per node, whatever k
 WORDS_PER_NODE_LAUNCH = 8
+RES_MAX_STEPS = 1024          # steps of one resident-tile launch (kernel 5)
 # published MI355X vector peaks (TFLOP/s); the FP32 figure needs packed FP32
 # instructions, which this build does not emit (non-packed FP32 issues at the
 # FP64 rate)
@@ -778,7 +779,11 @@ def main():
         tune_table = []
         if args.kernel == 0 and not args.no_graph:
             t = time.perf_counter()
-            best, tune_table = op.autotune(T=4, rho=args.rho, variant=args.variant)
+            # 2-D: candidates timed over a whole application (the resident
+            # kernel's per-launch set-up and its check after each application
+            # are spread over the real number of steps); 3-D over four periods
+            T_tune = (args.periods if args.periods > 0 else p.periods) if len(p.n) == 2 else 4
+            best, tune_table = op.autotune(T=T_tune, rho=args.rho, variant=args.variant)
             log(f"autotune ({(time.perf_counter() - t) * 1e3:.0f} ms): best {best}")
             for row in tune_table:
                 log(f"   kernel={int(row[0])} depth={int(row[1])} tile={int(row[2])}: "
@@ -799,7 +804,7 @@ def main():
             apply_ms, step_ms = sweep_timing(op, F, T, args.rho, args.profile_sweeps, stream,
                                              args.variant)
             tun = op.get_tuning()
-            per = {2: tun["tb_depth"], 4: 2}.get(tun["kernel"], 1)
+            per = {2: tun["tb_depth"], 4: 2, 5: RES_MAX_STEPS}.get(tun["kernel"], 1)
             launches = -(-Ns // per)
             if args.variant == 1 and tun["kernel"] != 1:
                 launches *= 2                    # two real passes
@@ -838,7 +843,7 @@ def main():
     bytes_per = words * word
     tun = op.get_tuning()
     blocked = tun["kernel"] == 2
-    steps_per_launch = tun["tb_depth"] if blocked else (2 if tun["kernel"] == 4 else 1)
+    steps_per_launch = {2: tun["tb_depth"], 4: 2, 5: min(RES_MAX_STEPS, Ns)}.get(tun["kernel"], 1)
     launches = -(-Ns // steps_per_launch)
     if args.variant == 1 and tun["kernel"] != 1:
         launches *= 2                            # Def. 4 and I_abd: two real passes
@@ -861,6 +866,9 @@ def main():
     elif tun["kernel"] == 2:
         kname = (f"k_sweep2d_{'tb2' if tun['tile'] >= 4 else 'tb'}<{tname}> "
                  f"depth={steps_per_launch} tile={tun['tile']}")
+    elif tun["kernel"] == 5:
+        kname = (f"k_sweep2d_res<{tname}> exchange depth={tun['tb_depth']} "
+                 f"(resident tiles, launches of up to {RES_MAX_STEPS} steps)")
     elif tun["kernel"] == 3:
         kname = f"k_sweep3d_stream<{tname}> shape={tun['tile']} z-chunk={tun['tb_depth']}"
     elif tun["kernel"] == 4:
@@ -879,7 +887,7 @@ def main():
     # complex field in one pass moves 10
     spl = Ns / launches
     cell = args.damping == "cell"
-    if tun["kernel"] in (2, 4) or cell and tun["kernel"] == 2:
+    if tun["kernel"] in (2, 4, 5) or cell and tun["kernel"] == 2:
         words_launch = WORDS_PER_NODE_LAUNCH
     else:
         words_launch = 10 if (args.variant == 1 and tun["kernel"] == 1) else WORDS_PER_NODE_STEP

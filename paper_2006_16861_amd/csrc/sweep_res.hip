@@ -18,7 +18,7 @@
 //   reads its halo from their bands.
 // A band is packed: the k top rows and the k bottom rows of the exact region
 // (full width), then the k left and the k right columns of the rows between
-// them (band_pos).  It is staged in LDS and copied out with whole-line
+// them, each a row-major block.  It is staged in LDS and copied out with whole-line
 // stores; a halo node is read from the band of the tile that owns it.
 // The exchange buffer and flags are accessed only with agent-scope relaxed
 // atomics, which the compiler emits with the coherent cache policy (sc1):
@@ -68,16 +68,6 @@ __device__ __forceinline__ int opaque_zero()
     int z;
     asm volatile("s_mov_b32 %0, 0" : "=s"(z));
     return z;
-}
-
-// Position of exact-region node (ly, lx) of a tile in its packed band (the
-// node must lie within k of the tile's unclipped border).
-__device__ __forceinline__ int band_pos(int ly, int lx, int k, int OX, int OY)
-{
-    if (ly < k) return ly * OX + lx;
-    if (ly >= OY - k) return (ly - (OY - 2 * k)) * OX + lx;
-    const int b = 2 * k * OX + (ly - k) * k;
-    return lx < k ? b + lx : b + (OY - 2 * k) * k + (lx - (OX - k));
 }
 
 // One step of the wave's R rows (the blocked tile's second form with d F read
@@ -163,7 +153,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_res(ResArgs a, Stencil<T> st
     const int ey0 = ty * OY, ey1 = min(ny, ey0 + OY);
     const int ex0 = tx * OX, ex1 = min(nx, ex0 + OX);
     const bool xexact = gx >= ex0 && gx < ex1;
-    // the band is defined on the unclipped tile (band_pos): a border cut by
+    // the band is defined on the unclipped tile: a border cut by
     // the domain edge has no neighbour to publish to
     const bool xband = xexact && (gx < ex0 + k || gx >= ex0 + OX - k);
     const bool xhalo = lane < k || lane >= k + OX;
@@ -257,17 +247,28 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_res(ResArgs a, Stencil<T> st
         gyw = gy0 + r0 + opaque_zero();
         if (blk > 0) {
             // publish the border band of the exact region (levels j and j-1):
-            // packed in LDS, then copied out with whole-line stores
+            // packed in LDS, then copied out with whole-line stores.  A row's
+            // block of the band and its offset there are uniform; a lane adds
+            // its column (top and bottom rows) or its place in the left and
+            // right column blocks (the rows between)
             const int par = (blk - 1) & 1;
+            const int lside = lx < k ? lx : (OY - 2 * k) * k + lx - (OX - k);
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                const int gy = gyw + i;
-                const bool yexact = gy >= ey0 && gy < ey1;
-                const bool inband = yexact && xexact && (xband || gy < ey0 + k || gy >= ey0 + OY - k);
-                if (inband) {
-                    const int pos = band_pos(gy - ey0, lx, k, OX, OY);
-                    sband[pos] = u0[i];
-                    sband[band + pos] = u1[i];
+                const int ly = gyw + i - ey0;
+                if (ly < 0 || gyw + i >= ey1) continue;
+                if (ly < k || ly >= OY - k) {
+                    const int rb = (ly < k ? ly : ly - (OY - 2 * k)) * OX;
+                    if (xexact) {
+                        sband[rb + lx] = u0[i];
+                        sband[band + rb + lx] = u1[i];
+                    }
+                } else {
+                    const int sb = 2 * k * OX + (ly - k) * k;
+                    if (xband) {
+                        sband[sb + lside] = u0[i];
+                        sband[band + sb + lside] = u1[i];
+                    }
                 }
             }
             __syncthreads();
@@ -294,22 +295,29 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_res(ResArgs a, Stencil<T> st
             }
             __syncthreads();
             if (s_abort) return;
-            // the halo from the owners' bands; the owner row and the local row
-            // are counted along the wave's rows (no division per row)
-            int tyo = gyw >= 0 ? gyw / OY : -1, ly = gyw - tyo * OY;
+            // the halo from the owners' bands: the owner's row and the part of
+            // the address it sets are uniform (counted along the rows, no
+            // division per row); a lane adds its owner's tile column and its
+            // column or place in the owner's left or right column block
+            int tyo = gyw >= 0 ? gyw / OY : -1, lyo = gyw - tyo * OY;
             const T *const base = shadow + (int64_t)par * ntl * 2 * band;
+            const int ltile = txo * 2 * band;
+            const int lsideo = lxo < k ? lxo : (OY - 2 * k) * k + lxo - (OX - k);
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 const int r = r0 + i, gy = gyw + i;
-                const bool halo = r < k || r >= k + OY || xhalo;
-                if (halo && xin && (unsigned)gy < (unsigned)ny) {
-                    const T *src = base + (int64_t)((tyo * a.tiles_x + txo) * 2) * band +
-                                   band_pos(ly, lxo, k, OX, OY);
+                const bool hrow = r < k || r >= k + OY;
+                if ((hrow || xhalo) && xin && (unsigned)gy < (unsigned)ny) {
+                    const bool full = lyo < k || lyo >= OY - k;
+                    const int ub = tyo * a.tiles_x * 2 * band +
+                                   (full ? (lyo < k ? lyo : lyo - (OY - 2 * k)) * OX
+                                         : 2 * k * OX + (lyo - k) * k);
+                    const T *src = base + ub + ltile + (full ? lxo : lsideo);
                     u0[i] = ld_coh(src);
                     u1[i] = ld_coh(src + band);
                 }
-                if (++ly == OY) {
-                    ly = 0;
+                if (++lyo == OY) {
+                    lyo = 0;
                     ++tyo;
                 }
             }
