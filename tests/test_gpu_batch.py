@@ -348,3 +348,24 @@ def test_batch_full_size_application_elementwise():
         note(f"  field {q} n={p.n}: vs single FP32 {e_single:.2e}, vs FP64 oracle {e_orc:.2e}")
         assert e_single <= 1e-6
         assert e_orc <= 1e-4
+
+
+def test_batch_rejected_table1_cycle_ends_its_field():
+    """Reading R19 in the batched form, which runs Table 1 only: a cycle that
+    lowers no true residual ends its field with ENOTCONV and the iterate of
+    least true residual (the single solve switches to Def. 4 on the same
+    problem and converges); the other field of the batch is unaffected."""
+    from paper_2006_16861_amd import tdp
+    pd, pc = inputs.disc2d(64, width=16), inputs.const2d()
+    note("batch with a rejected Table 1 cycle: disc2d-64 T=5 + const2d")
+    ops = [tdp.operator_from_problem(pd), tdp.operator_from_problem(pc)]
+    Ug, ig = ops[0].solve(dev(pd.F), T=5, tol=1e-6, max_iters=600)
+    assert ig.status == 0 and ig.switched == 1
+    b = tdp.Batch(ops, [1, 1])
+    Us, infos, rc = b.solve([dev(pd.F), dev(pc.F)], [5, pc.periods], tol=1e-6, max_iters=600)
+    assert rc == tdp.ENOTCONV
+    r0 = rel(oracle.Op.from_problem(pd).apply_H(Us[0].cpu().numpy()), pd.F)
+    assert infos[0].status == 1 and np.isfinite(r0) and r0 < 1.0
+    assert abs(infos[0].relres - r0) <= 1e-6 * r0
+    r1 = rel(oracle.Op.from_problem(pc).apply_H(Us[1].cpu().numpy()), pc.F)
+    assert infos[1].status == 0 and r1 <= 1e-6 * (1 + 1e-9)
