@@ -273,14 +273,16 @@ int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
  *               cell damping, tiles 5 and 7 in FP64 and 4..7 in FP32, mass
  *               tables without corner entries), 3 streamed along axis 0 (3-D, Table 1
  *               variant), 4 streamed along axis 0 with two steps per launch
- *               (3-D, Table 1 variant), 5 resident tiles (2-D, FP64, node
- *               damping, tables without corner mass entries: each 88x64
- *               tile stays on one compute unit for up to 1024 steps per
- *               launch and swaps k-wide halo bands with its neighbours
- *               through global memory every k steps; the tiles must fit the
- *               compute units and all be resident at once, so a concurrent
- *               kernel that holds compute units makes the application fail
- *               with TDP_EHIP; elsewhere kernel 5 falls back to the auto
+ *               (3-D, Table 1 variant), 5 resident tiles (2-D, node
+ *               damping, tables without corner mass entries: each tile,
+ *               88x64 in FP64 and 112x64 in FP32, stays on one compute unit
+ *               for up to 1024 steps per launch and swaps k-wide halo bands
+ *               with its neighbours through global memory every k steps; the
+ *               tiles must fit the compute units and all be resident at
+ *               once: when other work holds compute units a wait gives up,
+ *               the application is redone with the blocked sweep and the
+ *               op's tuning goes back to auto (tdp_op_info.res_aborts);
+ *               where kernel 5 does not apply it falls back to the auto
  *               choice); inapplicable choices fall back to 1
  *  tb_depth     kernel 2: steps per launch, 1..16 (0 auto);
  *               kernel 5: steps between halo exchanges, 2, 4, 6 or 8 (0: 4);

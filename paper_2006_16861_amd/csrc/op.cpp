@@ -542,15 +542,13 @@ static int ensure_complex_fields(tdp_op *op)
 // sweep on the 32 x 64 tile (FP64) or the 128 x 64 tile (FP32) at depth 8,
 // the streamed 3-D sweep on 8 x 64 columns, with the chunk below.
 // Kernel 5, the resident-tile 2-D sweep (exchange depth = depth), applies to
-// FP64 Table 1 fields with node damping and tables without corner mass
-// terms, on grids whose tiles fit the compute units (one workgroup each);
+// Table 1 fields with node damping and tables without corner mass terms, on grids whose tiles fit the compute units (one workgroup each);
 // elsewhere, and for the allocation-free entry point (resident = false), the
 // plan falls back to the blocked sweep.
 static bool res_applies(const tdp_op *op, int k)
 {
-    return op->ndim == 2 && op->dform == TDP_DAMP_NODE && op->mc <= 2 && op->prec == TDP_F64 &&
-           res_tiles(op->n[0], op->n[1], k, true, nullptr, nullptr) > 0 &&
-           res_tiles(op->n[0], op->n[1], k, true, nullptr, nullptr) <= op->ncu;
+    const int nt = res_tiles(op->n[0], op->n[1], k, op->prec == TDP_F64, nullptr, nullptr);
+    return op->ndim == 2 && op->dform == TDP_DAMP_NODE && op->mc <= 2 && nt > 0 && nt <= op->ncu;
 }
 
 static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth, int *tile,
@@ -693,16 +691,17 @@ static int issue_steps_res(tdp_op *op, const LoopBufs &lb, int T, double rho, in
     a.nx = op->n[1];
     a.sc = op->sc;
     a.k = k;
-    const int nt = res_tiles(a.ny, a.nx, k, true, &a.tiles_x, &a.tiles_y);
+    const bool f64 = op->prec == TDP_F64;
+    const int nt = res_tiles(a.ny, a.nx, k, f64, &a.tiles_x, &a.tiles_y);
     if (nt <= 0 || nt > op->res_ntiles) TDP_FAIL(TDP_EINVAL, "resident sweep: tile grid not set up");
-    a.m = op->m;
-    a.dn = op->dn;
+    a.m = f64 ? (const void *)op->m : (const void *)op->m32;
+    a.dn = f64 ? (const void *)op->dn : (const void *)op->dn32;
     a.F = Fin;
     a.shadow = op->res_shadow;
     a.flags = op->res_flags;
     a.poll_limit = op->res_force_abort ? 16 : (1 << 20);
     a.wait_bias = op->res_force_abort ? (1 << 30) : 0;
-    const size_t fb = sizeof(double) * op->N;
+    const size_t fb = (f64 ? sizeof(double) : sizeof(float)) * op->N;
     const size_t flag_bytes = sizeof(int) * ((size_t)nt * TDP_RES_FLAG_STRIDE + TDP_RES_FLAG_STRIDE);
     void *cur = lb.u0, *prev = lb.u1, *ncur = lb.v0, *nprev = lb.v1;
     TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
@@ -720,7 +719,10 @@ static int issue_steps_res(tdp_op *op, const LoopBufs &lb, int T, double rho, in
         a.out_step[1] = (Ns > j0 && Ns <= j0 + n) ? (int)(Ns - j0) : 0;
         a.out[1] = out_final;
         TDP_CHECK_HIP(launch_fill_zero(op->res_flags, flag_bytes, s));
-        TDP_CHECK_HIP(launch_sweep2d_res_f64(a, op->st_step, s));
+        if (f64)
+            TDP_CHECK_HIP(launch_sweep2d_res_f64(a, op->st_step, s));
+        else
+            TDP_CHECK_HIP(launch_sweep2d_res_f32(a, op->st_step32, s));
         std::swap(cur, ncur);
         std::swap(prev, nprev);
     }
@@ -733,8 +735,8 @@ static int issue_steps_res(tdp_op *op, const LoopBufs &lb, int T, double rho, in
 static int ensure_res(tdp_op *op, int T, double rho, int variant)
 {
     if (!op->res_shadow) {
-        const size_t n = 2 * (size_t)op->ncu * res_band_values(true);
-        if (hipMalloc(&op->res_shadow, sizeof(double) * n) != hipSuccess)
+        const size_t n = 2 * (size_t)op->ncu * std::max(res_band_bytes(true), res_band_bytes(false));
+        if (hipMalloc(&op->res_shadow, n) != hipSuccess)
             TDP_FAIL(TDP_ENOMEM, "device allocation of the exchange buffer failed");
     }
     if (!op->res_flags) {
@@ -992,7 +994,7 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
         if (kern == 2 || kern == 4 || kern == 5) TDP_CHECK(ensure_tb_fields(op));
         if (kern == 5) {
             TDP_CHECK(ensure_res(op, T, rho, variant));
-            res_nt = res_tiles(op->n[0], op->n[1], depth, true, nullptr, nullptr);
+            res_nt = res_tiles(op->n[0], op->n[1], depth, op->prec == TDP_F64, nullptr, nullptr);
         }
         launches = kern == 2 ? (Ns + depth - 1) / depth
                  : kern == 4 ? (Ns + 1) / 2

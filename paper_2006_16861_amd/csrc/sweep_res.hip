@@ -43,6 +43,7 @@ namespace {
 
 constexpr int kResW = 8;            // waves per workgroup (2 per SIMD)
 constexpr int kResR64 = 11;         // rows per lane, FP64: 88 x 64 extended tile
+constexpr int kResR32 = 14;         // rows per lane, FP32: 112 x 64 (one word per node value)
 constexpr int kResKMax = 8;
 
 // values per level of the largest band (depth 8) of a tile with EY rows
@@ -364,9 +365,13 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_res(ResArgs a, Stencil<T> st
 
 }  // namespace
 
-int res_tile_rows(bool f64) { return f64 ? kResR64 * kResW : 0; }
+int res_tile_rows(bool f64) { return (f64 ? kResR64 : kResR32) * kResW; }
 
-int res_band_values(bool f64) { return f64 ? 2 * res_band_max(kResR64 * kResW) : 0; }
+size_t res_band_bytes(bool f64)
+{
+    return f64 ? 2 * res_band_max(kResR64 * kResW) * sizeof(double)
+               : 2 * res_band_max(kResR32 * kResW) * sizeof(float);
+}
 
 int res_tiles(int ny, int nx, int k, bool f64, int *tiles_x, int *tiles_y)
 {
@@ -379,16 +384,25 @@ int res_tiles(int ny, int nx, int k, bool f64, int *tiles_x, int *tiles_y)
     return tx * tyc;
 }
 
-hipError_t launch_sweep2d_res_f64(const ResArgs &a, const Stencil<double> &st, hipStream_t s)
+template <typename T, int R>
+static hipError_t launch_res_t(const ResArgs &a, const Stencil<T> &st, hipStream_t s)
 {
     const int nt = a.tiles_x * a.tiles_y;
     if (a.sc > 2)
-        hipLaunchKernelGGL((k_sweep2d_res<double, 3, kResR64, kResW>), dim3(nt), dim3(64 * kResW),
-                           0, s, a, st);
+        hipLaunchKernelGGL((k_sweep2d_res<T, 3, R, kResW>), dim3(nt), dim3(64 * kResW), 0, s, a, st);
     else
-        hipLaunchKernelGGL((k_sweep2d_res<double, 2, kResR64, kResW>), dim3(nt), dim3(64 * kResW),
-                           0, s, a, st);
+        hipLaunchKernelGGL((k_sweep2d_res<T, 2, R, kResW>), dim3(nt), dim3(64 * kResW), 0, s, a, st);
     return hipGetLastError();
+}
+
+hipError_t launch_sweep2d_res_f64(const ResArgs &a, const Stencil<double> &st, hipStream_t s)
+{
+    return launch_res_t<double, kResR64>(a, st, s);
+}
+
+hipError_t launch_sweep2d_res_f32(const ResArgs &a, const Stencil<float> &st, hipStream_t s)
+{
+    return launch_res_t<float, kResR32>(a, st, s);
 }
 
 }  // namespace tdp

@@ -201,8 +201,9 @@ struct ResArgs {
     int wait_bias;              // added to the awaited flag value (0; > 0 forces the abort path)
 };
 hipError_t launch_sweep2d_res_f64(const ResArgs &a, const Stencil<double> &st, hipStream_t s);
-int res_tile_rows(bool f64);    // extended tile rows (64 columns)
-int res_band_values(bool f64);  // exchange-buffer values per tile and parity (largest depth)
+hipError_t launch_sweep2d_res_f32(const ResArgs &a, const Stencil<float> &st, hipStream_t s);
+int res_tile_rows(bool f64);      // extended tile rows (64 columns)
+size_t res_band_bytes(bool f64);  // exchange-buffer bytes per tile and parity (largest depth)
 // tiles of the resident grid at exchange depth k (0 if k is not supported)
 int res_tiles(int ny, int nx, int k, bool f64, int *tiles_x, int *tiles_y);
 

@@ -294,7 +294,7 @@ class Operator:
     def autotune(self, T=4, rho=0.25, variant=0):
         """Time the sweep variants and keep the fastest; returns (best, table)
         with table rows (kernel, tb_depth, tile, us_per_step)."""
-        cap = 128
+        cap = 256
         tab = (ctypes.c_double * (4 * cap))()
         best = Tuning()
         n = _check(load().tdp_op_autotune(self._h, int(T), float(rho), int(variant),

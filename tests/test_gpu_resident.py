@@ -6,8 +6,8 @@ against the one-step kernel to rounding: multi-tile grids with ragged edges
 and single tile rows or columns, every exchange depth, runs longer than one
 launch, the samples of Table 1 when n_P is not a multiple of 4 (blocks end at
 the sample step), the complex form as two real passes, the 5-point scheme,
-fixed-iteration GMRES, the benchmark grid, and the fall-back where the
-kernel does not apply."""
+fixed-iteration GMRES, the benchmark grid, FP32 fields, and the fall-back
+where the kernel does not apply."""
 import sys
 
 import numpy as np
@@ -71,6 +71,22 @@ def test_resident_matches_oracle(name, mk, k):
         assert rel(U, Uo) <= TOL64, graph
     g.set_tuning(kernel=1, use_graph=0)
     assert rel(U, host(g.precond(dev(p.F), T, 0.25))) <= 1e-13
+
+
+@pytest.mark.parametrize("k", [2, 4, 6, 8])
+@pytest.mark.parametrize("name,mk", [GRIDS[0], GRIDS[2], GRIDS[4]])
+def test_resident_f32(name, mk, k):
+    """FP32 fields (112 x 64 tiles): against the oracle at the FP32 bar and
+    against the FP32 one-step kernel to rounding."""
+    p = mk()
+    note(f"resident f32 {name} k={k}")
+    g, o = make_ops(p, prec=1)
+    T = min(p.periods, 3)
+    g.set_tuning(kernel=5, tb_depth=k)
+    U = host(g.precond(dev(p.F), T, 0.25))
+    assert rel(U, o.precond(p.F, T, 0.25)) <= 1e-4
+    g.set_tuning(kernel=1)
+    assert rel(U, host(g.precond(dev(p.F), T, 0.25))) <= 1e-5
 
 
 def test_resident_runs_longer_than_one_launch():
@@ -159,16 +175,18 @@ def test_resident_full_size_one_period_and_gmres():
 
 
 def test_resident_falls_back_where_it_does_not_apply():
-    """3-D, FP32, and corner mass terms: kernel 5 runs the automatic choice."""
+    """3-D, corner mass terms, and grids with more tiles than compute units:
+    kernel 5 runs the automatic choice."""
     from paper_2006_16861_amd import tdp
     p3 = inputs.random_medium((9, 11, 70), seed=3, width=2)
     g, o = make_ops(p3)
     g.set_tuning(kernel=5, tb_depth=4)
     assert rel(host(g.precond(dev(p3.F), 2, 0.25)), o.precond(p3.F, 2, 0.25)) <= TOL64
+    pb = inputs.random_medium((1400, 1200), seed=49, width=8)   # 18 x 22 tiles at depth 4
+    gb, ob = make_ops(pb)
+    gb.set_tuning(kernel=5, tb_depth=4)
+    assert rel(host(gb.precond(dev(pb.F), 1, 0.25)), ob.precond(pb.F, 1, 0.25)) <= TOL64
     p = inputs.random_medium((150, 200), seed=18, width=6)
-    g32, o = make_ops(p, prec=1)
-    g32.set_tuning(kernel=5, tb_depth=4)
-    assert rel(host(g32.precond(dev(p.F), 2, 0.25)), o.precond(p.F, 2, 0.25)) <= 1e-4
     stiff, mass = (2 / 3, -1 / 6, -1 / 3), (1 / 9, 1 / 18, 1 / 36)   # trilinear element tables
     oq = oracle.Op(p.n, p.h, p.omega, p.c, p.R, stiff=stiff, mass=mass)
     gq = tdp.Operator(dev(p.c), dev(p.R), p.omega, p.h, scheme="q1")
