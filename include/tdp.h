@@ -286,8 +286,12 @@ int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
  *               choice); inapplicable choices fall back to 1
  *  tb_depth     kernel 2: steps per launch, 1..16 (0 auto);
  *               kernel 5: steps between halo exchanges, 2, 4, 6 or 8 (0: 4);
- *               kernels 3, 4: planes per chunk (0 auto: 32, halved down
- *               to 8 until the launch has about 8192 waves)
+ *               kernel 3: planes per chunk (0 auto: 32, halved down
+ *               to 8 until the launch has about 8192 waves); kernel 4: the
+ *               fewest planes per workgroup run (0: 8; the launch is one
+ *               round of resident workgroups sharing the (column block,
+ *               plane) units equally, so this only limits how finely a
+ *               small grid is split)
  *  use_graph    1 capture the step loop in a hipGraph and replay it (loops
  *               of more than 2^17 launches are issued directly)
  *  tile         kernel 2 tile (rows x columns): 0 64x64 (8 rows per lane x
@@ -297,8 +301,11 @@ int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
  *               6 64x64 (8 x 8), 7 32x64 (2 x 16), 8 128x64 (8 x 16, FP32 only);
  *               kernel 3: 0 8x64 columns (4 waves x 2
  *               rows each), 1 16x64 (4 waves x 4 rows), 2 16x64 (8 x 2);
- *               kernel 4: the same three shapes for the first step, whose
- *               one-node rim is recomputed (output 6x62 / 14x62 / 14x62)   */
+ *               kernel 4: level 1 on a 66-wide block with a one-node rim,
+ *               level 2 (the output) on its interior: 0 66x15 on 512
+ *               threads (two nodes each, output 13x64), 1 66x15 on 1024
+ *               threads (one node each), 2 66x31 on 1024 threads (output
+ *               29x64; FP32 only, FP64 runs shape 1)                      */
 typedef struct {
     int kernel;
     int tb_depth;
@@ -320,8 +327,9 @@ int tdp_op_force_resident_abort(tdp_op *op, int on);
  * launch; blocked tile shapes x depths 2-10, 12, 16 (4 x depth
  * at most the tile's rows) and the resident tiles at exchange depths 2, 4, 6,
  * 8 for the 2-D Table 1 loop; the blocked I_abd tiles
- * x depths 2, 3, 4, 6, 8 with the 2-D cell damping; streamed column shapes x
- * chunk lengths 4, 8, 16, 32, 64 in 3-D, with one and two steps per launch) over
+ * x depths 2, 3, 4, 6, 8 with the 2-D cell damping; in 3-D the one-step
+ * streamed shapes x chunk lengths 4, 8, 16, 32, 64 and the two-step shapes x
+ * shortest runs 8 and 32) over
  * periods_T periods with HIP events on the op's stream, and makes
  * the fastest the op's tuning.  best (host, may be NULL) receives it; table
  * (host, may be NULL) receives up to cap rows of {kernel, tb_depth, tile,

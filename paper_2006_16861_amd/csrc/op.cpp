@@ -589,14 +589,18 @@ static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth, i
         if (4 * k > rows || 4 * k > tb2d_tile_cols(t)) k = rows / 8;   // keep at least half the tile exact
     } else if (kern == 3 || kern == 4) {
         if (t > 2) t = 1;
-        if (k == 0) {
+        if (k == 0 && kern == 4) {
+            // fewest planes per workgroup run: the two-step grid is one round
+            // of resident workgroups with equal runs, so this only bounds how
+            // finely a small grid is split
+            k = 8;
+        } else if (k == 0) {
             // default chunk length: halve from 32 (down to 8) until the launch
             // has about 8192 waves, so that small grids still fill the chip
             // (128^3: 8 planes, 2x faster than 32; 256^3: 16)
-            const int rows = kern == 3 ? (t == 0 ? 8 : 16) : (t == 0 ? 6 : 14);
-            const int cols = kern == 3 ? 64 : 62;
+            const int rows = t == 0 ? 8 : 16;
             const int waves = t == 2 ? 8 : 4;
-            const int64_t txy = (int64_t)((op->n[2] + cols - 1) / cols) * ((op->n[1] + rows - 1) / rows);
+            const int64_t txy = (int64_t)((op->n[2] + 63) / 64) * ((op->n[1] + rows - 1) / rows);
             k = 32;
             while (k > 8 && txy * ((op->n[0] + k - 1) / k) * waves < 8192) k /= 2;
         }
@@ -797,6 +801,7 @@ static int issue_steps_3d2(tdp_op *op, const LoopBufs &lb, int T, double rho, in
     a.sc = op->sc;
     a.mc = op->mc;
     a.zc = zc;
+    a.ncu = op->ncu;
     a.m = f64 ? (const void *)op->m : (const void *)op->m32;
     a.dn = f64 ? (const void *)op->dn : (const void *)op->dn32;
     a.F = Fin;
@@ -992,6 +997,7 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
         int kern, depth, tile;
         sweep_plan(op, variant, &kern, &depth, &tile);
         if (kern == 2 || kern == 4 || kern == 5) TDP_CHECK(ensure_tb_fields(op));
+        if (kern == 4) sweep3d_stream2_prepare(op->prec == TDP_F64, tile);
         if (kern == 5) {
             TDP_CHECK(ensure_res(op, T, rho, variant));
             res_nt = res_tiles(op->n[0], op->n[1], depth, op->prec == TDP_F64, nullptr, nullptr);
@@ -1163,8 +1169,12 @@ extern "C" int tdp_op_autotune(tdp_op *op, int periods_T, double rho, int varian
     if (op->ndim == 3 && op->dform == TDP_DAMP_NODE) {
         for (int shape = 0; shape < 3; ++shape)
             for (int zc : {4, 8, 16, 32, 64}) cand.push_back({3, zc, 1, shape});
-        for (int shape = 0; shape < 3; ++shape)
-            for (int zc : {4, 8, 16, 32, 64}) cand.push_back({4, zc, 1, shape});
+        // two-step kernel: the depth is only the fewest planes per workgroup
+        // run (it matters on small grids); FP64 runs shape 2 as shape 1
+        for (int shape = 0; shape < 3; ++shape) {
+            if (shape == 2 && op->prec == TDP_F64) continue;
+            for (int zc : {8, 32}) cand.push_back({4, zc, 1, shape});
+        }
     }
     const tdp_tuning saved = op->tune;
     void *tin = nullptr, *tout = nullptr;

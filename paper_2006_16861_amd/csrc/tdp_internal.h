@@ -222,7 +222,8 @@ hipError_t launch_sweep3d_stream_f32(const SweepArgs &a, const Stencil<float> &s
 struct Stream2Args {
     int n[3];
     int sc, mc;
-    int zc;                  // planes per chunk
+    int zc;                  // fewest planes per workgroup run
+    int ncu;                 // compute units (one round of resident workgroups)
     const void *u, *up;
     void *u2out, *u1out;
     const void *m, *dn, *F;
@@ -233,6 +234,8 @@ hipError_t launch_sweep3d_stream2_f64(const Stream2Args &a, const Stencil<double
                                       hipStream_t s);
 hipError_t launch_sweep3d_stream2_f32(const Stream2Args &a, const Stencil<float> &st, int shape,
                                       hipStream_t s);
+// queries the residency of the shape's kernels (call before any stream capture)
+void sweep3d_stream2_prepare(bool f64, int shape);
 
 // complex-linear variant: u, up are complex fields (re, im pairs of T); `out`
 // (if non-null) receives u_{j+1} as complex128.
