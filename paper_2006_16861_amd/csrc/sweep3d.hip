@@ -82,26 +82,69 @@ struct Fold3 {
     T c0, cw, ce, cs, cn, cd, cu, d;
 };
 
-// w[e], e = ex + 2 ey + 4 ez: the cells at offsets (ez, ey, ex) in {0, 1}^3
-// around the node, as in stencil27
+// Compact form, for a fold kept in registers until a later update: two
+// opposite faces share the node's eight cells between them, so their
+// coefficients sum to the same cx = d (2 s_1 + m_1 sum w) on every axis.  It
+// keeps the west, south and down coefficients and cx (east = cx - west, ...).
+template <typename T>
+struct Fold3c {
+    T c0, cx, cw, cs, cd, d;
+};
+
+template <typename T>
+struct CellSums {
+    T w0, ww, ws, wd, wu;     // all eight cells; those with ex = 0, ey = 0, ez = 0, ez = 1
+};
+
+template <typename T>
+__device__ __forceinline__ CellSums<T> cell_sums(const T (&w)[8])
+{
+    const T w01 = w[0] + w[1], w23 = w[2] + w[3], w45 = w[4] + w[5], w67 = w[6] + w[7];
+    CellSums<T> c;
+    c.wd = w01 + w23;
+    c.wu = w45 + w67;
+    c.ws = w01 + w45;
+    c.ww = (w[0] + w[2]) + (w[4] + w[6]);
+    c.w0 = c.wd + c.wu;
+    return c;
+}
+
 template <typename T>
 __device__ __forceinline__ Fold3<T> fold3(const T (&w)[8], T d, const Stencil<T> &st)
 {
-    const T w01 = w[0] + w[1], w23 = w[2] + w[3], w45 = w[4] + w[5], w67 = w[6] + w[7];
-    const T wd = w01 + w23, wu = w45 + w67;               // ez = 0, 1
-    const T ws = w01 + w45;                               // ey = 0
-    const T ww = (w[0] + w[2]) + (w[4] + w[6]);           // ex = 0
-    const T w0 = wd + wu;
+    const CellSums<T> c = cell_sums(w);
     Fold3<T> f;
-    f.c0 = d * (st.c0 + st.m[0] * w0);
-    f.cw = d * (st.s[1] + st.m[1] * ww);
-    f.ce = d * (st.s[1] + st.m[1] * (w0 - ww));
-    f.cs = d * (st.s[1] + st.m[1] * ws);
-    f.cn = d * (st.s[1] + st.m[1] * (w0 - ws));
-    f.cd = d * (st.s[1] + st.m[1] * wd);
-    f.cu = d * (st.s[1] + st.m[1] * wu);
+    f.c0 = d * (st.c0 + st.m[0] * c.w0);
+    f.cw = d * (st.s[1] + st.m[1] * c.ww);
+    f.ce = d * (st.s[1] + st.m[1] * (c.w0 - c.ww));
+    f.cs = d * (st.s[1] + st.m[1] * c.ws);
+    f.cn = d * (st.s[1] + st.m[1] * (c.w0 - c.ws));
+    f.cd = d * (st.s[1] + st.m[1] * c.wd);
+    f.cu = d * (st.s[1] + st.m[1] * c.wu);
     f.d = d;
     return f;
+}
+
+template <typename T>
+__device__ __forceinline__ Fold3c<T> fold3c(const T (&w)[8], T d, const Stencil<T> &st)
+{
+    const CellSums<T> c = cell_sums(w);
+    Fold3c<T> f;
+    f.c0 = d * (st.c0 + st.m[0] * c.w0);
+    f.cx = d * (T(2) * st.s[1] + st.m[1] * c.w0);
+    f.cw = d * (st.s[1] + st.m[1] * c.ww);
+    f.cs = d * (st.s[1] + st.m[1] * c.ws);
+    f.cd = d * (st.s[1] + st.m[1] * c.wd);
+    f.d = d;
+    return f;
+}
+
+template <typename T, typename LoadU>
+__device__ __forceinline__ T edge_sum(const LoadU &U)
+{
+    return ((U(-1, -1, 0) + U(-1, 1, 0)) + (U(-1, 0, -1) + U(-1, 0, 1))) +
+           ((U(1, -1, 0) + U(1, 1, 0)) + (U(1, 0, -1) + U(1, 0, 1))) +
+           ((U(0, -1, -1) + U(0, -1, 1)) + (U(0, 1, -1) + U(0, 1, 1)));
 }
 
 // U(oz, oy, ox) reads u_j around the node; dfr, dfi = d Re F, d Im F
@@ -109,9 +152,7 @@ template <typename T, typename LoadU>
 __device__ __forceinline__ T update3(const LoadU &U, const Fold3<T> &f, const Stencil<T> &st,
                                      T fa, T fb, T dfr, T dfi, T uprev)
 {
-    const T edges = ((U(-1, -1, 0) + U(-1, 1, 0)) + (U(-1, 0, -1) + U(-1, 0, 1))) +
-                    ((U(1, -1, 0) + U(1, 1, 0)) + (U(1, 0, -1) + U(1, 0, 1))) +
-                    ((U(0, -1, -1) + U(0, -1, 1)) + (U(0, 1, -1) + U(0, 1, 1)));
+    const T edges = edge_sum<T>(U);
     T acc = f.c0 * U(0, 0, 0);
     acc += f.cw * U(0, 0, -1);
     acc += f.ce * U(0, 0, 1);
@@ -119,6 +160,24 @@ __device__ __forceinline__ T update3(const LoadU &U, const Fold3<T> &f, const St
     acc += f.cn * U(0, 1, 0);
     acc += f.cd * U(-1, 0, 0);
     acc += f.cu * U(1, 0, 0);
+    acc += (f.d * st.s[2]) * edges;
+    acc += fa * dfr;
+    acc += fb * dfi;
+    return acc + (T(1) - T(2) * f.d) * uprev;
+}
+
+template <typename T, typename LoadU>
+__device__ __forceinline__ T update3(const LoadU &U, const Fold3c<T> &f, const Stencil<T> &st,
+                                     T fa, T fb, T dfr, T dfi, T uprev)
+{
+    const T edges = edge_sum<T>(U);
+    T acc = f.c0 * U(0, 0, 0);
+    acc += f.cw * U(0, 0, -1);
+    acc += (f.cx - f.cw) * U(0, 0, 1);
+    acc += f.cs * U(0, -1, 0);
+    acc += (f.cx - f.cs) * U(0, 1, 0);
+    acc += f.cd * U(-1, 0, 0);
+    acc += (f.cx - f.cd) * U(1, 0, 0);
     acc += (f.d * st.s[2]) * edges;
     acc += fa * dfr;
     acc += fb * dfi;
@@ -280,17 +339,19 @@ __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream(
 // Two steps per launch.  From u_j (level 0) and u_{j-1}, a workgroup computes
 // level 1 (u_{j+1}) on a 66 x LY node block and level 2 (u_{j+2}) on its
 // 64 x (LY-2) interior, walking along axis 0: in iteration i it forms level 1
-// on plane a = zb-1+i and level 2 on plane a-1.  The block's positions are
-// dealt to the NT threads in row-major order (t, t + NT, ...), so a 64-wide
-// output needs no 64-lane level-1 row and a 256-node axis takes exactly four
-// column blocks.  Level-0 planes rotate through a 4-slot LDS ring (the slot
-// freed in an iteration receives the plane prefetched into registers), level-1
-// planes through a 3-slot ring and cell planes through a 3-slot ring (4 when
-// level 2 refolds from the cells); u_{j-1}, d and F of plane a are fetched one
-// iteration ahead.  For the compact tables a node's coefficients are folded
-// once, at level 1, and carried in registers to its level-2 update one
-// iteration later.  Per node and launch this reads u_j, u_{j-1}, m, d, F once
-// and writes u_{j+1}, u_{j+2}: about 4 words per node-step instead of 7.
+// on plane a = zb-1+i and level 2 on plane a-2, whose level-1 inputs (planes
+// a-3 .. a-1) were all formed in earlier iterations, so one barrier per plane
+// orders everything.  The block's positions are dealt to the NT threads in
+// row-major order (t, t + NT, ...), so a 64-wide output needs no 64-lane
+// level-1 row and a 256-node axis takes exactly four column blocks.  LDS
+// rings: level-0 planes in 5 slots (a-2 .. a+1 read, a+2 arriving from the
+// registers it was prefetched into), level-1 planes in 4 (a written, a-3 ..
+// a-1 read), cell planes in 3 (5 when level 2 refolds from the cells).  u_{j-1},
+// d and F of plane a are fetched one iteration ahead.  For the compact tables a
+// node's coefficients are folded once, at level 1, and carried in registers to
+// its level-2 update two iterations later.  Per node and launch this reads
+// u_j, u_{j-1}, m, d, F once and writes u_{j+1}, u_{j+2}: about 4 words per
+// node-step instead of 7.
 //
 // Every column block is split along axis 0 at the same plane boundaries into
 // nrun runs, one workgroup each; the host picks nrun so that the workgroups
@@ -298,6 +359,7 @@ __global__ __launch_bounds__(64 * TY) void k_sweep3d_stream(
 // are ordered run-major and each XCD gets a contiguous range, so blocks that
 // are neighbours in the plane walk the same planes at the same time and their
 // halo re-reads hit that XCD's L2.  Outputs must not alias the inputs.
+
 // waves per SIMD the register allocation must allow: two 512-thread FP32
 // workgroups per compute unit (their LDS allows it); FP64 ones are held to
 // one by their LDS
@@ -319,9 +381,9 @@ __global__ __launch_bounds__(NT, (stream2_waves<T, NT>())) void k_sweep3d_stream
     constexpr int CX = LX + 1, NC = CX * (LY + 1);  // cell plane
     constexpr int UPT = (NE + NT - 1) / NT, CPT = (NC + NT - 1) / NT;
     constexpr bool FOLD = SC == 3 && MC == 2;
-    constexpr int NCS = FOLD ? 3 : 4;
-    __shared__ T s0[4][NE];
-    __shared__ T s1[3][NL];
+    constexpr int NCS = FOLD ? 3 : 5;
+    __shared__ T s0[5][NE];
+    __shared__ T s1[4][NL];
     __shared__ T scl[NCS][NC];
 
     const int id = blockIdx.x;
@@ -348,16 +410,14 @@ __global__ __launch_bounds__(NT, (stream2_waves<T, NT>())) void k_sweep3d_stream
     T ru[UPT], rc[CPT];
     int eo[UPT], co[CPT], no[P];   // in-plane offsets from the block origin, -1 outside
     T cum[P], cd[P], cfr[P], cfi[P];
-    Fold3<T> kf[FOLD ? P : 1], kp[FOLD ? P : 1];
-    // plane a's d F (folded: times d) and d, kept for its level-2 update in
-    // the next iteration (k*), and those of plane a-1 used in this one (p*)
-    T kfr[P], kfi[P], pfr[P], pfi[P], kd[FOLD ? 1 : P], pd[FOLD ? 1 : P];
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-        if constexpr (FOLD) kf[q] = kp[q] = Fold3<T>{};
-        else kd[q] = pd[q] = T(0);
-        kfr[q] = kfi[q] = pfr[q] = pfi[q] = T(0);
-    }
+    // what a node's level-2 update needs from plane a (k0, formed now), a-1
+    // (k1) and a-2 (k2, used now): the folded coefficients with d, and d F
+    // (unfolded tables: d and F)
+    struct Carry {
+        Fold3c<T> f;
+        T fr, fi;
+    };
+    Carry k0[P], k1[P], k2[P];
 
     const int x0 = (cblk % tiles_x) * OX, y0 = (cblk / tiles_x) * OY;
     const int64_t nb = (int64_t)(y0 - 1) * nx + (x0 - 1);          // node (r, c) = (0, 0)
@@ -383,9 +443,9 @@ __global__ __launch_bounds__(NT, (stream2_waves<T, NT>())) void k_sweep3d_stream
         no[q] = tid + q * NT < NL && (unsigned)gy < (unsigned)ny && (unsigned)gx < (unsigned)nx
                     ? rr[q] * nx + c : -1;
     }
-    auto slot = [&](int p) { return (p - zb + 2) & 3; };         // level-0 planes
+    auto slot = [&](int p) { return (p - zb + 2) % 5; };         // level-0 planes
     auto cslot = [&](int p) { return (p - zb + 2) % NCS; };      // cell planes
-    auto slot1 = [&](int p) { return (p - zb + 1) % 3; };        // level-1 planes
+    auto slot1 = [&](int p) { return (p - zb + 1) & 3; };        // level-1 planes
     auto fetch_u = [&](int p) {
         const bool zin = (unsigned)p < (unsigned)nz;
         const int64_t o = p * plane + eb;
@@ -438,71 +498,66 @@ __global__ __launch_bounds__(NT, (stream2_waves<T, NT>())) void k_sweep3d_stream
     }
     fetch_node(zb - 1);
     __syncthreads();
-    const int iters = ze - zb + 2;
+    // level 1 on planes zb-1 .. ze, level 2 on zb .. ze-1 (two planes behind)
+    const int iters = ze - zb + 3;
 #pragma unroll 1
     for (int it = 0; it < iters; ++it) {
-        const int a = zb - 1 + it, b = a - 1;
-        const bool more = it + 1 < iters;
-        if (more) {                // next iteration: planes a+2 (node data of a+1 after level 1)
+        const int a = zb - 1 + it, b = a - 2;
+        const bool lev1 = a <= ze, pref = a + 1 <= ze;
+        if (pref) {                // planes a+2 (level 0, cells); node data of a+1 after level 1
             fetch_u(a + 2);
             fetch_c(a + 2);
         }
         // level 1 on plane a (the whole block, rim included; zero outside the grid)
-        const bool ain = (unsigned)a < (unsigned)nz;
-        const bool aout = a >= zb && a < ze;
-        const T *p0 = s0[slot(a - 1)], *p1 = s0[slot(a)], *p2 = s0[slot(a + 1)];
-        const T *c0p = scl[cslot(a)], *c1p = scl[cslot(a + 1)];
-        T *l1 = s1[slot1(a)];
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-            const int t = tid + q * NT;
-            if (P * NT > NL && t >= NL) continue;
-            T v = T(0);
-            if (ain && no[q] >= 0) {
-                const int base = ub(q);
-                auto U = [&](int oz, int oy, int ox) -> T {
-                    const T *pl = oz < 0 ? p0 : (oz == 0 ? p1 : p2);
-                    return pl[base + oy * EX + ox];
-                };
-                T w[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
-                    w[e] = (ez ? c1p : c0p)[cb(q) + ey * CX + ex];
-                }
-                if constexpr (FOLD) {
-                    kf[q] = fold3(w, cd[q], st);
-                    kfr[q] = cd[q] * cfr[q];
-                    kfi[q] = cd[q] * cfi[q];
-                    v = update3(U, kf[q], st, fa1, fb1, kfr[q], kfi[q], cum[q]);
-                } else {
-                    const T acc = stencil27<SC, MC>(U, w, st);
-                    v = cd[q] * (acc + fa1 * cfr[q] + fb1 * cfi[q]) - (T(2) * cd[q] - T(1)) * cum[q];
-                }
-                if (aout && inner(q)) {
-                    const int64_t i = a * plane + nb + no[q];
-                    stnt<NTS>(v, u1o + i);
-                    if (out1) out1[2 * i] = (double)v;
-                }
-            }
-            l1[t] = v;
-        }
-        // level 2 needs the level-1 plane; the node data of plane a are
-        // consumed (the fold keeps d and d F): fetch those of plane a+1
-        if constexpr (!FOLD) {
+        if (lev1) {
+            const bool ain = (unsigned)a < (unsigned)nz;
+            const bool aout = a >= zb && a < ze;
+            const T *p0 = s0[slot(a - 1)], *p1 = s0[slot(a)], *p2 = s0[slot(a + 1)];
+            const T *c0p = scl[cslot(a)], *c1p = scl[cslot(a + 1)];
+            T *l1 = s1[slot1(a)];
 #pragma unroll
             for (int q = 0; q < P; ++q) {
-                kd[q] = cd[q];
-                kfr[q] = cfr[q];
-                kfi[q] = cfi[q];
+                const int t = tid + q * NT;
+                if (P * NT > NL && t >= NL) continue;
+                T v = T(0);
+                if (ain && no[q] >= 0) {
+                    const int base = ub(q);
+                    auto U = [&](int oz, int oy, int ox) -> T {
+                        const T *pl = oz < 0 ? p0 : (oz == 0 ? p1 : p2);
+                        return pl[base + oy * EX + ox];
+                    };
+                    T w[8];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+                        w[e] = (ez ? c1p : c0p)[cb(q) + ey * CX + ex];
+                    }
+                    if constexpr (FOLD) {
+                        k0[q].f = fold3c(w, cd[q], st);
+                        k0[q].fr = cd[q] * cfr[q];
+                        k0[q].fi = cd[q] * cfi[q];
+                        v = update3(U, k0[q].f, st, fa1, fb1, k0[q].fr, k0[q].fi, cum[q]);
+                    } else {
+                        const T acc = stencil27<SC, MC>(U, w, st);
+                        v = cd[q] * (acc + fa1 * cfr[q] + fb1 * cfi[q]) - (T(2) * cd[q] - T(1)) * cum[q];
+                        k0[q].f.d = cd[q];
+                        k0[q].fr = cfr[q];
+                        k0[q].fi = cfi[q];
+                    }
+                    if (aout && inner(q)) {
+                        const int64_t i = a * plane + nb + no[q];
+                        stnt<NTS>(v, u1o + i);
+                        if (out1) out1[2 * i] = (double)v;
+                    }
+                }
+                l1[t] = v;
             }
+            if (pref) fetch_node(a + 1);   // plane a's node data are consumed
         }
-        if (more) fetch_node(a + 1);
-        __syncthreads();
-        // level 2 on plane b (interior of the block)
-        if (it >= 2) {
+        // level 2 on plane b (interior of the block); its level-1 planes
+        // b-1 .. b+1 = a-3 .. a-1 were formed before the last barrier
+        if (b >= zb) {
             const T *q0 = s1[slot1(b - 1)], *q1 = s1[slot1(b)], *q2 = s1[slot1(b + 1)];
-            const T *d0p = scl[cslot(b)], *d1p = scl[cslot(b + 1)];
             const T *u0c = s0[slot(b)];
 #pragma unroll
             for (int q = 0; q < P; ++q) {
@@ -515,8 +570,9 @@ __global__ __launch_bounds__(NT, (stream2_waves<T, NT>())) void k_sweep3d_stream
                 const T uc = u0c[ub(q)];
                 T v;
                 if constexpr (FOLD) {
-                    v = update3(U, kp[q], st, fa2, fb2, pfr[q], pfi[q], uc);
+                    v = update3(U, k2[q].f, st, fa2, fb2, k2[q].fr, k2[q].fi, uc);
                 } else {
+                    const T *d0p = scl[cslot(b)], *d1p = scl[cslot(b + 1)];
                     T w[8];
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
@@ -524,24 +580,23 @@ __global__ __launch_bounds__(NT, (stream2_waves<T, NT>())) void k_sweep3d_stream
                         w[e] = (ez ? d1p : d0p)[cb(q) + ey * CX + ex];
                     }
                     const T acc = stencil27<SC, MC>(U, w, st);
-                    v = pd[q] * (acc + fa2 * pfr[q] + fb2 * pfi[q]) - (T(2) * pd[q] - T(1)) * uc;
+                    const T d2 = k2[q].f.d;
+                    v = d2 * (acc + fa2 * k2[q].fr + fb2 * k2[q].fi) - (T(2) * d2 - T(1)) * uc;
                 }
                 const int64_t i = b * plane + nb + no[q];
                 stnt<NTS>(v, u2o + i);
                 if (out2) out2[2 * i] = (double)v;
             }
         }
-        if (more) {                // slots of planes a-2 (level 0) and a-1 (cells) are free
+        if (pref) {                // slots of planes a-3 (level 0) and a-1 (cells) are free
             store_u(slot(a + 2));
             store_c(cslot(a + 2));
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-            if constexpr (FOLD) kp[q] = kf[q];
-            else pd[q] = kd[q];
-            pfr[q] = kfr[q];
-            pfi[q] = kfi[q];
+            k2[q] = k1[q];
+            k1[q] = k0[q];
         }
     }
 }
