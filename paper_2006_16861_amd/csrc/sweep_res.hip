@@ -13,9 +13,11 @@
 //   tile does (rows per lane, DPP x-neighbours, edge rows through LDS, one
 //   barrier per step);
 // - after each block of k steps it publishes the k-wide border band of its
-//   exact region (u_j and u_{j-1}) to its slot of a global exchange buffer,
-//   raises its flag, waits for the flags of its (up to) eight neighbours and
-//   reads its halo from their bands.
+//   exact region (u_j and u_{j-1}) to its slot of a global exchange buffer
+//   and raises its flag; each wave then waits for the flags of the
+//   neighbours whose bands it reads (west and east, and the three tiles above
+//   or below for the waves holding top or bottom halo rows: the tile as a
+//   whole waits for all eight) and reads its halo from their bands.
 // A band is packed: the k top rows and the k bottom rows of the exact region
 // (full width), then the k left and the k right columns of the rows between
 // them, each a row-major block.  It is staged in LDS and copied out with whole-line
@@ -278,10 +280,17 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_res(ResArgs a, Stencil<T> st
             __builtin_amdgcn_s_waitcnt(0);   // the band stores are complete
             __syncthreads();
             if (threadIdx.x == 0) st_coh(flags + tile * TDP_RES_FLAG_STRIDE, blk);
-            // wait for the neighbours' bands of the same block
-            if (threadIdx.x < 9 && threadIdx.x != 4) {
-                const int nty = ty + (int)threadIdx.x / 3 - 1, ntx = tx + (int)threadIdx.x % 3 - 1;
-                if ((unsigned)nty < (unsigned)a.tiles_y && (unsigned)ntx < (unsigned)a.tiles_x) {
+            // wait for the bands of the same block that this wave reads: its
+            // west and east neighbours', and those of the three tiles above
+            // (below) when it holds top (bottom) halo rows.  Across its waves
+            // the tile waits for all eight neighbours before the barrier after
+            // the halo loads, which is also where every wave sees an abort
+            {
+                const int l = lane, dy = l / 3 - 1;
+                const bool need = l < 9 && l != 4 &&
+                                  (dy == 0 || (dy < 0 ? r0 < k : r0 + R > k + OY));
+                const int nty = ty + dy, ntx = tx + l % 3 - 1;
+                if (need && (unsigned)nty < (unsigned)a.tiles_y && (unsigned)ntx < (unsigned)a.tiles_x) {
                     const int *fp = flags + (nty * a.tiles_x + ntx) * TDP_RES_FLAG_STRIDE;
                     int polls = 0;
                     while (ld_coh(fp) < blk + a.wait_bias) {
@@ -294,8 +303,6 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_res(ResArgs a, Stencil<T> st
                     }
                 }
             }
-            __syncthreads();
-            if (s_abort) return;
             // the halo from the owners' bands: the owner's row and the part of
             // the address it sets are uniform (counted along the rows, no
             // division per row); a lane adds its owner's tile column and its
@@ -325,6 +332,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep2d_res(ResArgs a, Stencil<T> st
             c0[wf] = u0[0];
             c0[wl] = u0[R - 1];
             __syncthreads();
+            if (s_abort) return;     // a wait gave up: halo values may be stale
         }
         bool odd = false;
 #pragma unroll
