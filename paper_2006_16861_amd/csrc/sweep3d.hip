@@ -410,14 +410,16 @@ __global__ __launch_bounds__(NT, (stream2_waves<T, NT>())) void k_sweep3d_stream
     T ru[UPT], rc[CPT];
     int eo[UPT], co[CPT], no[P];   // in-plane offsets from the block origin, -1 outside
     T cum[P], cd[P], cfr[P], cfi[P];
-    // what a node's level-2 update needs from plane a (k0, formed now), a-1
-    // (k1) and a-2 (k2, used now): the folded coefficients with d, and d F
-    // (unfolded tables: d and F)
+    // what a node's level-2 update needs from its plane: the folded
+    // coefficients with d, and d F (unfolded tables: d and F).  Three sets:
+    // iteration i writes set i mod 3 (plane a) and reads set (i + 1) mod 3
+    // (plane a-2, written two iterations earlier); the loop is unrolled by
+    // three so that the sets stay in place
     struct Carry {
         Fold3c<T> f;
         T fr, fi;
     };
-    Carry k0[P], k1[P], k2[P];
+    Carry kA[P], kB[P], kC[P];
 
     const int x0 = (cblk % tiles_x) * OX, y0 = (cblk / tiles_x) * OY;
     const int64_t nb = (int64_t)(y0 - 1) * nx + (x0 - 1);          // node (r, c) = (0, 0)
@@ -500,8 +502,7 @@ __global__ __launch_bounds__(NT, (stream2_waves<T, NT>())) void k_sweep3d_stream
     __syncthreads();
     // level 1 on planes zb-1 .. ze, level 2 on zb .. ze-1 (two planes behind)
     const int iters = ze - zb + 3;
-#pragma unroll 1
-    for (int it = 0; it < iters; ++it) {
+    auto step = [&](int it, Carry (&k0)[P], const Carry (&k2)[P]) {
         const int a = zb - 1 + it, b = a - 2;
         const bool lev1 = a <= ze, pref = a + 1 <= ze;
         if (pref) {                // planes a+2 (level 0, cells); node data of a+1 after level 1
@@ -593,11 +594,14 @@ __global__ __launch_bounds__(NT, (stream2_waves<T, NT>())) void k_sweep3d_stream
             store_c(cslot(a + 2));
         }
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-            k2[q] = k1[q];
-            k1[q] = k0[q];
-        }
+    };
+#pragma unroll 1
+    for (int it = 0; it < iters; it += 3) {
+        step(it, kA, kB);
+        __builtin_amdgcn_sched_barrier(0);
+        if (it + 1 < iters) step(it + 1, kB, kC);
+        __builtin_amdgcn_sched_barrier(0);
+        if (it + 2 < iters) step(it + 2, kC, kA);
     }
 }
 
