@@ -332,8 +332,11 @@ def form_precision(rho):
         PF1[name] = op.precond(F, 1, rho).cpu().numpy()
         word = 8 if prec == tdp.F64 else 4
         tun = op.get_tuning()
-        kname = (f"k_sweep3d_stream<{'double' if word == 8 else 'float'}> shape={tun['tile']} "
-                 f"z-chunk={tun['tb_depth']}" if tun["kernel"] == 3 else f"kernel {tun['kernel']}")
+        tname = 'double' if word == 8 else 'float'
+        kname = (f"k_sweep3d_stream<{tname}> shape={tun['tile']} z-chunk={tun['tb_depth']}"
+                 if tun["kernel"] == 3 else
+                 f"k_sweep3d_stream2<{tname}> shape={tun['tile']} (two steps per launch)"
+                 if tun["kernel"] == 4 else f"kernel {tun['kernel']}")
         spl = {4: 2}.get(tun["kernel"], 1)
         words_launch = WORDS_PER_NODE_LAUNCH if spl > 1 else WORDS_PER_NODE_STEP
         key = f"layered3d-256|{name}|v0|k{tun['kernel']}|d{tun['tb_depth']}|t{tun['tile']}"
@@ -345,7 +348,7 @@ def form_precision(rho):
                      "roofline": roofline_block(kname, us_step * spl,
                                                 p.N * word * words_launch,
                                                 flops_per_node_step(3, 19) * p.N * spl, word,
-                                                traffic=traffic if spl == 1 else None)}
+                                                traffic=traffic)}
         log(f"form precision {name}: {dt:.3f} s, iters {info.iters}, relres {r:.2e}")
         del op
     res["f32_rel_error_vs_f64_gpu_solution"] = float(
