@@ -65,6 +65,11 @@ struct tdp_batch {
     std::map<std::string, std::pair<hipGraphExec_t, int *>> graphs;
     double *hbuf = nullptr;       // pinned host scratch
     size_t hbuf_n = 0;
+    // batched Gram-Schmidt: per-field descriptors (pinned host copy and
+    // device copy) and the device array the coefficients are gathered into
+    GsField *gs_host = nullptr, *gs_dev = nullptr;
+    double *gstage = nullptr;
+    size_t gs_n = 0, gstage_n = 0;
 };
 
 static void free_batch(tdp_batch *b)
@@ -82,6 +87,9 @@ static void free_batch(tdp_batch *b)
     }
     (void)hipFree(b->dfields);
     if (b->hbuf) (void)hipHostFree(b->hbuf);
+    if (b->gs_host) (void)hipHostFree(b->gs_host);
+    (void)hipFree(b->gs_dev);
+    (void)hipFree(b->gstage);
     delete b;
 }
 
@@ -547,6 +555,25 @@ static int ensure_field_krylov(tdp_batch *b, int m)
             TDP_BFAIL(TDP_ENOMEM, "pinned host allocation failed");
         b->hbuf_n = need;
     }
+    if (need > b->gstage_n) {
+        (void)hipStreamSynchronize(b->s);
+        (void)hipFree(b->gstage);
+        b->gstage = nullptr;
+        if (hipMalloc(&b->gstage, sizeof(double) * need) != hipSuccess)
+            TDP_BFAIL(TDP_ENOMEM, "batch staging allocation failed");
+        b->gstage_n = need;
+    }
+    if (b->f.size() > b->gs_n) {
+        (void)hipStreamSynchronize(b->s);
+        if (b->gs_host) (void)hipHostFree(b->gs_host);
+        (void)hipFree(b->gs_dev);
+        b->gs_host = nullptr;
+        b->gs_dev = nullptr;
+        if (hipHostMalloc(&b->gs_host, sizeof(GsField) * b->f.size()) != hipSuccess ||
+            hipMalloc(&b->gs_dev, sizeof(GsField) * b->f.size()) != hipSuccess)
+            TDP_BFAIL(TDP_ENOMEM, "batch descriptor allocation failed");
+        b->gs_n = b->f.size();
+    }
     return TDP_OK;
 }
 
@@ -695,7 +722,13 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
         if (!any) break;
         // stage B: one batched preconditioner application
         TDP_CHECK(batch_precond(b, Tv.data(), cfg->rho, needP));
-        // stage C: orthogonalisation / normalisation (one sync for all)
+        // stage C: orthogonalisation / normalisation (one sync for all).  A
+        // field starting a cycle normalises its first vector on its own; the
+        // CGS2 steps of all other fields run as one batched launch sequence.
+        // Every field's coefficients land in the staging array at its host
+        // slot, which one copy brings to the host.
+        int ngs = 0, nv_max = 0, nblk_max = 0;
+        int64_t n_max = 0;
         for (size_t q = 0; q < nf; ++q) {
             if (!needP[q]) continue;
             FS &S = st[q];
@@ -704,20 +737,33 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
             if (S.ph == AWAIT_P0) {
                 TDP_CHECK(norm2_async(q, fl.pout, fl.dco));
                 TDP_CHECK_HIP(launch_scale_by_invnorm(col(q, 0), fl.pout, fl.dco, fl.N, s));
-                TDP_CHECK_HIP(hipMemcpyAsync(hb + q * hs, fl.dco, sizeof(double), hipMemcpyDeviceToHost, s));
+                TDP_CHECK_HIP(hipMemcpyAsync(b->gstage + q * hs, fl.dco, sizeof(double),
+                                             hipMemcpyDeviceToDevice, s));
             } else {
-                const int i = S.i, nblk = blas_nblocks(fl.N);
-                double *d1 = fl.dco, *d2 = fl.dco + 2 * (m + 1), *dn2 = fl.dco + 4 * (m + 1);
-                TDP_CHECK_HIP(launch_mdot(fl.V, fl.N, i + 1, fl.pout, fl.N, fl.red, nblk, d1, s));
-                TDP_CHECK_HIP(launch_maxpy(fl.pout, fl.V, fl.N, i + 1, d1, -1.0, fl.N, s));
-                TDP_CHECK_HIP(launch_mdot(fl.V, fl.N, i + 1, fl.pout, fl.N, fl.red, nblk, d2, s));
-                TDP_CHECK_HIP(launch_maxpy(fl.pout, fl.V, fl.N, i + 1, d2, -1.0, fl.N, s));
-                TDP_CHECK_HIP(launch_mdot(fl.pout, fl.N, 1, fl.pout, fl.N, fl.red, nblk, dn2, s));
-                TDP_CHECK_HIP(launch_scale_by_invnorm(col(q, i + 1), fl.pout, dn2, fl.N, s));
-                TDP_CHECK_HIP(hipMemcpyAsync(hb + q * hs, fl.dco, sizeof(double) * (4 * (m + 1) + 2),
-                                             hipMemcpyDeviceToHost, s));
+                GsField &g = b->gs_host[ngs++];
+                g.V = (const double2 *)fl.V;
+                g.w = (double2 *)fl.pout;
+                g.vnext = (double2 *)col(q, S.i + 1);
+                g.red = fl.red;
+                g.co = fl.dco;
+                g.gather = b->gstage + q * hs;
+                g.N = fl.N;
+                g.nv = S.i + 1;
+                g.nblk = blas_nblocks(fl.N);
+                g.off2 = 2 * (m + 1);
+                g.offn = 4 * (m + 1);
+                g.ncopy = 4 * (m + 1) + 2;
+                nv_max = std::max(nv_max, g.nv);
+                nblk_max = std::max(nblk_max, g.nblk);
+                n_max = std::max(n_max, fl.N);
             }
         }
+        if (ngs > 0) {
+            TDP_CHECK_HIP(hipMemcpyAsync(b->gs_dev, b->gs_host, sizeof(GsField) * ngs,
+                                         hipMemcpyHostToDevice, s));
+            TDP_CHECK_HIP(launch_gs_step_multi(b->gs_dev, ngs, nv_max, nblk_max, n_max, s));
+        }
+        TDP_CHECK_HIP(hipMemcpyAsync(hb, b->gstage, sizeof(double) * hs * nf, hipMemcpyDeviceToHost, s));
         TDP_CHECK_HIP(hipStreamSynchronize(s));
         // host: Givens, and (tolerance mode) the current iterates' residuals
         bool anyD = false;

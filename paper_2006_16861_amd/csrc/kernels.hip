@@ -839,6 +839,124 @@ hipError_t launch_scale_by_invnorm(void *v, const void *w, const double *nrm2, i
     return hipGetLastError();
 }
 
+// One CGS2 step of several fields at once (the lockstep GMRES of the batched
+// form), as the kernels above would do it field by field: h1 = V^H w,
+// w -= V h1, h2 = V^H w, w -= V h2, |w|^2, v_next = w / |w|, then each
+// field's coefficients are gathered for one copy to the host.  Block z (or
+// y) is the field; a field's reductions use its own block count and order,
+// so the results equal the single-field kernels' bit for bit.
+__global__ __launch_bounds__(256) void k_gs_dot_partial(const GsField *__restrict__ gf, int self)
+{
+    __shared__ double sm[8];
+    const GsField g = gf[blockIdx.z];
+    const int k = blockIdx.y, nv = self ? 1 : g.nv;
+    if ((int)blockIdx.x >= g.nblk || k >= nv) return;
+    const double2 *v = self ? g.w : g.V + (int64_t)k * g.N;
+    const double2 *w = g.w;
+    double re = 0.0, im = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.N;
+         i += (int64_t)g.nblk * blockDim.x) {
+        const double2 a = v[i], b = w[i];
+        re += a.x * b.x + a.y * b.y;     // conj(a) * b
+        im += a.x * b.y - a.y * b.x;
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if ((threadIdx.x & 63) == 0) {
+        sm[threadIdx.x >> 6] = re;
+        sm[4 + (threadIdx.x >> 6)] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double *p = g.red + 2 * ((int64_t)k * g.nblk + blockIdx.x);
+        p[0] = (sm[0] + sm[1]) + (sm[2] + sm[3]);
+        p[1] = (sm[4] + sm[5]) + (sm[6] + sm[7]);
+    }
+}
+
+// which: 0 -> h1, 1 -> h2, 2 -> |w|^2 (one value)
+__global__ __launch_bounds__(256) void k_gs_dot_final(const GsField *__restrict__ gf, int which)
+{
+    __shared__ double sm[8];
+    const GsField g = gf[blockIdx.y];
+    const int k = blockIdx.x, nv = which == 2 ? 1 : g.nv;
+    if (k >= nv) return;
+    const double *p = g.red + 2 * (int64_t)k * g.nblk;
+    double re = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < g.nblk; i += blockDim.x) {
+        re += p[2 * i];
+        im += p[2 * i + 1];
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if ((threadIdx.x & 63) == 0) {
+        sm[threadIdx.x >> 6] = re;
+        sm[4 + (threadIdx.x >> 6)] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double *out = g.co + (which == 0 ? 0 : which == 1 ? g.off2 : g.offn);
+        out[2 * k] = (sm[0] + sm[1]) + (sm[2] + sm[3]);
+        out[2 * k + 1] = (sm[4] + sm[5]) + (sm[6] + sm[7]);
+    }
+}
+
+// w -= V h (which: 0 -> h1, 1 -> h2)
+__global__ __launch_bounds__(256) void k_gs_axpy(const GsField *__restrict__ gf, int which)
+{
+    const GsField g = gf[blockIdx.y];
+    const double *coef = g.co + (which == 0 ? 0 : g.off2);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k < g.nv; ++k) {
+            const double2 v = g.V[(int64_t)k * g.N + i];
+            const double cr = coef[2 * k], ci = coef[2 * k + 1];
+            re += cr * v.x - ci * v.y;
+            im += cr * v.y + ci * v.x;
+        }
+        double2 o = g.w[i];
+        o.x += -1.0 * re;
+        o.y += -1.0 * im;
+        g.w[i] = o;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gs_scale(const GsField *__restrict__ gf)
+{
+    const GsField g = gf[blockIdx.y];
+    const double sc = 1.0 / sqrt(g.co[g.offn]);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double2 a = g.w[i];
+        g.vnext[i] = make_double2(a.x * sc, a.y * sc);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gs_gather(const GsField *__restrict__ gf)
+{
+    const GsField g = gf[blockIdx.x];
+    for (int i = threadIdx.x; i < g.ncopy; i += blockDim.x) g.gather[i] = g.co[i];
+}
+
+hipError_t launch_gs_step_multi(const GsField *gf, int nf, int nv_max, int nblk_max,
+                                int64_t n_max, hipStream_t s)
+{
+    if (nf <= 0) return hipSuccess;
+    if (nf > 65535 || nv_max > 65535) return hipErrorInvalidValue;
+    const dim3 gp(nblk_max, nv_max, nf), gn(nblk_max, 1, nf), ga(grid_for(n_max), nf);
+    for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_gs_dot_partial, gp, dim3(256), 0, s, gf, 0);
+        hipLaunchKernelGGL(k_gs_dot_final, dim3(nv_max, nf), dim3(256), 0, s, gf, pass);
+        hipLaunchKernelGGL(k_gs_axpy, ga, dim3(256), 0, s, gf, pass);
+    }
+    hipLaunchKernelGGL(k_gs_dot_partial, gn, dim3(256), 0, s, gf, 1);
+    hipLaunchKernelGGL(k_gs_dot_final, dim3(1, nf), dim3(256), 0, s, gf, 2);
+    hipLaunchKernelGGL(k_gs_scale, ga, dim3(256), 0, s, gf);
+    hipLaunchKernelGGL(k_gs_gather, dim3(nf), dim3(256), 0, s, gf);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // gradient: g_cell = w2 Re sum_{b,g in cell} M[Delta(b,g)] conj(lam_b) U_g
 struct MassTable {

@@ -281,6 +281,20 @@ hipError_t launch_mdot(const void *V, int64_t ldv, int nv, const void *w, int64_
                        double *partial, int nblk, double *out, hipStream_t s);
 hipError_t launch_maxpy(void *w, const void *V, int64_t ldv, int nv, const double *coef,
                         double sign, int64_t N, hipStream_t s);
+// one field of a batched CGS2 step (launch_gs_step_multi): V holds nv
+// columns of N (column stride N); w is orthogonalised in place and vnext =
+// w / |w|; red holds 2 nblk nv partial sums; co receives h1 at co[0..2nv),
+// h2 at co[off2..), |w|^2 at co[offn]; its first ncopy doubles are then
+// copied to gather
+struct GsField {
+    const double2 *V;
+    double2 *w, *vnext;
+    double *red, *co, *gather;
+    int64_t N;
+    int nv, nblk, off2, offn, ncopy;
+};
+hipError_t launch_gs_step_multi(const GsField *gf, int nf, int nv_max, int nblk_max,
+                                int64_t n_max, hipStream_t s);
 hipError_t launch_scale_by_invnorm(void *v, const void *w, const double *nrm2, int64_t N,
                                    hipStream_t s);
 
