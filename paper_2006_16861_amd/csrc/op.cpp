@@ -590,9 +590,9 @@ static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth, i
     } else if (kern == 3 || kern == 4) {
         if (t > 2) t = 1;
         if (k == 0 && kern == 4) {
-            // fewest planes per workgroup run: the two-step grid is one round
-            // of resident workgroups with equal runs, so this only bounds how
-            // finely a small grid is split
+            // fewest planes per workgroup run: the run count per column block
+            // is chosen to fill whole rounds of the resident workgroups, so
+            // this only bounds how finely a small grid is split
             k = 8;
         } else if (k == 0) {
             // default chunk length: halve from 32 (down to 8) until the launch

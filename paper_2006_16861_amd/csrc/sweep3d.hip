@@ -595,6 +595,8 @@ __global__ __launch_bounds__(NT, (stream2_waves<T, NT>())) void k_sweep3d_stream
         }
         __syncthreads();
     };
+    // the scheduling barriers keep the three bodies from being interleaved,
+    // which would hold more registers live than a lane has (spills)
 #pragma unroll 1
     for (int it = 0; it < iters; it += 3) {
         step(it, kA, kB);
