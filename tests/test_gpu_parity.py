@@ -297,6 +297,14 @@ def test_full_size_3d_one_period():
         g.set_tuning(kernel=4, tb_depth=zc, tile=shape)
         U4 = host(g.precond(F, 1, 0.25))
         assert rel(U4, Uo) <= TOL64 and rel(U4, U) <= 1e-13
+    # FP32 fields in the timed configurations (one-step chunk 32, two-step
+    # 66 x 31 blocks), against the same oracle period at the FP32 bar
+    from paper_2006_16861_amd import tdp
+    g32 = tdp.operator_from_problem(p, prec=tdp.F32)
+    for kern, zc, shape in ((3, 32, 0), (4, 8, 2)):
+        g32.set_tuning(kernel=kern, tb_depth=zc, tile=shape)
+        assert rel(host(g32.precond(F, 1, 0.25)), Uo) <= 1e-4, (kern, shape)
+    del g32
     g.set_tuning(kernel=0)
     rng = np.random.default_rng(4)
     x = (rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n))
