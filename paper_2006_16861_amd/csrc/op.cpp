@@ -973,14 +973,19 @@ static int issue_steps(tdp_op *op, const LoopBufs &lb, int T, double rho, int va
 }
 
 static int res_finish(tdp_op *op, int ntiles, int T, double rho, int variant, const void *F,
-                      void *U, bool direct);
+                      void *U, bool direct, int *pending);
 
 // direct: F and U are buffers owned by the op (GMRES work vectors), so the
 // loop may be captured on them; otherwise a captured loop works on the
 // staging buffers, with copies of F in and U out around the replay.
+// pending (GMRES): when the resident sweep ran, its abort word is copied to
+// op->res_host without waiting, and *pending receives its tile count (else
+// 0); the caller reads op->res_host at its next synchronisation and, if
+// the word is raised, calls res_redo for this application.
 static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *F, void *U,
-                        bool direct = false)
+                        bool direct = false, int *pending = nullptr)
 {
+    if (pending) *pending = 0;
     if (T < 1) TDP_FAIL(TDP_EINVAL, "periods_T must be >= 1");
     if (rho <= 0.0) rho = 1.0 / T;
     if (rho > 1.0) TDP_FAIL(TDP_EINVAL, "rho must be <= 1");
@@ -1019,7 +1024,7 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
             Fin = op->Fst;
         }
         TDP_CHECK(issue_steps(op, lb, T, rho, variant, Fin, U));
-        return res_nt ? res_finish(op, res_nt, T, rho, variant, F, U, direct) : TDP_OK;
+        return res_nt ? res_finish(op, res_nt, T, rho, variant, F, U, direct, pending) : TDP_OK;
     }
     // captured loop: on F and U themselves (direct), else reading op->Fstage
     // (F64) / op->Fst (F32) and writing op->Ustage
@@ -1064,7 +1069,7 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
     }
     if (direct) {
         TDP_CHECK_HIP(hipGraphLaunch(it->second, s));
-        return res_nt ? res_finish(op, res_nt, T, rho, variant, F, U, direct) : TDP_OK;
+        return res_nt ? res_finish(op, res_nt, T, rho, variant, F, U, direct, pending) : TDP_OK;
     }
     if (op->prec == TDP_F64)
         TDP_CHECK_HIP(hipMemcpyAsync(op->Fstage, F, 16 * op->N, hipMemcpyDeviceToDevice, s));
@@ -1072,21 +1077,33 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
         TDP_CHECK_HIP(launch_cvt_c128_to_c64(F, op->Fst, op->N, s));
     TDP_CHECK_HIP(hipGraphLaunch(it->second, s));
     TDP_CHECK_HIP(hipMemcpyAsync(U, op->Ustage, 16 * op->N, hipMemcpyDeviceToDevice, s));
-    return res_nt ? res_finish(op, res_nt, T, rho, variant, F, U, direct) : TDP_OK;
+    return res_nt ? res_finish(op, res_nt, T, rho, variant, F, U, direct, pending) : TDP_OK;
 }
 
 // A resident loop that ended early is redone with the blocked sweep, and the
 // op stops using the resident kernel (its tuning goes back to auto).
-static int res_finish(tdp_op *op, int ntiles, int T, double rho, int variant, const void *F,
-                      void *U, bool direct)
+static int res_redo(tdp_op *op, int T, double rho, int variant, const void *F, void *U,
+                    bool direct)
 {
-    const int rc = res_check(op, ntiles);
-    if (rc != 1) return rc;
     ++op->res_aborts;
     op->tune.kernel = 0;
     op->tune.tb_depth = 0;
     op->tune.tile = 0;
     return precond_impl(op, T, rho, variant, F, U, direct);
+}
+
+static int res_finish(tdp_op *op, int ntiles, int T, double rho, int variant, const void *F,
+                      void *U, bool direct, int *pending)
+{
+    if (pending) {          // the caller reads the word at its next synchronisation
+        TDP_CHECK_HIP(hipMemcpyAsync(op->res_host, op->res_flags + (size_t)ntiles * TDP_RES_FLAG_STRIDE,
+                                     sizeof(int), hipMemcpyDeviceToHost, op->stream));
+        *pending = ntiles;
+        return TDP_OK;
+    }
+    const int rc = res_check(op, ntiles);
+    if (rc != 1) return rc;
+    return res_redo(op, T, rho, variant, F, U, direct);
 }
 
 int precond_noalloc_impl(tdp_op *op, int T, double rho, const void *F, void *U,
@@ -1347,11 +1364,16 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
             pending[ph] = false;
         }
     };
+    // the resident sweep's abort word is read at the synchronisation that
+    // follows (no wait of its own); a raised word redoes the application
+    // and the work that used it
+    int res_pending = 0;
     auto precond_timed = [&](const void *x, void *y, int var) -> int {
         TDP_CHECK(mark(0, 0));
-        TDP_CHECK(precond_impl(op, T, cfg->rho, var, x, y, true));
+        TDP_CHECK(precond_impl(op, T, cfg->rho, var, x, y, true, &res_pending));
         return mark(0, 1);
     };
+    auto res_aborted = [&]() -> bool { return res_pending && *op->res_host; };
     auto apply_H_timed = [&](const void *x, const void *Fr, void *y) -> int {
         TDP_CHECK(mark(1, 0));
         TDP_CHECK(apply_H_impl(op, x, Fr, y));
@@ -1422,6 +1444,11 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
         ++napply;
         double z2;
         TDP_CHECK(norm2_host(op, col(0), &z2));
+        if (res_aborted()) {
+            res_pending = 0;
+            TDP_CHECK(res_redo(op, T, cfg->rho, variant, op->rv, col(0), true));
+            TDP_CHECK(norm2_host(op, col(0), &z2));
+        }
         collect_time();
         const double beta0 = std::sqrt(z2);
         if (pnorm0 < 0.0) pnorm0 = beta0;
@@ -1438,18 +1465,29 @@ static int gmres_impl(tdp_op *op, const tdp_gmres_cfg *cfg, const void *F, void 
             TDP_CHECK(precond_timed(op->tv, op->wv, variant));
             ++napply;
             ++its;
-            // classical Gram-Schmidt, two passes
-            TDP_CHECK(mark(2, 0));
-            TDP_CHECK_HIP(launch_mdot(op->V, N, i + 1, op->wv, N, op->red, nblk, d1, s));
-            TDP_CHECK_HIP(launch_maxpy(op->wv, op->V, N, i + 1, d1, -1.0, N, s));
-            TDP_CHECK_HIP(launch_mdot(op->V, N, i + 1, op->wv, N, op->red, nblk, d2, s));
-            TDP_CHECK_HIP(launch_maxpy(op->wv, op->V, N, i + 1, d2, -1.0, N, s));
-            TDP_CHECK_HIP(launch_mdot(op->wv, N, 1, op->wv, N, op->red, nblk, dn2, s));
-            TDP_CHECK_HIP(launch_scale_by_invnorm(col(i + 1), op->wv, dn2, N, s));
-            TDP_CHECK(mark(2, 1));
-            TDP_CHECK_HIP(hipMemcpyAsync(op->hres, op->dcoef, sizeof(double) * (4 * (m + 1) + 2),
-                                         hipMemcpyDeviceToHost, s));
-            TDP_CHECK_HIP(hipStreamSynchronize(s));
+            // classical Gram-Schmidt, two passes (w = P H v_i is only read
+            // and rewritten in place, v_{i+1} only written: both are redone
+            // from P H v_i if the application is)
+            auto cgs2 = [&]() -> int {
+                TDP_CHECK(mark(2, 0));
+                TDP_CHECK_HIP(launch_mdot(op->V, N, i + 1, op->wv, N, op->red, nblk, d1, s));
+                TDP_CHECK_HIP(launch_maxpy(op->wv, op->V, N, i + 1, d1, -1.0, N, s));
+                TDP_CHECK_HIP(launch_mdot(op->V, N, i + 1, op->wv, N, op->red, nblk, d2, s));
+                TDP_CHECK_HIP(launch_maxpy(op->wv, op->V, N, i + 1, d2, -1.0, N, s));
+                TDP_CHECK_HIP(launch_mdot(op->wv, N, 1, op->wv, N, op->red, nblk, dn2, s));
+                TDP_CHECK_HIP(launch_scale_by_invnorm(col(i + 1), op->wv, dn2, N, s));
+                TDP_CHECK(mark(2, 1));
+                TDP_CHECK_HIP(hipMemcpyAsync(op->hres, op->dcoef, sizeof(double) * (4 * (m + 1) + 2),
+                                             hipMemcpyDeviceToHost, s));
+                TDP_CHECK_HIP(hipStreamSynchronize(s));
+                return TDP_OK;
+            };
+            TDP_CHECK(cgs2());
+            if (res_aborted()) {
+                res_pending = 0;
+                TDP_CHECK(res_redo(op, T, cfg->rho, variant, op->tv, op->wv, true));
+                TDP_CHECK(cgs2());
+            }
             collect_time();
             const double *h1 = op->hres, *h2 = op->hres + 2 * (m + 1);
             for (int k = 0; k <= i; ++k)
