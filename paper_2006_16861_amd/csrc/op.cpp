@@ -568,9 +568,24 @@ static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth, i
         kern = k = t = 0;
     }
     if (kern == 0) {
-        kern = op->ndim == 2 ? 2 : 3;
-        k = kern == 2 ? 8 : 0;
-        t = kern == 2 ? (f64 ? 5 : 8) : 0;
+        if (op->ndim == 2) {
+            kern = 2;
+            k = 8;
+            t = f64 ? 5 : 8;
+        } else if (op->sc <= 3 && op->mc <= 2) {
+            // 3-D compact tables: two steps per launch, FP64 on 66 x 15
+            // blocks, FP32 on 66 x 31 blocks (66 x 15 below about 3 * 2^20
+            // nodes).  Measured per step against the one-step sweep: FP64
+            // 17.9 / 23.4 us at 128^3, 73 / 81 at 192^3, 132 / 146 at 256^3;
+            // FP32 14.3 / 17.5 at 128^3, 41 / 49 at 192^3, 77 / 84 at 224^3,
+            // but 82 / 79 at 256^3 (the autotuner decides there)
+            kern = 4;
+            k = 8;
+            t = f64 || op->N < (3 << 20) ? 1 : 2;
+        } else {
+            kern = 3;
+            k = t = 0;
+        }
         if (op->dform == TDP_DAMP_CELL) t = f64 ? 7 : 5;
     }
     // I_abd: the blocked 2-D kernel on the tiles that hold its per-node state
