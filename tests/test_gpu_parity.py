@@ -442,6 +442,28 @@ def test_precond_3d_streamed_f64(n, shape, zc, kern):
     assert rel(host(g.precond(dev(p.F), 2, 0.25)), U) <= 1e-13
 
 
+def test_precond_3d_two_step_many_column_blocks():
+    """The two-step sweep on a grid of 11 x 12 column blocks with ragged last
+    blocks along both in-plane axes, split into runs along axis 0 (one run
+    per block with shortest run 8; several with 1), every shape, FP64 and
+    FP32: against the oracle and the one-step kernel."""
+    p = inputs.random_medium((20, 150, 700), seed=24, width=3)
+    note("precond 3d two-step 20x150x700")
+    g, o = make_ops(p)
+    Uo = o.precond(p.F, 2, 0.25)
+    g.set_tuning(kernel=1)
+    U1 = host(g.precond(dev(p.F), 2, 0.25))
+    for shape in (0, 1, 2):
+        for zc in (8, 1):
+            g.set_tuning(kernel=4, tb_depth=zc, tile=shape)
+            U = host(g.precond(dev(p.F), 2, 0.25))
+            assert rel(U, Uo) <= TOL64 and rel(U, U1) <= 1e-13, (shape, zc)
+    g32, _ = make_ops(p, prec=1)
+    for shape in (1, 2):
+        g32.set_tuning(kernel=4, tb_depth=8, tile=shape)
+        assert rel(host(g32.precond(dev(p.F), 2, 0.25)), Uo) <= 1e-4, shape
+
+
 @pytest.mark.parametrize("kern,shape", [(3, 1), (4, 0), (4, 1), (4, 2)])
 def test_precond_3d_streamed_f32(kern, shape):
     p = inputs.random_medium((24, 30, 70), seed=22, width=3)
