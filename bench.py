@@ -367,6 +367,37 @@ def _traffic(key):
     return None if rec is None else rec["bytes_per_launch"]
 
 
+def profile_batched(args):
+    """Profiling mode of the batched form's shared-medium sweep: the 64
+    right-hand sides of form_batched on their 512^2 medium, at a fixed tuning,
+    after the same 256 MiB calibration copy as --profile-sweeps."""
+    import torch
+    from paper_2006_16861_amd import inputs, tdp
+    base = inputs.smooth2d(512, seed=4, src_seed=5)
+    srcs = inputs.random_sources(base.n, 64, seed=5, margin=32)
+    op = tdp.operator_from_problem(base, prec=tdp.F32)
+    Fs = [torch.as_tensor(srcs[k], device="cuda") for k in range(64)]
+    b = tdp.Batch([op], [64])
+    depth = args.tb_depth or 8
+    b.set_tuning(depth, args.tile, args.medium_tile)
+    src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)                       # plain copy: 256 MiB read + 256 MiB written
+    b.precond(Fs, [base.periods], args.rho)                             # warm (graph)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.profile_batched):
+        b.precond(Fs, [base.periods], args.rho)
+    torch.cuda.synchronize()
+    apply_ms = (time.perf_counter() - t) * 1e3 / args.profile_batched
+    launches = -(-base.periods * op.nP // depth)
+    print(json.dumps({"mode": "profile_batched", "fields": 64, "N": base.N,
+                      "tuning": {"depth": depth, "tile": args.tile, "medium_tile": args.medium_tile},
+                      "launches_per_apply": launches, "apply_ms": apply_ms,
+                      "us_per_launch": apply_ms * 1e3 / launches}), flush=True)
+    b.close()
+
+
 def form_batched(rho):
     """Batched form: 64 right-hand sides (seeded unit sources) on one 512^2
     smooth medium plus 32 independent problems of sizes 128..768 per side,
@@ -743,6 +774,12 @@ def main():
     ap.add_argument("--profile-sweeps", type=int, default=0,
                     help="profiling mode: one 256 MiB device copy (counter calibration), then "
                          "this many preconditioner applications, then exit")
+    ap.add_argument("--profile-batched", type=int, default=0,
+                    help="profiling mode for the batched form: one 256 MiB device copy, then this "
+                         "many applications of the 64 right-hand sides on one 512^2 medium (FP32 "
+                         "fields) with --tb-depth, --tile and --medium-tile, then exit")
+    ap.add_argument("--medium-tile", type=int, default=1,
+                    help="shared-medium tile of --profile-batched (-1: every field on its own tile)")
     ap.add_argument("--study", choices=["convergence", "shard"], default=None,
                     help="convergence: Sec. 5.1's convergence study on the constant and "
                          "resonant models; shard: the sweep at one GPU's slab of an 8-GPU "
@@ -755,6 +792,9 @@ def main():
         return
     if args.study == "shard":
         study_shard()
+        return
+    if args.profile_batched:
+        profile_batched(args)
         return
     if args.damping == "cell" and args.variant != 1:
         raise SystemExit("--damping cell runs S_T^abd: pass --variant 1")
