@@ -44,15 +44,16 @@ def flops_per_node_step(ndim, stencil_points):
 
 
 def roofline_block(kernel, launch_us, alg_bytes, alg_flops, word, traffic=None,
-                   effective_bytes=None, note=None):
+                   effective_bytes=None, note=None, effective_label="7word"):
     """Roofline of one launch of a kernel: the algorithmic bytes it must move
     (its inputs read once, its outputs written once) and its useful flops,
     each over the launch time, against the HBM peak and the vector ALU peak.
     frac is the larger of the two fractions (<= 1 by construction); bound names
     that roof, or "latency" when neither reaches half of its peak.
-    effective_bytes, if given, is the per-step 7-word model over the launch's
-    steps (no reuse across steps), reported separately: temporal blocking
-    takes it above the HBM peak."""
+    effective_bytes, if given, is a per-step word model over the launch's
+    steps (no reuse across steps; 7 words per node-step for the node damping,
+    named by effective_label), reported separately: temporal blocking takes it
+    above the HBM peak."""
     t = launch_us * 1e-6
     gbps = alg_bytes / t / 1e9
     tflops = alg_flops / t / 1e12
@@ -74,8 +75,8 @@ def roofline_block(kernel, launch_us, alg_bytes, alg_flops, word, traffic=None,
         out["traffic_GBps"] = traffic / t / 1e9
         out["traffic_frac"] = traffic / t / 1e9 / HBM_PEAK_GBS
     if effective_bytes:
-        out["effective_GBps_7word"] = effective_bytes / t / 1e9
-        out["effective_frac_7word"] = effective_bytes / t / 1e9 / HBM_PEAK_GBS
+        out[f"effective_GBps_{effective_label}"] = effective_bytes / t / 1e9
+        out[f"effective_frac_{effective_label}"] = effective_bytes / t / 1e9 / HBM_PEAK_GBS
     if note:
         out["note"] = note
     return out
@@ -513,6 +514,28 @@ def form_batched(rho):
     return res, handoff
 
 
+def abd_roofline(p, tun, us_step, word, prec):
+    """Roofline of the I_abd sweep's launch.  Blocked (kernel 2): one launch
+    runs k steps of one real pass, so a complex step is two passes and a
+    launch lasts us_step * k / 2; it must read x_n, x_{n-1}, the cell
+    slowness, the cell damping and F (both parts, the forcing scalars mix
+    them) and write x_{n+k}, x_{n+k-1}: 8 words per node.  A real node-step
+    is 31 flops: the I_acd stencil 14 (one product, four FMAs, three adds and
+    an FMA for the corners), the damping stencil on w = x_{n-1} - cos(theta)
+    x_n 10 plus 2 for w, the forcing 4, the -x_{n-1} term 1.  One step per
+    launch (kernel 1): the complex field, 10 words and 62 flops per node."""
+    if tun["kernel"] == 2:
+        K = tun["tb_depth"]
+        kname = (f"k_sweep2d_abd_tb<{'double' if word == 8 else 'float'}> tile={tun['tile']} "
+                 f"depth={K} (one real pass of {K} steps per launch)")
+        return roofline_block(kname, us_step * K / 2, 8 * word * p.N, 31 * K * p.N, word,
+                              traffic=measured_traffic("smooth2d-1024", prec, 1, tun, "cell"),
+                              effective_bytes=5 * word * p.N * K, effective_label="5word")
+    return roofline_block("k_sweep_abd (one complex step per launch)", us_step, 10 * word * p.N,
+                          62 * p.N, word,
+                          traffic=measured_traffic("smooth2d-1024", prec, 1, tun, "cell"))
+
+
 def form_cell_damping(rho):
     """Sec. 6 path on the headline workload: smooth2d-1024 with the cell
     (non-diagonal) damping Im H = omega sum_cells r_cell M_cell, preconditioned
@@ -537,11 +560,13 @@ def form_cell_damping(rho):
         word = 8 if prec == tdp.F64 else 4
         log(f"form cell damping {name}: {dt:.3f} s, iters {info.iters}, relres {r:.2e}, "
             f"{us:.2f} us/step")
+        tun = op.get_tuning()
         res[name] = {"n_P": op.nP, "omega_c": op.omega_c, "solves_per_s": 1.0 / dt,
                      "seconds": dt, "iters": info.iters,
                      "precond_applications": info.steps // (p.periods * op.nP), "true_relres": r,
-                     "sweep_us_per_step": us, "tuning": op.get_tuning(),
-                     "sweep_algorithmic_GBps": 10 * word * p.N / (us * 1e-6) / 1e9}
+                     "sweep_us_per_step": us, "tuning": tun,
+                     "sweep_algorithmic_GBps": 10 * word * p.N / (us * 1e-6) / 1e9,
+                     "roofline": abd_roofline(p, tun, us, word, name)}
         del op
     return res
 
