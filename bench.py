@@ -516,24 +516,23 @@ def form_batched(rho):
 
 def abd_roofline(p, tun, us_step, word, prec):
     """Roofline of the I_abd sweep's launch.  Blocked (kernel 2): one launch
-    runs k steps of one real pass, so a complex step is two passes and a
-    launch lasts us_step * k / 2; it must read x_n, x_{n-1}, the cell
-    slowness, the cell damping and F (both parts, the forcing scalars mix
-    them) and write x_{n+k}, x_{n+k-1}: 8 words per node.  A real node-step
-    is 31 flops: the I_acd stencil 14 (one product, four FMAs, three adds and
-    an FMA for the corners), the damping stencil on w = x_{n-1} - cos(theta)
-    x_n 10 plus 2 for w, the forcing 4, the -x_{n-1} term 1.  One step per
-    launch (kernel 1): the complex field, 10 words and 62 flops per node."""
+    runs k complex steps (both real parts of the field), so it lasts
+    us_step * k; it must read x_n, x_{n-1} (complex), the cell slowness, the
+    cell damping and F (complex) and write x_{n+k}, x_{n+k-1} (complex): 12
+    words per node.  Flops per real node-step follow flops_per_node_step over
+    the 9 points of A and the 5 of B (34), twice per complex node-step.  One
+    step per launch (kernel 1): 10 words and 68 flops per node."""
+    flops = 2 * flops_per_node_step(2, 9 + 5)
+    traffic = measured_traffic("smooth2d-1024", prec, 1, tun, "cell")
     if tun["kernel"] == 2:
         K = tun["tb_depth"]
-        kname = (f"k_sweep2d_abd_tb<{'double' if word == 8 else 'float'}> tile={tun['tile']} "
-                 f"depth={K} (one real pass of {K} steps per launch)")
-        return roofline_block(kname, us_step * K / 2, 8 * word * p.N, 31 * K * p.N, word,
-                              traffic=measured_traffic("smooth2d-1024", prec, 1, tun, "cell"),
-                              effective_bytes=5 * word * p.N * K, effective_label="5word")
+        kname = (f"k_sweep2d_abd_tb2<{'double' if word == 8 else 'float'}> tile={tun['tile']} "
+                 f"depth={K} (both real parts, {K} steps per launch)")
+        return roofline_block(kname, us_step * K, 12 * word * p.N, flops * K * p.N, word,
+                              traffic=traffic, effective_bytes=10 * word * p.N * K,
+                              effective_label="10word")
     return roofline_block("k_sweep_abd (one complex step per launch)", us_step, 10 * word * p.N,
-                          62 * p.N, word,
-                          traffic=measured_traffic("smooth2d-1024", prec, 1, tun, "cell"))
+                          flops * p.N, word, traffic=traffic)
 
 
 def form_cell_damping(rho):
@@ -874,8 +873,9 @@ def main():
             tun = op.get_tuning()
             per = {2: tun["tb_depth"], 4: 2, 5: RES_MAX_STEPS}.get(tun["kernel"], 1)
             launches = -(-Ns // per)
-            if args.variant == 1 and tun["kernel"] != 1:
-                launches *= 2                    # two real passes
+            if args.variant == 1 and tun["kernel"] != 1 and not (args.damping == "cell"
+                                                                  and tun["kernel"] == 2):
+                launches *= 2                    # two real passes (one launch for both: I_abd)
             print(json.dumps({"mode": "profile", "workload": args.workload, "N": p.N,
                               "N_s": Ns, "tuning": tun, "launches_per_apply": launches,
                               "apply_ms": apply_ms, "us_per_step": step_ms * 1e3,
@@ -913,8 +913,9 @@ def main():
     blocked = tun["kernel"] == 2
     steps_per_launch = {2: tun["tb_depth"], 4: 2, 5: min(RES_MAX_STEPS, Ns)}.get(tun["kernel"], 1)
     launches = -(-Ns // steps_per_launch)
-    if args.variant == 1 and tun["kernel"] != 1:
-        launches *= 2                            # Def. 4 and I_abd: two real passes
+    paired = args.damping == "cell" and tun["kernel"] == 2     # I_abd: both parts per launch
+    if args.variant == 1 and tun["kernel"] != 1 and not paired:
+        launches *= 2                            # Def. 4: two real passes
     napply = infos[-1].steps // Ns
     # average launch duration over the timed solves: the GPU time of their
     # preconditioner applications (HIP events on the op's stream around each
@@ -926,9 +927,9 @@ def main():
     # steps; above the HBM peak under temporal blocking)
     effective = p.N * bytes_per * (Ns / launches) / (launch_us * 1e-6) / 1e9
     tname = "double" if prec == tdp.F64 else "float"
-    if args.damping == "cell" and tun["kernel"] == 2:
-        kname = (f"k_sweep2d_abd_tb<{tname}> depth={steps_per_launch} tile={tun['tile']} "
-                 "(I_abd, two real passes)")
+    if paired:
+        kname = (f"k_sweep2d_abd_tb2<{tname}> depth={steps_per_launch} tile={tun['tile']} "
+                 "(I_abd, both real parts per launch)")
     elif args.damping == "cell":
         kname = f"k_sweep_abd<{tname}> (I_abd, one step per launch)"
     elif tun["kernel"] == 2:
@@ -951,11 +952,15 @@ def main():
     log(f"stream probe: copy {ceiling['copy']:.0f} GB/s, triad {ceiling['triad']:.0f} GB/s")
     # bytes one launch must move: a blocked or two-step launch reads u_j,
     # u_{j-1}, m, the damping factor and F once and writes two fields (8 words
-    # per node); a one-step launch moves the 7 words of one step; Def. 4 on the
-    # complex field in one pass moves 10
+    # per node); the blocked I_abd launch reads both parts of x_n and x_{n-1},
+    # the two cell arrays and F and writes both parts of two fields (12); a
+    # one-step launch moves the 7 words of one step; Def. 4 on the complex
+    # field in one pass moves 10
     spl = Ns / launches
     cell = args.damping == "cell"
-    if tun["kernel"] in (2, 4, 5) or cell and tun["kernel"] == 2:
+    if paired:
+        words_launch = 12
+    elif tun["kernel"] in (2, 4, 5):
         words_launch = WORDS_PER_NODE_LAUNCH
     else:
         words_launch = 10 if (args.variant == 1 and tun["kernel"] == 1) else WORDS_PER_NODE_STEP
@@ -963,7 +968,8 @@ def main():
               ("q1", 3): 27}[(args.scheme, len(p.n))]
     if cell:
         points += 5 if len(p.n) == 2 else 7           # the damping stencil of I_abd
-    flops = flops_per_node_step(len(p.n), points) * (2 if args.variant == 1 and tun["kernel"] == 1 else 1)
+    flops = flops_per_node_step(len(p.n), points) * (
+        2 if args.variant == 1 and (tun["kernel"] == 1 or paired) else 1)
     roof = roofline_block(kname, launch_us, p.N * word * words_launch, flops * p.N * spl, word,
                           traffic=traffic, effective_bytes=p.N * bytes_per * spl)
     log(f"precond apply {apply_ms:.3f} ms, {step_ms * 1e3:.2f} us/step; launch {launch_us:.2f} us: "

@@ -228,8 +228,8 @@ int tdp_precond_apply_noalloc(const tdp_op *op, int periods_T, double rho, const
  * (10 instead of 7 words per node-step).
  * With TDP_DAMP_CELL this is S_T^abd (Sec. 6, Def. 7): the same forcing
  * driving I_abd (Def. 6).  Its recurrence has real coefficients too: in 2-D
- * (mass tables without corner entries) it runs as two real passes of the
- * blocked I_abd kernel (k steps per launch), else, and with
+ * (mass tables without corner entries) the blocked I_abd kernel advances
+ * both real parts k steps per launch, else, and with
  * tdp_tuning.kernel = 1, on the complex field one step per launch (10 words
  * per node-step; u_{n-1} is read with its neighbours, so u_{n+1} goes to a
  * third field).

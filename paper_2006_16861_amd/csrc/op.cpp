@@ -116,7 +116,7 @@ static int free_op(tdp_op *op)
     (void)hipFree(op->gcell);
     for (auto &kv : op->graphs) (void)hipGraphExecDestroy(kv.second);
     void *bufs[] = {op->m, op->rw, op->dn, op->m32, op->dn32, op->rc32, op->u0, op->u1, op->u2, op->v0, op->v1,
-                    op->u3, op->u4, op->rc, op->Fst, op->scratch, op->V, op->wv, op->tv, op->rv,
+                    op->u3, op->u4, op->u5, op->rc, op->Fst, op->scratch, op->V, op->wv, op->tv, op->rv,
                     op->xv, op->red, op->dcoef};
     for (void *b : bufs) (void)hipFree(b);
     (void)hipFree(op->res_shadow);
@@ -531,7 +531,8 @@ static int ensure_complex_fields(tdp_op *op)
     const size_t fb = 2 * (op->prec == TDP_F64 ? sizeof(double) : sizeof(float)) * op->N;
     if (!op->u2 && (hipMalloc(&op->u2, fb) != hipSuccess || hipMalloc(&op->u3, fb) != hipSuccess))
         TDP_FAIL(TDP_ENOMEM, "device allocation of complex recurrence fields failed");
-    if (op->dform == TDP_DAMP_CELL && !op->u4 && hipMalloc(&op->u4, fb) != hipSuccess)
+    if (op->dform == TDP_DAMP_CELL && !op->u4 &&
+        (hipMalloc(&op->u4, fb) != hipSuccess || hipMalloc(&op->u5, fb) != hipSuccess))
         TDP_FAIL(TDP_ENOMEM, "device allocation of complex recurrence fields failed");
     return TDP_OK;
 }
@@ -642,8 +643,7 @@ static int ensure_tb_fields(tdp_op *op)
 // final field goes to out_final and, when out_snap is given, the sample
 // u_{N_s - q} to out_snap (stride-2 doubles inside a complex128 array).
 static int issue_steps_tb(tdp_op *op, const LoopBufs &lb, int T, double rho, int depth, int tile,
-                          const void *Fin, int tabv, double *out_final, double *out_snap,
-                          bool abd = false)
+                          const void *Fin, int tabv, double *out_final, double *out_snap)
 {
     hipStream_t s = op->stream;
     const ForcingSrc tab = forcing_src(op, T, rho, tabv, lb);
@@ -661,10 +661,6 @@ static int issue_steps_tb(tdp_op *op, const LoopBufs &lb, int T, double rho, int
     a.m = op->prec == TDP_F64 ? (const void *)op->m : (const void *)op->m32;
     a.dn = op->prec == TDP_F64 ? (const void *)op->dn : (const void *)op->dn32;
     a.F = Fin;
-    if (abd) {
-        a.rc = op->prec == TDP_F64 ? (const void *)op->rc : (const void *)op->rc32;
-        a.cth = op->cos_th;
-    }
     for (int64_t j0 = 0; j0 < Ns; j0 += depth) {
         const int k = (int)std::min<int64_t>(depth, Ns - j0);
         a.u_in = cur;
@@ -681,14 +677,60 @@ static int issue_steps_tb(tdp_op *op, const LoopBufs &lb, int T, double rho, int
         a.cf.out[0] = out_snap;
         a.cf.out_step[1] = (Ns > j0 && Ns <= j0 + k) ? (int)(Ns - j0) : 0;
         a.cf.out[1] = out_final;
-        if (abd && op->prec == TDP_F64)
-            TDP_CHECK_HIP(launch_sweep2d_abd_tb_f64(a, op->st_step, op->st_B, s));
-        else if (abd)
-            TDP_CHECK_HIP(launch_sweep2d_abd_tb_f32(a, op->st_step32, op->st_B32, s));
-        else if (op->prec == TDP_F64)
+        if (op->prec == TDP_F64)
             TDP_CHECK_HIP(launch_sweep2d_tb_f64(a, op->st_step, s));
         else
             TDP_CHECK_HIP(launch_sweep2d_tb_f32(a, op->st_step32, s));
+        std::swap(cur, ncur);
+        std::swap(prev, nprev);
+    }
+    return TDP_OK;
+}
+
+// Blocked I_abd loop on the complex field of S_T^abd: both real parts per
+// launch (the real part driven by the Table 1 form of the forcing table, the
+// imaginary part by (-fb, fa)), ping-ponging between the complex field pairs
+// (u2, u3) and (u4, u5); the final field goes to U (complex128).
+static int issue_steps_abd2(tdp_op *op, const LoopBufs &lb, int T, double rho, int depth,
+                            int tile, const void *Fin, double *U)
+{
+    hipStream_t s = op->stream;
+    const ForcingSrc tab = forcing_src(op, T, rho, 0, lb);
+    const int64_t Ns = (int64_t)T * op->nP;
+    const bool f64 = op->prec == TDP_F64;
+    const size_t fb = 2 * (f64 ? sizeof(double) : sizeof(float)) * op->N;
+    void *cur = op->u2, *prev = op->u3, *ncur = op->u4, *nprev = op->u5;
+    TDP_CHECK_HIP(launch_fill_zero(cur, fb, s));
+    TDP_CHECK_HIP(launch_fill_zero(prev, fb, s));
+    TBArgs a;
+    a.ny = op->n[0];
+    a.nx = op->n[1];
+    a.sc = op->sc;
+    a.mc = op->mc;
+    a.shape = tile;
+    a.m = f64 ? (const void *)op->m : (const void *)op->m32;
+    a.rc = f64 ? (const void *)op->rc : (const void *)op->rc32;
+    a.cth = op->cos_th;
+    a.F = Fin;
+    for (int64_t j0 = 0; j0 < Ns; j0 += depth) {
+        const int k = (int)std::min<int64_t>(depth, Ns - j0);
+        a.u_in = cur;
+        a.up_in = prev;
+        a.u_out = ncur;
+        a.up_out = nprev;
+        a.cf.k = k;
+        for (int q = 0; q < k; ++q) {
+            a.cf.fa[q] = tab.a(j0 + q);
+            a.cf.fb[q] = tab.b(j0 + q);
+        }
+        a.cf.out_step[0] = 0;
+        a.cf.out[0] = nullptr;
+        a.cf.out_step[1] = (Ns > j0 && Ns <= j0 + k) ? (int)(Ns - j0) : 0;
+        a.cf.out[1] = U;
+        if (f64)
+            TDP_CHECK_HIP(launch_sweep2d_abd2_tb_f64(a, op->st_step, op->st_B, s));
+        else
+            TDP_CHECK_HIP(launch_sweep2d_abd2_tb_f32(a, op->st_step32, op->st_B32, s));
         std::swap(cur, ncur);
         std::swap(prev, nprev);
     }
@@ -910,8 +952,8 @@ static int issue_steps_real1(tdp_op *op, const LoopBufs &lb, int T, double rho, 
 // real and imaginary parts of the forcing: with the blocked or streamed
 // kernels they run as two real passes (tables 0 and 2), with kernel 1 as one
 // complex pass.  The cell damping runs I_abd, whose recurrence has real
-// coefficients too: two real passes of the blocked 2-D kernel (tables 0 and
-// 2 again), or the complex field with kernel 1.
+// coefficients too: the blocked 2-D kernel advances both parts per launch
+// (sharing the coefficients and F), kernel 1 the complex field.
 static int issue_steps_loop(tdp_op *op, const LoopBufs &lb, int T, double rho, int variant,
                             const void *Fin, void *U)
 {
@@ -924,10 +966,8 @@ static int issue_steps_loop(tdp_op *op, const LoopBufs &lb, int T, double rho, i
         if (kern == 4) return issue_steps_3d2(op, lb, T, rho, depth, tile, Fin, tabv, fin, snap);
         return issue_steps_real1(op, lb, T, rho, kern, depth, tile, Fin, tabv, fin, snap);
     };
-    if (op->dform == TDP_DAMP_CELL && kern == 2) {
-        TDP_CHECK(issue_steps_tb(op, lb, T, rho, depth, tile, Fin, 0, Ud, nullptr, true));
-        return issue_steps_tb(op, lb, T, rho, depth, tile, Fin, 2, Ud + 1, nullptr, true);
-    }
+    if (op->dform == TDP_DAMP_CELL && kern == 2)
+        return issue_steps_abd2(op, lb, T, rho, depth, tile, Fin, Ud);
     if (variant == 0) return real_pass(0, Ud, Ud + 1);
     if (op->dform == TDP_DAMP_NODE && kern != 1) {
         TDP_CHECK(real_pass(0, Ud, nullptr));
@@ -1026,7 +1066,8 @@ static int precond_impl(tdp_op *op, int T, double rho, int variant, const void *
                  : kern == 4 ? (Ns + 1) / 2
                  : kern == 5 ? 2 * ((Ns + TDP_RES_MAXSTEPS - 1) / TDP_RES_MAXSTEPS)
                              : Ns;
-        if (variant == 1 && kern != 1) launches *= 2;     // two real passes
+        // two real passes (one launch for both with the blocked I_abd kernel)
+        if (variant == 1 && kern != 1 && !(op->dform == TDP_DAMP_CELL && kern == 2)) launches *= 2;
     }
     const LoopBufs lb{op->u0, op->u1, op->v0, op->v1, false};
     hipStream_t s = op->stream;

@@ -14,8 +14,8 @@
 //  - tb_tile2 (shapes 4..8, the default): per-node coefficients and the rows
 //    of u_j, u_{j-1} in registers, x-neighbours by DPP, only each wave's edge
 //    rows through LDS (same integrator);
-//  - tb_tile_abd: the same register form for I_abd (Sec. 6, cell damping) on
-//    one real part of the complex field.
+//  - tb_tile_abd2: the same register form for I_abd (Sec. 6, cell damping) on
+//    both real parts of the complex field at once.
 //
 // Workgroups are mapped XCD-aware: the hardware deals consecutive workgroup
 // ids round-robin to the 8 XCDs, so id -> tile is remapped to give each XCD a
@@ -1076,9 +1076,9 @@ void k_sweep2d_tb_mrhs(const BFieldT<T> *__restrict__ fields, const int *__restr
     tb_tile_mrhs<T, SC, MC, R, W, NR>(xl, fields, slab, k, K, ty * OY - K, tx * OX - K, j0, parity);
 }
 
-// Frequency-adapted backward-differences damped leapfrog I_abd (Sec. 6) with
-// the cell damping, blocked like tb_tile2, on one real part of the complex
-// field of S_T^abd.  Its recurrence has real coefficients,
+// One step of the frequency-adapted backward-differences damped leapfrog
+// I_abd (Sec. 6) with the cell damping, blocked like tb_tile2, on one real
+// part of the complex field of S_T^abd.  Its recurrence has real coefficients,
 //   x_{n+1} = A[x_n] + B[x_{n-1} - cos(theta) x_n] - x_{n-1} + fa Re F + fb Im F,
 // with A the I_acd step stencil over the cell slowness and B the damping
 // stencil (mass classes only) over the cell damping, so the real and
@@ -1089,6 +1089,7 @@ void k_sweep2d_tb_mrhs(const BFieldT<T> *__restrict__ fields, const int *__restr
 // come from DPP.  A step still reaches one node, so the exact region, the
 // window of rows a wave must update and the output rules are those of
 // tb_tile2.  Mass tables with corner entries are not covered here.
+// tb_tile_abd2 below applies it to both parts.
 template <typename T, int R, int US>
 __device__ __forceinline__ void abd_step(const T *__restrict__ xc, const T *__restrict__ wc,
                                          T *__restrict__ xn, T *__restrict__ wn, int rs, int rn,
@@ -1137,20 +1138,34 @@ __device__ __forceinline__ void abd_step(const T *__restrict__ xc, const T *__re
     wn[rn - US] = a[R - 1] - cth * b[R - 1];
 }
 
+// I_abd on both real parts of the complex field of S_T^abd in one launch.
+// The two recurrences share A, B and F and differ only in their forcing
+// scalars: the real part takes (fa, fb) of the launch's table (the Table 1
+// form, fa Re F + fb Im F = Re of the complex forcing) and the imaginary part
+// (-fb, fa), which is Im of the same complex forcing.  So one tile loads the
+// cells and F and folds A and B once for both, keeps x_n and x_{n-1} of both
+// parts in registers, and gives every step two independent updates.  Fields
+// are complex (the two parts interleaved).  LDS holds, per part, two copies
+// of x and of w; each copy keeps only the wave edge rows, in packed slots:
+// wave v's first row at slot 2v+1 and its last at 2v+2, so its south and
+// north neighbours (the previous wave's last row, the next wave's first) sit
+// at 2v and 2v+3, and slots 0 and 2W+1 are the zero pads of the tile.
 template <typename T, int R, int W>
-__device__ __forceinline__ void tb_tile_abd(T *__restrict__ ul, const T *__restrict__ u_in,
-                                            const T *__restrict__ up_in, T *__restrict__ u_out,
-                                            T *__restrict__ up_out, const T *__restrict__ m,
-                                            const T *__restrict__ rc,
-                                            const typename V2t<T>::type *__restrict__ F, int ny,
-                                            int nx, const Stencil<T> &sa, const Stencil<T> &sb,
-                                            T cth, int k, int halo, int gy0, int gx0,
-                                            const double *fa, const double *fb,
-                                            const int *out_step, double *const *out)
+__device__ __forceinline__ void tb_tile_abd2(T *__restrict__ ul,
+                                             const typename V2t<T>::type *__restrict__ u_in,
+                                             const typename V2t<T>::type *__restrict__ up_in,
+                                             typename V2t<T>::type *__restrict__ u_out,
+                                             typename V2t<T>::type *__restrict__ up_out,
+                                             const T *__restrict__ m, const T *__restrict__ rc,
+                                             const typename V2t<T>::type *__restrict__ F, int ny,
+                                             int nx, const Stencil<T> &sa, const Stencil<T> &sb,
+                                             T cth, int k, int halo, int gy0, int gx0,
+                                             const double *fa, const double *fb,
+                                             const int *out_step, double *const *out)
 {
     constexpr int EX = 64, EY = R * W;
     constexpr int US = EX + 2;
-    constexpr int UB = (EY + 2) * US;
+    constexpr int CB = (2 * W + 2) * US;     // one copy of one part's x or w
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r0 = wv * R;
@@ -1164,7 +1179,7 @@ __device__ __forceinline__ void tb_tile_abd(T *__restrict__ ul, const T *__restr
     // zero their update as in tb_tile2.
     T ca[R][6], cb[R][5];
     T fr[R], fi[R];
-    T u0[R], u1[R];   // x_n and x_{n-1} of the wave's nodes
+    T u0[2][R], u1[2][R];   // x_n and x_{n-1} of the real (0) and imaginary (1) part
     {
         T ma[R + 1], mb[R + 1], ra[R + 1], rb[R + 1];
         T on[R];
@@ -1185,12 +1200,16 @@ __device__ __forceinline__ void tb_tile_abd(T *__restrict__ ul, const T *__restr
             const int gy = gy0 + r0 + i;
             const bool in = xin && (unsigned)gy < (unsigned)ny;
             const int64_t row = (int64_t)gy * nx;
-            u0[i] = u1[i] = fr[i] = fi[i] = T(0);
+            u0[0][i] = u0[1][i] = u1[0][i] = u1[1][i] = fr[i] = fi[i] = T(0);
             on[i] = in ? T(1) : T(0);
             if (in) {
-                u0[i] = (u_in + row)[gx];
-                u1[i] = (up_in + row)[gx];
+                const auto a = (u_in + row)[gx];
+                const auto b = (up_in + row)[gx];
                 const auto f = (F + row)[gx];
+                u0[0][i] = a.x;
+                u0[1][i] = a.y;
+                u1[0][i] = b.x;
+                u1[1][i] = b.y;
                 fr[i] = f.x;
                 fi[i] = f.y;
             }
@@ -1216,29 +1235,22 @@ __device__ __forceinline__ void tb_tile_abd(T *__restrict__ ul, const T *__restr
             }
         }
     }
-    // LDS: x copies 0 and 1, then w copies 0 and 1; copy c holds level c (mod
-    // 2) of the first and last row of every wave at row r+1; the pads are zero
-    for (int t = threadIdx.x; t < US; t += 64 * W)
+    // copies per part p: x0 at (4p)CB, x1 at (4p+1)CB, w0 at (4p+2)CB, w1 at (4p+3)CB
+    for (int t = threadIdx.x; t < 8 * CB; t += 64 * W) ul[t] = T(0);
+    __syncthreads();
+    const int rs = 2 * wv * US + lane + 1, rn = (2 * wv + 3) * US + lane + 1;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            ul[c * UB + t] = T(0);
-            ul[c * UB + (EY + 1) * US + t] = T(0);
-        }
-    for (int t = threadIdx.x; t < EY + 2; t += 64 * W)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            ul[c * UB + t * US] = T(0);
-            ul[c * UB + t * US + EX + 1] = T(0);
-        }
-    ul[(r0 + 1) * US + lane + 1] = u0[0];
-    ul[(r0 + R) * US + lane + 1] = u0[R - 1];
-    ul[2 * UB + (r0 + 1) * US + lane + 1] = u1[0] - cth * u0[0];
-    ul[2 * UB + (r0 + R) * US + lane + 1] = u1[R - 1] - cth * u0[R - 1];
+    for (int p = 0; p < 2; ++p) {
+        ul[4 * p * CB + rs + US] = u0[p][0];
+        ul[4 * p * CB + rn - US] = u0[p][R - 1];
+        ul[(4 * p + 2) * CB + rs + US] = u1[p][0] - cth * u0[p][0];
+        ul[(4 * p + 2) * CB + rn - US] = u1[p][R - 1] - cth * u0[p][R - 1];
+    }
     __syncthreads();
 
-    const int rs = r0 * US + lane + 1, rn = (r0 + R + 1) * US + lane + 1;
     const bool xout = lane >= halo && lane < EX - halo && xin;
-    auto snapshot = [&](int s, const T(&v)[R]) {
+    // complex outputs: both parts of a node in one 16-byte (8-byte) store
+    auto snapshot = [&](int s, const T(&v0)[R], const T(&v1)[R]) {
         if (s + 1 == out_step[0] || s + 1 == out_step[1]) {
             double *o = (s + 1 == out_step[0]) ? out[0] : out[1];
 #pragma unroll
@@ -1246,24 +1258,31 @@ __device__ __forceinline__ void tb_tile_abd(T *__restrict__ ul, const T *__restr
                 const int r = r0 + i;
                 const int gy = gy0 + r;
                 if (r >= halo && r < EY - halo && (unsigned)gy < (unsigned)ny && xout)
-                    (o + 2 * (int64_t)gy * nx)[2 * gx] = (double)v[i];
+                    ((double2 *)o)[(int64_t)gy * nx + gx] = make_double2((double)v0[i], (double)v1[i]);
             }
         }
     };
     auto active = [&](int s) { return r0 + R > s + 1 && r0 < EY - 1 - s; };
-    T *x0 = ul, *x1 = ul + UB, *w0 = ul + 2 * UB, *w1 = ul + 3 * UB;
     for (int s = 0; s < k; s += 2) {
         if (active(s)) {
-            abd_step<T, R, US>(x0, w0, x1, w1, rs, rn, ca, cb, fr, fi, cth, u0, u1,
-                               (T)fa[s], (T)fb[s]);
-            snapshot(s, u1);
+            const T fa0 = (T)fa[s], fb0 = (T)fb[s];
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+                abd_step<T, R, US>(ul + 4 * p * CB, ul + (4 * p + 2) * CB, ul + (4 * p + 1) * CB,
+                                   ul + (4 * p + 3) * CB, rs, rn, ca, cb, fr, fi, cth, u0[p], u1[p],
+                                   p ? -fb0 : fa0, p ? fa0 : fb0);
+            snapshot(s, u1[0], u1[1]);
         }
         __syncthreads();
         if (s + 1 == k) break;
         if (active(s + 1)) {
-            abd_step<T, R, US>(x1, w1, x0, w0, rs, rn, ca, cb, fr, fi, cth, u1, u0,
-                               (T)fa[s + 1], (T)fb[s + 1]);
-            snapshot(s + 1, u0);
+            const T fa0 = (T)fa[s + 1], fb0 = (T)fb[s + 1];
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+                abd_step<T, R, US>(ul + (4 * p + 1) * CB, ul + (4 * p + 3) * CB, ul + 4 * p * CB,
+                                   ul + (4 * p + 2) * CB, rs, rn, ca, cb, fr, fi, cth, u1[p], u0[p],
+                                   p ? -fb0 : fa0, p ? fa0 : fb0);
+            snapshot(s + 1, u0[0], u0[1]);
         }
         __syncthreads();
     }
@@ -1273,35 +1292,42 @@ __device__ __forceinline__ void tb_tile_abd(T *__restrict__ ul, const T *__restr
         const int gy = gy0 + r;
         if (r >= halo && r < EY - halo && (unsigned)gy < (unsigned)ny && xout) {
             const int64_t row = (int64_t)gy * nx;
-            (u_out + row)[gx] = (k & 1) ? u1[i] : u0[i];
-            (up_out + row)[gx] = (k & 1) ? u0[i] : u1[i];
+            typename V2t<T>::type a, b;
+            a.x = (k & 1) ? u1[0][i] : u0[0][i];
+            a.y = (k & 1) ? u1[1][i] : u0[1][i];
+            b.x = (k & 1) ? u0[0][i] : u1[0][i];
+            b.y = (k & 1) ? u0[1][i] : u1[1][i];
+            (u_out + row)[gx] = a;
+            (up_out + row)[gx] = b;
         }
     }
 }
 
 template <typename T, int R, int W>
-__global__ __launch_bounds__(64 * W) void k_sweep2d_abd_tb(const T *__restrict__ u_in, const T *__restrict__ up_in,
-                      T *__restrict__ u_out, T *__restrict__ up_out, const T *__restrict__ m,
-                      const T *__restrict__ rc, const typename V2t<T>::type *__restrict__ F,
-                      int ny, int nx, Stencil<T> sa, Stencil<T> sb, T cth, TBCoef cf,
-                      int tiles_x, int ntiles, int per_xcd)
+__global__ __launch_bounds__(64 * W) void k_sweep2d_abd_tb2(
+    const typename V2t<T>::type *__restrict__ u_in, const typename V2t<T>::type *__restrict__ up_in,
+    typename V2t<T>::type *__restrict__ u_out, typename V2t<T>::type *__restrict__ up_out,
+    const T *__restrict__ m, const T *__restrict__ rc, const typename V2t<T>::type *__restrict__ F,
+    int ny, int nx, Stencil<T> sa, Stencil<T> sb, T cth, TBCoef cf, int tiles_x, int ntiles,
+    int per_xcd)
 {
     constexpr int EX = 64, EY = R * W;
-    __shared__ T ul[4 * (EY + 2) * (EX + 2)];
+    __shared__ T ul[8 * (2 * W + 2) * (EX + 2)];
     const int id = blockIdx.x;
     const int tile = (id % 8) * per_xcd + id / 8;
     if (tile >= ntiles) return;
     const int k = cf.k;
     const int OX = EX - 2 * k, OY = EY - 2 * k;
     const int ty = tile / tiles_x, tx = tile % tiles_x;
-    tb_tile_abd<T, R, W>(ul, u_in, up_in, u_out, up_out, m, rc, F, ny, nx, sa, sb, cth, k, k,
-                         ty * OY - k, tx * OX - k, cf.fa, cf.fb, cf.out_step, cf.out);
+    tb_tile_abd2<T, R, W>(ul, u_in, up_in, u_out, up_out, m, rc, F, ny, nx, sa, sb, cth, k, k,
+                          ty * OY - k, tx * OX - k, cf.fa, cf.fb, cf.out_step, cf.out);
 }
 
 template <typename T, int R, int W>
-static hipError_t launch_abd_tb_t(const TBArgs &a, const Stencil<T> &sa, const Stencil<T> &sb,
-                                  hipStream_t s)
+static hipError_t launch_abd_tb2_t(const TBArgs &a, const Stencil<T> &sa, const Stencil<T> &sb,
+                                   hipStream_t s)
 {
+    using V2 = typename V2t<T>::type;
     constexpr int EX = 64, EY = R * W;
     const int k = a.cf.k;
     const int OX = EX - 2 * k, OY = EY - 2 * k;
@@ -1309,11 +1335,10 @@ static hipError_t launch_abd_tb_t(const TBArgs &a, const Stencil<T> &sa, const S
     const int tiles_x = (a.nx + OX - 1) / OX, tiles_y = (a.ny + OY - 1) / OY;
     const int ntiles = tiles_x * tiles_y;
     const int per_xcd = (ntiles + 7) / 8;
-    hipLaunchKernelGGL((k_sweep2d_abd_tb<T, R, W>), dim3(8 * per_xcd), dim3(64 * W), 0, s,
-                       (const T *)a.u_in, (const T *)a.up_in, (T *)a.u_out, (T *)a.up_out,
-                       (const T *)a.m, (const T *)a.rc,
-                       (const typename V2t<T>::type *)a.F, a.ny, a.nx, sa, sb, (T)a.cth, a.cf,
-                       tiles_x, ntiles, per_xcd);
+    hipLaunchKernelGGL((k_sweep2d_abd_tb2<T, R, W>), dim3(8 * per_xcd), dim3(64 * W), 0, s,
+                       (const V2 *)a.u_in, (const V2 *)a.up_in, (V2 *)a.u_out, (V2 *)a.up_out,
+                       (const T *)a.m, (const T *)a.rc, (const V2 *)a.F, a.ny, a.nx, sa, sb,
+                       (T)a.cth, a.cf, tiles_x, ntiles, per_xcd);
     return hipGetLastError();
 }
 
@@ -1564,29 +1589,30 @@ hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hip
     }
 }
 
-// I_abd: shapes 4..7 as for tb_tile2 in FP32, 5 and 7 in FP64 (its 12 words
-// of per-node state do not fit the register file in the others); mass tables
-// with corner entries are refused (the one-step kernel runs them)
-hipError_t launch_sweep2d_abd_tb_f64(const TBArgs &a, const Stencil<double> &sa,
-                                     const Stencil<double> &sb, hipStream_t s)
+// I_abd on both parts of a complex field: shapes 4..7 as for tb_tile2 in
+// FP32, 5 and 7 in FP64 (its 17 words of per-node state do not fit the
+// register file in the others); mass tables with corner entries are refused
+// (the one-step kernel runs them)
+hipError_t launch_sweep2d_abd2_tb_f64(const TBArgs &a, const Stencil<double> &sa,
+                                      const Stencil<double> &sb, hipStream_t s)
 {
     if (a.sc > 3 || a.mc > 2) return hipErrorInvalidValue;
     switch (a.shape) {
-    case 5: return launch_abd_tb_t<double, 4, 8>(a, sa, sb, s);
-    case 7: return launch_abd_tb_t<double, 2, 16>(a, sa, sb, s);
+    case 5: return launch_abd_tb2_t<double, 4, 8>(a, sa, sb, s);
+    case 7: return launch_abd_tb2_t<double, 2, 16>(a, sa, sb, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sweep2d_abd_tb_f32(const TBArgs &a, const Stencil<float> &sa,
-                                     const Stencil<float> &sb, hipStream_t s)
+hipError_t launch_sweep2d_abd2_tb_f32(const TBArgs &a, const Stencil<float> &sa,
+                                      const Stencil<float> &sb, hipStream_t s)
 {
     if (a.sc > 3 || a.mc > 2) return hipErrorInvalidValue;
     switch (a.shape) {
-    case 4: return launch_abd_tb_t<float, 4, 16>(a, sa, sb, s);
-    case 5: return launch_abd_tb_t<float, 4, 8>(a, sa, sb, s);
-    case 6: return launch_abd_tb_t<float, 8, 8>(a, sa, sb, s);
-    case 7: return launch_abd_tb_t<float, 2, 16>(a, sa, sb, s);
+    case 4: return launch_abd_tb2_t<float, 4, 16>(a, sa, sb, s);
+    case 5: return launch_abd_tb2_t<float, 4, 8>(a, sa, sb, s);
+    case 6: return launch_abd_tb2_t<float, 8, 8>(a, sa, sb, s);
+    case 7: return launch_abd_tb2_t<float, 2, 16>(a, sa, sb, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -165,12 +165,14 @@ int tb2d_tiles(int shape, int K, int ny, int nx);
 
 hipError_t launch_sweep2d_tb_f64(const TBArgs &a, const Stencil<double> &st, hipStream_t s);
 hipError_t launch_sweep2d_tb_f32(const TBArgs &a, const Stencil<float> &st, hipStream_t s);
-// blocked I_abd on one real part of the complex field (shapes 4..8, mass
-// tables without corner entries)
-hipError_t launch_sweep2d_abd_tb_f64(const TBArgs &a, const Stencil<double> &sa,
-                                     const Stencil<double> &sb, hipStream_t s);
-hipError_t launch_sweep2d_abd_tb_f32(const TBArgs &a, const Stencil<float> &sa,
-                                     const Stencil<float> &sb, hipStream_t s);
+// blocked I_abd (shapes 4..7, mass tables without corner entries) on both
+// real parts of a complex field in one launch: u_in, up_in, u_out, up_out
+// complex (parts interleaved), forcing table of the real part in its Table 1
+// form (the imaginary part takes (-fb, fa)), out[] complex128
+hipError_t launch_sweep2d_abd2_tb_f64(const TBArgs &a, const Stencil<double> &sa,
+                                      const Stencil<double> &sb, hipStream_t s);
+hipError_t launch_sweep2d_abd2_tb_f32(const TBArgs &a, const Stencil<float> &sa,
+                                      const Stencil<float> &sb, hipStream_t s);
 int tb2d_tile_rows(int shape, bool f64);
 int tb2d_tile_cols(int shape);            // 64, or 128 for the two-column shapes 9..13
 inline bool tb2d_f32_only(int shape) { return shape == 2 || shape == 8 || shape == 12 || shape == 13; }
@@ -360,7 +362,7 @@ struct tdp_op {
     tdp::Stencil<double> st_I{}, st_B{};    // Im H and (beta dt/(alpha omega)) Im H (mass classes)
     tdp::Stencil<float> st_B32{};
     float *rc32 = nullptr;                  // FP32 copy of the cell damping
-    void *u4 = nullptr;                     // third complex field of the I_abd loop
+    void *u4 = nullptr, *u5 = nullptr;      // third and fourth complex fields of the I_abd loops
     tdp::Stencil<float> st_step32{};
     // device buffers
     double *m = nullptr;       // cell slowness

@@ -134,7 +134,7 @@ ABD_GRIDS = [(37, 150), (130, 77), (1, 9), (5, 200), (64, 64)]
 
 @pytest.mark.parametrize("n", ABD_GRIDS)
 def test_abd_blocked_tiles_and_depths(n):
-    """The blocked I_abd kernel (two real passes of k steps per launch) on every
+    """The blocked I_abd kernel (both real parts, k steps per launch) on every
     FP64 tile shape it takes, depths 1..8 (odd, and not dividing N_s), graph
     on and off, against the oracle's S_T^abd; grids of one row, ragged, and
     spanning several tiles."""
@@ -192,7 +192,7 @@ def test_abd_autotune_picks_a_candidate():
 def test_abd_blocked_degenerate_damping():
     """Degenerate cell damping: R = 0 everywhere (B vanishes, only the
     constant centre term of the damping stencil is left) and R nonzero on a
-    single node; the blocked two-pass I_abd against the oracle."""
+    single node; the blocked I_abd against the oracle."""
     p, R = problem((50, 90), 21)
     for name, RR in (("zero", np.zeros_like(R)), ("one node", np.where(np.arange(R.size).reshape(R.shape) == 2000, 3.0 * p.omega, 0.0))):
         g, o = ops(p, RR)
