@@ -70,6 +70,12 @@ struct tdp_batch {
     GsField *gs_host = nullptr, *gs_dev = nullptr;
     double *gstage = nullptr;
     size_t gs_n = 0, gstage_n = 0;
+    // the other batched GMRES steps (update, H-apply, residual norm):
+    // descriptors (pinned host, device) and the |r|^2 of every field (two
+    // doubles per field, device and pinned host)
+    TrField *tr_host = nullptr, *tr_dev = nullptr;
+    double *tr_out = nullptr, *tr_outh = nullptr;
+    size_t tr_n = 0;
 };
 
 static void free_batch(tdp_batch *b)
@@ -90,6 +96,10 @@ static void free_batch(tdp_batch *b)
     if (b->gs_host) (void)hipHostFree(b->gs_host);
     (void)hipFree(b->gs_dev);
     (void)hipFree(b->gstage);
+    if (b->tr_host) (void)hipHostFree(b->tr_host);
+    if (b->tr_outh) (void)hipHostFree(b->tr_outh);
+    (void)hipFree(b->tr_dev);
+    (void)hipFree(b->tr_out);
     delete b;
 }
 
@@ -192,6 +202,7 @@ static int build_fields(tdp_batch *b, const int *T_op, double rho)
         x.m = (const T *)(b->f64 ? (const void *)op->m : (const void *)op->m32);
         x.dn = (const T *)(b->f64 ? (const void *)op->dn : (const void *)op->dn32);
         x.F = b->f64 ? fl.pin : fl.Fst;
+        x.Fin = fl.pin;
         x.a0 = (T *)fl.a0;
         x.a1 = (T *)fl.a1;
         x.b0 = (T *)fl.b0;
@@ -306,6 +317,11 @@ static int batch_precond(tdp_batch *b, const int *T_op, double rho, const std::v
             sc.stiles = spre.back();
             launches.push_back(sc);
         }
+        // the active fields, for the stage-in launch
+        const int ao = (int)host.size();
+        host.insert(host.end(), act.begin(), act.end());
+        int64_t n_max = 0;
+        for (int q : act) n_max = std::max(n_max, b->f[q].N);
         int *dsched = nullptr;
         if (hipMalloc(&dsched, sizeof(int) * std::max<size_t>(1, host.size())) != hipSuccess)
             TDP_BFAIL(TDP_ENOMEM, "schedule allocation failed");
@@ -314,14 +330,8 @@ static int batch_precond(tdp_batch *b, const int *T_op, double rho, const std::v
         TDP_CHECK_HIP(hipStreamSynchronize(s));
         hipGraph_t g;
         TDP_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        hipError_t le = hipSuccess;
-        const size_t es = b->f64 ? sizeof(double) : sizeof(float);
-        for (int q : act) {
-            const auto &fl = b->f[q];
-            if (le == hipSuccess && !b->f64) le = launch_cvt_c128_to_c64(fl.pin, fl.Fst, fl.N, s);
-            if (le == hipSuccess) le = launch_fill_zero(fl.a0, es * fl.N, s);
-            if (le == hipSuccess) le = launch_fill_zero(fl.a1, es * fl.N, s);
-        }
+        hipError_t le = launch_batch_stage_in(b->dfields, dsched + ao, (int)act.size(), n_max,
+                                              b->f64, s);
         for (int L = 0; L < nl && le == hipSuccess; ++L) {
             const Sched &sc = launches[L];
             if (sc.n > 0) {
@@ -574,6 +584,24 @@ static int ensure_field_krylov(tdp_batch *b, int m)
             TDP_BFAIL(TDP_ENOMEM, "batch descriptor allocation failed");
         b->gs_n = b->f.size();
     }
+    if (b->f.size() > b->tr_n) {
+        (void)hipStreamSynchronize(b->s);
+        if (b->tr_host) (void)hipHostFree(b->tr_host);
+        if (b->tr_outh) (void)hipHostFree(b->tr_outh);
+        (void)hipFree(b->tr_dev);
+        (void)hipFree(b->tr_out);
+        b->tr_host = nullptr;
+        b->tr_outh = nullptr;
+        b->tr_dev = nullptr;
+        b->tr_out = nullptr;
+        const size_t n = b->f.size();
+        if (hipHostMalloc(&b->tr_host, sizeof(TrField) * n) != hipSuccess ||
+            hipHostMalloc(&b->tr_outh, sizeof(double) * 2 * n) != hipSuccess ||
+            hipMalloc(&b->tr_dev, sizeof(TrField) * n) != hipSuccess ||
+            hipMalloc(&b->tr_out, sizeof(double) * 2 * n) != hipSuccess)
+            TDP_BFAIL(TDP_ENOMEM, "batch descriptor allocation failed");
+        b->tr_n = n;
+    }
     return TDP_OK;
 }
 
@@ -654,6 +682,51 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
         TDP_CHECK_HIP(launch_maxpy(x_out, fl.V, fl.N, S.k_used, dy, 1.0, fl.N, s));
         return TDP_OK;
     };
+    // batched per-field steps: descriptors collected by tr_add, issued as one
+    // launch sequence by tr_launch (r = F - H xh or H xh, optionally after
+    // x_out = x_in + V y and followed by |r|^2 into b->tr_out at 2q)
+    int ntr = 0, tr_nblk = 0, tr_ny = 0, tr_nx = 0;
+    int64_t tr_nmax = 0;
+    auto tr_add = [&](size_t q, const void *xh, const void *Fq, void *r, bool norm, int k,
+                      void *x_out, const void *x_in, const double *ydev) {
+        const auto &fl = b->f[q];
+        const tdp_op *op = b->ops[fl.op];
+        TrField &g = b->tr_host[ntr++];
+        g.V = (const double2 *)fl.V;
+        g.x_in = (const double2 *)x_in;
+        g.x_out = (double2 *)x_out;
+        g.y = ydev;
+        g.xh = (const double2 *)xh;
+        g.F = (const double2 *)Fq;
+        g.r = (double2 *)r;
+        g.m = op->m;
+        g.rw = op->rw;
+        g.red = fl.red;
+        g.out = norm ? b->tr_out + 2 * q : nullptr;
+        g.st = op->st_H;
+        g.N = fl.N;
+        g.k = k;
+        g.nblk = blas_nblocks(fl.N);
+        g.ny = op->n[0];
+        g.nx = op->n[1];
+        tr_nblk = std::max(tr_nblk, g.nblk);
+        tr_ny = std::max(tr_ny, g.ny);
+        tr_nx = std::max(tr_nx, g.nx);
+        tr_nmax = std::max(tr_nmax, g.N);
+    };
+    auto tr_launch = [&](bool upd, bool norm) -> int {
+        if (ntr == 0) return TDP_OK;
+        TDP_CHECK_HIP(hipMemcpyAsync(b->tr_dev, b->tr_host, sizeof(TrField) * ntr,
+                                     hipMemcpyHostToDevice, s));
+        TDP_CHECK_HIP(launch_tr_multi(b->tr_dev, ntr, upd, norm, b->general, tr_nblk, tr_nmax,
+                                      tr_ny, tr_nx, s));
+        if (norm)
+            TDP_CHECK_HIP(hipMemcpyAsync(b->tr_outh, b->tr_out, sizeof(double) * 2 * nf,
+                                         hipMemcpyDeviceToHost, s));
+        ntr = tr_nblk = tr_ny = tr_nx = 0;
+        tr_nmax = 0;
+        return TDP_OK;
+    };
     auto end_cycle = [&](size_t q) -> int {
         FS &S = st[q];
         ++S.restarts;
@@ -683,19 +756,19 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
         bool anyA = false;
         for (size_t q = 0; q < nf; ++q)
             if (st[q].ph == NEED_RES) {
-                tdp_op *op = b->ops[b->f[q].op];
-                TDP_CHECK(apply_H_on(op, U[q], F[q], b->f[q].rv, s));
-                TDP_CHECK(norm2_async(q, b->f[q].rv, b->f[q].dco));
-                TDP_CHECK_HIP(hipMemcpyAsync(hb + q * hs, b->f[q].dco, sizeof(double), hipMemcpyDeviceToHost, s));
+                tr_add(q, U[q], F[q], b->f[q].rv, true, 0, nullptr, nullptr, nullptr);
                 anyA = true;
             }
-        if (anyA) TDP_CHECK_HIP(hipStreamSynchronize(s));
+        if (anyA) {
+            TDP_CHECK(tr_launch(false, true));
+            TDP_CHECK_HIP(hipStreamSynchronize(s));
+        }
         bool any = false;
         for (size_t q = 0; q < nf; ++q) {
             FS &S = st[q];
             needP[q] = 0;
             if (S.ph == NEED_RES) {
-                S.rel = std::sqrt(hb[q * hs]) / S.bnorm;
+                S.rel = std::sqrt(b->tr_outh[2 * q]) / S.bnorm;
                 if (!std::isfinite(S.rel) && S.its == 0 && S.restarts == 0)
                     TDP_BFAIL(TDP_EINVAL, "non-finite residual of field %zu: U holds NaN or Inf", q);
                 if (tolmode && S.rel <= cfg->tol) {
@@ -712,13 +785,13 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
                 S.ph = AWAIT_P0;
                 needP[q] = 1;
             } else if (S.ph == NEED_HV) {
-                tdp_op *op = b->ops[b->f[q].op];
-                TDP_CHECK(apply_H_on(op, col(q, S.i), nullptr, b->f[q].pin, s));
+                tr_add(q, col(q, S.i), nullptr, b->f[q].pin, false, 0, nullptr, nullptr, nullptr);
                 S.ph = AWAIT_P;
                 needP[q] = 1;
             }
             any = any || needP[q];
         }
+        TDP_CHECK(tr_launch(false, false));
         if (!any) break;
         // stage B: one batched preconditioner application
         TDP_CHECK(batch_precond(b, Tv.data(), cfg->rho, needP));
@@ -824,16 +897,25 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
             h1 = nullptr;
             hb[q * hs + 4 * (m + 1) + 1] = hn;
             if (tolmode) {
+                // x = U + V y and its true residual, batched below (y goes
+                // through the host slot to the staging array)
                 solve_y(S);
-                TDP_CHECK(update(q, b->f[q].xv, U[q]));
-                tdp_op *op = b->ops[b->f[q].op];
-                TDP_CHECK(apply_H_on(op, b->f[q].xv, F[q], b->f[q].rv, s));
-                TDP_CHECK(norm2_async(q, b->f[q].rv, b->f[q].dco));
-                TDP_CHECK_HIP(hipMemcpyAsync(hb + q * hs, b->f[q].dco, sizeof(double), hipMemcpyDeviceToHost, s));
+                double *hy = hb + q * hs + 4 * (m + 1) + 2;
+                for (int k = 0; k < S.k_used; ++k) {
+                    hy[2 * k] = S.y[k].real();
+                    hy[2 * k + 1] = S.y[k].imag();
+                }
+                tr_add(q, b->f[q].xv, F[q], b->f[q].rv, true, S.k_used, b->f[q].xv, U[q],
+                       b->gstage + q * hs + 4 * (m + 1) + 2);
                 anyD = true;
             }
         }
-        if (anyD) TDP_CHECK_HIP(hipStreamSynchronize(s));
+        if (anyD) {
+            TDP_CHECK_HIP(hipMemcpyAsync(b->gstage, hb, sizeof(double) * hs * nf,
+                                         hipMemcpyHostToDevice, s));
+            TDP_CHECK(tr_launch(true, true));
+            TDP_CHECK_HIP(hipStreamSynchronize(s));
+        }
         // stage D: decisions
         for (size_t q = 0; q < nf; ++q) {
             if (!needP[q] || st[q].ph != AWAIT_P) continue;
@@ -842,7 +924,7 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
             const double est_cycle = std::abs(S.gv[S.k_used]) / S.beta0;
             bool end = false;
             if (tolmode) {
-                const double relt = std::sqrt(hb[q * hs]) / S.bnorm;
+                const double relt = std::sqrt(b->tr_outh[2 * q]) / S.bnorm;
                 S.rel = relt;
                 if (relt < S.best_rel) {
                     S.best_rel = relt;

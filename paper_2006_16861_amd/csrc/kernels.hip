@@ -436,20 +436,14 @@ hipError_t launch_sweep_abd_f32(const SweepArgs &a, void *uout, const float *rc,
 // With the cell damping (CD), Im H = omega sum_cells r_cell M_cell is the
 // mass-class stencil stI over the cell damping rc instead of diag(rw).
 template <int D, int SC, int MC, bool CD, bool NT>
-__global__ __launch_bounds__(256) void k_apply_H(const double *__restrict__ m,
-                                                 const double *__restrict__ rw,
-                                                 const double *__restrict__ rc,
-                                                 Stencil<double> st, Stencil<double> stI,
-                                                 const double2 *__restrict__ xv,
-                                                 const double2 *__restrict__ F,
-                                                 double2 *__restrict__ y_out, int nz, int ny,
-                                                 int nx)
+__device__ __forceinline__ double2 apply_H_at(const double *__restrict__ m,
+                                              const double *__restrict__ rw,
+                                              const double *__restrict__ rc,
+                                              const Stencil<double> &st, const Stencil<double> &stI,
+                                              const double2 *__restrict__ xv,
+                                              const double2 *__restrict__ F, int z, int y, int x,
+                                              int64_t i, int nz, int ny, int nx)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= nx || y >= ny) return;
-    const int64_t i = ((int64_t)z * ny + y) * nx + x;
     double w[1 << D];
     load_cells<D>(m, z, y, x, ny, nx, w);
     const double *xs = (const double *)xv;
@@ -481,6 +475,25 @@ __global__ __launch_bounds__(256) void k_apply_H(const double *__restrict__ m,
         o.x = ldnt<NT>(&F[i].x) - o.x;
         o.y = ldnt<NT>(&F[i].y) - o.y;
     }
+    return o;
+}
+
+template <int D, int SC, int MC, bool CD, bool NT>
+__global__ __launch_bounds__(256) void k_apply_H(const double *__restrict__ m,
+                                                 const double *__restrict__ rw,
+                                                 const double *__restrict__ rc,
+                                                 Stencil<double> st, Stencil<double> stI,
+                                                 const double2 *__restrict__ xv,
+                                                 const double2 *__restrict__ F,
+                                                 double2 *__restrict__ y_out, int nz, int ny,
+                                                 int nx)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= nx || y >= ny) return;
+    const int64_t i = ((int64_t)z * ny + y) * nx + x;
+    const double2 o = apply_H_at<D, SC, MC, CD, NT>(m, rw, rc, st, stI, xv, F, z, y, x, i, nz, ny, nx);
     stnt<NT>(o.x, &y_out[i].x);
     stnt<NT>(o.y, &y_out[i].y);
 }
@@ -954,6 +967,112 @@ hipError_t launch_gs_step_multi(const GsField *gf, int nf, int nv_max, int nblk_
     hipLaunchKernelGGL(k_gs_dot_final, dim3(1, nf), dim3(256), 0, s, gf, 2);
     hipLaunchKernelGGL(k_gs_scale, ga, dim3(256), 0, s, gf);
     hipLaunchKernelGGL(k_gs_gather, dim3(nf), dim3(256), 0, s, gf);
+    return hipGetLastError();
+}
+
+// The other per-field steps of the lockstep GMRES, for several 2-D fields
+// at once (block z or y is the field), each as the single-field kernels
+// would do it: x_out = x_in + V y (a copy and k_maxpy), r = F - H xh or
+// r = H xh (k_apply_H), |r|^2 (launch_mdot with the field's own block
+// count), so the results equal the field-by-field path bit for bit.
+__global__ __launch_bounds__(256) void k_tr_update(const TrField *__restrict__ tf)
+{
+    const TrField g = tf[blockIdx.y];
+    if (g.k <= 0) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k < g.k; ++k) {
+            const double2 v = g.V[(int64_t)k * g.N + i];
+            const double cr = g.y[2 * k], ci = g.y[2 * k + 1];
+            re += cr * v.x - ci * v.y;
+            im += cr * v.y + ci * v.x;
+        }
+        double2 o = g.x_in[i];
+        o.x += 1.0 * re;
+        o.y += 1.0 * im;
+        g.x_out[i] = o;
+    }
+}
+
+template <int SC, int MC>
+__global__ __launch_bounds__(256) void k_tr_H(const TrField *__restrict__ tf)
+{
+    const TrField &g = tf[blockIdx.z];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int ny = g.ny, nx = g.nx;
+    if (x >= nx || y >= ny) return;
+    const int64_t i = (int64_t)y * nx + x;
+    g.r[i] = apply_H_at<2, SC, MC, false, false>(g.m, g.rw, nullptr, g.st, g.st, g.xh, g.F, 0, y,
+                                                 x, i, 1, ny, nx);
+}
+
+__global__ __launch_bounds__(256) void k_tr_norm_partial(const TrField *__restrict__ tf)
+{
+    __shared__ double sm[8];
+    const TrField g = tf[blockIdx.y];
+    if (!g.out || (int)blockIdx.x >= g.nblk) return;
+    double re = 0.0, im = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.N;
+         i += (int64_t)g.nblk * blockDim.x) {
+        const double2 a = g.r[i], b = g.r[i];
+        re += a.x * b.x + a.y * b.y;
+        im += a.x * b.y - a.y * b.x;
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if ((threadIdx.x & 63) == 0) {
+        sm[threadIdx.x >> 6] = re;
+        sm[4 + (threadIdx.x >> 6)] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double *p = g.red + 2 * (int64_t)blockIdx.x;
+        p[0] = (sm[0] + sm[1]) + (sm[2] + sm[3]);
+        p[1] = (sm[4] + sm[5]) + (sm[6] + sm[7]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tr_norm_final(const TrField *__restrict__ tf)
+{
+    __shared__ double sm[8];
+    const TrField g = tf[blockIdx.x];
+    if (!g.out) return;
+    double re = 0.0, im = 0.0;
+    for (int i = threadIdx.x; i < g.nblk; i += blockDim.x) {
+        re += g.red[2 * i];
+        im += g.red[2 * i + 1];
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if ((threadIdx.x & 63) == 0) {
+        sm[threadIdx.x >> 6] = re;
+        sm[4 + (threadIdx.x >> 6)] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        g.out[0] = (sm[0] + sm[1]) + (sm[2] + sm[3]);
+        g.out[1] = (sm[4] + sm[5]) + (sm[6] + sm[7]);
+    }
+}
+
+hipError_t launch_tr_multi(const TrField *tf, int nf, bool update, bool norm, bool general,
+                           int nblk_max, int64_t n_max, int ny_max, int nx_max, hipStream_t s)
+{
+    if (nf <= 0) return hipSuccess;
+    if (nf > 65535 || ny_max < 1 || nx_max < 1) return hipErrorInvalidValue;
+    if (update)
+        hipLaunchKernelGGL(k_tr_update, dim3(grid_for(n_max), nf), dim3(256), 0, s, tf);
+    const dim3 gh((nx_max + 63) / 64, (ny_max + 3) / 4, nf), bh(64, 4, 1);
+    if (general)
+        hipLaunchKernelGGL((k_tr_H<3, 3>), gh, bh, 0, s, tf);
+    else
+        hipLaunchKernelGGL((k_tr_H<3, 2>), gh, bh, 0, s, tf);
+    if (norm) {
+        hipLaunchKernelGGL(k_tr_norm_partial, dim3(nblk_max, nf), dim3(256), 0, s, tf);
+        hipLaunchKernelGGL(k_tr_norm_final, dim3(nf), dim3(256), 0, s, tf);
+    }
     return hipGetLastError();
 }
 

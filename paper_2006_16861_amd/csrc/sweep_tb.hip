@@ -23,6 +23,8 @@
 // that XCD's L2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "tdp_internal.h"
 #include "lanes.h"
 
@@ -1455,6 +1457,41 @@ static hipError_t launch_tb_batch_t(const TBBatchLaunch &L, hipStream_t s)
         else TDP_BL(3, 2, false);
     }
 #undef TDP_BL
+    return hipGetLastError();
+}
+
+// Start of a batched application: every listed field's recurrence fields
+// are zeroed and (FP32) its right-hand side is rounded to the staged copy,
+// one launch for all fields (block y is the list entry).
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_stage_in(const BFieldT<T> *__restrict__ fields,
+                                                        const int *__restrict__ list)
+{
+    const BFieldT<T> &f = fields[list[blockIdx.y]];
+    const int64_t N = (int64_t)f.ny * f.nx;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if constexpr (sizeof(T) == 4) {
+            const double2 v = ((const double2 *)f.Fin)[i];
+            ((float2 *)f.F)[i] = make_float2((float)v.x, (float)v.y);
+        }
+        f.a0[i] = T(0);
+        f.a1[i] = T(0);
+    }
+}
+
+hipError_t launch_batch_stage_in(const void *fields, const int *list, int n, int64_t n_max,
+                                 bool f64, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (n > 65535) return hipErrorInvalidValue;
+    const int blocks = (int)std::min<int64_t>(std::max<int64_t>((n_max + 255) / 256, 1), 2048);
+    if (f64)
+        hipLaunchKernelGGL(k_batch_stage_in<double>, dim3(blocks, n), dim3(256), 0, s,
+                           (const BFieldT<double> *)fields, list);
+    else
+        hipLaunchKernelGGL(k_batch_stage_in<float>, dim3(blocks, n), dim3(256), 0, s,
+                           (const BFieldT<float> *)fields, list);
     return hipGetLastError();
 }
 

@@ -136,6 +136,7 @@ struct BFieldT {
     int Ns, jsnap;
     const T *m, *dn;
     const void *F;              // staged right-hand side (complex, T pairs)
+    const void *Fin;            // the complex128 right-hand side it is staged from
     T *a0, *a1, *b0, *b1;
     const double *tab;          // forcing scalars (fa, fb) of steps 0..Ns-1
     double *U;                  // complex128 output
@@ -149,6 +150,11 @@ struct TBBatchLaunch {
     bool general;               // class pattern (3,3) instead of (3,2)
 };
 hipError_t launch_sweep2d_tb_batch(const TBBatchLaunch &L, bool f64, hipStream_t s);
+// Start of a batched application for the n fields listed (device indices into
+// the BFieldT<T> array): both recurrence fields a0, a1 zeroed and, in FP32,
+// Fin converted to the staged F.  n_max: the largest field.
+hipError_t launch_batch_stage_in(const void *fields, const int *list, int n, int64_t n_max,
+                                 bool f64, hipStream_t s);
 // Shared-medium batched tile: workgroup -> (slab, tile); a slab lists up to
 // mrhs_nr(shape) fields of one medium (-1 past its end), nslab x NR ints.
 struct TBMrhsLaunch {
@@ -299,6 +305,25 @@ hipError_t launch_gs_step_multi(const GsField *gf, int nf, int nv_max, int nblk_
                                 int64_t n_max, hipStream_t s);
 hipError_t launch_scale_by_invnorm(void *v, const void *w, const double *nrm2, int64_t N,
                                    hipStream_t s);
+// The other per-field steps of the lockstep GMRES on several 2-D fields at
+// once: (update) x_out = x_in + V y for fields with k > 0; r = F - H xh, or
+// r = H xh when F is null, with the field's operator (m, rw, st = its H
+// stencil; diagonal damping); (norm) |r|^2 to out[0] (and the imaginary
+// part, 0, to out[1]) for fields with out set, through red (2 nblk doubles).
+struct TrField {
+    const double2 *V, *x_in;
+    double2 *x_out;
+    const double *y;
+    const double2 *xh, *F;
+    double2 *r;
+    const double *m, *rw;
+    double *red, *out;
+    Stencil<double> st;
+    int64_t N;
+    int k, nblk, ny, nx;
+};
+hipError_t launch_tr_multi(const TrField *tf, int nf, bool update, bool norm, bool general,
+                           int nblk_max, int64_t n_max, int ny_max, int nx_max, hipStream_t s);
 
 // gradient
 hipError_t launch_grad_cells(int ndim, const int *n, double w2, const double *mass,
