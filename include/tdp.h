@@ -18,7 +18,9 @@
  * Conventions for every entry point:
  *  - Arrays are DEVICE pointers owned by the caller, contiguous, row-major
  *    [n0][n1][n2] (last axis fastest).  Complex arrays are interleaved
- *    complex128 (re, im pairs; torch.complex128).  Real node arrays are FP64.
+ *    complex128 (re, im pairs; torch.complex128), 16-byte aligned (as every
+ *    element of a torch.complex128 tensor is; others get TDP_EINVAL).  Real
+ *    node arrays are FP64.
  *  - All work is issued on the op's stream (tdp_op_desc.stream).  Calls that
  *    return results to the host (gmres) synchronise that stream.
  *  - Return value: TDP_OK (0), a positive status for a completed call with a

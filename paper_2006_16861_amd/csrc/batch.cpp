@@ -412,7 +412,8 @@ extern "C" int tdp_batch_precond(tdp_batch *b, const int *periods_T, double rho,
     StreamJoin join(b->ops[0]->user_stream, b->s, b->ops[0]->ev);
     std::vector<char> active(b->f.size(), 1);
     for (size_t q = 0; q < b->f.size(); ++q) {
-        if (!F[q] || !U[q] || F[q] == U[q]) TDP_BFAIL(TDP_EINVAL, "bad F/U pointer for field %zu", q);
+        if (!F[q] || !U[q] || F[q] == U[q] || misaligned16(F[q]) || misaligned16(U[q]))
+            TDP_BFAIL(TDP_EINVAL, "bad F/U pointer for field %zu (NULL, aliased or not 16-byte aligned)", q);
         TDP_CHECK_HIP(hipMemcpyAsync(b->f[q].pin, F[q], 16 * b->f[q].N, hipMemcpyDeviceToDevice, b->s));
     }
     TDP_CHECK(batch_precond(b, periods_T, rho, active));
@@ -618,7 +619,8 @@ extern "C" int tdp_batch_solve(tdp_batch *b, const tdp_gmres_cfg *cfg, const int
     TDP_CHECK(check_periods(b, periods_T));
     const size_t nf = b->f.size();
     for (size_t q = 0; q < nf; ++q)
-        if (!F[q] || !U[q] || F[q] == U[q]) TDP_BFAIL(TDP_EINVAL, "bad F/U pointer for field %zu", q);
+        if (!F[q] || !U[q] || F[q] == U[q] || misaligned16(F[q]) || misaligned16(U[q]))
+            TDP_BFAIL(TDP_EINVAL, "bad F/U pointer for field %zu (NULL, aliased or not 16-byte aligned)", q);
     TDP_CHECK(ensure_field_krylov(b, m));
     StreamJoin join(b->ops[0]->user_stream, b->s, b->ops[0]->ev);
     hipStream_t s = b->s;

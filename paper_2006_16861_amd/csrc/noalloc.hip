@@ -55,6 +55,10 @@ extern "C" int tdp_precond_apply_noalloc(const tdp_op *cop, int periods_T, doubl
         set_error("F and U must not alias");
         return TDP_EINVAL;
     }
+    if (misaligned16(F) || misaligned16(U)) {
+        set_error("complex arrays must be 16-byte aligned");
+        return TDP_EINVAL;
+    }
     tdp_op *op = const_cast<tdp_op *>(cop);
     void *base = nullptr;
     {

@@ -445,6 +445,7 @@ extern "C" int tdp_apply_H(const tdp_op *op, const void *x, void *y)
     clear_error();
     if (!op || !x || !y) TDP_FAIL(TDP_EINVAL, "NULL argument");
     if (x == y) TDP_FAIL(TDP_EINVAL, "x and y must not alias");
+    if (misaligned16(x) || misaligned16(y)) TDP_FAIL(TDP_EINVAL, "complex arrays must be 16-byte aligned");
     StreamJoin join(op->user_stream, op->stream, op->ev);
     return apply_H_impl(op, x, nullptr, y);
 }
@@ -1188,6 +1189,7 @@ static int precond_entry(const tdp_op *cop, int T, double rho, int variant, cons
     clear_error();
     if (!cop || !F || !U) TDP_FAIL(TDP_EINVAL, "NULL argument");
     if (F == U) TDP_FAIL(TDP_EINVAL, "F and U must not alias");
+    if (misaligned16(F) || misaligned16(U)) TDP_FAIL(TDP_EINVAL, "complex arrays must be 16-byte aligned");
     tdp_op *op = const_cast<tdp_op *>(cop);
     StreamJoin join(op->user_stream, op->stream, op->ev);
     return precond_impl(op, T, rho, variant, F, U);
@@ -1676,6 +1678,7 @@ extern "C" int tdp_gmres_solve(const tdp_op *cop, const tdp_gmres_cfg *cfg, cons
     clear_error();
     if (!cop || !cfg || !F || !U) TDP_FAIL(TDP_EINVAL, "NULL argument");
     if (F == U) TDP_FAIL(TDP_EINVAL, "F and U must not alias");
+    if (misaligned16(F) || misaligned16(U)) TDP_FAIL(TDP_EINVAL, "complex arrays must be 16-byte aligned");
     tdp_op *op = const_cast<tdp_op *>(cop);
     StreamJoin join(op->user_stream, op->stream, op->ev);
     return gmres_impl(op, cfg, F, U, info);
@@ -1686,6 +1689,7 @@ extern "C" int tdp_grad_m(const tdp_op *cop, const void *lam, const void *U, dou
 {
     clear_error();
     if (!cop || !lam || !U || !grad) TDP_FAIL(TDP_EINVAL, "NULL argument");
+    if (misaligned16(lam) || misaligned16(U)) TDP_FAIL(TDP_EINVAL, "complex arrays must be 16-byte aligned");
     tdp_op *op = const_cast<tdp_op *>(cop);
     if (!op->gcell && hipMalloc(&op->gcell, sizeof(double) * op->Nc) != hipSuccess)
         TDP_FAIL(TDP_ENOMEM, "allocation failed");

@@ -55,6 +55,8 @@ struct Stencil {
 // The choice is a template parameter of the kernels (a run-time select between
 // the two load forms would be merged into one plain load).
 inline bool stream_nt(int64_t bytes) { return bytes > ((int64_t)192 << 20); }
+// complex128 arrays are read and written as 16-byte vectors
+inline bool misaligned16(const void *p) { return ((uintptr_t)p & 15) != 0; }
 template <bool NT, typename T>
 __device__ __forceinline__ T ldnt(const T *p)
 {

@@ -177,6 +177,18 @@ def test_zero_rhs_and_errors():
     with pytest.raises(tdp.TdpError) as ei:
         g.solve(dev(p.F), T=2, tol=1e-6, x0=dev(U0))
     assert ei.value.code == tdp.EINVAL
+    # complex arrays 8 bytes off a 16-byte boundary are refused before any
+    # work (the kernels move complex128 values as 16-byte vectors)
+    import ctypes
+    L = tdp.load()
+    buf = torch.zeros(2 * g.N + 2, dtype=torch.float64, device="cuda")
+    out = torch.zeros(p.n, dtype=torch.complex128, device="cuda")
+    odd = ctypes.c_void_p(buf.data_ptr() + 8)
+    good = ctypes.c_void_p(out.data_ptr())
+    assert L.tdp_precond_apply(g._h, 2, ctypes.c_double(0.25), odd, good) == tdp.EINVAL
+    assert L.tdp_apply_H(g._h, good, odd) == tdp.EINVAL
+    assert "16-byte" in tdp.last_error()
+    assert not out.abs().sum().item()
 
 
 def test_precond_f32_close_to_oracle():
