@@ -604,12 +604,18 @@ def form_adjoint(rho):
     op = tdp.Operator(torch.rsqrt(torch.as_tensor(m0, device="cuda")).contiguous(), R, p.omega,
                       p.h, steps_per_period=-1)
     napply = []
-    for s_ in range(F.shape[0]):
-        _, info = op.solve(F[s_].contiguous(), T=p.periods, tol=1e-6)
+    Fs = [F[s_].contiguous() for s_ in range(F.shape[0])]
+    for Fk in Fs:
+        _, info = op.solve(Fk, T=p.periods, tol=1e-6)
         napply.append(info.steps // (p.periods * op.nP))
+    # the plain FP64 GPU path on the same configuration: the forward solves
+    # alone, without autograd, the adjoint solves and the gradient kernels
+    _, dt_plain = _timed(lambda: [op.solve(Fk, T=p.periods, tol=1e-6) for Fk in Fs])
     res = {"workload": "smooth3d-128, 4 sources, 256 receivers", "gradients_per_s": 1.0 / dt,
            "solves_per_s": 8.0 / dt, "seconds": dt, "grad_norm": float(torch.linalg.norm(g)),
-           "forward_precond_applications": napply}
+           "forward_precond_applications": napply,
+           "plain_f64_solves_per_s": len(Fs) / dt_plain,
+           "solves_per_s_vs_plain_f64": (8.0 / dt) / (len(Fs) / dt_plain)}
     return res, {"problem": p, "n_P": op.nP, "napply_per_gradient": 2 * sum(napply)}
 
 
