@@ -269,7 +269,7 @@ int tdp_grad_m(const tdp_op *op, const void *lam, const void *U, double *grad);
 /* Tuning of the recurrence sweep (no effect on results beyond rounding).
  *  kernel       0 auto (kernel, depth and tile chosen by the library: the
  *               blocked 2-D sweep on tile 5 (FP64) or 8 (FP32) at depth 8, with
- *               the cell damping on tile 7 (FP64) or 5 (FP32); in 3-D the
+ *               the cell damping on tile 7 (FP64) or 4 (FP32); in 3-D the
  *               two-step streamed sweep for tables without corner entries
  *               (FP64 tile 1; FP32 tile 2, tile 1 below 3 * 2^20 nodes) and
  *               the one-step streamed sweep on tile 0 otherwise; tb_depth and

@@ -588,7 +588,7 @@ static void sweep_plan(const tdp_op *op, int variant, int *kernel, int *depth, i
             kern = 3;
             k = t = 0;
         }
-        if (op->dform == TDP_DAMP_CELL) t = f64 ? 7 : 5;
+        if (op->dform == TDP_DAMP_CELL) t = f64 ? 7 : 4;
     }
     // I_abd: the blocked 2-D kernel on the tiles that hold its per-node state
     // (mass tables without corner entries), else one step per launch
