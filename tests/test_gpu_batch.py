@@ -369,3 +369,31 @@ def test_batch_rejected_table1_cycle_ends_its_field():
     assert abs(infos[0].relres - r0) <= 1e-6 * r0
     r1 = rel(oracle.Op.from_problem(pc).apply_H(Us[1].cpu().numpy()), pc.F)
     assert infos[1].status == 0 and r1 <= 1e-6 * (1 + 1e-9)
+
+
+def test_batch_field_results_do_not_depend_on_the_other_fields():
+    """Lockstep GMRES runs each per-field step (CGS2, the true residual, the
+    H-apply) as one launch sequence over all live fields, with each field's
+    own reductions: a field solved in a batch of six ends bit for bit where it
+    ends solved alone (every field on its own tile), in tolerance mode and in
+    fixed-iteration mode."""
+    import torch
+    from paper_2006_16861_amd import tdp
+    probs, nrhs, ops, Fs = small_batch()
+    T = [p.periods for p in probs]
+    big = tdp.Batch(ops, nrhs)
+    big.set_tuning(8, 5, -1)
+    for op_i, mode in [(0, "tol"), (0, "fixed"), (2, "tol")]:
+        field = {0: 1, 2: 5}[op_i]
+        note(f"batch independence: field {field} ({mode})")
+        kw = dict(tol=1e-8) if mode == "tol" else dict(restart=4, fixed_iters=7)
+        Us, infos, rc = big.solve([dev(F) for F in Fs], T, **kw)
+        one = tdp.Batch([ops[op_i]], [1])
+        one.set_tuning(8, 5, -1)
+        U1, info1, rc1 = one.solve([dev(Fs[field])], [T[op_i]], **kw)
+        assert rc1 == rc == 0
+        assert info1[0].iters == infos[field].iters
+        assert info1[0].restarts == infos[field].restarts
+        assert torch.equal(U1[0], Us[field]), (field, mode)
+        one.close()
+    big.close()
